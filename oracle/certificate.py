@@ -22,7 +22,7 @@ from .ipm_dense import hessian_apply
 class Certificate:
     eps_d: float      # scaled stationarity residual
     eps_p: float      # scaled primal infeasibility
-    eps_c: float      # largest multiplier * slack product
+    eps_c: float      # largest multiplier * slack product, relative to the objective size
     gap: float        # relative primal-dual objective gap
     sign_ok: bool     # multipliers only on finite sides
     objective: float
@@ -76,10 +76,13 @@ def kkt_certificate(prob, x: np.ndarray, y_x: np.ndarray, y_A: Optional[np.ndarr
     eps_d = float(np.abs(rH).max(initial=0.0) / (1.0 + max(dscale)))
     cscale = 1.0 + max((float(c.max()) for c in cvals if c.size), default=0.0)
     eps_p = float(max((float(v.max()) for v in viol if v.size), default=0.0) / cscale)
-    eps_c = float(max((float(np.abs(c).max()) for c in comp if c.size), default=0.0))
+    # multiplier * slack has the units of the objective: measure it, and the
+    # gap, against the size of the objective's two terms
+    oscale = 1.0 + 0.5 * abs(float(x @ Hx)) + abs(float(prob.p @ x))
+    eps_c = float(max((float(np.abs(c).max()) for c in comp if c.size), default=0.0)) / oscale
     # dual objective of the QP: -1/2 x^T H x + c^T lambda
     d = -0.5 * float(x @ Hx) + dual_c
-    gap = abs(f - d) / (1.0 + abs(f))
+    gap = abs(f - d) / oscale
     return Certificate(eps_d=eps_d, eps_p=eps_p, eps_c=eps_c, gap=gap, sign_ok=sign_ok,
                        objective=f)
 

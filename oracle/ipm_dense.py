@@ -34,7 +34,10 @@ What it computes (Section 3.1 and Section 4 of the paper):
   "if ||r|| < mu: if mu <= mu_tol return; mu <- mu/10".
 
 Readings where the paper is silent (the same values are the GPU library's
-defaults): initial point x0 = bound midpoint (or bound +-1, or 0),
+defaults): the objective is divided by zeta = max(1, ||H x0 + p||_inf), the
+gradient size at the start point, before iterating (multipliers are scaled
+back on return; the minimiser is unchanged), so that mu_tol is measured in
+units where the multipliers are of order one; initial point x0 = bound midpoint (or bound +-1, or 0),
 s0 = max(G x0 - c, 1), lambda0 = 1, mu0 = s0^T lambda0 / m_tot; fraction to
 the boundary tau = 0.995; mu_tol = 1e-10; ||r|| is the infinity norm of the
 stacked scaled residuals r_H/(1 + ||p||_inf + ||Hx||_inf),
@@ -71,6 +74,7 @@ class OracleResult:
     converged: bool
     objective: float
     history: List[dict] = field(default_factory=list)
+    zeta: float = 1.0
 
 
 # ----------------------------------------------------------------------------
@@ -253,12 +257,33 @@ def max_step(v: Dict[str, np.ndarray], dv: Dict[str, np.ndarray], tau: float) ->
     return a
 
 
+def objective_scale(prob, H: np.ndarray) -> float:
+    """zeta = max(1, ||H x0 + p||_inf) at the start point x0."""
+    G = make_groups(prob)
+    x0, _, _ = initial_point(prob, G)
+    return max(1.0, float(np.abs(H @ x0 + prob.p).max(initial=0.0)))
+
+
 def solve(prob, settings: Optional[OracleSettings] = None, H: Optional[np.ndarray] = None,
           record: bool = False) -> OracleResult:
-    """Algorithm 1 with a dense Cholesky Newton solve."""
+    """Algorithm 1 with a dense Cholesky Newton solve, on the objective
+    divided by zeta (see the module docstring)."""
+    import copy
     st = settings or OracleSettings()
     if H is None:
         H = hessian_dense(prob)
+    zeta = objective_scale(prob, H)
+    sprob = copy.copy(prob)
+    sprob.p = prob.p / zeta
+    H = H / zeta
+    res = _solve_scaled(sprob, st, H, record)
+    res.lam = {g: v * zeta for g, v in res.lam.items()}
+    res.objective = res.objective * zeta
+    res.zeta = zeta
+    return res
+
+
+def _solve_scaled(prob, st: OracleSettings, H: np.ndarray, record: bool) -> OracleResult:
     G = make_groups(prob)
     x, s, lam = initial_point(prob, G)
     m_tot = G.m_tot()
@@ -292,8 +317,6 @@ def solve(prob, settings: Optional[OracleSettings] = None, H: Optional[np.ndarra
                 converged = True
                 break
             mu = mu / 10.0
-            # r_c is defined with the current mu
-            rc = {g: lam[g] * s[g] - mu for g in GROUPS}
     return OracleResult(x=x, s=s, lam=lam, mu=mu, iters=it, converged=converged,
                         objective=float(0.5 * x @ Hx + prob.p @ x), history=hist)
 
