@@ -1,0 +1,182 @@
+/*
+ * qpgpu.h -- C ABI of the MI355X (gfx950) interior point search-direction library.
+ *
+ * The library solves the convex QP of Section 3.1, eq. (qp), of Liu,
+ * Fredriksson and Markidis, "A GPU-Accelerated Interior Point Method for
+ * Radiation Therapy Optimization":
+ *
+ *     min  1/2 x^T H x + p^T x
+ *     s.t. lo_A <= A x <= hi_A,   lo_x <= x <= hi_x,
+ *
+ * with the variable bounds kept apart from the rows of A (Section 4, the text
+ * before eq. (2x2_reduced)) and the Hessian in the matrix-free form of
+ * eq. (bfgs_hessian), H = H_0 + U diag(w) U^T, where here
+ * H_0 = gamma*I + J^T diag(W) J for a sparse dose-influence matrix J.
+ *
+ * Every search direction is the solution of the condensed Newton system
+ * (H + A^T Sigma_A A + Sigma_x) dx = r (the Schur complement of the doubly
+ * augmented system eq. (2x2_augmented)), computed by Jacobi-preconditioned
+ * conjugate gradients (Section 4.1) on the GPU; the rest of Algorithm 1
+ * (direction recovery, step lengths, updates, residuals, the barrier rule)
+ * also runs on the GPU.
+ *
+ * Conventions shared by every entry point:
+ *  - All array arguments are HOST pointers unless the name says otherwise;
+ *    the library copies inputs to device memory it owns and copies outputs
+ *    back into caller buffers of the stated length.  The caller keeps
+ *    ownership of every buffer it passes and may free it on return.
+ *  - Sparse matrices are 0-based CSR with strictly increasing column indices
+ *    in each row; nnz must be below 2^31.
+ *  - Infinite bounds (+-INFINITY) mark an absent side.
+ *  - Errors are returned as qp_status codes; no C++ exception crosses the
+ *    ABI.  Inputs are validated before any GPU call: on QP_ERR_INVALID no
+ *    device work was done and outputs are untouched.  qp_last_error() gives a
+ *    message for the most recent failure.
+ *  - One handle is used by one host thread at a time.  Distinct handles may
+ *    run concurrently on distinct streams.
+ */
+#ifndef QPGPU_H
+#define QPGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qp_handle qp_handle;
+
+typedef enum {
+    QP_OK = 0,
+    QP_ERR_INVALID = 1,        /* bad argument; nothing was done */
+    QP_ERR_NOMEM = 2,          /* device or host allocation failed */
+    QP_ERR_DEVICE = 3,         /* a HIP call failed (no GPU, launch error, ...) */
+    QP_ERR_NOT_CONVERGED = 4,  /* iteration limit reached; best iterate returned */
+    QP_ERR_NUMERIC = 5         /* PCG breakdown (p^T K p <= 0 or non-finite) */
+} qp_status;
+
+/* Storage of the J values inside the PCG operator (Section 4.1 keeps FP64).
+ * FP32/BF16 keep a rounded copy (round to nearest even) with FP32
+ * accumulation; residuals, PCG scalars and dot products stay FP64, and the
+ * direction is refined against the FP64 operator (refine_steps). */
+typedef enum { QP_FP64 = 0, QP_FP32 = 1, QP_BF16 = 2 } qp_precision;
+
+typedef struct {
+    int32_t rows, cols;
+    int64_t nnz;
+    const int64_t* row_ptr;   /* rows+1 entries, row_ptr[0] = 0, nondecreasing */
+    const int32_t* col_idx;   /* nnz entries, sorted strictly increasing per row */
+    const double*  val;       /* nnz entries, finite */
+} qp_csr;
+
+/* H = gamma*I + J^T diag(W) J + U diag(w) U^T (eq. (bfgs_hessian)); the J part
+ * is passed to qp_create separately. */
+typedef struct {
+    double gamma;             /* >= 0 */
+    const double* p;          /* n: linear term of eq. (qp) */
+    int32_t k;                /* columns of U; 0 = no low-rank term */
+    const double* U;          /* n*k, column-major (U[j + n*c]); may be NULL when k = 0 */
+    const double* w;          /* k, >= 0 */
+} qp_hessian;
+
+typedef struct {
+    const double* lo;         /* may be NULL: all -INFINITY */
+    const double* hi;         /* may be NULL: all +INFINITY */
+} qp_range;
+
+typedef struct {
+    int32_t precision;        /* qp_precision, default QP_FP64 */
+    int32_t refine_steps;     /* FP64 refinement passes of each low-precision direction, default 2 */
+    double  pcg_tol;          /* stop at ||r||_2 <= pcg_tol*||rhs||_2, default 1e-8 */
+    int32_t pcg_max_iter;     /* per PCG solve, default 20000 */
+    double  mu0;              /* <= 0: average complementarity of the start point (default) */
+    double  mu_tol;           /* barrier rule exit, default 1e-10 (objective scaled, see below) */
+    double  tau;              /* fraction to the boundary, default 0.995 */
+    int32_t max_ipm_iter;     /* default 200 */
+    int32_t step_mode;        /* 0: separate primal/dual steps (Algorithm 1), 1: equal */
+    int32_t scale_objective;  /* 1 (default): divide H, p by max(1, ||H x0 + p||_inf) */
+    int32_t schedule;         /* 0: automatic SpMV row grouping, else lanes per row (4..64) */
+    int32_t timing;           /* 1: time the J and J^T SpMV launches with HIP events */
+    int32_t log_level;        /* 0: quiet */
+} qp_settings;
+
+typedef struct {
+    int32_t status;           /* qp_status of the call */
+    int32_t ipm_iters;
+    int64_t pcg_iters;        /* all PCG iterations of the call, refinement solves included */
+    int32_t pcg_solves;
+    int32_t pcg_capped;       /* PCG solves that stopped at pcg_max_iter */
+    double  mu;               /* final barrier parameter (scaled units) */
+    double  rnorm;            /* final ||r|| of the barrier rule */
+    double  zeta;             /* objective scale used */
+    double  objective;        /* 1/2 x^T H x + p^T x at the returned x */
+    double  pcg_relres;       /* last PCG solve: ||r||_2 / ||rhs||_2 */
+    double  t_solve_ms;       /* wall time of the call on the device stream */
+    double  t_pcg_ms;         /* part of it inside PCG loops */
+    double  t_spmv_fwd_ms;    /* summed J (and A) SpMV launch time, when timing = 1 */
+    double  t_spmv_bwd_ms;    /* summed J^T (and A^T) SpMV launch time, when timing = 1 */
+    int64_t n_spmv_fwd, n_spmv_bwd;
+} qp_info;
+
+/* Defaults listed above. */
+void qp_default_settings(qp_settings* s);
+
+/* qp_create: validate, copy to the device, build the stored transposes J^T
+ * and A^T (Section 4.1: transposes are precomputed so every SpMV is
+ * transpose-free), the low-precision J copies, diag(H) (cached once, Section
+ * 4.1.2) and the SpMV row schedule.
+ *   H      : gamma, p (n), optional U (n x k), w (k); n = J->cols.
+ *   J      : nJ x n dose matrix; W: nJ weights >= 0.
+ *   A      : m x n constraint matrix or NULL (m = 0); b: its row bounds (m).
+ *   bounds : variable bounds (n); NULL = free variables.
+ *   s      : NULL = defaults.  hip_stream: hipStream_t to enqueue on, NULL =
+ *            a stream the handle creates and owns.
+ * Errors: QP_ERR_INVALID (shapes, unsorted or out-of-range indices, non-finite
+ * values, lo > hi, W < 0, gamma < 0, w < 0), QP_ERR_NOMEM, QP_ERR_DEVICE. */
+qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const double* W,
+                    const qp_csr* A, const qp_range* b, const qp_range* bounds,
+                    const qp_settings* s, void* hip_stream);
+
+/* qp_solve: run Algorithm 1 from the default start point.
+ *   x     (n) : minimiser.
+ *   lam_A (m) : lambda_uA - lambda_lA per row of A (> 0 where the upper side
+ *               binds); may be NULL.
+ *   lam_x (n) : lambda_ux - lambda_lx per variable; may be NULL.
+ *   info      : may be NULL.
+ * Returns QP_OK, QP_ERR_NOT_CONVERGED (best iterate in the outputs),
+ * QP_ERR_NUMERIC or QP_ERR_DEVICE. */
+qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_info* info);
+
+/* qp_newton_step: one PCG solve of (H + diag(sigma_x) + A^T diag(sigma_A) A) dx = rhs
+ * (the system of Algorithm 1's second line in condensed form) with the
+ * handle's precision and refinement settings and no objective scaling.
+ *   sigma_x (n) >= 0, sigma_A (m) >= 0 (may be NULL when m = 0), rhs (n),
+ *   dx (n) output.  Returns QP_OK, QP_ERR_NOT_CONVERGED (pcg_max_iter hit;
+ *   dx holds the last iterate), QP_ERR_NUMERIC, QP_ERR_INVALID. */
+qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigma_A,
+                         const double* rhs, double* dx, qp_info* info);
+
+/* qp_operator_apply: y = (H + diag(sigma_x) + A^T diag(sigma_A) A) v, the
+ * matrix-free product of Section 4.1.1 in condensed form, with the J values
+ * stored in `precision` (FP64 accumulation for QP_FP64, FP32 otherwise).
+ * reps > 1 repeats the product (for timing); the result is the same. */
+qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* sigma_A,
+                            const double* v, double* y, int32_t precision, int32_t reps,
+                            qp_info* info);
+
+/* Text of the last error on this handle; h == NULL gives the calling
+ * thread's last qp_create error.  Valid until the next call on h. */
+const char* qp_last_error(const qp_handle* h);
+
+/* Free all device memory of h (NULL is a no-op). */
+void qp_destroy(qp_handle* h);
+
+/* Problem sizes of a handle (any pointer may be NULL). */
+void qp_sizes(const qp_handle* h, int32_t* n, int32_t* m, int32_t* nJ, int64_t* nnzJ,
+              int64_t* nnzA);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QPGPU_H */

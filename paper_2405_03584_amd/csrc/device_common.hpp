@@ -1,0 +1,188 @@
+// Device kernels of the IPM search-direction path for gfx950 (wave64).
+//
+// Operator of every PCG iteration (condensed Newton system, Section 4 of the
+// paper, in the matrix-free style of Section 4.1.1):
+//
+//     q = hs*(gamma*p + J^T (W .* (J p)) [+ U(w .* (U^T p))]) + Sigma_x .* p
+//         + A^T (Sigma_A .* (A p))
+//
+// with hs = 1/zeta the objective scale.  J and its stored transpose J^T (the
+// paper stores transposes so every SpMV is transpose-free, Section 4.1.1) are
+// CSR; each row is handled by a group of G lanes of one wavefront (G picked
+// per matrix from its row lengths).  No atomics: every sum has a fixed order,
+// reductions across blocks are two-stage (per-block partials reduced by the
+// consumer in a fixed order), so results are bitwise reproducible run to run
+// (the reproducibility requirement the paper meets with a deterministic
+// sparse library mode, Section 6.1.2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qpg {
+
+constexpr int kBlock = 256;         // 4 wavefronts
+constexpr int kMaxPartials = 2048;  // cap on blocks that emit reduction partials
+
+// --------------------------------------------------------------------------
+// scalar state shared by kernels (device memory)
+// --------------------------------------------------------------------------
+struct PcgScal {
+    double rho;        // r^T z of the current iteration (K3 writes, K4 reads)
+    double rho_next;   // next r^T z (K4/init writes, K3 reads)
+    double bnorm2;     // ||rhs||^2
+    double tol2;       // pcg_tol^2 * ||rhs||^2
+    double rr;         // ||r||^2 after the last update
+    double alpha;
+    int32_t iters;
+    int32_t converged;
+    int32_t breakdown;
+    int32_t capped;
+    int32_t max_iter;
+    int32_t pad;
+};
+
+struct IpmScal {
+    double mu;
+    double mu_tol;
+    double hs;         // 1/zeta
+    double zeta;
+    double pmax;       // ||p/zeta||_inf
+    double cscale;     // 1 + ||c||_inf over finite bounds
+    double rnorm;
+    double alpha_p, alpha_d;
+    double tau;
+    double xHx, px;    // scaled x^T H x, p^T x at the last residual pass
+    double mtot;
+    int32_t done;
+    int32_t iter;
+    int32_t step_mode;
+    int32_t pad;
+};
+
+// flags the host polls (one small struct copied to pinned memory)
+struct Flags {
+    int32_t pcg_converged, pcg_breakdown, pcg_capped, ipm_done;
+    int32_t pcg_iters, ipm_iter, pad0, pad1;
+};
+
+// --------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------
+struct bf16_t { uint16_t b; };
+
+__device__ __forceinline__ double to_f64(double v) { return v; }
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(bf16_t v) { return __uint_as_float(uint32_t(v.b) << 16); }
+__device__ __forceinline__ double to_f64(float v) { return double(v); }
+__device__ __forceinline__ double to_f64(bf16_t v) { return double(__uint_as_float(uint32_t(v.b) << 16)); }
+
+template <typename AT, typename VT> __device__ __forceinline__ AT cvt(VT v);
+template <> __device__ __forceinline__ double cvt<double, double>(double v) { return v; }
+template <> __device__ __forceinline__ double cvt<double, float>(float v) { return double(v); }
+template <> __device__ __forceinline__ double cvt<double, bf16_t>(bf16_t v) { return to_f64(v); }
+template <> __device__ __forceinline__ float cvt<float, float>(float v) { return v; }
+template <> __device__ __forceinline__ float cvt<float, bf16_t>(bf16_t v) { return to_f32(v); }
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Remap so that each XCD works on one contiguous range of logical
+// blocks: neighbouring rows gather neighbouring vector entries, which then
+// share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, i = b >> 3;
+    // XCD x owns q (+1 if x < r) consecutive logical blocks
+    const int start = x * q + (x < r ? x : r);
+    const int cnt = q + (x < r ? 1 : 0);
+    return (i < cnt) ? start + i : b;  // i < cnt always holds; keep b as a guard
+}
+
+template <typename T, int W>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+    return v;
+}
+
+// Sum over the block in a fixed order; result valid in every thread.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = group_sum<double, 64>(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) s += sh[i];
+    return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = sh[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) s = fmax(s, sh[i]);
+    return s;
+}
+
+__device__ __forceinline__ double block_min(double v, double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = sh[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) s = fmin(s, sh[i]);
+    return s;
+}
+
+// Reduce `count` per-block partials (stride `stride` between them) in a fixed
+// order; every block that calls this gets the identical value.
+__device__ __forceinline__ double reduce_partials_sum(const double* part, int count, int stride, double* sh) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) v += part[size_t(i) * stride];
+    return block_sum(v, sh);
+}
+__device__ __forceinline__ double reduce_partials_max(const double* part, int count, int stride, double* sh) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) v = fmax(v, part[size_t(i) * stride]);
+    return block_max(v, sh);
+}
+__device__ __forceinline__ double reduce_partials_min(const double* part, int count, int stride, double* sh) {
+    double v = 1.0e300;
+    for (int i = threadIdx.x; i < count; i += kBlock) v = fmin(v, part[size_t(i) * stride]);
+    return block_min(v, sh);
+}
+
+// Dot product of CSR row `row` with x by a group of G lanes (lane in [0,G)).
+// Each lane sums its strided share with four independent accumulators (more
+// loads in flight), combined in a fixed order; the group sum is done by the
+// caller.
+template <int G, typename VT, typename AT>
+__device__ __forceinline__ AT row_dot_lane(const int* __restrict__ ptr, const int* __restrict__ col,
+                                           const VT* __restrict__ val, const double* __restrict__ x,
+                                           int row, int lane) {
+    const int a = ptr[row], b = ptr[row + 1];
+    AT a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int k = a + lane;
+    for (; k + 3 * G < b; k += 4 * G) {
+        const int c0 = col[k], c1 = col[k + G], c2 = col[k + 2 * G], c3 = col[k + 3 * G];
+        const AT v0 = cvt<AT>(val[k]), v1 = cvt<AT>(val[k + G]);
+        const AT v2 = cvt<AT>(val[k + 2 * G]), v3 = cvt<AT>(val[k + 3 * G]);
+        a0 += v0 * AT(x[c0]);
+        a1 += v1 * AT(x[c1]);
+        a2 += v2 * AT(x[c2]);
+        a3 += v3 * AT(x[c3]);
+    }
+    for (; k < b; k += G) a0 += cvt<AT>(val[k]) * AT(x[col[k]]);
+    return (a0 + a1) + (a2 + a3);
+}
+
+}  // namespace qpg

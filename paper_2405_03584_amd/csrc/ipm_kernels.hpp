@@ -1,0 +1,685 @@
+// Kernels of one IPM iteration (Algorithm 1 of the paper, all on the device).
+//
+// Constraint groups (bounds kept apart from the rows of A, Section 4):
+//   lx: x_j >= lo_j        ux: -x_j >= -hi_j
+//   lA: (Ax)_i >= lo_i     uA: -(Ax)_i >= -hi_i
+// Each present side has a slack s > 0 and a multiplier lambda > 0; an absent
+// side (infinite bound) is stored as s = 1, lambda = 0 and is skipped by every
+// norm, ratio test and sum.  Residuals follow eq. (perturbed_KKT) with the
+// s_u sign of eq. (qp_barrier):
+//   r_H = H x + p - sum_g G_g^T lambda_g,  r_g = G_g x - s_g - c_g,
+//   r_c = lambda_g s_g - mu.
+// The direction solves the condensed form of eq. (newton_system):
+//   (H + Sigma_x + A^T Sigma_A A) dx
+//       = -(H x + p) + sum_g G_g^T (mu/s_g - Sigma_g r_g),   Sigma_g = lambda_g/s_g,
+// then ds_g = G_g dx + r_g and dlambda_g = -lambda_g + mu/s_g - Sigma_g ds_g.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace qpg {
+
+__device__ __forceinline__ bool finite_d(double v) { return __builtin_isfinite(v); }
+
+__device__ __forceinline__ bool pcg_stopped_raw(const Flags* fl) {
+    return fl && (fl->pcg_converged | fl->pcg_breakdown | fl->pcg_capped | fl->ipm_done);
+}
+
+// Stop test that every thread of the block answers the same way: thread 0
+// reads the flags once and broadcasts through LDS.  (Block 0 of a kernel may
+// set a flag while other blocks start, so per-thread reads could disagree
+// inside one block and split it around a barrier.)
+__device__ __forceinline__ bool block_flag(bool v_thread0) {
+    __shared__ int s_flag;
+    if (threadIdx.x == 0) s_flag = v_thread0 ? 1 : 0;
+    __syncthreads();
+    const bool r = s_flag != 0;
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ bool pcg_stopped(const Flags* fl) {
+    return block_flag(threadIdx.x == 0 && pcg_stopped_raw(fl));
+}
+__device__ __forceinline__ bool ipm_finished(const Flags* fl) {
+    return block_flag(threadIdx.x == 0 && fl->ipm_done);
+}
+
+// ==========================================================================
+// Operator kernels (one PCG product q = K p)
+// ==========================================================================
+
+template <typename VT>
+struct FwdArgs {
+    const int* Jp; const int* Jc; const VT* Jv; const double* W; int nJ;
+    const int* Ap; const int* Ac; const double* Av; int m;
+    const double* x;       // gathered vector (n)
+    double* t;             // W .* (J x)        (nJ)
+    double* u;             // sigA .* (A x)     (m), or A x when sigA is null
+    const double* sigA;
+    int nbJ;               // blocks of the grid that work on rows of J
+    const Flags* fl;
+};
+
+// t = W .* (J x) and u = Sigma_A .* (A x).  Rows of J: G lanes per row; rows
+// of A: a full wavefront per row.
+template <int G, typename VT, typename AT>
+__global__ __launch_bounds__(kBlock) void k_op_fwd(FwdArgs<VT> a) {
+    if (pcg_stopped(a.fl)) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    if (b < a.nbJ) {
+        constexpr int RPB = kBlock / G;
+        const int row = b * RPB + threadIdx.x / G;
+        const int lane = threadIdx.x % G;
+        if (row < a.nJ) {   // whole groups are uniform: inactive groups skip together
+            AT s = row_dot_lane<G, VT, AT>(a.Jp, a.Jc, a.Jv, a.x, row, lane);
+            s = group_sum<AT, G>(s);
+            if (lane == 0) a.t[row] = a.W[row] * double(s);
+        }
+    } else {
+        const int row = (b - a.nbJ) * (kBlock / 64) + (threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        if (row < a.m) {
+            double s = row_dot_lane<64, double, double>(a.Ap, a.Ac, a.Av, a.x, row, lane);
+            s = group_sum<double, 64>(s);
+            if (lane == 0) a.u[row] = a.sigA ? a.sigA[row] * s : s;
+        }
+    }
+}
+
+template <typename VT>
+struct BwdArgs {
+    const int* Jtp; const int* Jtc; const VT* Jtv; int n;
+    const int* Atp; const int* Atc; const double* Atv; int hasA;
+    const double* t; const double* u; const double* p;
+    const double* sigx;    // may be null
+    double hs, gamma;
+    double* q;
+    double* part;          // per-block partial p^T q (may be null)
+    const Flags* fl;
+};
+
+// q_j = hs*(J^T t + gamma p)_j + Sigma_x,j p_j + (A^T u)_j and per-block
+// partials of p^T q.  Grid-stride over row groups with a capped grid so the
+// partial count stays small.
+template <int G, typename VT, typename AT>
+__global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
+    __shared__ double sh[kBlock / 64];
+    if (pcg_stopped(a.fl)) return;
+    constexpr int RPB = kBlock / G;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x % G;
+    double dot = 0.0;
+    for (int base = b * RPB; base < a.n; base += gridDim.x * RPB) {
+        const int row = base + threadIdx.x / G;
+        if (row < a.n) {
+            AT sj = row_dot_lane<G, VT, AT>(a.Jtp, a.Jtc, a.Jtv, a.t, row, lane);
+            double s = a.hs * double(sj);
+            if (a.hasA) s += row_dot_lane<G, double, double>(a.Atp, a.Atc, a.Atv, a.u, row, lane);
+            s = group_sum<double, G>(s);
+            if (lane == 0) {
+                const double pj = a.p[row];
+                double y = s + a.hs * a.gamma * pj;
+                if (a.sigx) y += a.sigx[row] * pj;
+                a.q[row] = y;
+                dot += pj * y;
+            }
+        }
+    }
+    if (a.part) {
+        const double tot = block_sum(dot, sh);
+        if (threadIdx.x == 0) a.part[b] = tot;
+    }
+}
+
+// ==========================================================================
+// PCG vector updates (Jacobi preconditioner z = r ./ d, Section 4.1.2)
+// ==========================================================================
+struct PcgArgs {
+    int n;
+    double* x; double* r; double* z; double* p; const double* q; const double* d;
+    const double* part_pq; int n_pq;     // partials from k_op_bwd
+    double* part2; int n2;               // this grid's partials (2 per block)
+    PcgScal* sc;
+    Flags* fl;
+};
+
+// alpha = rho / p^T q; x += alpha p; r -= alpha q; z = r ./ d; partials of
+// r^T z and r^T r.
+__global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
+    __shared__ double sh[kBlock / 64];
+    if (pcg_stopped(a.fl)) return;
+    const double pq = reduce_partials_sum(a.part_pq, a.n_pq, 1, sh);
+    const double rho = a.sc->rho_next;
+    const double alpha = rho / pq;
+    const bool bad = !(pq > 0.0) || !finite_d(alpha);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.sc->rho = rho;
+        a.sc->alpha = alpha;
+        if (bad) a.fl->pcg_breakdown = 1;
+    }
+    if (bad) return;
+    double rz = 0.0, rr = 0.0;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+        a.x[j] += alpha * a.p[j];
+        const double rj = a.r[j] - alpha * a.q[j];
+        const double zj = rj / a.d[j];
+        a.r[j] = rj;
+        a.z[j] = zj;
+        rz += rj * zj;
+        rr += rj * rj;
+    }
+    rz = block_sum(rz, sh);
+    rr = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        a.part2[2 * blockIdx.x] = rz;
+        a.part2[2 * blockIdx.x + 1] = rr;
+    }
+}
+
+// beta = rho_new / rho; p = z + beta p; convergence and iteration cap.
+__global__ __launch_bounds__(kBlock) void k_pcg_p(PcgArgs a) {
+    __shared__ double sh[kBlock / 64];
+    if (pcg_stopped(a.fl)) return;
+    const double rz = reduce_partials_sum(a.part2, a.n2, 2, sh);
+    const double rr = reduce_partials_sum(a.part2 + 1, a.n2, 2, sh);
+    const double beta = rz / a.sc->rho;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.sc->rho_next = rz;
+        a.sc->rr = rr;
+        const int it = a.sc->iters + 1;
+        a.sc->iters = it;
+        a.fl->pcg_iters = it;
+        if (rr <= a.sc->tol2) a.fl->pcg_converged = 1;
+        else if (it >= a.sc->max_iter) a.fl->pcg_capped = 1;
+    }
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock)
+        a.p[j] = a.z[j] + beta * a.p[j];
+}
+
+struct PcgInitArgs {
+    int n;
+    const double* rhs_a;   // may be null: rhs = rhs_b
+    const double* rhs_b;
+    const IpmScal* ipm;    // mu for rhs = mu*rhs_a + rhs_b (null: mu = 0)
+    double* x; double* r; double* z; double* p; const double* d;
+    double* part2;
+    const Flags* fl;
+};
+
+// x = 0; r = rhs; z = r ./ d; p = z; partials of r^T z, r^T r.
+__global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
+    __shared__ double sh[kBlock / 64];
+    if (a.fl && ipm_finished(a.fl)) return;
+    const double mu = a.ipm ? a.ipm->mu : 0.0;
+    double rz = 0.0, rr = 0.0;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+        const double rj = a.rhs_a ? mu * a.rhs_a[j] + a.rhs_b[j] : a.rhs_b[j];
+        const double zj = rj / a.d[j];
+        a.x[j] = 0.0;
+        a.r[j] = rj;
+        a.z[j] = zj;
+        a.p[j] = zj;
+        rz += rj * zj;
+        rr += rj * rj;
+    }
+    rz = block_sum(rz, sh);
+    rr = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        a.part2[2 * blockIdx.x] = rz;
+        a.part2[2 * blockIdx.x + 1] = rr;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg_init1(const double* part2, int n2, double tol,
+                                                      int max_iter, PcgScal* sc, Flags* fl) {
+    __shared__ double sh[kBlock / 64];
+    if (ipm_finished(fl)) return;
+    const double rz = reduce_partials_sum(part2, n2, 2, sh);
+    const double rr = reduce_partials_sum(part2 + 1, n2, 2, sh);
+    if (threadIdx.x == 0) {
+        sc->rho_next = rz;
+        sc->rho = rz;
+        sc->bnorm2 = rr;
+        sc->rr = rr;
+        sc->tol2 = tol * tol * rr;
+        sc->iters = 0;
+        sc->max_iter = max_iter;
+        fl->pcg_iters = 0;
+        fl->pcg_breakdown = 0;
+        fl->pcg_capped = 0;
+        fl->pcg_converged = (rr == 0.0) ? 1 : 0;
+    }
+}
+
+// ==========================================================================
+// IPM state, residuals and the right-hand side
+// ==========================================================================
+struct IpmVec {
+    int n, m;
+    const double* xlo; const double* xhi; const double* alo; const double* ahi;
+    const double* p;          // unscaled linear term
+    const double* diagH;      // unscaled diag(H)
+    double* x;
+    double* s_lx; double* s_ux; double* l_lx; double* l_ux;
+    double* s_lA; double* s_uA; double* l_lA; double* l_uA;
+    double* ax;               // A x
+    double* r_lx; double* r_ux; double* r_lA; double* r_uA;
+    double* sigx; double* sigA;
+    double* va; double* vb; double* ya;       // m-vectors feeding A^T
+    double* hx;               // scaled H x
+    double* d;                // Jacobi diagonal
+    double* rhs_a; double* rhs_b;
+    double* dx;
+    double* ds_lx; double* ds_ux; double* dl_lx; double* dl_ux;
+    double* ds_lA; double* ds_uA; double* dl_lA; double* dl_uA;
+};
+
+// Start point: x0 = bound midpoint, or a finite bound +- 1, or 0; slacks of
+// the bounds max(x0 - lo, 1) / max(hi - x0, 1); multipliers 1.  Partials of
+// the slack sum (for mu0) over present sides.
+__global__ __launch_bounds__(kBlock) void k_ipm_init_x(IpmVec v, double* part) {
+    __shared__ double sh[kBlock / 64];
+    double ssum = 0.0;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < v.n; j += gridDim.x * kBlock) {
+        const double lo = v.xlo[j], hi = v.xhi[j];
+        const bool hl = finite_d(lo), hu = finite_d(hi);
+        double x0 = 0.0;
+        if (hl && hu) x0 = 0.5 * (lo + hi);
+        else if (hl) x0 = lo + 1.0;
+        else if (hu) x0 = hi - 1.0;
+        v.x[j] = x0;
+        v.s_lx[j] = hl ? fmax(x0 - lo, 1.0) : 1.0;
+        v.l_lx[j] = hl ? 1.0 : 0.0;
+        v.s_ux[j] = hu ? fmax(hi - x0, 1.0) : 1.0;
+        v.l_ux[j] = hu ? 1.0 : 0.0;
+        ssum += (hl ? v.s_lx[j] : 0.0) + (hu ? v.s_ux[j] : 0.0);
+    }
+    ssum = block_sum(ssum, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = ssum;
+}
+
+// Slacks of the rows of A at x0: max(ax - lo, 1), max(hi - ax, 1).
+__global__ __launch_bounds__(kBlock) void k_ipm_init_A(IpmVec v, const int* Ap, const int* Ac,
+                                                       const double* Av, double* part) {
+    __shared__ double sh[kBlock / 64];
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double ssum = 0.0;
+    if (row < v.m) {
+        double s = row_dot_lane<64, double, double>(Ap, Ac, Av, v.x, row, lane);
+        s = group_sum<double, 64>(s);
+        if (lane == 0) {
+            const double lo = v.alo[row], hi = v.ahi[row];
+            const bool hl = finite_d(lo), hu = finite_d(hi);
+            v.s_lA[row] = hl ? fmax(s - lo, 1.0) : 1.0;
+            v.l_lA[row] = hl ? 1.0 : 0.0;
+            v.s_uA[row] = hu ? fmax(hi - s, 1.0) : 1.0;
+            v.l_uA[row] = hu ? 1.0 : 0.0;
+            ssum = (hl ? v.s_lA[row] : 0.0) + (hu ? v.s_uA[row] : 0.0);
+        }
+    }
+    ssum = block_sum(ssum, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = ssum;
+}
+
+// zeta = max(1, ||H x0 + p||_inf) (q holds H x0), hs = 1/zeta, pmax, and
+// mu0 = sum of start slacks / m_tot (multipliers are all 1).
+__global__ __launch_bounds__(kBlock) void k_ipm_scale(const double* q, const double* p, int n,
+                                                      const double* part_s, int n_s, double mtot,
+                                                      int scale, double mu0_user, IpmScal* sc) {
+    __shared__ double sh[kBlock / 64];
+    double g = 0.0, pm = 0.0;
+    for (int j = threadIdx.x; j < n; j += kBlock) {
+        g = fmax(g, fabs(q[j] + p[j]));
+        pm = fmax(pm, fabs(p[j]));
+    }
+    g = block_max(g, sh);
+    pm = block_max(pm, sh);
+    const double ssum = reduce_partials_sum(part_s, n_s, 1, sh);
+    if (threadIdx.x == 0) {
+        const double zeta = scale ? fmax(1.0, g) : 1.0;
+        sc->zeta = zeta;
+        sc->hs = 1.0 / zeta;
+        sc->pmax = pm / zeta;
+        sc->mtot = mtot;
+        sc->mu = mu0_user > 0.0 ? mu0_user : (mtot > 0.0 ? ssum / mtot : sc->mu_tol);
+        sc->done = 0;
+        sc->iter = 0;
+        sc->rnorm = 0.0;
+        sc->alpha_p = sc->alpha_d = 0.0;
+    }
+}
+
+// Residual pass, part 1: t = W .* (J x) for rows of J; for rows of A: A x,
+// the group residuals, Sigma_A, and the m-vectors va (mu coefficient of the
+// rhs), vb (mu-free part) and ya = lambda_uA - lambda_lA that the next kernel
+// multiplies by A^T.  Per-block partial maxima of |r_g| and |lambda s - mu|.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_ipm_fwd(FwdArgs<double> a, IpmVec v, const IpmScal* sc,
+                                                    double* part, const Flags* fl) {
+    __shared__ double sh[kBlock / 64];
+    if (ipm_finished(fl)) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    if (b < a.nbJ) {
+        constexpr int RPB = kBlock / G;
+        const int row = b * RPB + threadIdx.x / G;
+        const int lane = threadIdx.x % G;
+        if (row < a.nJ) {
+            double s = row_dot_lane<G, double, double>(a.Jp, a.Jc, a.Jv, a.x, row, lane);
+            s = group_sum<double, G>(s);
+            if (lane == 0) a.t[row] = a.W[row] * s;
+        }
+        return;
+    }
+    const int ab = b - a.nbJ;
+    const int row = ab * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double rg = 0.0, rc = 0.0;
+    if (row < a.m) {
+        double s = row_dot_lane<64, double, double>(a.Ap, a.Ac, a.Av, a.x, row, lane);
+        s = group_sum<double, 64>(s);
+        if (lane == 0) {
+            const double mu = sc->mu;
+            const double lo = v.alo[row], hi = v.ahi[row];
+            const bool hl = finite_d(lo), hu = finite_d(hi);
+            const double sl = v.s_lA[row], su = v.s_uA[row], ll = v.l_lA[row], lu = v.l_uA[row];
+            const double rl = hl ? s - sl - lo : 0.0;
+            const double ru = hu ? -s - su + hi : 0.0;
+            const double gl = hl ? ll / sl : 0.0, gu = hu ? lu / su : 0.0;
+            v.ax[row] = s;
+            v.r_lA[row] = rl;
+            v.r_uA[row] = ru;
+            v.sigA[row] = gl + gu;
+            v.va[row] = (hl ? 1.0 / sl : 0.0) - (hu ? 1.0 / su : 0.0);
+            v.vb[row] = -gl * rl + gu * ru;
+            v.ya[row] = lu - ll;
+            rg = fmax(fabs(rl), fabs(ru));
+            rc = fmax(hl ? fabs(ll * sl - mu) : 0.0, hu ? fabs(lu * su - mu) : 0.0);
+        }
+    }
+    rg = block_max(rg, sh);
+    rc = block_max(rc, sh);
+    if (threadIdx.x == 0) {
+        part[2 * ab] = rg;
+        part[2 * ab + 1] = rc;
+    }
+}
+
+struct IpmBwdArgs {
+    const int* Jtp; const int* Jtc; const double* Jtv;
+    const int* Atp; const int* Atc; const double* Atv; int hasA;
+    const double* t;
+    double gamma;
+};
+
+// Residual pass, part 2, per variable j: H x (scaled), the A^T products of
+// ya, va, vb and of the squared values with Sigma_A (Jacobi diagonal of
+// A^T Sigma_A A), then r_H, the bound residuals, Sigma_x, the Jacobi diagonal
+// d, and the two rhs parts.  Partials (6 per block): max|r_H|, max|Hx|,
+// max|r_g| and max|r_c| of the bounds, sum x.Hx, sum p.x.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_ipm_bwd(IpmBwdArgs a, IpmVec v, const IpmScal* sc,
+                                                    double* part, const Flags* fl) {
+    __shared__ double sh[kBlock / 64];
+    if (ipm_finished(fl)) return;
+    constexpr int RPB = kBlock / G;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x % G;
+    const double hs = sc->hs, mu = sc->mu;
+    double mrH = 0.0, mHx = 0.0, mrg = 0.0, mrc = 0.0, sxh = 0.0, spx = 0.0;
+    for (int base = b * RPB; base < v.n; base += gridDim.x * RPB) {
+        const int j = base + threadIdx.x / G;
+        if (j < v.n) {
+            double hj = hs * row_dot_lane<G, double, double>(a.Jtp, a.Jtc, a.Jtv, a.t, j, lane);
+            double aty = 0.0, ava = 0.0, avb = 0.0, a2s = 0.0;
+            if (a.hasA) {
+                const int s0 = a.Atp[j], s1 = a.Atp[j + 1];
+                for (int k = s0 + lane; k < s1; k += G) {
+                    const int i = a.Atc[k];
+                    const double av = a.Atv[k];
+                    aty += av * v.ya[i];
+                    ava += av * v.va[i];
+                    avb += av * v.vb[i];
+                    a2s += av * av * v.sigA[i];
+                }
+            }
+            hj = group_sum<double, G>(hj);
+            aty = group_sum<double, G>(aty);
+            ava = group_sum<double, G>(ava);
+            avb = group_sum<double, G>(avb);
+            a2s = group_sum<double, G>(a2s);
+            if (lane == 0) {
+                const double xj = v.x[j];
+                const double hx = hj + hs * a.gamma * xj;
+                const double pj = v.p[j] * hs;
+                const double lo = v.xlo[j], hi = v.xhi[j];
+                const bool hl = finite_d(lo), hu = finite_d(hi);
+                const double sl = v.s_lx[j], su = v.s_ux[j], ll = v.l_lx[j], lu = v.l_ux[j];
+                const double rl = hl ? xj - sl - lo : 0.0;
+                const double ru = hu ? -xj - su + hi : 0.0;
+                const double gl = hl ? ll / sl : 0.0, gu = hu ? lu / su : 0.0;
+                const double rH = hx + pj + (lu - ll) + aty;
+                v.hx[j] = hx;
+                v.r_lx[j] = rl;
+                v.r_ux[j] = ru;
+                v.sigx[j] = gl + gu;
+                v.d[j] = hs * v.diagH[j] + gl + gu + a2s;
+                v.rhs_a[j] = (hl ? 1.0 / sl : 0.0) - (hu ? 1.0 / su : 0.0) + ava;
+                v.rhs_b[j] = -(hx + pj) - gl * rl + gu * ru + avb;
+                mrH = fmax(mrH, fabs(rH));
+                mHx = fmax(mHx, fabs(hx));
+                mrg = fmax(mrg, fmax(fabs(rl), fabs(ru)));
+                mrc = fmax(mrc, fmax(hl ? fabs(ll * sl - mu) : 0.0, hu ? fabs(lu * su - mu) : 0.0));
+                sxh += xj * hx;
+                spx += pj * xj;
+            }
+        }
+    }
+    mrH = block_max(mrH, sh);
+    mHx = block_max(mHx, sh);
+    mrg = block_max(mrg, sh);
+    mrc = block_max(mrc, sh);
+    sxh = block_sum(sxh, sh);
+    spx = block_sum(spx, sh);
+    if (threadIdx.x == 0) {
+        double* o = part + 6 * size_t(b);
+        o[0] = mrH; o[1] = mHx; o[2] = mrg; o[3] = mrc; o[4] = sxh; o[5] = spx;
+    }
+}
+
+// Residual norm and the barrier rule of Algorithm 1:
+//   if ||r|| < mu: if mu <= mu_tol: done; else mu <- mu/10.
+// ||r|| = max(||r_H||/(1 + max(||p||, ||Hx||)), ||r_g||/cscale, ||r_c||), all
+// infinity norms in scaled units.  apply = 0 evaluates without the rule (the
+// start point).
+__global__ __launch_bounds__(kBlock) void k_ipm_check(const double* partA, int nA, const double* partX,
+                                                      int nX, int apply, IpmScal* sc, Flags* fl,
+                                                      double* log) {
+    __shared__ double sh[kBlock / 64];
+    if (ipm_finished(fl)) return;
+    const double rgA = nA ? reduce_partials_max(partA, nA, 2, sh) : 0.0;
+    const double rcA = nA ? reduce_partials_max(partA + 1, nA, 2, sh) : 0.0;
+    const double rH = reduce_partials_max(partX, nX, 6, sh);
+    const double Hx = reduce_partials_max(partX + 1, nX, 6, sh);
+    const double rgx = reduce_partials_max(partX + 2, nX, 6, sh);
+    const double rcx = reduce_partials_max(partX + 3, nX, 6, sh);
+    const double xHx = reduce_partials_sum(partX + 4, nX, 6, sh);
+    const double px = reduce_partials_sum(partX + 5, nX, 6, sh);
+    if (threadIdx.x == 0) {
+        const double dscale = 1.0 + fmax(sc->pmax, Hx);
+        const double rn = fmax(rH / dscale, fmax(fmax(rgA, rgx) / sc->cscale, fmax(rcA, rcx)));
+        sc->rnorm = rn;
+        sc->xHx = xHx;
+        sc->px = px;
+        if (apply) {
+            const int it = sc->iter + 1;
+            sc->iter = it;
+            fl->ipm_iter = it;
+            if (log) {
+                double* e = log + 4 * size_t(it - 1);
+                e[0] = sc->mu; e[1] = rn; e[2] = sc->alpha_p; e[3] = sc->alpha_d;
+            }
+            if (rn < sc->mu) {
+                if (sc->mu <= sc->mu_tol) {
+                    sc->done = 1;
+                    fl->ipm_done = 1;
+                } else {
+                    sc->mu = sc->mu / 10.0;
+                }
+            }
+        }
+    }
+}
+
+// Direction recovery and ratio test.  Blocks [0, nbA) handle rows of A
+// (A dx by a wavefront per row), the rest handle the bounds of x.  Per-block
+// partial minima of -s/ds over ds < 0 and of -lambda/dl over dl < 0.
+__global__ __launch_bounds__(kBlock) void k_ipm_recover(IpmVec v, const int* Ap, const int* Ac,
+                                                        const double* Av, int nbA, const IpmScal* sc,
+                                                        double* part, const Flags* fl) {
+    __shared__ double sh[kBlock / 64];
+    if (ipm_finished(fl)) return;
+    const double mu = sc->mu;
+    double mp = 1.0e300, md = 1.0e300;
+    if ((int)blockIdx.x < nbA) {
+        const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        if (row < v.m) {
+            double s = row_dot_lane<64, double, double>(Ap, Ac, Av, v.dx, row, lane);
+            s = group_sum<double, 64>(s);
+            if (lane == 0) {
+                const bool hl = finite_d(v.alo[row]), hu = finite_d(v.ahi[row]);
+                const double sl = v.s_lA[row], su = v.s_uA[row], ll = v.l_lA[row], lu = v.l_uA[row];
+                const double dsl = hl ? s + v.r_lA[row] : 0.0;
+                const double dsu = hu ? -s + v.r_uA[row] : 0.0;
+                const double dll = hl ? -ll + mu / sl - (ll / sl) * dsl : 0.0;
+                const double dlu = hu ? -lu + mu / su - (lu / su) * dsu : 0.0;
+                v.ds_lA[row] = dsl; v.ds_uA[row] = dsu;
+                v.dl_lA[row] = dll; v.dl_uA[row] = dlu;
+                if (dsl < 0.0) mp = fmin(mp, -sl / dsl);
+                if (dsu < 0.0) mp = fmin(mp, -su / dsu);
+                if (dll < 0.0) md = fmin(md, -ll / dll);
+                if (dlu < 0.0) md = fmin(md, -lu / dlu);
+            }
+        }
+    } else {
+        const int nbx = gridDim.x - nbA;
+        for (int j = (blockIdx.x - nbA) * kBlock + threadIdx.x; j < v.n; j += nbx * kBlock) {
+            const bool hl = finite_d(v.xlo[j]), hu = finite_d(v.xhi[j]);
+            const double dxj = v.dx[j];
+            const double sl = v.s_lx[j], su = v.s_ux[j], ll = v.l_lx[j], lu = v.l_ux[j];
+            const double dsl = hl ? dxj + v.r_lx[j] : 0.0;
+            const double dsu = hu ? -dxj + v.r_ux[j] : 0.0;
+            const double dll = hl ? -ll + mu / sl - (ll / sl) * dsl : 0.0;
+            const double dlu = hu ? -lu + mu / su - (lu / su) * dsu : 0.0;
+            v.ds_lx[j] = dsl; v.ds_ux[j] = dsu;
+            v.dl_lx[j] = dll; v.dl_ux[j] = dlu;
+            if (dsl < 0.0) mp = fmin(mp, -sl / dsl);
+            if (dsu < 0.0) mp = fmin(mp, -su / dsu);
+            if (dll < 0.0) md = fmin(md, -ll / dll);
+            if (dlu < 0.0) md = fmin(md, -lu / dlu);
+        }
+    }
+    mp = block_min(mp, sh);
+    md = block_min(md, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = mp;
+        part[2 * blockIdx.x + 1] = md;
+    }
+}
+
+// Step lengths alpha_P = min(1, tau*min ratio) and alpha_D likewise (equal
+// when step_mode = 1), then x += alpha_P dx, s += alpha_P ds,
+// lambda += alpha_D dl.  Every block reduces the same partials.
+__global__ __launch_bounds__(kBlock) void k_ipm_update(IpmVec v, const double* part, int np,
+                                                       IpmScal* sc, const Flags* fl) {
+    __shared__ double sh[kBlock / 64];
+    if (ipm_finished(fl)) return;
+    const double mp = reduce_partials_min(part, np, 2, sh);
+    const double md = reduce_partials_min(part + 1, np, 2, sh);
+    double ap = fmin(1.0, sc->tau * mp);
+    double ad = fmin(1.0, sc->tau * md);
+    if (sc->step_mode == 1) ap = ad = fmin(ap, ad);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->alpha_p = ap;
+        sc->alpha_d = ad;
+    }
+    const int tot = v.n + v.m;
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < tot; k += gridDim.x * kBlock) {
+        if (k < v.n) {
+            const int j = k;
+            v.x[j] += ap * v.dx[j];
+            if (finite_d(v.xlo[j])) { v.s_lx[j] += ap * v.ds_lx[j]; v.l_lx[j] += ad * v.dl_lx[j]; }
+            if (finite_d(v.xhi[j])) { v.s_ux[j] += ap * v.ds_ux[j]; v.l_ux[j] += ad * v.dl_ux[j]; }
+        } else {
+            const int i = k - v.n;
+            if (finite_d(v.alo[i])) { v.s_lA[i] += ap * v.ds_lA[i]; v.l_lA[i] += ad * v.dl_lA[i]; }
+            if (finite_d(v.ahi[i])) { v.s_uA[i] += ap * v.ds_uA[i]; v.l_uA[i] += ad * v.dl_uA[i]; }
+        }
+    }
+}
+
+// Multipliers in original units: lam_x = zeta(lambda_ux - lambda_lx),
+// lam_A = zeta(lambda_uA - lambda_lA).
+__global__ __launch_bounds__(kBlock) void k_ipm_output(IpmVec v, const IpmScal* sc, double* lam_x,
+                                                       double* lam_A) {
+    const double z = sc->zeta;
+    const int tot = v.n + v.m;
+    for (int k = blockIdx.x * kBlock + threadIdx.x; k < tot; k += gridDim.x * kBlock) {
+        if (k < v.n) lam_x[k] = z * (v.l_ux[k] - v.l_lx[k]);
+        else lam_A[k - v.n] = z * (v.l_uA[k - v.n] - v.l_lA[k - v.n]);
+    }
+}
+
+// ==========================================================================
+// Setup kernels
+// ==========================================================================
+
+// diag(H)_j = gamma + sum_i W_i J_ij^2 (+ sum_c w_c U_jc^2), from the rows of J^T.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_diag_h(const int* Jtp, const int* Jtc, const double* Jtv,
+                                                   const double* W, int n, double gamma,
+                                                   const double* U, const double* w, int k,
+                                                   double* diagH) {
+    constexpr int RPB = kBlock / G;
+    const int j = blockIdx.x * RPB + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int e = Jtp[j] + lane; e < Jtp[j + 1]; e += G) {
+        const double v = Jtv[e];
+        s += W[Jtc[e]] * v * v;
+    }
+    s = group_sum<double, G>(s);
+    if (lane == 0) {
+        double dj = gamma + s;
+        for (int c = 0; c < k; ++c) {
+            const double u = U[j + size_t(n) * c];
+            dj += w[c] * u * u;
+        }
+        diagH[j] = dj;
+    }
+}
+
+// Jacobi diagonal for a given Sigma: d_j = diagH_j + sigx_j + sum_i (A^T)_ji^2 sigA_i.
+__global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double* Atv, const int* Atc,
+                                                   int hasA, const double* sigA, const double* sigx,
+                                                   const double* diagH, int n, double* d) {
+    const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= n) return;
+    double s = 0.0;
+    if (hasA)
+        for (int e = Atp[j] + lane; e < Atp[j + 1]; e += 64) {
+            const double v = Atv[e];
+            s += v * v * sigA[Atc[e]];
+        }
+    s = group_sum<double, 64>(s);
+    if (lane == 0) d[j] = diagH[j] + sigx[j] + s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double* a, double v, int n) {
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) a[j] = v;
+}
+
+}  // namespace qpg

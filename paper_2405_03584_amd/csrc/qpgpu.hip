@@ -1,0 +1,787 @@
+// Host side of the C ABI declared in include/qpgpu.h: handle lifecycle, device
+// memory, kernel launch schedule, and the Algorithm 1 loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_prep.h"
+#include "ipm_kernels.hpp"
+#include "qpgpu.h"
+
+using namespace qpg;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHK(call)                                             \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) throw HipError{e_, #call};         \
+    } while (0)
+
+int pick_lanes(int64_t nnz, int64_t rows) {
+    const double L = rows > 0 ? double(nnz) / double(rows) : 0.0;
+    if (L <= 12) return 4;
+    if (L <= 24) return 8;
+    if (L <= 96) return 16;
+    if (L <= 320) return 32;
+    return 64;
+}
+
+}  // namespace
+
+struct qp_handle {
+    std::string err;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    qp_settings set{};
+
+    int32_t n = 0, m = 0, nJ = 0, k = 0;
+    int64_t nnzJ = 0, nnzA = 0;
+    double gamma = 0.0, cscale = 1.0, mtot = 0.0;
+    int GJ = 16, GJt = 64;   // lanes per row of J and of J^T (and A^T)
+
+    std::vector<void*> allocs;
+
+    // matrices
+    int *Jp = nullptr, *Jc = nullptr, *Jtp = nullptr, *Jtc = nullptr;
+    double *Jv = nullptr, *Jtv = nullptr;
+    float *Jv32 = nullptr, *Jtv32 = nullptr;
+    bf16_t *Jv16 = nullptr, *Jtv16 = nullptr;
+    std::vector<double> hJv, hJtv;     // kept to build low-precision copies on demand
+    double* W = nullptr;
+    int *Ap = nullptr, *Ac = nullptr, *Atp = nullptr, *Atc = nullptr;
+    double *Av = nullptr, *Atv = nullptr;
+    double *xlo = nullptr, *xhi = nullptr, *alo = nullptr, *ahi = nullptr;
+    double *p = nullptr, *diagH = nullptr, *U = nullptr, *w = nullptr;
+
+    // work
+    IpmVec iv{};
+    double *t = nullptr, *u = nullptr;
+    double *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;
+    double *zero_n = nullptr, *zero_m = nullptr, *tmp_n = nullptr, *tmp_n2 = nullptr, *tmp_m = nullptr;
+    double *part = nullptr, *part2 = nullptr, *partA = nullptr;
+    size_t part_len = 0;
+    double* log = nullptr;
+    IpmScal* isc = nullptr;
+    PcgScal* psc = nullptr;
+    Flags* fl = nullptr;
+    Flags* fl_host = nullptr;   // pinned, 2 slots
+
+    std::vector<hipEvent_t> tev;  // timing events, pairs
+    hipEvent_t ev_chunk[2] = {nullptr, nullptr};
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_p0 = nullptr, ev_p1 = nullptr;
+
+    template <typename T>
+    T* dalloc(size_t count) {
+        if (count == 0) count = 1;
+        void* ptr = nullptr;
+        hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+        if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+        allocs.push_back(ptr);
+        return static_cast<T*>(ptr);
+    }
+    template <typename T>
+    T* upload(const T* src, size_t count) {
+        T* d = dalloc<T>(count);
+        if (count) HIPCHK(hipMemcpyAsync(d, src, count * sizeof(T), hipMemcpyHostToDevice, stream));
+        return d;
+    }
+    ~qp_handle() {
+        // teardown: errors here have no caller to go to
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* a : allocs) (void)hipFree(a);
+        if (fl_host) (void)hipHostFree(fl_host);
+        for (auto e : tev) (void)hipEventDestroy(e);
+        for (auto e : {ev_chunk[0], ev_chunk[1], ev_t0, ev_t1, ev_p0, ev_p1})
+            if (e) (void)hipEventDestroy(e);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+// ==========================================================================
+// launch helpers
+// ==========================================================================
+namespace {
+
+int grid_elems(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    return int(std::max<int64_t>(1, std::min<int64_t>(g, kMaxPartials)));
+}
+int grid_rows(int64_t rows, int G) {
+    const int rpb = kBlock / G;
+    return int(std::max<int64_t>(1, (rows + rpb - 1) / rpb));
+}
+int grid_rows_capped(int64_t rows, int G) { return std::min(grid_rows(rows, G), kMaxPartials); }
+
+template <typename VT, typename AT>
+void launch_fwd(qp_handle* h, int G, const FwdArgs<VT>& a0, int nbA) {
+    FwdArgs<VT> a = a0;
+    a.nbJ = (a.nJ > 0) ? grid_rows(a.nJ, G) : 0;
+    const int grid = a.nbJ + nbA;
+    if (grid == 0) return;
+    switch (G) {
+        case 4: hipLaunchKernelGGL((k_op_fwd<4, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        case 8: hipLaunchKernelGGL((k_op_fwd<8, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        case 16: hipLaunchKernelGGL((k_op_fwd<16, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        case 32: hipLaunchKernelGGL((k_op_fwd<32, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        default: hipLaunchKernelGGL((k_op_fwd<64, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+    }
+    HIPCHK(hipGetLastError());
+}
+
+template <typename VT, typename AT>
+int launch_bwd(qp_handle* h, int G, const BwdArgs<VT>& a) {
+    const int grid = grid_rows_capped(a.n, G);
+    switch (G) {
+        case 4: hipLaunchKernelGGL((k_op_bwd<4, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        case 8: hipLaunchKernelGGL((k_op_bwd<8, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        case 16: hipLaunchKernelGGL((k_op_bwd<16, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        case 32: hipLaunchKernelGGL((k_op_bwd<32, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        default: hipLaunchKernelGGL((k_op_bwd<64, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+    }
+    HIPCHK(hipGetLastError());
+    return grid;
+}
+
+template <typename VT>
+void mat_ptrs(qp_handle* h, const VT*& jv, const VT*& jtv);
+template <>
+void mat_ptrs<double>(qp_handle* h, const double*& jv, const double*& jtv) { jv = h->Jv; jtv = h->Jtv; }
+template <>
+void mat_ptrs<float>(qp_handle* h, const float*& jv, const float*& jtv) { jv = h->Jv32; jtv = h->Jtv32; }
+template <>
+void mat_ptrs<bf16_t>(qp_handle* h, const bf16_t*& jv, const bf16_t*& jtv) { jv = h->Jv16; jtv = h->Jtv16; }
+
+// q = K p with K = hs*H + diag(sigx) + A^T diag(sigA) A; returns the number of
+// p^T q partials written to `part` (0 when part is null).
+template <typename VT, typename AT>
+int apply_op(qp_handle* h, const double* p, double* q, const double* sigx, const double* sigA, double hs,
+             double* part, const Flags* fl, bool timed, int tslot) {
+    FwdArgs<VT> f{};
+    const VT *jv = nullptr, *jtv = nullptr;
+    mat_ptrs<VT>(h, jv, jtv);
+    f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = jv; f.W = h->W; f.nJ = h->nJ;
+    f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
+    f.x = p; f.t = h->t; f.u = h->u; f.sigA = sigA; f.fl = fl;
+    const int nbA = f.m > 0 ? grid_rows(f.m, 64) : 0;
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
+    launch_fwd<VT, AT>(h, h->GJ, f, nbA);
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
+    BwdArgs<VT> b{};
+    b.Jtp = h->Jtp; b.Jtc = h->Jtc; b.Jtv = jtv; b.n = h->n;
+    b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = f.m > 0;
+    b.t = h->t; b.u = h->u; b.p = p; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
+    b.q = q; b.part = part; b.fl = fl;
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], h->stream));
+    const int g = launch_bwd<VT, AT>(h, h->GJt, b);
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], h->stream));
+    return part ? g : 0;
+}
+
+int apply_op_prec(qp_handle* h, int prec, const double* p, double* q, const double* sigx, const double* sigA,
+                  double hs, double* part, const Flags* fl, bool timed, int tslot) {
+    switch (prec) {
+        case QP_FP32: return apply_op<float, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
+        case QP_BF16: return apply_op<bf16_t, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
+        default: return apply_op<double, double>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
+    }
+}
+
+void ensure_lowp(qp_handle* h, int prec) {
+    if (prec == QP_FP32 && !h->Jv32) {
+        std::vector<uint32_t> a(h->hJv.size()), b(h->hJtv.size());
+        for (size_t i = 0; i < a.size(); ++i) a[i] = f64_to_f32_bits(h->hJv[i]);
+        for (size_t i = 0; i < b.size(); ++i) b[i] = f64_to_f32_bits(h->hJtv[i]);
+        h->Jv32 = reinterpret_cast<float*>(h->upload(a.data(), a.size()));
+        h->Jtv32 = reinterpret_cast<float*>(h->upload(b.data(), b.size()));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    if (prec == QP_BF16 && !h->Jv16) {
+        std::vector<uint16_t> a(h->hJv.size()), b(h->hJtv.size());
+        for (size_t i = 0; i < a.size(); ++i) a[i] = f64_to_bf16_bits(h->hJv[i]);
+        for (size_t i = 0; i < b.size(); ++i) b[i] = f64_to_bf16_bits(h->hJtv[i]);
+        h->Jv16 = reinterpret_cast<bf16_t*>(h->upload(a.data(), a.size()));
+        h->Jtv16 = reinterpret_cast<bf16_t*>(h->upload(b.data(), b.size()));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+}
+
+struct TimingAcc {
+    int pairs = 0;   // recorded operator applications
+};
+
+// One Jacobi-PCG solve of K dx = rhs (rhs = mu*rhs_a + rhs_b when rhs_a is
+// given, mu read on the device).  dx is written to h->px.  Returns the flags
+// after the solve.
+Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, const double* sigx,
+              const double* sigA, const double* d, double hs, bool ipm_mode, TimingAcc* tacc) {
+    const int n = h->n;
+    const int ge = grid_elems(n);
+    PcgInitArgs ia{};
+    ia.n = n; ia.rhs_a = rhs_a; ia.rhs_b = rhs_b; ia.ipm = ipm_mode ? h->isc : nullptr;
+    ia.x = h->px; ia.r = h->pr; ia.z = h->pz; ia.p = h->pp; ia.d = d; ia.part2 = h->part2; ia.fl = h->fl;
+    hipLaunchKernelGGL(k_pcg_init0, dim3(ge), dim3(kBlock), 0, h->stream, ia);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_pcg_init1, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part2, ge,
+                       h->set.pcg_tol, h->set.pcg_max_iter, h->psc, h->fl);
+    HIPCHK(hipGetLastError());
+
+    PcgArgs pa{};
+    pa.n = n; pa.x = h->px; pa.r = h->pr; pa.z = h->pz; pa.p = h->pp; pa.q = h->pq; pa.d = d;
+    pa.part_pq = h->part; pa.part2 = h->part2; pa.n2 = ge; pa.sc = h->psc; pa.fl = h->fl;
+
+    const bool timing = h->set.timing != 0 && tacc != nullptr;
+    auto one_iter = [&]() {
+        bool timed = false;
+        int slot = 0;
+        if (timing && tacc->pairs < int(h->tev.size() / 4)) {
+            timed = true;
+            slot = tacc->pairs++;
+        }
+        pa.n_pq = apply_op_prec(h, prec, h->pp, h->pq, sigx, sigA, hs, h->part, h->fl, timed, slot);
+        hipLaunchKernelGGL(k_pcg_xr, dim3(ge), dim3(kBlock), 0, h->stream, pa);
+        hipLaunchKernelGGL(k_pcg_p, dim3(ge), dim3(kBlock), 0, h->stream, pa);
+    };
+    auto snapshot = [&](int slot) {
+        HIPCHK(hipMemcpyAsync(&h->fl_host[slot], h->fl, sizeof(Flags), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipEventRecord(h->ev_chunk[slot], h->stream));
+    };
+    auto stop = [&](const Flags& f) {
+        return f.pcg_converged || f.pcg_breakdown || f.pcg_capped || f.ipm_done;
+    };
+    // Chunks of iterations are queued ahead of the host check: kernels of a
+    // finished solve return at once, so the GPU never waits on the host.
+    int chunk = 4;
+    int64_t launched = 0;
+    const int64_t guard = int64_t(h->set.pcg_max_iter) + 4096;
+    int cur = 0;
+    for (int i = 0; i < chunk; ++i) one_iter();
+    launched += chunk;
+    snapshot(cur);
+    Flags f{};
+    while (true) {
+        chunk = std::min(chunk * 2, 64);
+        for (int i = 0; i < chunk; ++i) one_iter();
+        launched += chunk;
+        snapshot(cur ^ 1);
+        HIPCHK(hipEventSynchronize(h->ev_chunk[cur]));
+        f = h->fl_host[cur];
+        if (stop(f) || launched > guard) {
+            HIPCHK(hipEventSynchronize(h->ev_chunk[cur ^ 1]));
+            f = h->fl_host[cur ^ 1];
+            break;
+        }
+        cur ^= 1;
+    }
+    return f;
+}
+
+void reset_flags(qp_handle* h) {
+    Flags z{};
+    HIPCHK(hipMemcpyAsync(h->fl, &z, sizeof(Flags), hipMemcpyHostToDevice, h->stream));
+}
+
+void harvest_timing(qp_handle* h, const TimingAcc& ta, qp_info* info) {
+    if (!info) return;
+    double f = 0.0, b = 0.0;
+    for (int i = 0; i < ta.pairs; ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->tev[4 * i], h->tev[4 * i + 1]));
+        f += ms;
+        HIPCHK(hipEventElapsedTime(&ms, h->tev[4 * i + 2], h->tev[4 * i + 3]));
+        b += ms;
+    }
+    info->t_spmv_fwd_ms += f;
+    info->t_spmv_bwd_ms += b;
+    info->n_spmv_fwd += ta.pairs;
+    info->n_spmv_bwd += ta.pairs;
+}
+
+void ensure_timing_events(qp_handle* h) {
+    if (h->set.timing && h->tev.empty()) {
+        h->tev.resize(4 * 1024);
+        for (auto& e : h->tev) HIPCHK(hipEventCreate(&e));
+    }
+}
+
+qp_status fail(qp_handle* h, qp_status st, const std::string& msg) {
+    if (h) h->err = msg;
+    return st;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+void qp_default_settings(qp_settings* s) {
+    if (!s) return;
+    std::memset(s, 0, sizeof(*s));
+    s->precision = QP_FP64;
+    s->refine_steps = 2;
+    s->pcg_tol = 1e-8;
+    s->pcg_max_iter = 20000;
+    s->mu0 = -1.0;
+    s->mu_tol = 1e-10;
+    s->tau = 0.995;
+    s->max_ipm_iter = 200;
+    s->step_mode = 0;
+    s->scale_objective = 1;
+    s->schedule = 0;
+    s->timing = 0;
+    s->log_level = 0;
+}
+
+const char* qp_last_error(const qp_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+void qp_destroy(qp_handle* h) { delete h; }
+
+void qp_sizes(const qp_handle* h, int32_t* n, int32_t* m, int32_t* nJ, int64_t* nnzJ, int64_t* nnzA) {
+    if (!h) return;
+    if (n) *n = h->n;
+    if (m) *m = h->m;
+    if (nJ) *nJ = h->nJ;
+    if (nnzJ) *nnzJ = h->nnzJ;
+    if (nnzA) *nnzA = h->nnzA;
+}
+
+qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const double* W,
+                    const qp_csr* A, const qp_range* b, const qp_range* bounds, const qp_settings* s,
+                    void* hip_stream) {
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "out is NULL";
+        return QP_ERR_INVALID;
+    }
+    *out = nullptr;
+    std::string e = validate_problem(H, J, W, A, b, bounds, s);
+    if (!e.empty()) {
+        g_create_error = e;
+        return QP_ERR_INVALID;
+    }
+    qp_handle* h = new (std::nothrow) qp_handle();
+    if (!h) {
+        g_create_error = "host allocation failed";
+        return QP_ERR_NOMEM;
+    }
+    try {
+        if (s) h->set = *s;
+        else qp_default_settings(&h->set);
+        h->n = J->cols;
+        h->nJ = J->rows;
+        h->m = A ? A->rows : 0;
+        h->k = H->k;
+        h->gamma = H->gamma;
+        const int n = h->n, m = h->m, nJ = h->nJ;
+
+        // host preparation (no device calls yet)
+        HostCsr hJ = to_host_csr(J);
+        HostCsr hJt = transpose(hJ);
+        HostCsr hA, hAt;
+        if (m > 0) {
+            hA = to_host_csr(A);
+            hAt = transpose(hA);
+        }
+        h->nnzJ = hJ.nnz();
+        h->nnzA = m > 0 ? hA.nnz() : 0;
+        std::vector<double> xlo(n, -INFINITY), xhi(n, INFINITY), alo(m, -INFINITY), ahi(m, INFINITY);
+        if (bounds) {
+            if (bounds->lo) std::copy(bounds->lo, bounds->lo + n, xlo.begin());
+            if (bounds->hi) std::copy(bounds->hi, bounds->hi + n, xhi.begin());
+        }
+        if (m > 0) {
+            if (b->lo) std::copy(b->lo, b->lo + m, alo.begin());
+            if (b->hi) std::copy(b->hi, b->hi + m, ahi.begin());
+        }
+        double cmax = 0.0, mt = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (std::isfinite(xlo[j])) { cmax = std::max(cmax, std::fabs(xlo[j])); mt += 1; }
+            if (std::isfinite(xhi[j])) { cmax = std::max(cmax, std::fabs(xhi[j])); mt += 1; }
+        }
+        for (int i = 0; i < m; ++i) {
+            if (std::isfinite(alo[i])) { cmax = std::max(cmax, std::fabs(alo[i])); mt += 1; }
+            if (std::isfinite(ahi[i])) { cmax = std::max(cmax, std::fabs(ahi[i])); mt += 1; }
+        }
+        h->cscale = 1.0 + cmax;
+        h->mtot = mt;
+        if (h->set.schedule != 0) {
+            h->GJ = h->GJt = h->set.schedule;
+        } else {
+            h->GJ = pick_lanes(h->nnzJ, nJ);
+            const int64_t col_nnz = h->nnzJ + h->nnzA;
+            h->GJt = pick_lanes(col_nnz, n);
+        }
+
+        // device
+        HIPCHK(hipGetDevice(&h->device));
+        if (hip_stream) {
+            h->stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+            h->own_stream = true;
+        }
+        h->Jp = h->upload(hJ.ptr.data(), hJ.ptr.size());
+        h->Jc = h->upload(hJ.col.data(), hJ.col.size());
+        h->Jv = h->upload(hJ.val.data(), hJ.val.size());
+        h->Jtp = h->upload(hJt.ptr.data(), hJt.ptr.size());
+        h->Jtc = h->upload(hJt.col.data(), hJt.col.size());
+        h->Jtv = h->upload(hJt.val.data(), hJt.val.size());
+        h->hJv = std::move(hJ.val);
+        h->hJtv = std::move(hJt.val);
+        h->W = h->upload(W ? W : xlo.data(), size_t(nJ));
+        if (m > 0) {
+            h->Ap = h->upload(hA.ptr.data(), hA.ptr.size());
+            h->Ac = h->upload(hA.col.data(), hA.col.size());
+            h->Av = h->upload(hA.val.data(), hA.val.size());
+            h->Atp = h->upload(hAt.ptr.data(), hAt.ptr.size());
+            h->Atc = h->upload(hAt.col.data(), hAt.col.size());
+            h->Atv = h->upload(hAt.val.data(), hAt.val.size());
+        }
+        h->xlo = h->upload(xlo.data(), n);
+        h->xhi = h->upload(xhi.data(), n);
+        h->alo = h->upload(alo.data(), std::max(m, 1));
+        h->ahi = h->upload(ahi.data(), std::max(m, 1));
+        h->p = h->upload(H->p, n);
+        if (h->k > 0) {
+            h->U = h->upload(H->U, size_t(n) * h->k);
+            h->w = h->upload(H->w, size_t(h->k));
+        }
+        h->diagH = h->dalloc<double>(n);
+
+        // work vectors
+        IpmVec& v = h->iv;
+        v.n = n; v.m = m;
+        v.xlo = h->xlo; v.xhi = h->xhi; v.alo = h->alo; v.ahi = h->ahi; v.p = h->p; v.diagH = h->diagH;
+        double** nvec[] = {&v.x, &v.s_lx, &v.s_ux, &v.l_lx, &v.l_ux, &v.r_lx, &v.r_ux, &v.sigx, &v.hx, &v.d,
+                           &v.rhs_a, &v.rhs_b, &v.ds_lx, &v.ds_ux, &v.dl_lx, &v.dl_ux};
+        for (double** pv : nvec) *pv = h->dalloc<double>(n);
+        double** mvec[] = {&v.s_lA, &v.s_uA, &v.l_lA, &v.l_uA, &v.ax, &v.r_lA, &v.r_uA, &v.sigA,
+                           &v.va, &v.vb, &v.ya, &v.ds_lA, &v.ds_uA, &v.dl_lA, &v.dl_uA};
+        for (double** pv : mvec) *pv = h->dalloc<double>(std::max(m, 1));
+        h->t = h->dalloc<double>(std::max(nJ, 1));
+        h->u = h->dalloc<double>(std::max(m, 1));
+        h->px = h->dalloc<double>(n);
+        h->pr = h->dalloc<double>(n);
+        h->pz = h->dalloc<double>(n);
+        h->pp = h->dalloc<double>(n);
+        h->pq = h->dalloc<double>(n);
+        v.dx = h->px;
+        h->zero_n = h->dalloc<double>(n);
+        h->zero_m = h->dalloc<double>(std::max(m, 1));
+        h->tmp_n = h->dalloc<double>(n);
+        h->tmp_n2 = h->dalloc<double>(n);
+        h->tmp_m = h->dalloc<double>(std::max(m, 1));
+        const size_t nbA = size_t((m + 3) / 4) + 1;
+        h->part_len = 8 * (size_t(kMaxPartials) + nbA + 64);
+        h->part = h->dalloc<double>(h->part_len);
+        h->part2 = h->dalloc<double>(h->part_len);
+        h->partA = h->dalloc<double>(h->part_len);
+        h->log = h->dalloc<double>(4 * size_t(h->set.max_ipm_iter + 1));
+        h->isc = h->dalloc<IpmScal>(1);
+        h->psc = h->dalloc<PcgScal>(1);
+        h->fl = h->dalloc<Flags>(1);
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->fl_host), 2 * sizeof(Flags), hipHostMallocDefault));
+        for (auto& ev : h->ev_chunk) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCHK(hipEventCreate(&h->ev_t0));
+        HIPCHK(hipEventCreate(&h->ev_t1));
+        HIPCHK(hipEventCreate(&h->ev_p0));
+        HIPCHK(hipEventCreate(&h->ev_p1));
+        HIPCHK(hipMemsetAsync(h->zero_n, 0, sizeof(double) * n, h->stream));
+        HIPCHK(hipMemsetAsync(h->zero_m, 0, sizeof(double) * std::max(m, 1), h->stream));
+
+        // cached diag(H) (Section 4.1.2: computed once, H does not change)
+        {
+            const int G = 64;
+            hipLaunchKernelGGL(k_diag_h<G>, dim3(grid_rows(n, G)), dim3(kBlock), 0, h->stream,
+                               (const int*)h->Jtp, (const int*)h->Jtc, (const double*)h->Jtv,
+                               (const double*)h->W, n, h->gamma, (const double*)h->U, (const double*)h->w,
+                               h->k, h->diagH);
+            HIPCHK(hipGetLastError());
+        }
+        if (h->set.precision != QP_FP64) ensure_lowp(h, h->set.precision);
+        HIPCHK(hipStreamSynchronize(h->stream));
+    } catch (const HipError& he) {
+        g_create_error = std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e);
+        delete h;
+        return he.e == hipErrorOutOfMemory ? QP_ERR_NOMEM : QP_ERR_DEVICE;
+    } catch (const std::bad_alloc&) {
+        g_create_error = "host allocation failed";
+        delete h;
+        return QP_ERR_NOMEM;
+    }
+    *out = h;
+    return QP_OK;
+}
+
+qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* sigma_A, const double* v,
+                            double* y, int32_t precision, int32_t reps, qp_info* info) {
+    if (!h) return QP_ERR_INVALID;
+    if (!sigma_x || !v || !y || (h->m > 0 && !sigma_A)) return fail(h, QP_ERR_INVALID, "NULL argument");
+    if (precision < QP_FP64 || precision > QP_BF16) return fail(h, QP_ERR_INVALID, "precision out of range");
+    if (reps < 1) reps = 1;
+    for (int j = 0; j < h->n; ++j)
+        if (!(sigma_x[j] >= 0.0) || !std::isfinite(sigma_x[j]) || !std::isfinite(v[j]))
+            return fail(h, QP_ERR_INVALID, "sigma_x must be finite >= 0 and v finite");
+    for (int i = 0; i < h->m; ++i)
+        if (!(sigma_A[i] >= 0.0) || !std::isfinite(sigma_A[i]))
+            return fail(h, QP_ERR_INVALID, "sigma_A must be finite and >= 0");
+    try {
+        ensure_lowp(h, precision);
+        ensure_timing_events(h);
+        HIPCHK(hipMemcpyAsync(h->tmp_n, sigma_x, sizeof(double) * h->n, hipMemcpyHostToDevice, h->stream));
+        if (h->m > 0)
+            HIPCHK(hipMemcpyAsync(h->tmp_m, sigma_A, sizeof(double) * h->m, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->tmp_n2, v, sizeof(double) * h->n, hipMemcpyHostToDevice, h->stream));
+        TimingAcc ta;
+        HIPCHK(hipEventRecord(h->ev_t0, h->stream));
+        for (int r = 0; r < reps; ++r) {
+            const bool timed = h->set.timing && ta.pairs < int(h->tev.size() / 4);
+            const int slot = timed ? ta.pairs++ : 0;
+            apply_op_prec(h, precision, h->tmp_n2, h->pq, h->tmp_n, h->m > 0 ? h->tmp_m : nullptr, 1.0,
+                          nullptr, nullptr, timed, slot);
+        }
+        HIPCHK(hipEventRecord(h->ev_t1, h->stream));
+        HIPCHK(hipMemcpyAsync(y, h->pq, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
+            info->t_solve_ms = ms;
+            harvest_timing(h, ta, info);
+        }
+    } catch (const HipError& he) {
+        return fail(h, QP_ERR_DEVICE, std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e));
+    }
+    return QP_OK;
+}
+
+qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigma_A, const double* rhs,
+                         double* dx, qp_info* info) {
+    if (!h) return QP_ERR_INVALID;
+    if (!sigma_x || !rhs || !dx || (h->m > 0 && !sigma_A)) return fail(h, QP_ERR_INVALID, "NULL argument");
+    for (int j = 0; j < h->n; ++j)
+        if (!(sigma_x[j] >= 0.0) || !std::isfinite(sigma_x[j]))
+            return fail(h, QP_ERR_INVALID, "sigma_x must be finite and >= 0");
+    for (int i = 0; i < h->m; ++i)
+        if (!(sigma_A[i] >= 0.0) || !std::isfinite(sigma_A[i]))
+            return fail(h, QP_ERR_INVALID, "sigma_A must be finite and >= 0");
+    qp_status st = QP_OK;
+    try {
+        ensure_timing_events(h);
+        const int n = h->n, m = h->m;
+        double* sigx = h->iv.sigx;
+        double* sigA = h->iv.sigA;
+        double* d = h->iv.d;
+        double* b = h->iv.rhs_b;
+        HIPCHK(hipMemcpyAsync(sigx, sigma_x, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+        if (m > 0) HIPCHK(hipMemcpyAsync(sigA, sigma_A, sizeof(double) * m, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(b, rhs, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+        reset_flags(h);
+        hipLaunchKernelGGL(k_jacobi, dim3(grid_rows(n, 64)), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
+                           (const double*)h->Atv, (const int*)h->Atc, m > 0 ? 1 : 0, (const double*)sigA,
+                           (const double*)sigx, (const double*)h->diagH, n, d);
+        HIPCHK(hipGetLastError());
+        TimingAcc ta;
+        HIPCHK(hipEventRecord(h->ev_t0, h->stream));
+        Flags f = run_pcg(h, QP_FP64, nullptr, b, sigx, m > 0 ? sigA : nullptr, d, 1.0, false, &ta);
+        HIPCHK(hipEventRecord(h->ev_t1, h->stream));
+        HIPCHK(hipMemcpyAsync(dx, h->px, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+        PcgScal ps{};
+        HIPCHK(hipMemcpyAsync(&ps, h->psc, sizeof(PcgScal), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (f.pcg_breakdown) st = QP_ERR_NUMERIC;
+        else if (!f.pcg_converged) st = QP_ERR_NOT_CONVERGED;
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->status = st;
+            info->pcg_iters = ps.iters;
+            info->pcg_solves = 1;
+            info->pcg_capped = f.pcg_capped;
+            info->pcg_relres = ps.bnorm2 > 0 ? std::sqrt(ps.rr / ps.bnorm2) : 0.0;
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
+            info->t_solve_ms = info->t_pcg_ms = ms;
+            harvest_timing(h, ta, info);
+        }
+    } catch (const HipError& he) {
+        return fail(h, QP_ERR_DEVICE, std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e));
+    }
+    if (st == QP_ERR_NUMERIC) h->err = "PCG breakdown";
+    else if (st == QP_ERR_NOT_CONVERGED) h->err = "PCG reached pcg_max_iter";
+    return st;
+}
+
+qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_info* info) {
+    if (!h) return QP_ERR_INVALID;
+    if (!x) return fail(h, QP_ERR_INVALID, "x is NULL");
+    if (h->set.precision != QP_FP64)
+        return fail(h, QP_ERR_INVALID, "this build solves with precision QP_FP64 only");
+    qp_status st = QP_OK;
+    try {
+        ensure_timing_events(h);
+        const int n = h->n, m = h->m;
+        IpmVec& v = h->iv;
+        reset_flags(h);
+        {
+            IpmScal s0{};
+            s0.mu_tol = h->set.mu_tol;
+            s0.tau = h->set.tau;
+            s0.cscale = h->cscale;
+            s0.step_mode = h->set.step_mode;
+            HIPCHK(hipMemcpyAsync(h->isc, &s0, sizeof(IpmScal), hipMemcpyHostToDevice, h->stream));
+        }
+        HIPCHK(hipEventRecord(h->ev_t0, h->stream));
+        // start point, objective scale, mu0
+        const int gx = grid_elems(n);
+        hipLaunchKernelGGL(k_ipm_init_x, dim3(gx), dim3(kBlock), 0, h->stream, v, h->partA);
+        HIPCHK(hipGetLastError());
+        int nps = gx;
+        if (m > 0) {
+            const int ga = grid_rows(m, 64);
+            hipLaunchKernelGGL(k_ipm_init_A, dim3(ga), dim3(kBlock), 0, h->stream, v, (const int*)h->Ap,
+                               (const int*)h->Ac, (const double*)h->Av, h->partA + gx);
+            HIPCHK(hipGetLastError());
+            nps += ga;
+        }
+        apply_op<double, double>(h, v.x, h->tmp_n, nullptr, nullptr, 1.0, nullptr, nullptr, false, 0);
+        hipLaunchKernelGGL(k_ipm_scale, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->tmp_n,
+                           (const double*)h->p, n, (const double*)h->partA, nps, h->mtot,
+                           h->set.scale_objective, h->set.mu0, h->isc);
+        HIPCHK(hipGetLastError());
+        IpmScal sc{};
+        HIPCHK(hipMemcpyAsync(&sc, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        const double hs = sc.hs;
+
+        // residual pass + barrier rule
+        const int G = h->GJ, Gt = h->GJt;
+        auto residuals = [&](int apply) {
+            FwdArgs<double> f{};
+            f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = h->Jv; f.W = h->W; f.nJ = h->nJ;
+            f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = m;
+            f.x = v.x; f.t = h->t; f.u = h->u; f.sigA = nullptr; f.fl = nullptr;
+            f.nbJ = h->nJ > 0 ? grid_rows(h->nJ, G) : 0;
+            const int nbA = m > 0 ? grid_rows(m, 64) : 0;
+            const int grid = std::max(1, f.nbJ + nbA);
+            switch (G) {
+                case 4: hipLaunchKernelGGL(k_ipm_fwd<4>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
+                case 8: hipLaunchKernelGGL(k_ipm_fwd<8>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
+                case 16: hipLaunchKernelGGL(k_ipm_fwd<16>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
+                case 32: hipLaunchKernelGGL(k_ipm_fwd<32>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
+                default: hipLaunchKernelGGL(k_ipm_fwd<64>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
+            }
+            HIPCHK(hipGetLastError());
+            IpmBwdArgs ba{};
+            ba.Jtp = h->Jtp; ba.Jtc = h->Jtc; ba.Jtv = h->Jtv;
+            ba.Atp = h->Atp; ba.Atc = h->Atc; ba.Atv = h->Atv; ba.hasA = m > 0;
+            ba.t = h->t; ba.gamma = h->gamma;
+            const int gb = grid_rows_capped(n, Gt);
+            switch (Gt) {
+                case 4: hipLaunchKernelGGL(k_ipm_bwd<4>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
+                case 8: hipLaunchKernelGGL(k_ipm_bwd<8>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
+                case 16: hipLaunchKernelGGL(k_ipm_bwd<16>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
+                case 32: hipLaunchKernelGGL(k_ipm_bwd<32>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
+                default: hipLaunchKernelGGL(k_ipm_bwd<64>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
+            }
+            HIPCHK(hipGetLastError());
+            hipLaunchKernelGGL(k_ipm_check, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->partA, nbA,
+                               (const double*)h->part, gb, apply, h->isc, h->fl, h->log);
+            HIPCHK(hipGetLastError());
+        };
+        residuals(0);
+
+        TimingAcc ta;
+        int64_t pcg_total = 0;
+        int pcg_solves = 0, capped = 0;
+        double last_relres = 0.0;
+        float pcg_ms = 0.f;
+        Flags f{};
+        for (int it = 0; it < h->set.max_ipm_iter; ++it) {
+            HIPCHK(hipEventRecord(h->ev_p0, h->stream));
+            f = run_pcg(h, QP_FP64, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d, hs, true, &ta);
+            HIPCHK(hipEventRecord(h->ev_p1, h->stream));
+            if (f.ipm_done) break;
+            {
+                HIPCHK(hipEventSynchronize(h->ev_p1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, h->ev_p0, h->ev_p1));
+                pcg_ms += ms;
+            }
+            pcg_total += f.pcg_iters;
+            pcg_solves += 1;
+            capped += f.pcg_capped;
+            if (f.pcg_breakdown) {
+                st = QP_ERR_NUMERIC;
+                break;
+            }
+            // recovery, ratio test, update
+            const int nbA = m > 0 ? grid_rows(m, 64) : 0;
+            const int nbx = grid_elems(n);
+            hipLaunchKernelGGL(k_ipm_recover, dim3(nbA + nbx), dim3(kBlock), 0, h->stream, v, (const int*)h->Ap,
+                               (const int*)h->Ac, (const double*)h->Av, nbA, (const IpmScal*)h->isc, h->part2,
+                               (const Flags*)h->fl);
+            HIPCHK(hipGetLastError());
+            hipLaunchKernelGGL(k_ipm_update, dim3(grid_elems(int64_t(n) + m)), dim3(kBlock), 0, h->stream, v,
+                               (const double*)h->part2, nbA + nbx, h->isc, (const Flags*)h->fl);
+            HIPCHK(hipGetLastError());
+            residuals(1);
+        }
+        // outputs
+        HIPCHK(hipEventRecord(h->ev_t1, h->stream));
+        double* lx = h->tmp_n;
+        double* lA = h->tmp_m;
+        hipLaunchKernelGGL(k_ipm_output, dim3(grid_elems(int64_t(n) + m)), dim3(kBlock), 0, h->stream, v,
+                           (const IpmScal*)h->isc, lx, lA);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(x, v.x, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+        if (lam_x) HIPCHK(hipMemcpyAsync(lam_x, lx, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+        if (lam_A && m > 0) HIPCHK(hipMemcpyAsync(lam_A, lA, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(&sc, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
+        PcgScal ps{};
+        HIPCHK(hipMemcpyAsync(&ps, h->psc, sizeof(PcgScal), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (st == QP_OK && !sc.done) st = QP_ERR_NOT_CONVERGED;
+        last_relres = ps.bnorm2 > 0 ? std::sqrt(ps.rr / ps.bnorm2) : 0.0;
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->status = st;
+            info->ipm_iters = sc.iter;
+            info->pcg_iters = pcg_total;
+            info->pcg_solves = pcg_solves;
+            info->pcg_capped = capped;
+            info->mu = sc.mu;
+            info->rnorm = sc.rnorm;
+            info->zeta = sc.zeta;
+            info->objective = sc.zeta * (0.5 * sc.xHx + sc.px);
+            info->pcg_relres = last_relres;
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
+            info->t_solve_ms = ms;
+            info->t_pcg_ms = pcg_ms;
+            harvest_timing(h, ta, info);
+        }
+    } catch (const HipError& he) {
+        return fail(h, QP_ERR_DEVICE, std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e));
+    }
+    if (st == QP_ERR_NUMERIC) h->err = "PCG breakdown";
+    else if (st == QP_ERR_NOT_CONVERGED) h->err = "IPM reached max_ipm_iter";
+    return st;
+}
+
+}  // extern "C"

@@ -68,15 +68,26 @@ def _csr(indptr, indices, data, shape) -> sp.csr_matrix:
 def round_to_bf16(v: np.ndarray) -> np.ndarray:
     """Round float64 values to the nearest bfloat16 value (ties to even).
 
-    Goes through float32 first (round to nearest even), then drops the low 16
-    bits of the float32 pattern with round-to-nearest-even.  Used only to
-    *define* problem data whose values are bfloat16 numbers.
+    Goes through binary32 with round-to-odd (truncate, then set the last bit
+    when any dropped bit was set), then rounds the binary32 pattern to its top
+    16 bits with round-to-nearest-even; rounding to odd first keeps the two
+    steps equal to one correct rounding.  Used only to *define* problem data
+    whose values are bfloat16 numbers (finite, within the binary32 normal
+    range, or zero).
     """
-    f = np.asarray(v, dtype=np.float64).astype(np.float32)
-    b = f.view(np.uint32).astype(np.uint64)
-    lsb = (b >> 16) & 1
-    b = (b + 0x7FFF + lsb) >> 16
-    out = (b.astype(np.uint32) << 16).view(np.float32)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    d = v.view(np.uint64)
+    sign = d >> np.uint64(63)
+    e = ((d >> np.uint64(52)) & np.uint64(0x7FF)).astype(np.int64) - 1023 + 127
+    m = d & np.uint64((1 << 52) - 1)
+    normal = (e >= 1) & (e <= 254)
+    b = ((sign << np.uint64(31)) | (np.clip(e, 0, 255).astype(np.uint64) << np.uint64(23))
+         | (m >> np.uint64(29)))
+    b = b | ((m & np.uint64((1 << 29) - 1)) != 0).astype(np.uint64)
+    b = np.where(normal, b, v.astype(np.float32).view(np.uint32).astype(np.uint64))
+    lsb = (b >> np.uint64(16)) & np.uint64(1)
+    b = (b + np.uint64(0x7FFF) + lsb) >> np.uint64(16)
+    out = (b.astype(np.uint32) << np.uint32(16)).view(np.float32)
     return out.astype(np.float64)
 
 

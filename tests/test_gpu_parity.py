@@ -1,0 +1,225 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (derived in the design doc):
+* operator y = K v in FP64: |y - y_ref|_i <= 1e-12 * (|K| |v|)_i;
+* low-precision operator: |y - y_ref|_i <= c_p * (|K| |v|)_i with c_p from the
+  value rounding (2^-24 FP32, 2^-8 BF16) plus FP32 accumulation over the row;
+* Newton step (PCG, tol 1e-10): ||K dx - rhs|| <= 1.01e-10 ||rhs|| (up to
+  rounding) and dx within 1e-6 (relative) of the Cholesky solution;
+* full solve: ||x - x_oracle||_inf <= 1e-6 (1 + ||x_oracle||_inf), relative
+  objective error <= 1e-8 plus the gap the stopping rule allows, KKT
+  certificate <= 1e-9, bitwise identical x on a second run.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import qpsynth
+from paper_2405_03584_amd import qpgpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _gap_bound(res_or, prob, mu_tol=1e-10):
+    m_tot = sum(len(v) for v in res_or.lam.values())
+    return 2.0 * m_tot * mu_tol * res_or.zeta
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return [qpsynth.config1(i) for i in range(5)]
+
+
+def _abs_op(prob, sigma_x, sigma_A):
+    """|K| as a dense matrix (entrywise absolute values of each term)."""
+    J = abs(prob.J).toarray()
+    K = J.T @ (prob.W[:, None] * J) + prob.gamma * np.eye(prob.n)
+    K[np.diag_indices(prob.n)] += sigma_x
+    if prob.m:
+        Ad = abs(prob.A).toarray()
+        K += (Ad * sigma_A[:, None]).T @ Ad
+    return K
+
+
+# ----------------------------------------------------------------------------
+# operator (a4) and the matrix kernels
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["cfg1", "tiny3", "tiny12", "band"])
+def test_operator_fp64(which):
+    prob = {"cfg1": lambda: qpsynth.config1(1), "tiny3": lambda: qpsynth.tiny(3),
+            "tiny12": lambda: qpsynth.tiny(12), "band": lambda: qpsynth.config2(scale=0.02)}[which]()
+    it = qpsynth.random_iterate(prob, 7)
+    print(f"operator fp64 on {prob.name} n={prob.n} m={prob.m}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob)
+    sA = it["sigma_A"] if prob.m else None
+    y, _ = qpgpu.qp_operator_apply(h, it["sigma_x"], sA, it["v"])
+    K = oracle.condensed_operator_dense(prob, it["sigma_x"], sA)
+    ref = K @ it["v"]
+    bound = _abs_op(prob, it["sigma_x"], sA) @ np.abs(it["v"])
+    assert np.all(np.abs(y - ref) <= 1e-12 * bound + 1e-300)
+
+
+@pytest.mark.parametrize("prec,unit", [("fp32", 2.0 ** -24), ("bf16", 2.0 ** -8)])
+def test_operator_low_precision(prec, unit):
+    prob = qpsynth.config2(scale=0.02)
+    it = qpsynth.random_iterate(prob, 9)
+    print(f"operator {prec} on {prob.name}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob)
+    y, _ = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
+    ref = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"]) @ it["v"]
+    Lj = np.diff(prob.J.indptr).max()
+    Lt = np.diff(prob.J.tocsc().indptr).max()
+    # value rounding (twice: J and J^T) + FP32 accumulation over both passes
+    c = 2 * unit + (Lj + Lt + 2) * 2.0 ** -24
+    bound = _abs_op(prob, it["sigma_x"], it["sigma_A"]) @ np.abs(it["v"])
+    err = np.abs(y - ref)
+    assert np.all(err <= c * bound), float((err / bound).max())
+    # and it is not exact: the low-precision copy is really used
+    assert np.abs(y - ref).max() > 0
+
+
+def test_operator_deterministic():
+    prob = qpsynth.config2(scale=0.02)
+    it = qpsynth.random_iterate(prob, 3)
+    h = qpgpu.qp_create_from_problem(prob)
+    y1, _ = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"])
+    y2, _ = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], reps=3)
+    assert y1.tobytes() == y2.tobytes()
+
+
+@pytest.mark.parametrize("sched", [4, 8, 16, 32, 64])
+def test_operator_every_schedule(sched):
+    prob = qpsynth.config1(2)
+    it = qpsynth.random_iterate(prob, 5)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(schedule=sched))
+    y, _ = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"])
+    ref = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"]) @ it["v"]
+    bound = _abs_op(prob, it["sigma_x"], it["sigma_A"]) @ np.abs(it["v"])
+    assert np.all(np.abs(y - ref) <= 1e-12 * bound)
+
+
+# ----------------------------------------------------------------------------
+# one Newton direction (a3-a5): Jacobi PCG vs dense Cholesky
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["cfg1", "band"])
+def test_newton_step_matches_cholesky(which):
+    prob = qpsynth.config1(0) if which == "cfg1" else qpsynth.config2(scale=0.02)
+    it = qpsynth.random_iterate(prob, 11)
+    print(f"newton step on {prob.name}", flush=True)
+    s = qpgpu.qp_default_settings(pcg_tol=1e-10, pcg_max_iter=50000)
+    h = qpgpu.qp_create_from_problem(prob, settings=s)
+    st, dx, info = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], it["rhs"])
+    assert st == qpgpu.QP_OK, info
+    K = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"])
+    ref = oracle.newton_solve_dense(K, it["rhs"])
+    res = np.linalg.norm(K @ dx - it["rhs"]) / np.linalg.norm(it["rhs"])
+    assert res <= 1e-9
+    assert np.abs(dx - ref).max() <= 1e-6 * np.abs(ref).max()
+    assert info["pcg_iters"] > 0
+
+
+def test_newton_step_nan_rhs_is_numeric_error():
+    prob = qpsynth.config1(0)
+    it = qpsynth.random_iterate(prob, 1)
+    h = qpgpu.qp_create_from_problem(prob)
+    rhs = it["rhs"].copy()
+    rhs[4] = np.nan
+    st, _, _ = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], rhs)
+    assert st == qpgpu.QP_ERR_NUMERIC
+
+
+def test_newton_step_zero_rhs():
+    prob = qpsynth.config1(0)
+    it = qpsynth.random_iterate(prob, 1)
+    h = qpgpu.qp_create_from_problem(prob)
+    st, dx, info = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], np.zeros(prob.n))
+    assert st == qpgpu.QP_OK and np.all(dx == 0) and info["pcg_iters"] == 0
+
+
+def test_newton_step_iteration_cap():
+    prob = qpsynth.config1(0)
+    it = qpsynth.random_iterate(prob, 1)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(pcg_max_iter=3))
+    st, dx, info = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], it["rhs"])
+    assert st == qpgpu.QP_ERR_NOT_CONVERGED and info["pcg_iters"] == 3
+
+
+# ----------------------------------------------------------------------------
+# whole solve (a2-a9)
+# ----------------------------------------------------------------------------
+
+def _check_solve(prob, res, ref, x_tol=1e-6):
+    assert res.status == qpgpu.QP_OK, (qpgpu.STATUS_NAMES[res.status], res.info)
+    xs = 1 + np.abs(ref.x).max()
+    dx = np.abs(res.x - ref.x).max()
+    assert dx <= x_tol * xs, dx
+    dobj = abs(res.info["objective"] - ref.objective)
+    assert dobj <= 1e-8 * (1 + abs(ref.objective)) + _gap_bound(ref, prob), dobj
+    cert = oracle.kkt_certificate(prob, res.x, res.lam_x, res.lam_A if prob.m else None)
+    assert cert.worst() <= 1e-9, cert
+    return dx, cert
+
+
+@pytest.mark.parametrize("inst", range(5))
+def test_solve_config1(cfg1, inst):
+    prob = cfg1[inst]
+    print(f"solve {prob.name}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob)
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    _check_solve(prob, res, ref)
+
+
+@pytest.mark.parametrize("inst", list(range(0, 40, 3)))
+def test_solve_tiny_vs_bruteforce(inst):
+    prob = qpsynth.tiny(inst)
+    print(f"solve {prob.name} n={prob.n} m={prob.m}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob)
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    bf = oracle.bruteforce_qp(prob)
+    _check_solve(prob, res, ref)
+    assert np.abs(res.x - bf.x).max() <= 1e-6 * (1 + np.abs(bf.x).max())
+
+
+def test_solve_band_small():
+    prob = qpsynth.config2(scale=0.02)
+    print(f"solve {prob.name} n={prob.n} m={prob.m}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob)
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    _check_solve(prob, res, ref)
+
+
+def test_solve_is_bitwise_deterministic():
+    prob = qpsynth.config1(3)
+    h = qpgpu.qp_create_from_problem(prob)
+    a = qpgpu.qp_solve(h)
+    b = qpgpu.qp_solve(h)
+    assert a.x.tobytes() == b.x.tobytes()
+    assert a.lam_A.tobytes() == b.lam_A.tobytes()
+    assert a.info["pcg_iters"] == b.info["pcg_iters"]
+
+
+def test_solve_without_constraints_or_bounds():
+    prob = qpsynth.config1(0)
+    n = prob.n
+    free = qpsynth.QPProblem(gamma=prob.gamma, p=prob.p, J=prob.J, W=prob.W,
+                             x_lo=np.full(n, -np.inf), x_hi=np.full(n, np.inf))
+    h = qpgpu.qp_create_from_problem(free)
+    res = qpgpu.qp_solve(h)
+    H = oracle.hessian_dense(free)
+    x_ref = np.linalg.solve(H, -free.p)
+    assert res.status == qpgpu.QP_OK
+    assert np.abs(res.x - x_ref).max() <= 1e-6 * (1 + np.abs(x_ref).max())
+
+
+def test_solve_iteration_limit_returns_not_converged():
+    prob = qpsynth.config1(0)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(max_ipm_iter=2))
+    res = qpgpu.qp_solve(h)
+    assert res.status == qpgpu.QP_ERR_NOT_CONVERGED
+    assert res.info["ipm_iters"] == 2
+    assert np.all(np.isfinite(res.x))
