@@ -1,0 +1,189 @@
+"""Benchmark: QP time-to-solution, PCG iterations/s and SpMV HBM GB/s vs peak.
+
+One step = one whole QP solve (qp_solve: start point, residuals, every Jacobi
+PCG direction, recovery, ratio test, update, barrier rule) of the banded-dose
+QP with n = 20,000 spots, J 400,000 x 20,000 (40M nnz), A 2,000 x 20,000 at 2%,
+bounds [0, 50], PCG tolerance 1e-8.  Problem data are resident in HBM (created
+once by qp_create) before the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
+                    [--scale 1.0] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QP time-to-solution & PCG iters/s; SpMV HBM GB/s vs peak, mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes=8):
+    """Algorithmic HBM bytes of one operator product, per kernel.
+
+    Each matrix value and int32 index read once, row pointers once, every
+    dense vector read or written once (gathered vectors counted once)."""
+    fwd = (nnzJ * (vbytes + 4) + (nJ + 1) * 4 + n * 8 + nJ * 8 + nJ * 8
+           + nnzA * 12 + (m + 1) * 4 + m * 8 + m * 8)
+    bwd = (nnzJ * (vbytes + 4) + (n + 1) * 4 + nJ * 8
+           + nnzA * 12 + (n + 1) * 4 + m * 8 + n * 8 * 3)
+    return fwd, bwd
+
+
+def cpu_baseline(prob, ipm_iters):
+    """The FP64 dense-Cholesky oracle on a bounded sample of the same QP: the
+    dense Hessian formation plus one IPM iteration (condensed matrix,
+    Cholesky, recovery, update), extrapolated to a whole solve of `ipm_iters`
+    iterations."""
+    import threadpoolctl
+    import oracle
+    from oracle import ipm_dense as O
+
+    cores = len(os.sched_getaffinity(0))
+    with threadpoolctl.threadpool_limits(cores):
+        t0 = time.perf_counter()
+        H = oracle.hessian_dense(prob)
+        t1 = time.perf_counter()
+        zeta = O.objective_scale(prob, H)
+        H /= zeta
+        import copy
+        sp_ = copy.copy(prob)
+        sp_.p = prob.p / zeta
+        G = O.make_groups(sp_)
+        x, s, lam = O.initial_point(sp_, G)
+        mu = float(sum(s[g] @ lam[g] for g in O.GROUPS) / G.m_tot())
+        t2 = time.perf_counter()
+        Hx, rH, rg, rc = O.residuals(sp_, G, H, x, s, lam, mu)
+        dx, ds, dl = O.newton_direction(sp_, G, H, x, s, lam, mu, Hx, rg)
+        ax = O.max_step(s, ds, 0.995)
+        x = x + ax * dx
+        t3 = time.perf_counter()
+        used = threadpoolctl.threadpool_info()
+    nthreads = max([u.get("num_threads", 1) for u in used] + [1])
+    t_qp = (t1 - t0) + (t2 - t1) + ipm_iters * (t3 - t2)
+    return {"value": 1.0 / t_qp, "unit": "QP/s", "cores": int(nthreads), "kind": "oracle",
+            "sample": (f"dense H formation ({t1 - t0:.1f} s) + 1 IPM iteration ({t3 - t2:.1f} s) of the "
+                       f"FP64 dense-Cholesky oracle on the same n={prob.n} QP, extrapolated to "
+                       f"{ipm_iters} IPM iterations"),
+            "seconds_per_qp_extrapolated": t_qp}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--log", type=int, default=1, help="per-IPM-iteration progress on stderr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import qpsynth
+    from paper_2405_03584_amd import qpgpu
+
+    t0 = time.perf_counter()
+    prob = qpsynth.config2(scale=args.scale)
+    n, m, nJ = prob.n, prob.m, prob.J.shape[0]
+    nnzJ, nnzA = int(prob.J.nnz), int(prob.A.nnz)
+    print(f"[bench] generated n={n} nJ={nJ} nnzJ={nnzJ} m={m} nnzA={nnzA} in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    settings = qpgpu.qp_default_settings(precision=args.precision, timing=1, log_level=args.log)
+    t0 = time.perf_counter()
+    h = qpgpu.qp_create_from_problem(prob, settings=settings)
+    t_create = time.perf_counter() - t0
+    print(f"[bench] qp_create {t_create:.2f}s", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        r = qpgpu.qp_solve(h)
+        print(f"[bench] warmup {i}: status={r.status} ipm={r.info['ipm_iters']} "
+              f"pcg={r.info['pcg_iters']} {r.info['t_solve_ms']:.1f} ms", file=sys.stderr, flush=True)
+
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = qpgpu.qp_solve(h)
+        infos.append(r.info)
+        print(f"[bench] step {i}: status={r.status} ipm={r.info['ipm_iters']} pcg={r.info['pcg_iters']} "
+              f"{r.info['t_solve_ms']:.1f} ms", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    x_last = r.x
+    status_ok = all(i["status"] == qpgpu.QP_OK for i in infos)
+
+    pcg_iters = sum(i["pcg_iters"] for i in infos)
+    pcg_ms = sum(i["t_pcg_ms"] for i in infos)
+    fwd_ms = sum(i["t_spmv_fwd_ms"] for i in infos)
+    bwd_ms = sum(i["t_spmv_bwd_ms"] for i in infos)
+    nf = sum(i["n_spmv_fwd"] for i in infos)
+    nb = sum(i["n_spmv_bwd"] for i in infos)
+    vbytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
+    bf, bb = spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes)
+    fwd_us = 1e3 * fwd_ms / max(nf, 1)
+    bwd_us = 1e3 * bwd_ms / max(nb, 1)
+    gbs_f = bf / (fwd_us * 1e-6) / 1e9
+    gbs_b = bb / (bwd_us * 1e-6) / 1e9
+    dom = ("k_op_bwd (J^T + A^T SpMV, fused epilogue and p.q partials)", bb, bwd_us, gbs_b) \
+        if bwd_us >= fwd_us else ("k_op_fwd (J + A SpMV, fused W / Sigma_A scaling)", bf, fwd_us, gbs_f)
+
+    parity = None
+    gold = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")
+    if args.scale == 1.0 and os.path.exists(gold):
+        g = json.load(open(gold))
+        step = g["sample_index_step"]
+        xs = np.array(g["x_sample"])
+        parity = {"x_sample_max_abs_err_vs_oracle": float(np.abs(x_last[::step] - xs).max()),
+                  "objective_rel_err_vs_oracle": abs(infos[-1]["objective"] - g["objective"]) / abs(g["objective"])}
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "QP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32 values, f32 accum, f64 scalars",
+                  "bf16": "bf16 values, f32 accum, f64 scalars"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"banded-dose QP n={n} (J {nJ}x{n}, {nnzJ} nnz; A {m}x{n}, {nnzA} nnz; "
+                               f"bounds [0,50]; PCG tol 1e-8)", "precision": args.precision,
+                   "scale": args.scale},
+        "time_to_solution_ms": 1e3 * elapsed / args.steps,
+        "ipm_iters": infos[-1]["ipm_iters"],
+        "pcg_iters_per_qp": pcg_iters / args.steps,
+        "pcg_iters_per_s": pcg_iters / (pcg_ms * 1e-3) if pcg_ms > 0 else None,
+        "status_ok": status_ok,
+        "spmv": {"fwd_us": fwd_us, "bwd_us": bwd_us, "fwd_GBs": gbs_f, "bwd_GBs": gbs_b,
+                 "fwd_bytes": bf, "bwd_bytes": bb, "timed_launches": nb},
+        "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": dom[3], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dom[3] / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": dom[1], "avg_launch_us": dom[2]},
+        "create_s": t_create,
+        "parity": parity,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
+        iters = infos[-1]["ipm_iters"]
+        if args.scale == 1.0 and os.path.exists(gold):
+            iters = json.load(open(gold))["ipm_iters"]
+        out["cpu_baseline"] = cpu_baseline(prob, iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,7 +97,11 @@ typedef struct {
     int32_t scale_objective;  /* 1 (default): divide H, p by max(1, ||H x0 + p||_inf) */
     int32_t schedule;         /* 0: automatic SpMV row grouping, else lanes per row (4..64) */
     int32_t timing;           /* 1: time the J and J^T SpMV launches with HIP events */
-    int32_t log_level;        /* 0: quiet */
+    int32_t log_level;        /* 0: quiet; 1: one line per IPM iteration on stderr */
+    int32_t precond;          /* 0: Jacobi, diag(K) (Section 4.1.2); 1 (default): Jacobi on the H
+                                 part, diag(H + Sigma_x), with the constraint block A^T Sigma_A A
+                                 applied exactly through a dense m x m Cholesky (Woodbury identity);
+                                 falls back to 0 when m = 0 or m > 8192 */
 } qp_settings;
 
 typedef struct {

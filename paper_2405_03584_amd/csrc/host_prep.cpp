@@ -125,6 +125,7 @@ std::string validate_settings(const qp_settings* s) {
     if (s->schedule != 0 && s->schedule != 4 && s->schedule != 8 && s->schedule != 16 &&
         s->schedule != 32 && s->schedule != 64)
         return "settings.schedule must be 0, 4, 8, 16, 32 or 64";
+    if (s->precond != 0 && s->precond != 1) return "settings.precond must be 0 or 1";
     return "";
 }
 

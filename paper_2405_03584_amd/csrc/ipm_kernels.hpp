@@ -132,19 +132,25 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
 }
 
 // ==========================================================================
-// PCG vector updates (Jacobi preconditioner z = r ./ d, Section 4.1.2)
+// PCG vector updates
 // ==========================================================================
+// Preconditioner z = P^{-1} r.  Jacobi (the paper, Section 4.1.2): z = r ./ d
+// with d = diag(K).  Constraint block (woodbury = 1): y = r ./ D with
+// D = diag(Hs + Sigma_x), then z = y - D^{-1} A^T Sigma^{1/2} S^{-1}
+// Sigma^{1/2} A y by k_prec_a, k_prec_symv and k_prec_at.
 struct PcgArgs {
     int n;
     double* x; double* r; double* z; double* p; const double* q; const double* d;
-    const double* part_pq; int n_pq;     // partials from k_op_bwd
-    double* part2; int n2;               // this grid's partials (2 per block)
+    const double* part_pq; int n_pq;     // partials of p^T q from k_op_bwd
+    double* part_rz; int n_rz;           // partials of r^T z
+    double* part_rr; int n_rr;           // partials of r^T r (this grid)
+    int woodbury;
     PcgScal* sc;
     Flags* fl;
 };
 
-// alpha = rho / p^T q; x += alpha p; r -= alpha q; z = r ./ d; partials of
-// r^T z and r^T r.
+// alpha = rho / p^T q; x += alpha p; r -= alpha q; z (Jacobi) or y = r ./ D
+// (constraint block, stored in z until k_prec_at finishes it); partials.
 __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped(a.fl)) return;
@@ -171,8 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
     rz = block_sum(rz, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        a.part2[2 * blockIdx.x] = rz;
-        a.part2[2 * blockIdx.x + 1] = rr;
+        if (!a.woodbury) a.part_rz[blockIdx.x] = rz;
+        a.part_rr[blockIdx.x] = rr;
     }
 }
 
@@ -180,8 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
 __global__ __launch_bounds__(kBlock) void k_pcg_p(PcgArgs a) {
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped(a.fl)) return;
-    const double rz = reduce_partials_sum(a.part2, a.n2, 2, sh);
-    const double rr = reduce_partials_sum(a.part2 + 1, a.n2, 2, sh);
+    const double rz = reduce_partials_sum(a.part_rz, a.n_rz, 1, sh);
+    const double rr = reduce_partials_sum(a.part_rr, a.n_rr, 1, sh);
     const double beta = rz / a.sc->rho;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.sc->rho_next = rz;
@@ -202,14 +208,22 @@ struct PcgInitArgs {
     const double* rhs_b;
     const IpmScal* ipm;    // mu for rhs = mu*rhs_a + rhs_b (null: mu = 0)
     double* x; double* r; double* z; double* p; const double* d;
-    double* part2;
-    const Flags* fl;
+    double* part_rz; double* part_rr;
+    int woodbury;
+    Flags* fl;
 };
 
-// x = 0; r = rhs; z = r ./ d; p = z; partials of r^T z, r^T r.
+// x = 0; r = rhs; z = r ./ d (Jacobi: also p = z) ; partials.  Clears the
+// PCG flags of the previous solve (no other block of this kernel reads them;
+// later kernels of this solve see them cleared).
 __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
     __shared__ double sh[kBlock / 64];
-    if (a.fl && ipm_finished(a.fl)) return;
+    if (ipm_finished(a.fl)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.fl->pcg_converged = 0;
+        a.fl->pcg_breakdown = 0;
+        a.fl->pcg_capped = 0;
+    }
     const double mu = a.ipm ? a.ipm->mu : 0.0;
     double rz = 0.0, rr = 0.0;
     for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
@@ -218,24 +232,25 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
         a.x[j] = 0.0;
         a.r[j] = rj;
         a.z[j] = zj;
-        a.p[j] = zj;
+        if (!a.woodbury) a.p[j] = zj;
         rz += rj * zj;
         rr += rj * rj;
     }
     rz = block_sum(rz, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        a.part2[2 * blockIdx.x] = rz;
-        a.part2[2 * blockIdx.x + 1] = rr;
+        if (!a.woodbury) a.part_rz[blockIdx.x] = rz;
+        a.part_rr[blockIdx.x] = rr;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_init1(const double* part2, int n2, double tol,
-                                                      int max_iter, PcgScal* sc, Flags* fl) {
+__global__ __launch_bounds__(kBlock) void k_pcg_init1(const double* part_rz, int n_rz, const double* part_rr,
+                                                      int n_rr, double tol, int max_iter, PcgScal* sc,
+                                                      Flags* fl) {
     __shared__ double sh[kBlock / 64];
     if (ipm_finished(fl)) return;
-    const double rz = reduce_partials_sum(part2, n2, 2, sh);
-    const double rr = reduce_partials_sum(part2 + 1, n2, 2, sh);
+    const double rz = reduce_partials_sum(part_rz, n_rz, 1, sh);
+    const double rr = reduce_partials_sum(part_rr, n_rr, 1, sh);
     if (threadIdx.x == 0) {
         sc->rho_next = rz;
         sc->rho = rz;
@@ -249,6 +264,71 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init1(const double* part2, int n
         fl->pcg_capped = 0;
         fl->pcg_converged = (rr == 0.0) ? 1 : 0;
     }
+}
+
+// Constraint-block preconditioner, step 1: w_i = sqrt(Sigma_A,i) (A y)_i (a
+// wavefront per row); rows m..ld-1 of w are the identity padding and get 0.
+__global__ __launch_bounds__(kBlock) void k_prec_a(const int* Ap, const int* Ac, const double* Av,
+                                                   const double* y, const double* sigA, int m, int ld,
+                                                   double* w, const Flags* fl) {
+    if (pcg_stopped(fl)) return;
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= ld) return;
+    double s = 0.0;
+    if (row < m) s = row_dot_lane<64, double, double>(Ap, Ac, Av, y, row, lane);
+    s = group_sum<double, 64>(s);
+    if (lane == 0) w[row] = row < m ? sqrt(sigA[row]) * s : 0.0;
+}
+
+// Step 2: v_r = sqrt(Sigma_A,r) (S^{-1} w)_r, a wavefront per row of the dense
+// symmetric inverse (row-major, leading dimension ld).
+__global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, int ld, const double* w,
+                                                      const double* sigA, int m, double* v, const Flags* fl) {
+    if (pcg_stopped(fl)) return;
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= ld) return;
+    const double* srow = Sinv + size_t(row) * ld;
+    double s0 = 0.0, s1 = 0.0;
+    int c = lane;
+    for (; c + 64 < ld; c += 128) {
+        s0 += srow[c] * w[c];
+        s1 += srow[c + 64] * w[c + 64];
+    }
+    if (c < ld) s0 += srow[c] * w[c];
+    double s = group_sum<double, 64>(s0 + s1);
+    if (lane == 0) v[row] = row < m ? sqrt(sigA[row]) * s : 0.0;
+}
+
+// Step 3: z_j = y_j - (A^T v)_j / D_j (y held in z), partials of r^T z; at the
+// start of a solve (init = 1) also p = z.  G lanes per row of A^T, grid-stride
+// with a capped grid.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* Atc, const double* Atv,
+                                                    const double* v, const double* D, const double* r,
+                                                    double* z, double* p, int n, int init, double* part_rz,
+                                                    const Flags* fl) {
+    __shared__ double sh[kBlock / 64];
+    if (pcg_stopped(fl)) return;
+    constexpr int RPB = kBlock / G;
+    const int lane = threadIdx.x % G;
+    double rz = 0.0;
+    for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+        const int j = base + threadIdx.x / G;
+        if (j < n) {
+            double s = row_dot_lane<G, double, double>(Atp, Atc, Atv, v, j, lane);
+            s = group_sum<double, G>(s);
+            if (lane == 0) {
+                const double zj = z[j] - s / D[j];
+                z[j] = zj;
+                if (init) p[j] = zj;
+                rz += r[j] * zj;
+            }
+        }
+    }
+    rz = block_sum(rz, sh);
+    if (threadIdx.x == 0) part_rz[blockIdx.x] = rz;
 }
 
 // ==========================================================================
@@ -267,7 +347,8 @@ struct IpmVec {
     double* sigx; double* sigA;
     double* va; double* vb; double* ya;       // m-vectors feeding A^T
     double* hx;               // scaled H x
-    double* d;                // Jacobi diagonal
+    double* d;                // Jacobi diagonal of K
+    double* dh;               // diag(Hs + Sigma_x), the H part of the constraint-block preconditioner
     double* rhs_a; double* rhs_b;
     double* dx;
     double* ds_lx; double* ds_ux; double* dl_lx; double* dl_ux;
@@ -463,7 +544,8 @@ __global__ __launch_bounds__(kBlock) void k_ipm_bwd(IpmBwdArgs a, IpmVec v, cons
                 v.r_lx[j] = rl;
                 v.r_ux[j] = ru;
                 v.sigx[j] = gl + gu;
-                v.d[j] = hs * v.diagH[j] + gl + gu + a2s;
+                v.dh[j] = hs * v.diagH[j] + gl + gu;
+                v.d[j] = v.dh[j] + a2s;
                 v.rhs_a[j] = (hl ? 1.0 / sl : 0.0) - (hu ? 1.0 / su : 0.0) + ava;
                 v.rhs_b[j] = -(hx + pj) - gl * rl + gu * ru + avb;
                 mrH = fmax(mrH, fabs(rH));
@@ -661,10 +743,11 @@ __global__ __launch_bounds__(kBlock) void k_diag_h(const int* Jtp, const int* Jt
     }
 }
 
-// Jacobi diagonal for a given Sigma: d_j = diagH_j + sigx_j + sum_i (A^T)_ji^2 sigA_i.
+// Jacobi diagonals for a given Sigma: dh_j = diagH_j + sigx_j and
+// d_j = dh_j + sum_i (A^T)_ji^2 sigA_i.
 __global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double* Atv, const int* Atc,
                                                    int hasA, const double* sigA, const double* sigx,
-                                                   const double* diagH, int n, double* d) {
+                                                   const double* diagH, int n, double* d, double* dh) {
     const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (j >= n) return;
@@ -675,7 +758,10 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double*
             s += v * v * sigA[Atc[e]];
         }
     s = group_sum<double, 64>(s);
-    if (lane == 0) d[j] = diagH[j] + sigx[j] + s;
+    if (lane == 0) {
+        dh[j] = diagH[j] + sigx[j];
+        d[j] = dh[j] + s;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(double* a, double v, int n) {

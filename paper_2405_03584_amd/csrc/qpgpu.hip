@@ -11,6 +11,7 @@
 
 #include "host_prep.h"
 #include "ipm_kernels.hpp"
+#include "schur_kernels.hpp"
 #include "qpgpu.h"
 
 using namespace qpg;
@@ -72,7 +73,10 @@ struct qp_handle {
     double *t = nullptr, *u = nullptr;
     double *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;
     double *zero_n = nullptr, *zero_m = nullptr, *tmp_n = nullptr, *tmp_n2 = nullptr, *tmp_m = nullptr;
-    double *part = nullptr, *part2 = nullptr, *partA = nullptr;
+    double *part = nullptr, *part2 = nullptr, *partA = nullptr, *part_rz = nullptr, *part_rr = nullptr;
+    // constraint-block preconditioner (dense m x m, leading dimension ld)
+    int woodbury = 0, ld = 0, T = 0;
+    double *Sm = nullptr, *Xm = nullptr, *Sinv = nullptr, *Linv = nullptr, *wpre = nullptr, *vpre = nullptr;
     size_t part_len = 0;
     double* log = nullptr;
     IpmScal* isc = nullptr;
@@ -223,25 +227,79 @@ struct TimingAcc {
     int pairs = 0;   // recorded operator applications
 };
 
-// One Jacobi-PCG solve of K dx = rhs (rhs = mu*rhs_a + rhs_b when rhs_a is
-// given, mu read on the device).  dx is written to h->px.  Returns the flags
-// after the solve.
+// Constraint-block preconditioner for the current D = diag(Hs + Sigma_x) and
+// Sigma_A: form S, factor it, and build S^{-1} (schur_kernels.hpp).  `stop`
+// (device int, may be null) turns every launch into a no-op once set.
+void build_precond(qp_handle* h, const double* D, const double* sigA, const int* stop) {
+    if (!h->woodbury) return;
+    const int ld = h->ld, T = h->T, m = h->m;
+    hipLaunchKernelGGL(k_schur_form, dim3(ld), dim3(64), size_t(ld) * sizeof(double), h->stream,
+                       (const int*)h->Ap, (const int*)h->Ac, (const double*)h->Av, (const int*)h->Atp,
+                       (const int*)h->Atc, (const double*)h->Atv, D, sigA, m, ld, h->Sm, stop);
+    HIPCHK(hipGetLastError());
+    for (int b = 0; b < T; ++b) {
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, h->stream, h->Sm, ld, b, h->Linv, stop);
+        const int rest = T - b - 1;
+        if (rest > 0) {
+            hipLaunchKernelGGL(k_chol_panel, dim3(rest), dim3(256), 0, h->stream, h->Sm, ld, b,
+                               (const double*)h->Linv, stop);
+            hipLaunchKernelGGL(k_chol_update, dim3(rest, rest), dim3(256), 0, h->stream, h->Sm, ld, b, stop);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_trinv_diag, dim3(T), dim3(256), 0, h->stream, (const double*)h->Linv, ld, T, h->Xm,
+                       stop);
+    for (int i = 1; i < T; ++i)
+        hipLaunchKernelGGL(k_trinv_row, dim3(i), dim3(256), 0, h->stream, (const double*)h->Sm, ld, i,
+                           (const double*)h->Linv, h->Xm, stop);
+    hipLaunchKernelGGL(k_inv_product, dim3(T, T), dim3(256), 0, h->stream, (const double*)h->Xm, ld, T, h->Sinv,
+                       stop);
+    HIPCHK(hipGetLastError());
+}
+
+// z = P^{-1} r for the constraint-block preconditioner, given y = r ./ D in z.
+int apply_precond(qp_handle* h, const double* D, const double* sigA, int init) {
+    const int ld = h->ld;
+    hipLaunchKernelGGL(k_prec_a, dim3((ld + 3) / 4), dim3(kBlock), 0, h->stream, (const int*)h->Ap,
+                       (const int*)h->Ac, (const double*)h->Av, (const double*)h->pz, sigA, h->m, ld, h->wpre,
+                       (const Flags*)h->fl);
+    hipLaunchKernelGGL(k_prec_symv, dim3((ld + 3) / 4), dim3(kBlock), 0, h->stream, (const double*)h->Sinv, ld,
+                       (const double*)h->wpre, sigA, h->m, h->vpre, (const Flags*)h->fl);
+    const int G = 16;
+    const int grid = grid_rows_capped(h->n, G);
+    hipLaunchKernelGGL(k_prec_at<G>, dim3(grid), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
+                       (const int*)h->Atc, (const double*)h->Atv, (const double*)h->vpre, D, (const double*)h->pr,
+                       h->pz, h->pp, h->n, init, h->part_rz, (const Flags*)h->fl);
+    HIPCHK(hipGetLastError());
+    return grid;
+}
+
+// One PCG solve of K dx = rhs (rhs = mu*rhs_a + rhs_b when rhs_a is given, mu
+// read on the device).  Preconditioner: Jacobi with d, or (h->woodbury and
+// sigA given) the constraint block with D = dh.  dx is written to h->px.
+// Returns the flags after the solve.
 Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, const double* sigx,
-              const double* sigA, const double* d, double hs, bool ipm_mode, TimingAcc* tacc) {
+              const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode, TimingAcc* tacc) {
     const int n = h->n;
     const int ge = grid_elems(n);
+    const int wb = (h->woodbury && sigA) ? 1 : 0;
+    const double* dd = wb ? dh : d;
     PcgInitArgs ia{};
     ia.n = n; ia.rhs_a = rhs_a; ia.rhs_b = rhs_b; ia.ipm = ipm_mode ? h->isc : nullptr;
-    ia.x = h->px; ia.r = h->pr; ia.z = h->pz; ia.p = h->pp; ia.d = d; ia.part2 = h->part2; ia.fl = h->fl;
+    ia.x = h->px; ia.r = h->pr; ia.z = h->pz; ia.p = h->pp; ia.d = dd;
+    ia.part_rz = h->part_rz; ia.part_rr = h->part_rr; ia.woodbury = wb; ia.fl = h->fl;
     hipLaunchKernelGGL(k_pcg_init0, dim3(ge), dim3(kBlock), 0, h->stream, ia);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_pcg_init1, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part2, ge,
-                       h->set.pcg_tol, h->set.pcg_max_iter, h->psc, h->fl);
+    int n_rz = ge;
+    if (wb) n_rz = apply_precond(h, dh, sigA, 1);
+    hipLaunchKernelGGL(k_pcg_init1, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
+                       (const double*)h->part_rr, ge, h->set.pcg_tol, h->set.pcg_max_iter, h->psc, h->fl);
     HIPCHK(hipGetLastError());
 
     PcgArgs pa{};
-    pa.n = n; pa.x = h->px; pa.r = h->pr; pa.z = h->pz; pa.p = h->pp; pa.q = h->pq; pa.d = d;
-    pa.part_pq = h->part; pa.part2 = h->part2; pa.n2 = ge; pa.sc = h->psc; pa.fl = h->fl;
+    pa.n = n; pa.x = h->px; pa.r = h->pr; pa.z = h->pz; pa.p = h->pp; pa.q = h->pq; pa.d = dd;
+    pa.part_pq = h->part; pa.part_rz = h->part_rz; pa.n_rz = n_rz; pa.part_rr = h->part_rr; pa.n_rr = ge;
+    pa.woodbury = wb; pa.sc = h->psc; pa.fl = h->fl;
 
     const bool timing = h->set.timing != 0 && tacc != nullptr;
     auto one_iter = [&]() {
@@ -253,6 +311,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         }
         pa.n_pq = apply_op_prec(h, prec, h->pp, h->pq, sigx, sigA, hs, h->part, h->fl, timed, slot);
         hipLaunchKernelGGL(k_pcg_xr, dim3(ge), dim3(kBlock), 0, h->stream, pa);
+        if (wb) apply_precond(h, dh, sigA, 0);
         hipLaunchKernelGGL(k_pcg_p, dim3(ge), dim3(kBlock), 0, h->stream, pa);
     };
     auto snapshot = [&](int slot) {
@@ -345,6 +404,7 @@ void qp_default_settings(qp_settings* s) {
     s->schedule = 0;
     s->timing = 0;
     s->log_level = 0;
+    s->precond = 1;
 }
 
 const char* qp_last_error(const qp_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
@@ -374,6 +434,7 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         g_create_error = e;
         return QP_ERR_INVALID;
     }
+    (void)hipGetLastError();  // drop an error left by an earlier, unrelated call
     qp_handle* h = new (std::nothrow) qp_handle();
     if (!h) {
         g_create_error = "host allocation failed";
@@ -399,7 +460,9 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         }
         h->nnzJ = hJ.nnz();
         h->nnzA = m > 0 ? hA.nnz() : 0;
-        std::vector<double> xlo(n, -INFINITY), xhi(n, INFINITY), alo(m, -INFINITY), ahi(m, INFINITY);
+        // m = 0 keeps one padding entry so every device array has a valid source
+        std::vector<double> xlo(n, -INFINITY), xhi(n, INFINITY), alo(std::max(m, 1), -INFINITY),
+            ahi(std::max(m, 1), INFINITY);
         if (bounds) {
             if (bounds->lo) std::copy(bounds->lo, bounds->lo + n, xlo.begin());
             if (bounds->hi) std::copy(bounds->hi, bounds->hi + n, xhi.begin());
@@ -443,7 +506,7 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->Jtv = h->upload(hJt.val.data(), hJt.val.size());
         h->hJv = std::move(hJ.val);
         h->hJtv = std::move(hJt.val);
-        h->W = h->upload(W ? W : xlo.data(), size_t(nJ));
+        h->W = nJ > 0 ? h->upload(W, size_t(nJ)) : h->dalloc<double>(1);
         if (m > 0) {
             h->Ap = h->upload(hA.ptr.data(), hA.ptr.size());
             h->Ac = h->upload(hA.col.data(), hA.col.size());
@@ -491,6 +554,26 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->part = h->dalloc<double>(h->part_len);
         h->part2 = h->dalloc<double>(h->part_len);
         h->partA = h->dalloc<double>(h->part_len);
+        h->part_rz = h->dalloc<double>(h->part_len);
+        h->part_rr = h->dalloc<double>(h->part_len);
+        v.dh = h->dalloc<double>(n);
+        h->woodbury = (h->set.precond == 1 && m > 0) ? 1 : 0;
+        if (h->woodbury) {
+            h->ld = ((m + TS - 1) / TS) * TS;
+            h->T = h->ld / TS;
+            if (size_t(h->ld) * sizeof(double) > 64 * 1024) {
+                // the dense block would not fit one workgroup's LDS row buffer
+                h->woodbury = 0;
+            } else {
+                const size_t mm = size_t(h->ld) * h->ld;
+                h->Sm = h->dalloc<double>(mm);
+                h->Xm = h->dalloc<double>(mm);
+                h->Sinv = h->dalloc<double>(mm);
+                h->Linv = h->dalloc<double>(size_t(h->T) * TS * TS);
+                h->wpre = h->dalloc<double>(h->ld);
+                h->vpre = h->dalloc<double>(h->ld);
+            }
+        }
         h->log = h->dalloc<double>(4 * size_t(h->set.max_ipm_iter + 1));
         h->isc = h->dalloc<IpmScal>(1);
         h->psc = h->dalloc<PcgScal>(1);
@@ -531,6 +614,7 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
 qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* sigma_A, const double* v,
                             double* y, int32_t precision, int32_t reps, qp_info* info) {
     if (!h) return QP_ERR_INVALID;
+    (void)hipGetLastError();  // drop an error left by an earlier, unrelated call
     if (!sigma_x || !v || !y || (h->m > 0 && !sigma_A)) return fail(h, QP_ERR_INVALID, "NULL argument");
     if (precision < QP_FP64 || precision > QP_BF16) return fail(h, QP_ERR_INVALID, "precision out of range");
     if (reps < 1) reps = 1;
@@ -574,6 +658,7 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
 qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigma_A, const double* rhs,
                          double* dx, qp_info* info) {
     if (!h) return QP_ERR_INVALID;
+    (void)hipGetLastError();  // drop an error left by an earlier, unrelated call
     if (!sigma_x || !rhs || !dx || (h->m > 0 && !sigma_A)) return fail(h, QP_ERR_INVALID, "NULL argument");
     for (int j = 0; j < h->n; ++j)
         if (!(sigma_x[j] >= 0.0) || !std::isfinite(sigma_x[j]))
@@ -593,13 +678,15 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         if (m > 0) HIPCHK(hipMemcpyAsync(sigA, sigma_A, sizeof(double) * m, hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(b, rhs, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
         reset_flags(h);
+        double* dh = h->iv.dh;
         hipLaunchKernelGGL(k_jacobi, dim3(grid_rows(n, 64)), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
                            (const double*)h->Atv, (const int*)h->Atc, m > 0 ? 1 : 0, (const double*)sigA,
-                           (const double*)sigx, (const double*)h->diagH, n, d);
+                           (const double*)sigx, (const double*)h->diagH, n, d, dh);
         HIPCHK(hipGetLastError());
         TimingAcc ta;
         HIPCHK(hipEventRecord(h->ev_t0, h->stream));
-        Flags f = run_pcg(h, QP_FP64, nullptr, b, sigx, m > 0 ? sigA : nullptr, d, 1.0, false, &ta);
+        if (m > 0) build_precond(h, dh, sigA, nullptr);
+        Flags f = run_pcg(h, QP_FP64, nullptr, b, sigx, m > 0 ? sigA : nullptr, d, dh, 1.0, false, &ta);
         HIPCHK(hipEventRecord(h->ev_t1, h->stream));
         HIPCHK(hipMemcpyAsync(dx, h->px, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
         PcgScal ps{};
@@ -629,6 +716,7 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
 
 qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_info* info) {
     if (!h) return QP_ERR_INVALID;
+    (void)hipGetLastError();  // drop an error left by an earlier, unrelated call
     if (!x) return fail(h, QP_ERR_INVALID, "x is NULL");
     if (h->set.precision != QP_FP64)
         return fail(h, QP_ERR_INVALID, "this build solves with precision QP_FP64 only");
@@ -704,7 +792,9 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
                                (const double*)h->part, gb, apply, h->isc, h->fl, h->log);
             HIPCHK(hipGetLastError());
         };
+        const int* ipm_stop = reinterpret_cast<const int*>(&h->fl->ipm_done);
         residuals(0);
+        if (m > 0) build_precond(h, v.dh, v.sigA, ipm_stop);
 
         TimingAcc ta;
         int64_t pcg_total = 0;
@@ -714,7 +804,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
         Flags f{};
         for (int it = 0; it < h->set.max_ipm_iter; ++it) {
             HIPCHK(hipEventRecord(h->ev_p0, h->stream));
-            f = run_pcg(h, QP_FP64, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d, hs, true, &ta);
+            f = run_pcg(h, QP_FP64, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d, v.dh, hs, true, &ta);
             HIPCHK(hipEventRecord(h->ev_p1, h->stream));
             if (f.ipm_done) break;
             {
@@ -726,6 +816,14 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             pcg_total += f.pcg_iters;
             pcg_solves += 1;
             capped += f.pcg_capped;
+            if (h->set.log_level > 0) {
+                IpmScal cur{};
+                HIPCHK(hipMemcpy(&cur, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost));
+                std::fprintf(stderr, "[qpgpu] ipm %3d mu %.3e rnorm %.3e pcg %6d%s alpha %.3f/%.3f\n",
+                             cur.iter, cur.mu, cur.rnorm, f.pcg_iters, f.pcg_capped ? " (cap)" : "",
+                             cur.alpha_p, cur.alpha_d);
+                std::fflush(stderr);
+            }
             if (f.pcg_breakdown) {
                 st = QP_ERR_NUMERIC;
                 break;
@@ -741,6 +839,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
                                (const double*)h->part2, nbA + nbx, h->isc, (const Flags*)h->fl);
             HIPCHK(hipGetLastError());
             residuals(1);
+            if (m > 0) build_precond(h, v.dh, v.sigA, ipm_stop);
         }
         // outputs
         HIPCHK(hipEventRecord(h->ev_t1, h->stream));

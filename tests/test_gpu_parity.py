@@ -223,3 +223,46 @@ def test_solve_iteration_limit_returns_not_converged():
     assert res.status == qpgpu.QP_ERR_NOT_CONVERGED
     assert res.info["ipm_iters"] == 2
     assert np.all(np.isfinite(res.x))
+
+
+# ----------------------------------------------------------------------------
+# preconditioners: Jacobi (precond=0) and Jacobi + constraint block (precond=1)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precond", [0, 1])
+@pytest.mark.parametrize("spread", [1.0, 8.0])
+def test_newton_step_preconditioners(precond, spread):
+    """Same direction from either preconditioner, including Sigma_A spread over
+    16 orders of magnitude (active rows late in the IPM)."""
+    prob = qpsynth.config2(scale=0.02)
+    it = qpsynth.random_iterate(prob, 21)
+    rng = np.random.default_rng(5)
+    sA = np.exp(rng.uniform(-spread, spread, size=prob.m) * np.log(10.0) / 2) ** 2
+    s = qpgpu.qp_default_settings(pcg_tol=1e-10, pcg_max_iter=200000, precond=precond)
+    h = qpgpu.qp_create_from_problem(prob, settings=s)
+    st, dx, info = qpgpu.qp_newton_step(h, it["sigma_x"], sA, it["rhs"])
+    assert st == qpgpu.QP_OK, info
+    K = oracle.condensed_operator_dense(prob, it["sigma_x"], sA)
+    res = np.linalg.norm(K @ dx - it["rhs"]) / np.linalg.norm(it["rhs"])
+    assert res <= 1e-9
+    if precond == 1:
+        assert info["pcg_iters"] <= 200, info["pcg_iters"]
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_solve_config1_both_preconditioners(precond):
+    prob = qpsynth.config1(4)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precond=precond))
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    _check_solve(prob, res, ref)
+
+
+def test_solve_band_medium():
+    prob = qpsynth.config2(scale=0.05)
+    print(f"solve {prob.name} n={prob.n} m={prob.m}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob)
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    _check_solve(prob, res, ref)
+    assert res.info["pcg_iters"] < 100 * res.info["ipm_iters"]
