@@ -76,6 +76,40 @@ def cpu_baseline(prob, ipm_iters):
             "seconds_per_qp_extrapolated": t_qp}
 
 
+def operator_only(args, prob):
+    """Repeated operator products q = K v at a fixed seeded Sigma (one forward
+    and one backward SpMV launch each)."""
+    from paper_2405_03584_amd import qpgpu
+    import qpsynth
+    it = qpsynth.random_iterate(prob, 1)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(timing=1))
+    y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=args.precision,
+                                      reps=args.reps)
+    n, m, nJ = prob.n, prob.m, prob.J.shape[0]
+    vbytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
+    bf, bb = spmv_bytes(n, nJ, m, int(prob.J.nnz), int(prob.A.nnz), vbytes)
+    fus = 1e3 * info["t_spmv_fwd_ms"] / max(info["n_spmv_fwd"], 1)
+    bus = 1e3 * info["t_spmv_bwd_ms"] / max(info["n_spmv_bwd"], 1)
+    print(json.dumps({"mode": "operator", "precision": args.precision, "reps": args.reps,
+                      "fwd_us": fus, "bwd_us": bus, "fwd_GBs": bf / fus / 1e3, "bwd_GBs": bb / bus / 1e3,
+                      "fwd_bytes": bf, "bwd_bytes": bb, "checksum": float(np.abs(y).sum())}), flush=True)
+
+
+def copy_calibration(args):
+    """A plain device-to-device copy of a known byte count with torch's copy
+    kernel: what the HBM counters read for it calibrates the counter scale."""
+    import torch
+    nbytes = 480_000_000
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(args.reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "reps": args.reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +119,11 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--log", type=int, default=1, help="per-IPM-iteration progress on stderr")
+    ap.add_argument("--mode", default="solve", choices=["solve", "operator", "copy"],
+                    help="solve: whole QP solves (the benchmark); operator: repeated operator "
+                         "products only (for counter runs); copy: a plain device copy of the "
+                         "J value+index bytes (counter calibration)")
+    ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
@@ -94,8 +133,12 @@ def main():
     import qpsynth
     from paper_2405_03584_amd import qpgpu
 
+    if args.mode == "copy":
+        return copy_calibration(args)
     t0 = time.perf_counter()
     prob = qpsynth.config2(scale=args.scale)
+    if args.mode == "operator":
+        return operator_only(args, prob)
     n, m, nJ = prob.n, prob.m, prob.J.shape[0]
     nnzJ, nnzA = int(prob.J.nnz), int(prob.A.nnz)
     print(f"[bench] generated n={n} nJ={nJ} nnzJ={nnzJ} m={m} nnzA={nnzA} in "

@@ -224,7 +224,8 @@ void ensure_lowp(qp_handle* h, int prec) {
 }
 
 struct TimingAcc {
-    int pairs = 0;   // recorded operator applications
+    int pairs = 0;              // event pairs handed out
+    std::vector<char> valid;    // slot ran real work (not a no-op launch after convergence)
 };
 
 // Constraint-block preconditioner for the current D = diag(Hs + Sigma_x) and
@@ -302,12 +303,14 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     pa.woodbury = wb; pa.sc = h->psc; pa.fl = h->fl;
 
     const bool timing = h->set.timing != 0 && tacc != nullptr;
+    const int slot_begin = tacc ? tacc->pairs : 0;
     auto one_iter = [&]() {
         bool timed = false;
         int slot = 0;
         if (timing && tacc->pairs < int(h->tev.size() / 4)) {
             timed = true;
             slot = tacc->pairs++;
+            tacc->valid.push_back(1);
         }
         pa.n_pq = apply_op_prec(h, prec, h->pp, h->pq, sigx, sigA, hs, h->part, h->fl, timed, slot);
         hipLaunchKernelGGL(k_pcg_xr, dim3(ge), dim3(kBlock), 0, h->stream, pa);
@@ -345,6 +348,12 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         }
         cur ^= 1;
     }
+    if (timing) {
+        // launches past the last executed iteration returned at once: drop them
+        for (int sl = slot_begin + std::max(f.pcg_iters, 0); sl < tacc->pairs; ++sl) tacc->valid[sl] = 0;
+        if (f.ipm_done)
+            for (int sl = slot_begin; sl < tacc->pairs; ++sl) tacc->valid[sl] = 0;
+    }
     return f;
 }
 
@@ -356,7 +365,10 @@ void reset_flags(qp_handle* h) {
 void harvest_timing(qp_handle* h, const TimingAcc& ta, qp_info* info) {
     if (!info) return;
     double f = 0.0, b = 0.0;
+    int64_t cnt = 0;
     for (int i = 0; i < ta.pairs; ++i) {
+        if (i < int(ta.valid.size()) && !ta.valid[i]) continue;
+        ++cnt;
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, h->tev[4 * i], h->tev[4 * i + 1]));
         f += ms;
@@ -365,8 +377,8 @@ void harvest_timing(qp_handle* h, const TimingAcc& ta, qp_info* info) {
     }
     info->t_spmv_fwd_ms += f;
     info->t_spmv_bwd_ms += b;
-    info->n_spmv_fwd += ta.pairs;
-    info->n_spmv_bwd += ta.pairs;
+    info->n_spmv_fwd += cnt;
+    info->n_spmv_bwd += cnt;
 }
 
 void ensure_timing_events(qp_handle* h) {
@@ -636,6 +648,7 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
         for (int r = 0; r < reps; ++r) {
             const bool timed = h->set.timing && ta.pairs < int(h->tev.size() / 4);
             const int slot = timed ? ta.pairs++ : 0;
+            if (timed) ta.valid.push_back(1);
             apply_op_prec(h, precision, h->tmp_n2, h->pq, h->tmp_n, h->m > 0 ? h->tmp_m : nullptr, 1.0,
                           nullptr, nullptr, timed, slot);
         }
