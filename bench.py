@@ -76,6 +76,30 @@ def cpu_baseline(prob, ipm_iters):
             "seconds_per_qp_extrapolated": t_qp}
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("device_common.hpp", "ipm_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2405_03584_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel_tag, precision):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"op_traffic_config2_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    for name, v in rec["kernels"].items():
+        if name.startswith(kernel_tag):
+            return v["hbm_bytes"]
+    return None
+
+
 def operator_only(args, prob):
     """Repeated operator products q = K v at a fixed seeded Sigma (one forward
     and one backward SpMV launch each)."""
@@ -214,7 +238,8 @@ def main():
         "spmv": {"fwd_us": fwd_us, "bwd_us": bwd_us, "fwd_GBs": gbs_f, "bwd_GBs": gbs_b,
                  "fwd_bytes": bf, "bwd_bytes": bb, "timed_launches": nb},
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": dom[3], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dom[3] / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": dom[3] / HBM_PEAK_GBS,
+                     "traffic": counter_traffic(dom[0].split()[0], args.precision) if args.scale == 1.0 else None,
                      "bytes_per_launch": dom[1], "avg_launch_us": dom[2]},
         "create_s": t_create,
         "parity": parity,

@@ -764,6 +764,30 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double*
     }
 }
 
+// Mixed-precision refinement helpers (skipped once the IPM has finished).
+// rhs = mu*rhs_a + rhs_b with mu read on the device.
+__global__ __launch_bounds__(kBlock) void k_rhs_combine(int n, const double* rhs_a, const double* rhs_b,
+                                                        const IpmScal* sc, double* out, const Flags* fl) {
+    if (ipm_finished(fl)) return;
+    const double mu = sc->mu;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock)
+        out[j] = mu * rhs_a[j] + rhs_b[j];
+}
+
+// out = rhs - q (the FP64 residual of the current direction).
+__global__ __launch_bounds__(kBlock) void k_sub(int n, const double* rhs, const double* q, double* out,
+                                                const Flags* fl) {
+    if (ipm_finished(fl)) return;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) out[j] = rhs[j] - q[j];
+}
+
+// acc = px (init) or acc += px.
+__global__ __launch_bounds__(kBlock) void k_acc(int n, double* acc, const double* px, int init, const Flags* fl) {
+    if (ipm_finished(fl)) return;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock)
+        acc[j] = init ? px[j] : acc[j] + px[j];
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(double* a, double v, int n) {
     for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) a[j] = v;
 }

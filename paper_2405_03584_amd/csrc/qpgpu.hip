@@ -73,6 +73,7 @@ struct qp_handle {
     double *t = nullptr, *u = nullptr;
     double *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;
     double *zero_n = nullptr, *zero_m = nullptr, *tmp_n = nullptr, *tmp_n2 = nullptr, *tmp_m = nullptr;
+    double *rhs_full = nullptr, *rho = nullptr, *dxacc = nullptr;   // refinement of low-precision directions
     double *part = nullptr, *part2 = nullptr, *partA = nullptr, *part_rz = nullptr, *part_rr = nullptr;
     // constraint-block preconditioner (dense m x m, leading dimension ld)
     int woodbury = 0, ld = 0, T = 0;
@@ -357,6 +358,55 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     return f;
 }
 
+// One Newton direction into h->px.  FP64: one PCG solve.  FP32/BF16: PCG on
+// the low-precision operator, then `refine_steps` passes of
+// rho = rhs - K_64 dx (FP64 operator), delta = PCG_lo(rho), dx += delta.
+// rhs = mu*rhs_a + rhs_b (ipm_mode) or rhs_b.  The returned flags carry the
+// PCG iteration count summed over the solves; `solves` counts them.
+Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, const double* sigx,
+                       const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode,
+                       TimingAcc* tacc, int* solves) {
+    if (prec == QP_FP64) {
+        *solves = 1;
+        return run_pcg(h, QP_FP64, rhs_a, rhs_b, sigx, sigA, d, dh, hs, ipm_mode, tacc);
+    }
+    const int n = h->n;
+    const int ge = grid_elems(n);
+    const double* rhs = rhs_b;
+    if (rhs_a) {
+        hipLaunchKernelGGL(k_rhs_combine, dim3(ge), dim3(kBlock), 0, h->stream, n, rhs_a, rhs_b,
+                           (const IpmScal*)h->isc, h->rhs_full, (const Flags*)h->fl);
+        HIPCHK(hipGetLastError());
+        rhs = h->rhs_full;
+    }
+    Flags f = run_pcg(h, prec, nullptr, rhs, sigx, sigA, d, dh, hs, false, tacc);
+    *solves = 1;
+    int total = f.pcg_iters;
+    if (f.ipm_done || f.pcg_breakdown) return f;
+    hipLaunchKernelGGL(k_acc, dim3(ge), dim3(kBlock), 0, h->stream, n, h->dxacc, (const double*)h->px, 1,
+                       (const Flags*)h->fl);
+    for (int k = 0; k < h->set.refine_steps; ++k) {
+        apply_op<double, double>(h, h->dxacc, h->pq, sigx, sigA, hs, nullptr, nullptr, false, 0);
+        hipLaunchKernelGGL(k_sub, dim3(ge), dim3(kBlock), 0, h->stream, n, rhs, (const double*)h->pq, h->rho,
+                           (const Flags*)h->fl);
+        Flags f2 = run_pcg(h, prec, nullptr, h->rho, sigx, sigA, d, dh, hs, false, tacc);
+        *solves += 1;
+        total += f2.pcg_iters;
+        f.pcg_capped |= f2.pcg_capped;
+        if (f2.pcg_breakdown) {
+            // a zero residual (exact direction) is not a breakdown; rr == 0 stops at init
+            f.pcg_breakdown = 1;
+            break;
+        }
+        hipLaunchKernelGGL(k_acc, dim3(ge), dim3(kBlock), 0, h->stream, n, h->dxacc, (const double*)h->px, 0,
+                           (const Flags*)h->fl);
+    }
+    HIPCHK(hipMemcpyAsync(h->px, h->dxacc, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipGetLastError());
+    f.pcg_iters = total;
+    return f;
+}
+
 void reset_flags(qp_handle* h) {
     Flags z{};
     HIPCHK(hipMemcpyAsync(h->fl, &z, sizeof(Flags), hipMemcpyHostToDevice, h->stream));
@@ -561,6 +611,9 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->tmp_n = h->dalloc<double>(n);
         h->tmp_n2 = h->dalloc<double>(n);
         h->tmp_m = h->dalloc<double>(std::max(m, 1));
+        h->rhs_full = h->dalloc<double>(n);
+        h->rho = h->dalloc<double>(n);
+        h->dxacc = h->dalloc<double>(n);
         const size_t nbA = size_t((m + 3) / 4) + 1;
         h->part_len = 8 * (size_t(kMaxPartials) + nbA + 64);
         h->part = h->dalloc<double>(h->part_len);
@@ -699,7 +752,9 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         TimingAcc ta;
         HIPCHK(hipEventRecord(h->ev_t0, h->stream));
         if (m > 0) build_precond(h, dh, sigA, nullptr);
-        Flags f = run_pcg(h, QP_FP64, nullptr, b, sigx, m > 0 ? sigA : nullptr, d, dh, 1.0, false, &ta);
+        int nsolves = 0;
+        Flags f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d, dh, 1.0,
+                                   false, &ta, &nsolves);
         HIPCHK(hipEventRecord(h->ev_t1, h->stream));
         HIPCHK(hipMemcpyAsync(dx, h->px, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
         PcgScal ps{};
@@ -710,8 +765,8 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         if (info) {
             std::memset(info, 0, sizeof(*info));
             info->status = st;
-            info->pcg_iters = ps.iters;
-            info->pcg_solves = 1;
+            info->pcg_iters = f.pcg_iters;
+            info->pcg_solves = nsolves;
             info->pcg_capped = f.pcg_capped;
             info->pcg_relres = ps.bnorm2 > 0 ? std::sqrt(ps.rr / ps.bnorm2) : 0.0;
             float ms = 0.f;
@@ -731,8 +786,6 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
     if (!h) return QP_ERR_INVALID;
     (void)hipGetLastError();  // drop an error left by an earlier, unrelated call
     if (!x) return fail(h, QP_ERR_INVALID, "x is NULL");
-    if (h->set.precision != QP_FP64)
-        return fail(h, QP_ERR_INVALID, "this build solves with precision QP_FP64 only");
     qp_status st = QP_OK;
     try {
         ensure_timing_events(h);
@@ -817,7 +870,9 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
         Flags f{};
         for (int it = 0; it < h->set.max_ipm_iter; ++it) {
             HIPCHK(hipEventRecord(h->ev_p0, h->stream));
-            f = run_pcg(h, QP_FP64, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d, v.dh, hs, true, &ta);
+            int nsolves = 0;
+            f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
+                                 v.dh, hs, true, &ta, &nsolves);
             HIPCHK(hipEventRecord(h->ev_p1, h->stream));
             if (f.ipm_done) break;
             {
@@ -827,7 +882,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
                 pcg_ms += ms;
             }
             pcg_total += f.pcg_iters;
-            pcg_solves += 1;
+            pcg_solves += nsolves;
             capped += f.pcg_capped;
             if (h->set.log_level > 0) {
                 IpmScal cur{};

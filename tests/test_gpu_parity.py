@@ -266,3 +266,56 @@ def test_solve_band_medium():
     ref = oracle.solve(prob)
     _check_solve(prob, res, ref)
     assert res.info["pcg_iters"] < 100 * res.info["ipm_iters"]
+
+
+# ----------------------------------------------------------------------------
+# mixed precision (a6): low-precision J inside PCG, FP64 refinement
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_newton_step_mixed_precision_refined(prec):
+    """After refinement the direction solves the FP64 system to about the PCG
+    tolerance times the contraction of the low-precision operator."""
+    prob = qpsynth.config2(scale=0.02)
+    it = qpsynth.random_iterate(prob, 31)
+    s = qpgpu.qp_default_settings(precision=prec, refine_steps=3, pcg_tol=1e-10)
+    h = qpgpu.qp_create_from_problem(prob, settings=s)
+    st, dx, info = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], it["rhs"])
+    assert st == qpgpu.QP_OK, info
+    assert info["pcg_solves"] == 4
+    K = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"])
+    res = np.linalg.norm(K @ dx - it["rhs"]) / np.linalg.norm(it["rhs"])
+    assert res <= 1e-8, res
+    # without refinement the low-precision operator leaves a visible residual
+    s0 = qpgpu.qp_default_settings(precision=prec, refine_steps=0, pcg_tol=1e-10)
+    h0 = qpgpu.qp_create_from_problem(prob, settings=s0)
+    st0, dx0, _ = qpgpu.qp_newton_step(h0, it["sigma_x"], it["sigma_A"], it["rhs"])
+    res0 = np.linalg.norm(K @ dx0 - it["rhs"]) / np.linalg.norm(it["rhs"])
+    assert res0 > 10 * res
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("inst", [0, 2])
+def test_solve_mixed_precision_config1(prec, inst):
+    """Spec bars for the low-precision J: x within 1e-5 (inf-norm) and
+    objective within 1e-6 (relative) of the FP64 oracle; certificate 1e-9."""
+    prob = qpsynth.config1(inst)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    assert res.status == qpgpu.QP_OK, res.info
+    assert np.abs(res.x - ref.x).max() <= 1e-5
+    assert abs(res.info["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
+    cert = oracle.kkt_certificate(prob, res.x, res.lam_x, res.lam_A)
+    assert cert.worst() <= 1e-9, cert
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_solve_mixed_precision_band(prec):
+    prob = qpsynth.config2(scale=0.05)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    assert res.status == qpgpu.QP_OK, res.info
+    assert np.abs(res.x - ref.x).max() <= 1e-5
+    assert abs(res.info["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
