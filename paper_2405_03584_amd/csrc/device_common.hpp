@@ -22,7 +22,8 @@
 namespace qpg {
 
 constexpr int kBlock = 256;         // 4 wavefronts
-constexpr int kMaxPartials = 2048;  // cap on blocks that emit reduction partials
+constexpr int kMaxPartials = 8192;  // cap on blocks that emit reduction partials
+constexpr int kMaxElemGrid = 2048;  // cap on grid-stride elementwise grids
 
 // --------------------------------------------------------------------------
 // scalar state shared by kernels (device memory)
@@ -162,27 +163,39 @@ __device__ __forceinline__ double reduce_partials_min(const double* part, int co
 }
 
 // Dot product of CSR row `row` with x by a group of G lanes (lane in [0,G)).
-// Each lane sums its strided share with four independent accumulators (more
-// loads in flight), combined in a fixed order; the group sum is done by the
-// caller.
-template <int G, typename VT, typename AT>
+// Each pass lets every lane issue U index/value loads at once (predicated
+// past the row end), then U gathers, so a row costs about one index latency
+// plus one gather latency per U*G entries instead of one per entry; U
+// independent accumulators are combined in a fixed order.  The group sum is
+// done by the caller.
+template <int G, typename VT, typename AT, int U = 4>
 __device__ __forceinline__ AT row_dot_lane(const int* __restrict__ ptr, const int* __restrict__ col,
                                            const VT* __restrict__ val, const double* __restrict__ x,
                                            int row, int lane) {
     const int a = ptr[row], b = ptr[row + 1];
-    AT a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    int k = a + lane;
-    for (; k + 3 * G < b; k += 4 * G) {
-        const int c0 = col[k], c1 = col[k + G], c2 = col[k + 2 * G], c3 = col[k + 3 * G];
-        const AT v0 = cvt<AT>(val[k]), v1 = cvt<AT>(val[k + G]);
-        const AT v2 = cvt<AT>(val[k + 2 * G]), v3 = cvt<AT>(val[k + 3 * G]);
-        a0 += v0 * AT(x[c0]);
-        a1 += v1 * AT(x[c1]);
-        a2 += v2 * AT(x[c2]);
-        a3 += v3 * AT(x[c3]);
+    AT acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = AT(0);
+    for (int k = a + lane; k < b; k += U * G) {
+        int c[U];
+        AT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kk = k + u * G;
+            const bool ok = kk < b;
+            c[u] = ok ? col[kk] : 0;
+            v[u] = ok ? cvt<AT>(val[kk]) : AT(0);
+        }
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += v[u] * AT(xv[u]);
     }
-    for (; k < b; k += G) a0 += cvt<AT>(val[k]) * AT(x[col[k]]);
-    return (a0 + a1) + (a2 + a3);
+    AT s = acc[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u) s += acc[u];
+    return s;
 }
 
 }  // namespace qpg

@@ -96,9 +96,21 @@ struct BwdArgs {
     double* q;
     double* part;          // per-block partial p^T q (may be null)
     const Flags* fl;
+    const double* U;       // n x lr_k column-major low-rank factor (lr_k = 0: none)
+    const double* lr_v;    // w .* (U^T p), lr_k entries
+    int lr_k;
 };
 
-// q_j = hs*(J^T t + gamma p)_j + Sigma_x,j p_j + (A^T u)_j and per-block
+// Low-rank part of row j: sum_c U_jc v_c, split over the group's lanes (lane l
+// takes c = l, l+G, ...) so it joins the group sum of the SpMV.
+template <int G>
+__device__ __forceinline__ double lowrank_lane(const double* U, const double* v, int k, int n, int j, int lane) {
+    double s = 0.0;
+    for (int c = lane; c < k; c += G) s += U[j + size_t(n) * c] * v[c];
+    return s;
+}
+
+// q_j = hs*(J^T t + gamma p + U(w .* U^T p))_j + Sigma_x,j p_j + (A^T u)_j and per-block
 // partials of p^T q.  Grid-stride over row groups with a capped grid so the
 // partial count stays small.
 template <int G, typename VT, typename AT>
@@ -112,8 +124,9 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
     for (int base = b * RPB; base < a.n; base += gridDim.x * RPB) {
         const int row = base + threadIdx.x / G;
         if (row < a.n) {
-            AT sj = row_dot_lane<G, VT, AT>(a.Jtp, a.Jtc, a.Jtv, a.t, row, lane);
+            AT sj = row_dot_lane<G, VT, AT, 8>(a.Jtp, a.Jtc, a.Jtv, a.t, row, lane);
             double s = a.hs * double(sj);
+            if (a.lr_k) s += a.hs * lowrank_lane<G>(a.U, a.lr_v, a.lr_k, a.n, row, lane);
             if (a.hasA) s += row_dot_lane<G, double, double>(a.Atp, a.Atc, a.Atv, a.u, row, lane);
             s = group_sum<double, G>(s);
             if (lane == 0) {
@@ -266,29 +279,32 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init1(const double* part_rz, int
     }
 }
 
-// Constraint-block preconditioner, step 1: w_i = sqrt(Sigma_A,i) (A y)_i (a
-// wavefront per row); rows m..ld-1 of w are the identity padding and get 0.
+// Constraint-block preconditioner, step 1: w_r = sqrt(Sigma_i) (A y)_i for the
+// strong rows i = idx[r] (a wavefront per row; padding rows k..ld-1 get 0),
+// and vm = 0 on all m rows (step 2 fills the strong ones).
 __global__ __launch_bounds__(kBlock) void k_prec_a(const int* Ap, const int* Ac, const double* Av,
-                                                   const double* y, const double* sigA, int m, int ld,
-                                                   double* w, const Flags* fl) {
+                                                   const double* y, const double* sigA, const int* idx, int k,
+                                                   int ld, int m, double* w, double* vm, const Flags* fl) {
     if (pcg_stopped(fl)) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    for (int q = row * 64 + lane; q < m && q < (row + 1) * 64; q += 64) vm[q] = 0.0;
     if (row >= ld) return;
     double s = 0.0;
-    if (row < m) s = row_dot_lane<64, double, double>(Ap, Ac, Av, y, row, lane);
+    if (row < k) s = row_dot_lane<64, double, double>(Ap, Ac, Av, y, idx[row], lane);
     s = group_sum<double, 64>(s);
-    if (lane == 0) w[row] = row < m ? sqrt(sigA[row]) * s : 0.0;
+    if (lane == 0) w[row] = row < k ? sqrt(sigA[idx[row]]) * s : 0.0;
 }
 
-// Step 2: v_r = sqrt(Sigma_A,r) (S^{-1} w)_r, a wavefront per row of the dense
-// symmetric inverse (row-major, leading dimension ld).
+// Step 2: vm[idx[r]] = sqrt(Sigma) (S^{-1} w)_r, a wavefront per row of the
+// dense symmetric inverse (row-major, leading dimension ld).
 __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, int ld, const double* w,
-                                                      const double* sigA, int m, double* v, const Flags* fl) {
+                                                      const double* sigA, const int* idx, int k, double* vm,
+                                                      const Flags* fl) {
     if (pcg_stopped(fl)) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (row >= ld) return;
+    if (row >= k) return;
     const double* srow = Sinv + size_t(row) * ld;
     double s0 = 0.0, s1 = 0.0;
     int c = lane;
@@ -298,7 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, int ld
     }
     if (c < ld) s0 += srow[c] * w[c];
     double s = group_sum<double, 64>(s0 + s1);
-    if (lane == 0) v[row] = row < m ? sqrt(sigA[row]) * s : 0.0;
+    if (lane == 0) {
+        const int i = idx[row];
+        vm[i] = sqrt(sigA[i]) * s;
+    }
 }
 
 // Step 3: z_j = y_j - (A^T v)_j / D_j (y held in z), partials of r^T z; at the
@@ -491,6 +510,7 @@ struct IpmBwdArgs {
     const int* Atp; const int* Atc; const double* Atv; int hasA;
     const double* t;
     double gamma;
+    const double* U; const double* lr_v; int lr_k;   // low-rank part of H (lr_v = w .* U^T x)
 };
 
 // Residual pass, part 2, per variable j: H x (scaled), the A^T products of
@@ -512,6 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_ipm_bwd(IpmBwdArgs a, IpmVec v, cons
         const int j = base + threadIdx.x / G;
         if (j < v.n) {
             double hj = hs * row_dot_lane<G, double, double>(a.Jtp, a.Jtc, a.Jtv, a.t, j, lane);
+            if (a.lr_k) hj += hs * lowrank_lane<G>(a.U, a.lr_v, a.lr_k, v.n, j, lane);
             double aty = 0.0, ava = 0.0, avb = 0.0, a2s = 0.0;
             if (a.hasA) {
                 const int s0 = a.Atp[j], s1 = a.Atp[j + 1];
@@ -761,6 +782,40 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double*
     if (lane == 0) {
         dh[j] = diagH[j] + sigx[j];
         d[j] = dh[j] + s;
+    }
+}
+
+// Low-rank factor product U^T p (eq. (bfgs_hessian) applied matrix-free):
+// per-block partials of up to 32 columns (grid.y walks column groups), then a
+// one-block fixed-order reduction v_c = w_c * sum_b partial[b][c].
+__global__ __launch_bounds__(kBlock) void k_lr_partial(const double* U, int n, int k, const double* p,
+                                                       double* part, const Flags* fl) {
+    __shared__ double sh[kBlock / 64];
+    if (pcg_stopped(fl)) return;
+    const int c0 = blockIdx.y * 32;
+    const int kc = min(32, k - c0);
+    double acc[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) acc[c] = 0.0;
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) {
+        const double pj = p[j];
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+            if (c < kc) acc[c] += U[j + size_t(n) * (c0 + c)] * pj;
+    }
+    for (int c = 0; c < kc; ++c) {
+        const double t = block_sum(acc[c], sh);
+        if (threadIdx.x == 0) part[size_t(blockIdx.x) * k + c0 + c] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_lr_reduce(const double* part, int nb, int k, const double* w,
+                                                      double* v, const Flags* fl) {
+    __shared__ double sh[kBlock / 64];
+    if (pcg_stopped(fl)) return;
+    for (int c = 0; c < k; ++c) {
+        const double t = reduce_partials_sum(part + c, nb, k, sh);
+        if (threadIdx.x == 0) v[c] = w[c] * t;
     }
 }
 

@@ -65,6 +65,7 @@ struct qp_handle {
     double* W = nullptr;
     int *Ap = nullptr, *Ac = nullptr, *Atp = nullptr, *Atc = nullptr;
     double *Av = nullptr, *Atv = nullptr;
+    int last_pcg_iters = 0;   // iterations of the previous PCG solve (chunk size predictor)
     double *xlo = nullptr, *xhi = nullptr, *alo = nullptr, *ahi = nullptr;
     double *p = nullptr, *diagH = nullptr, *U = nullptr, *w = nullptr;
 
@@ -76,8 +77,12 @@ struct qp_handle {
     double *rhs_full = nullptr, *rho = nullptr, *dxacc = nullptr;   // refinement of low-precision directions
     double *part = nullptr, *part2 = nullptr, *partA = nullptr, *part_rz = nullptr, *part_rr = nullptr;
     // constraint-block preconditioner (dense m x m, leading dimension ld)
-    int woodbury = 0, ld = 0, T = 0;
+    int woodbury = 0, ld = 0, T = 0;            // allocation sizes (all m rows)
+    int kcur = 0, ldcur = 0, Tcur = 0;           // strong rows of the current build
     double *Sm = nullptr, *Xm = nullptr, *Sinv = nullptr, *Linv = nullptr, *wpre = nullptr, *vpre = nullptr;
+    double* Dw = nullptr;                        // D plus the weak rows' diagonal
+    double *lr_part = nullptr, *lr_v = nullptr;  // low-rank term: U^T p partials and w .* U^T p
+    int *rflag = nullptr, *rpos = nullptr, *ridx = nullptr, *kdev = nullptr;
     size_t part_len = 0;
     double* log = nullptr;
     IpmScal* isc = nullptr;
@@ -121,9 +126,22 @@ struct qp_handle {
 // ==========================================================================
 namespace {
 
+constexpr int kLrBlocks = 256;   // blocks of the U^T p partial pass
+
+// v = w .* (U^T p) for the low-rank part of H (no-op when k = 0).
+void lowrank_prepare(qp_handle* h, const double* p, const Flags* fl) {
+    if (h->k == 0) return;
+    const int gy = (h->k + 31) / 32;
+    hipLaunchKernelGGL(k_lr_partial, dim3(kLrBlocks, gy), dim3(kBlock), 0, h->stream, (const double*)h->U, h->n,
+                       h->k, p, h->lr_part, fl);
+    hipLaunchKernelGGL(k_lr_reduce, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->lr_part, kLrBlocks,
+                       h->k, (const double*)h->w, h->lr_v, fl);
+    HIPCHK(hipGetLastError());
+}
+
 int grid_elems(int64_t n) {
     int64_t g = (n + kBlock - 1) / kBlock;
-    return int(std::max<int64_t>(1, std::min<int64_t>(g, kMaxPartials)));
+    return int(std::max<int64_t>(1, std::min<int64_t>(g, kMaxElemGrid)));
 }
 int grid_rows(int64_t rows, int G) {
     const int rpb = kBlock / G;
@@ -185,11 +203,13 @@ int apply_op(qp_handle* h, const double* p, double* q, const double* sigx, const
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
     launch_fwd<VT, AT>(h, h->GJ, f, nbA);
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
+    lowrank_prepare(h, p, fl);
     BwdArgs<VT> b{};
     b.Jtp = h->Jtp; b.Jtc = h->Jtc; b.Jtv = jtv; b.n = h->n;
     b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = f.m > 0;
     b.t = h->t; b.u = h->u; b.p = p; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
     b.q = q; b.part = part; b.fl = fl;
+    b.U = h->U; b.lr_v = h->lr_v; b.lr_k = h->k;
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], h->stream));
     const int g = launch_bwd<VT, AT>(h, h->GJt, b);
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], h->stream));
@@ -230,14 +250,33 @@ struct TimingAcc {
 };
 
 // Constraint-block preconditioner for the current D = diag(Hs + Sigma_x) and
-// Sigma_A: form S, factor it, and build S^{-1} (schur_kernels.hpp).  `stop`
+// Sigma_A: select the strong rows, fold the weak ones into Dw, form S over the
+// strong rows, factor it and build S^{-1} (schur_kernels.hpp).  `stop`
 // (device int, may be null) turns every launch into a no-op once set.
-void build_precond(qp_handle* h, const double* D, const double* sigA, const int* stop) {
-    if (!h->woodbury) return;
-    const int ld = h->ld, T = h->T, m = h->m;
+// Returns true when the dense block is non-empty (else Jacobi with d applies).
+bool build_precond(qp_handle* h, const double* D, const double* sigA, const int* stop) {
+    if (!h->woodbury) return false;
+    const int m = h->m, n = h->n;
+    hipLaunchKernelGGL(k_row_strength, dim3((m + 3) / 4), dim3(256), 0, h->stream, (const int*)h->Ap,
+                       (const int*)h->Ac, (const double*)h->Av, D, sigA, m, h->rflag, stop);
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, h->stream, (const int*)h->rflag, m, h->rpos, h->ridx,
+                       h->kdev, stop);
+    hipLaunchKernelGGL(k_fold_weak, dim3((n + 15) / 16), dim3(256), 0, h->stream, (const int*)h->Atp,
+                       (const int*)h->Atc, (const double*)h->Atv, sigA, (const int*)h->rpos, D, n, h->Dw, stop);
+    HIPCHK(hipGetLastError());
+    int k = 0;
+    HIPCHK(hipMemcpyAsync(&k, h->kdev, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (k < 0 || k > m) k = 0;   // never happens; keeps launch shapes in range
+    h->kcur = k;
+    h->ldcur = ((k + TS - 1) / TS) * TS;
+    h->Tcur = h->ldcur / TS;
+    if (k == 0) return false;
+    const int ld = h->ldcur, T = h->Tcur;
     hipLaunchKernelGGL(k_schur_form, dim3(ld), dim3(64), size_t(ld) * sizeof(double), h->stream,
                        (const int*)h->Ap, (const int*)h->Ac, (const double*)h->Av, (const int*)h->Atp,
-                       (const int*)h->Atc, (const double*)h->Atv, D, sigA, m, ld, h->Sm, stop);
+                       (const int*)h->Atc, (const double*)h->Atv, (const double*)h->Dw, sigA,
+                       (const int*)h->rpos, (const int*)h->ridx, k, ld, h->Sm, stop);
     HIPCHK(hipGetLastError());
     for (int b = 0; b < T; ++b) {
         hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, h->stream, h->Sm, ld, b, h->Linv, stop);
@@ -257,16 +296,18 @@ void build_precond(qp_handle* h, const double* D, const double* sigA, const int*
     hipLaunchKernelGGL(k_inv_product, dim3(T, T), dim3(256), 0, h->stream, (const double*)h->Xm, ld, T, h->Sinv,
                        stop);
     HIPCHK(hipGetLastError());
+    return true;
 }
 
-// z = P^{-1} r for the constraint-block preconditioner, given y = r ./ D in z.
+// z = P^{-1} r for the constraint-block preconditioner, given y = r ./ Dw in z.
 int apply_precond(qp_handle* h, const double* D, const double* sigA, int init) {
-    const int ld = h->ld;
-    hipLaunchKernelGGL(k_prec_a, dim3((ld + 3) / 4), dim3(kBlock), 0, h->stream, (const int*)h->Ap,
-                       (const int*)h->Ac, (const double*)h->Av, (const double*)h->pz, sigA, h->m, ld, h->wpre,
-                       (const Flags*)h->fl);
-    hipLaunchKernelGGL(k_prec_symv, dim3((ld + 3) / 4), dim3(kBlock), 0, h->stream, (const double*)h->Sinv, ld,
-                       (const double*)h->wpre, sigA, h->m, h->vpre, (const Flags*)h->fl);
+    const int ld = h->ldcur, k = h->kcur, m = h->m;
+    const int rows_a = std::max(ld, (m + 63) / 64);
+    hipLaunchKernelGGL(k_prec_a, dim3((rows_a + 3) / 4), dim3(kBlock), 0, h->stream, (const int*)h->Ap,
+                       (const int*)h->Ac, (const double*)h->Av, (const double*)h->pz, sigA, (const int*)h->ridx,
+                       k, ld, m, h->wpre, h->vpre, (const Flags*)h->fl);
+    hipLaunchKernelGGL(k_prec_symv, dim3((k + 3) / 4), dim3(kBlock), 0, h->stream, (const double*)h->Sinv, ld,
+                       (const double*)h->wpre, sigA, (const int*)h->ridx, k, h->vpre, (const Flags*)h->fl);
     const int G = 16;
     const int grid = grid_rows_capped(h->n, G);
     hipLaunchKernelGGL(k_prec_at<G>, dim3(grid), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
@@ -284,7 +325,8 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
               const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode, TimingAcc* tacc) {
     const int n = h->n;
     const int ge = grid_elems(n);
-    const int wb = (h->woodbury && sigA) ? 1 : 0;
+    // dh != null selects the constraint-block preconditioner (built for this Sigma)
+    const int wb = (h->woodbury && sigA && dh) ? 1 : 0;
     const double* dd = wb ? dh : d;
     PcgInitArgs ia{};
     ia.n = n; ia.rhs_a = rhs_a; ia.rhs_b = rhs_b; ia.ipm = ipm_mode ? h->isc : nullptr;
@@ -326,8 +368,10 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         return f.pcg_converged || f.pcg_breakdown || f.pcg_capped || f.ipm_done;
     };
     // Chunks of iterations are queued ahead of the host check: kernels of a
-    // finished solve return at once, so the GPU never waits on the host.
-    int chunk = 4;
+    // finished solve return at once, so the GPU never waits on the host.  The
+    // first chunk covers most of the previous solve's iteration count; later
+    // chunks are short, so few no-op launches trail the converged iteration.
+    int chunk = std::max(4, std::min(512, (h->last_pcg_iters * 3) / 4));
     int64_t launched = 0;
     const int64_t guard = int64_t(h->set.pcg_max_iter) + 4096;
     int cur = 0;
@@ -336,7 +380,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     snapshot(cur);
     Flags f{};
     while (true) {
-        chunk = std::min(chunk * 2, 64);
+        chunk = std::min(std::max(8, chunk / 4), 32);
         for (int i = 0; i < chunk; ++i) one_iter();
         launched += chunk;
         snapshot(cur ^ 1);
@@ -349,6 +393,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         }
         cur ^= 1;
     }
+    if (!f.ipm_done) h->last_pcg_iters = f.pcg_iters;
     if (timing) {
         // launches past the last executed iteration returned at once: drop them
         for (int sl = slot_begin + std::max(f.pcg_iters, 0); sl < tacc->pairs; ++sl) tacc->valid[sl] = 0;
@@ -612,6 +657,10 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->tmp_n2 = h->dalloc<double>(n);
         h->tmp_m = h->dalloc<double>(std::max(m, 1));
         h->rhs_full = h->dalloc<double>(n);
+        if (h->k > 0) {
+            h->lr_part = h->dalloc<double>(size_t(kLrBlocks) * h->k);
+            h->lr_v = h->dalloc<double>(h->k);
+        }
         h->rho = h->dalloc<double>(n);
         h->dxacc = h->dalloc<double>(n);
         const size_t nbA = size_t((m + 3) / 4) + 1;
@@ -636,7 +685,13 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
                 h->Sinv = h->dalloc<double>(mm);
                 h->Linv = h->dalloc<double>(size_t(h->T) * TS * TS);
                 h->wpre = h->dalloc<double>(h->ld);
-                h->vpre = h->dalloc<double>(h->ld);
+                h->vpre = h->dalloc<double>(std::max(h->ld, m));
+                h->Dw = h->dalloc<double>(n);
+                h->rflag = h->dalloc<int>(m);
+                h->rpos = h->dalloc<int>(m);
+                h->ridx = h->dalloc<int>(m);
+                h->kdev = h->dalloc<int>(1);
+                HIPCHK(hipMemsetAsync(h->kdev, 0, sizeof(int), h->stream));
             }
         }
         h->log = h->dalloc<double>(4 * size_t(h->set.max_ipm_iter + 1));
@@ -751,10 +806,10 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         HIPCHK(hipGetLastError());
         TimingAcc ta;
         HIPCHK(hipEventRecord(h->ev_t0, h->stream));
-        if (m > 0) build_precond(h, dh, sigA, nullptr);
+        const bool wbp = (m > 0) && build_precond(h, dh, sigA, nullptr);
         int nsolves = 0;
-        Flags f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d, dh, 1.0,
-                                   false, &ta, &nsolves);
+        Flags f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d,
+                                   wbp ? h->Dw : nullptr, 1.0, false, &ta, &nsolves);
         HIPCHK(hipEventRecord(h->ev_t1, h->stream));
         HIPCHK(hipMemcpyAsync(dx, h->px, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
         PcgScal ps{};
@@ -845,6 +900,8 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             ba.Jtp = h->Jtp; ba.Jtc = h->Jtc; ba.Jtv = h->Jtv;
             ba.Atp = h->Atp; ba.Atc = h->Atc; ba.Atv = h->Atv; ba.hasA = m > 0;
             ba.t = h->t; ba.gamma = h->gamma;
+            ba.U = h->U; ba.lr_v = h->lr_v; ba.lr_k = h->k;
+            lowrank_prepare(h, v.x, nullptr);
             const int gb = grid_rows_capped(n, Gt);
             switch (Gt) {
                 case 4: hipLaunchKernelGGL(k_ipm_bwd<4>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
@@ -860,7 +917,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
         };
         const int* ipm_stop = reinterpret_cast<const int*>(&h->fl->ipm_done);
         residuals(0);
-        if (m > 0) build_precond(h, v.dh, v.sigA, ipm_stop);
+        bool wbp = (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop);
 
         TimingAcc ta;
         int64_t pcg_total = 0;
@@ -872,7 +929,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             HIPCHK(hipEventRecord(h->ev_p0, h->stream));
             int nsolves = 0;
             f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
-                                 v.dh, hs, true, &ta, &nsolves);
+                                 wbp ? h->Dw : nullptr, hs, true, &ta, &nsolves);
             HIPCHK(hipEventRecord(h->ev_p1, h->stream));
             if (f.ipm_done) break;
             {
@@ -907,7 +964,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
                                (const double*)h->part2, nbA + nbx, h->isc, (const Flags*)h->fl);
             HIPCHK(hipGetLastError());
             residuals(1);
-            if (m > 0) build_precond(h, v.dh, v.sigA, ipm_stop);
+            wbp = (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop);
         }
         // outputs
         HIPCHK(hipEventRecord(h->ev_t1, h->stream));

@@ -14,8 +14,12 @@
 // (Sherman-Morrison-Woodbury).  S is formed densely without atomics, factored
 // by a blocked Cholesky (its pivots cannot drop below 1), inverted through the
 // triangular inverse, and applied as one dense symmetric matrix-vector product
-// per PCG iteration.  Dense m x m storage is row-major with leading dimension
-// ld = m rounded up to 32; padding rows/columns hold the identity.
+// per PCG iteration.  Only the "strong" rows of A enter the dense block: a
+// row i with M_ii = Sigma_i sum_j A_ij^2 / D_j below 1 changes P little and is
+// folded into the Jacobi diagonal instead (D_j += Sigma_i A_ij^2), so the
+// dense block has k <= m rows, about the number of active constraints late in
+// the IPM.  Dense k x k storage is row-major with leading dimension ld = k
+// rounded up to 32; padding rows/columns hold the identity.
 #pragma once
 
 #include "device_common.hpp"
@@ -24,36 +28,111 @@ namespace qpg {
 
 constexpr int TS = 32;   // tile edge of the dense kernels
 
-// S = I + Sigma^{1/2} A D^{-1} A^T Sigma^{1/2}: one wavefront per row i, the
-// row accumulated in LDS.  For each nonzero A_ij of row i (in column order),
-// the column j of A (row j of the stored A^T) is added with weight A_ij/D_j;
-// within one column all row indices k differ, so no two lanes touch the same
+constexpr double kStrongRow = 1.0;   // M_ii threshold for the dense block
+
+// M_ii = Sigma_i sum_j A_ij^2 / D_j (a wavefront per row) and the strong flag.
+__global__ __launch_bounds__(256) void k_row_strength(const int* Ap, const int* Ac, const double* Av,
+                                                      const double* D, const double* sigA, int m, int* flag,
+                                                      const int* stop) {
+    if (stop && *stop) return;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int e = Ap[i] + lane; e < Ap[i + 1]; e += 64) {
+        const double a = Av[e];
+        s += a * a / D[Ac[e]];
+    }
+    s = group_sum<double, 64>(s);
+    if (lane == 0) flag[i] = (sigA[i] * s >= kStrongRow) ? 1 : 0;
+}
+
+// Deterministic compaction by one block: pos[i] = rank of strong row i (or
+// -1), idx[r] = i, count in *k_out.
+__global__ __launch_bounds__(1024) void k_compact(const int* flag, int m, int* pos, int* idx, int* k_out,
+                                                  const int* stop) {
+    __shared__ int sh[1024];
+    if (stop && *stop) return;
+    int base = 0;
+    for (int c0 = 0; c0 < m; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int f = (i < m) ? flag[i] : 0;
+        sh[threadIdx.x] = f;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
+            const int v = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (i < m) {
+            const int r = base + sh[threadIdx.x] - f;
+            pos[i] = f ? r : -1;
+            if (f) idx[r] = i;
+        }
+        const int tot = sh[1023];
+        __syncthreads();
+        base += tot;
+    }
+    if (threadIdx.x == 0) *k_out = base;
+}
+
+// Dw_j = dh_j + sum over weak rows i of Sigma_i A_ij^2 (rows of A^T, G = 16).
+__global__ __launch_bounds__(256) void k_fold_weak(const int* Atp, const int* Atc, const double* Atv,
+                                                   const double* sigA, const int* pos, const double* dh,
+                                                   int n, double* Dw, const int* stop) {
+    if (stop && *stop) return;
+    const int j = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int lane = threadIdx.x & 15;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int e = Atp[j] + lane; e < Atp[j + 1]; e += 16) {
+        const int i = Atc[e];
+        if (pos[i] < 0) {
+            const double a = Atv[e];
+            s += a * a * sigA[i];
+        }
+    }
+    s = group_sum<double, 16>(s);
+    if (lane == 0) Dw[j] = dh[j] + s;
+}
+
+// S = I + Sigma^{1/2} A_s D^{-1} A_s^T Sigma^{1/2} over the k strong rows: one
+// wavefront per strong row r (row i = idx[r] of A), the row accumulated in
+// LDS.  For each nonzero A_ij of row i (in column order), the strong entries
+// of column j of A (row j of the stored A^T) are added with weight A_ij/D_j;
+// within one column all row indices differ, so no two lanes touch the same
 // LDS word in a step, and steps of one wavefront execute in order.
 __global__ __launch_bounds__(64) void k_schur_form(const int* __restrict__ Ap, const int* __restrict__ Ac,
                                                   const double* __restrict__ Av, const int* __restrict__ Atp,
                                                   const int* __restrict__ Atc, const double* __restrict__ Atv,
                                                   const double* __restrict__ D, const double* __restrict__ sigA,
-                                                  int m, int ld, double* __restrict__ S, const int* stop) {
+                                                  const int* __restrict__ pos, const int* __restrict__ idx, int k,
+                                                  int ld, double* __restrict__ S, const int* stop) {
     extern __shared__ double acc[];
     if (stop && *stop) return;
-    const int i = blockIdx.x;
+    const int r = blockIdx.x;
     const int lane = threadIdx.x;
-    for (int k = lane; k < ld; k += 64) acc[k] = 0.0;
+    for (int c = lane; c < ld; c += 64) acc[c] = 0.0;
     __syncthreads();
-    if (i < m) {
+    if (r < k) {
+        const int i = idx[r];
         const int e0 = Ap[i], e1 = Ap[i + 1];
         for (int e = e0; e < e1; ++e) {
             const int j = Ac[e];
             const double c = Av[e] / D[j];
-            for (int f = Atp[j] + lane; f < Atp[j + 1]; f += 64) acc[Atc[f]] += c * Atv[f];
+            for (int f = Atp[j] + lane; f < Atp[j + 1]; f += 64) {
+                const int q = pos[Atc[f]];
+                if (q >= 0) acc[q] += c * Atv[f];
+            }
         }
     }
     __syncthreads();
-    const double si = (i < m) ? sqrt(sigA[i]) : 0.0;
-    for (int k = lane; k < ld; k += 64) {
-        double v = (i < m && k < m) ? si * sqrt(sigA[k]) * acc[k] : 0.0;
-        if (k == i) v += 1.0;
-        S[size_t(i) * ld + k] = v;
+    const double si = (r < k) ? sqrt(sigA[idx[r]]) : 0.0;
+    for (int c = lane; c < ld; c += 64) {
+        double v = (r < k && c < k) ? si * sqrt(sigA[idx[c]]) * acc[c] : 0.0;
+        if (c == r) v += 1.0;
+        S[size_t(r) * ld + c] = v;
     }
 }
 

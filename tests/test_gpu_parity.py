@@ -319,3 +319,34 @@ def test_solve_mixed_precision_band(prec):
     assert res.status == qpgpu.QP_OK, res.info
     assert np.abs(res.x - ref.x).max() <= 1e-5
     assert abs(res.info["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
+
+
+# ----------------------------------------------------------------------------
+# low-rank Hessian term (eq. (bfgs_hessian)) and the config-5 shape, scaled down
+# ----------------------------------------------------------------------------
+
+def test_operator_with_lowrank_term():
+    prob = qpsynth.config5(scale=0.01)
+    assert prob.k == 20
+    it = qpsynth.random_iterate(prob, 13)
+    h = qpgpu.qp_create_from_problem(prob)
+    y, _ = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"])
+    K = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"])
+    ref = K @ it["v"]
+    bound = _abs_op(prob, it["sigma_x"], it["sigma_A"]) @ np.abs(it["v"])
+    bound += np.abs(prob.U) @ (prob.w * (np.abs(prob.U).T @ np.abs(it["v"])))
+    assert np.all(np.abs(y - ref) <= 1e-12 * bound)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_solve_config5_scaled(prec):
+    """BF16-valued J (exact in every storage), rank-20 U, rows of A at 1%."""
+    prob = qpsynth.config5(scale=0.01)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    assert res.status == qpgpu.QP_OK, res.info
+    assert np.abs(res.x - ref.x).max() <= 1e-5
+    assert abs(res.info["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
+    cert = oracle.kkt_certificate(prob, res.x, res.lam_x, res.lam_A)
+    assert cert.worst() <= 1e-9, cert
