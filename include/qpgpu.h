@@ -102,6 +102,8 @@ typedef struct {
                                  part, diag(H + Sigma_x), with the constraint block A^T Sigma_A A
                                  applied exactly through a dense m x m Cholesky (Woodbury identity);
                                  falls back to 0 when m = 0 or m > 8192 */
+    int32_t spmv_format;      /* 0 (default): line format for J when its rows come in lines of 64
+                                 sharing one column list (the 64-voxel bands), else CSR; 1: CSR */
 } qp_settings;
 
 typedef struct {
@@ -120,6 +122,7 @@ typedef struct {
     double  t_spmv_fwd_ms;    /* summed J (and A) SpMV launch time, when timing = 1 */
     double  t_spmv_bwd_ms;    /* summed J^T (and A^T) SpMV launch time, when timing = 1 */
     int64_t n_spmv_fwd, n_spmv_bwd;
+    int32_t spmv_format;      /* format the PCG operator used: 0 CSR, 1 line format */
 } qp_info;
 
 /* Defaults listed above. */

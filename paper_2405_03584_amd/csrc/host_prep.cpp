@@ -68,6 +68,53 @@ HostCsr transpose(const HostCsr& M) {
     return T;
 }
 
+bool build_line_format(const HostCsr& M, int32_t R, LineFormat& lf) {
+    if (R <= 0 || M.rows == 0 || M.rows % R != 0) return false;
+    const int32_t L = M.rows / R;
+    for (int32_t l = 0; l < L; ++l) {
+        const int32_t r0 = l * R;
+        const int32_t len = M.ptr[r0 + 1] - M.ptr[r0];
+        const int32_t* c0 = M.col.data() + M.ptr[r0];
+        for (int32_t r = 1; r < R; ++r) {
+            if (M.ptr[r0 + r + 1] - M.ptr[r0 + r] != len) return false;
+            if (len && std::memcmp(c0, M.col.data() + M.ptr[r0 + r], sizeof(int32_t) * size_t(len)) != 0)
+                return false;
+        }
+    }
+    LineFormat f;
+    f.R = R;
+    f.lines = L;
+    f.cols = M.cols;
+    f.ptr.assign(size_t(L) + 1, 0);
+    for (int32_t l = 0; l < L; ++l) f.ptr[l + 1] = f.ptr[l] + (M.ptr[l * R + 1] - M.ptr[l * R]);
+    f.col.resize(size_t(f.ptr[L]));
+    f.val.resize(M.val.size());
+    for (int32_t l = 0; l < L; ++l) {
+        const int32_t len = f.ptr[l + 1] - f.ptr[l];
+        std::memcpy(f.col.data() + f.ptr[l], M.col.data() + M.ptr[l * R], sizeof(int32_t) * size_t(len));
+        for (int32_t r = 0; r < R; ++r) {
+            const double* src = M.val.data() + M.ptr[l * R + r];
+            for (int32_t k = 0; k < len; ++k) f.val[(size_t(f.ptr[l]) + k) * R + r] = src[k];
+        }
+    }
+    // transpose of the (line x spot) incidence, counting sort over spots
+    f.sptr.assign(size_t(M.cols) + 1, 0);
+    for (int32_t s : f.col) f.sptr[size_t(s) + 1]++;
+    for (int32_t j = 0; j < M.cols; ++j) f.sptr[j + 1] += f.sptr[j];
+    f.sline.resize(f.col.size());
+    f.sslot.resize(f.col.size());
+    std::vector<int32_t> next(f.sptr.begin(), f.sptr.end() - 1);
+    for (int32_t l = 0; l < L; ++l)
+        for (int32_t k = f.ptr[l]; k < f.ptr[l + 1]; ++k) {
+            const int32_t j = f.col[k];
+            const int32_t d = next[j]++;
+            f.sline[d] = l;
+            f.sslot[d] = k;
+        }
+    lf = std::move(f);
+    return true;
+}
+
 // binary64 -> binary32 with round to nearest, ties to even.  The C++ cast
 // rounds with the current rounding mode, which is round-to-nearest-even by
 // default; values beyond the float range become +-inf.
@@ -126,6 +173,7 @@ std::string validate_settings(const qp_settings* s) {
         s->schedule != 32 && s->schedule != 64)
         return "settings.schedule must be 0, 4, 8, 16, 32 or 64";
     if (s->precond != 0 && s->precond != 1) return "settings.precond must be 0 or 1";
+    if (s->spmv_format != 0 && s->spmv_format != 1) return "settings.spmv_format must be 0 or 1";
     return "";
 }
 

@@ -29,6 +29,27 @@ HostCsr to_host_csr(const qp_csr* M);
 // lists the rows i of M with M_ij != 0 in increasing i (stable, deterministic).
 HostCsr transpose(const HostCsr& M);
 
+// Line format of a dose matrix whose rows come in groups of R consecutive
+// rows sharing one column list (a line of R voxels; every spot covering the
+// line touches all R rows).  Column ids are stored once per line; values are
+// slot-major with the R rows of a slot contiguous:
+//   row R*l + r, slot k of line l  ->  val[(ptr[l] + k) * R + r], column col[ptr[l] + k].
+// The transpose is a per-spot list of (line, slot) pairs in increasing line
+// order, so J^T reads the same value array.
+struct LineFormat {
+    int32_t R = 64, lines = 0, cols = 0;
+    std::vector<int32_t> ptr;      // lines + 1
+    std::vector<int32_t> col;      // sum of line lengths
+    std::vector<double> val;       // nnz, slot-major
+    std::vector<int32_t> sptr;     // cols + 1
+    std::vector<int32_t> sline;    // per spot: lines covered
+    std::vector<int32_t> sslot;    // per spot: slot index ptr[l] + k
+};
+
+// True (and fills lf) when every group of R consecutive rows of M shares one
+// column list; false leaves lf untouched.
+bool build_line_format(const HostCsr& M, int32_t R, LineFormat& lf);
+
 // Round-to-nearest-even conversions (IEEE 754 binary32 / bfloat16 formats).
 uint32_t f64_to_f32_bits(double v);
 uint16_t f64_to_bf16_bits(double v);

@@ -12,6 +12,7 @@
 #include "host_prep.h"
 #include "ipm_kernels.hpp"
 #include "schur_kernels.hpp"
+#include "line_kernels.hpp"
 #include "qpgpu.h"
 
 using namespace qpg;
@@ -66,6 +67,14 @@ struct qp_handle {
     int *Ap = nullptr, *Ac = nullptr, *Atp = nullptr, *Atc = nullptr;
     double *Av = nullptr, *Atv = nullptr;
     int last_pcg_iters = 0;   // iterations of the previous PCG solve (chunk size predictor)
+    // line format of J (64-row lines sharing a column list), used by the PCG operator
+    bool line = false;
+    int L = 0;
+    int *lptr = nullptr, *lcol = nullptr, *sptr = nullptr, *sline = nullptr, *sslot = nullptr;
+    double* lval = nullptr;
+    float* lval32 = nullptr;
+    bf16_t* lval16 = nullptr;
+    std::vector<double> hlval;
     double *xlo = nullptr, *xhi = nullptr, *alo = nullptr, *ahi = nullptr;
     double *p = nullptr, *diagH = nullptr, *U = nullptr, *w = nullptr;
 
@@ -188,6 +197,44 @@ void mat_ptrs<float>(qp_handle* h, const float*& jv, const float*& jtv) { jv = h
 template <>
 void mat_ptrs<bf16_t>(qp_handle* h, const bf16_t*& jv, const bf16_t*& jtv) { jv = h->Jv16; jtv = h->Jtv16; }
 
+template <typename VT>
+const VT* line_vals(qp_handle* h);
+template <>
+const double* line_vals<double>(qp_handle* h) { return h->lval; }
+template <>
+const float* line_vals<float>(qp_handle* h) { return h->lval32; }
+template <>
+const bf16_t* line_vals<bf16_t>(qp_handle* h) { return h->lval16; }
+
+// q = K p on the line format of J (same contract as apply_op).
+template <typename VT, typename AT>
+int apply_op_line(qp_handle* h, const double* p, double* q, const double* sigx, const double* sigA, double hs,
+                  double* part, const Flags* fl, bool timed, int tslot) {
+    LineFwdArgs<VT> f{};
+    f.lptr = h->lptr; f.lcol = h->lcol; f.lval = line_vals<VT>(h); f.L = h->L; f.W = h->W;
+    f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
+    f.x = p; f.t = h->t; f.u = h->u; f.sigA = sigA; f.fl = fl;
+    f.nbL = (h->L + 3) / 4;
+    const int nbA = f.m > 0 ? grid_rows(f.m, 64) : 0;
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
+    hipLaunchKernelGGL((k_op_fwd_line<VT, AT>), dim3(std::max(1, f.nbL + nbA)), dim3(kBlock), 0, h->stream, f);
+    HIPCHK(hipGetLastError());
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
+    lowrank_prepare(h, p, fl);
+    LineBwdArgs<VT> b{};
+    b.sptr = h->sptr; b.sline = h->sline; b.sslot = h->sslot; b.lval = line_vals<VT>(h); b.n = h->n;
+    b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = f.m > 0;
+    b.t = h->t; b.u = h->u; b.p = p; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
+    b.q = q; b.part = part; b.fl = fl;
+    b.U = h->U; b.lr_v = h->lr_v; b.lr_k = h->k;
+    const int grid = std::min((h->n + 3) / 4, kMaxPartials);
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], h->stream));
+    hipLaunchKernelGGL((k_op_bwd_line<VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, b);
+    HIPCHK(hipGetLastError());
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], h->stream));
+    return part ? grid : 0;
+}
+
 // q = K p with K = hs*H + diag(sigx) + A^T diag(sigA) A; returns the number of
 // p^T q partials written to `part` (0 when part is null).
 template <typename VT, typename AT>
@@ -218,6 +265,13 @@ int apply_op(qp_handle* h, const double* p, double* q, const double* sigx, const
 
 int apply_op_prec(qp_handle* h, int prec, const double* p, double* q, const double* sigx, const double* sigA,
                   double hs, double* part, const Flags* fl, bool timed, int tslot) {
+    if (h->line) {
+        switch (prec) {
+            case QP_FP32: return apply_op_line<float, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
+            case QP_BF16: return apply_op_line<bf16_t, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
+            default: return apply_op_line<double, double>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
+        }
+    }
     switch (prec) {
         case QP_FP32: return apply_op<float, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
         case QP_BF16: return apply_op<bf16_t, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
@@ -226,6 +280,18 @@ int apply_op_prec(qp_handle* h, int prec, const double* p, double* q, const doub
 }
 
 void ensure_lowp(qp_handle* h, int prec) {
+    if (h->line && prec == QP_FP32 && !h->lval32) {
+        std::vector<uint32_t> a(h->hlval.size());
+        for (size_t i = 0; i < a.size(); ++i) a[i] = f64_to_f32_bits(h->hlval[i]);
+        h->lval32 = reinterpret_cast<float*>(h->upload(a.data(), a.size()));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    if (h->line && prec == QP_BF16 && !h->lval16) {
+        std::vector<uint16_t> a(h->hlval.size());
+        for (size_t i = 0; i < a.size(); ++i) a[i] = f64_to_bf16_bits(h->hlval[i]);
+        h->lval16 = reinterpret_cast<bf16_t*>(h->upload(a.data(), a.size()));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
     if (prec == QP_FP32 && !h->Jv32) {
         std::vector<uint32_t> a(h->hJv.size()), b(h->hJtv.size());
         for (size_t i = 0; i < a.size(); ++i) a[i] = f64_to_f32_bits(h->hJv[i]);
@@ -431,7 +497,7 @@ Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double
     hipLaunchKernelGGL(k_acc, dim3(ge), dim3(kBlock), 0, h->stream, n, h->dxacc, (const double*)h->px, 1,
                        (const Flags*)h->fl);
     for (int k = 0; k < h->set.refine_steps; ++k) {
-        apply_op<double, double>(h, h->dxacc, h->pq, sigx, sigA, hs, nullptr, nullptr, false, 0);
+        apply_op_prec(h, QP_FP64, h->dxacc, h->pq, sigx, sigA, hs, nullptr, nullptr, false, 0);
         hipLaunchKernelGGL(k_sub, dim3(ge), dim3(kBlock), 0, h->stream, n, rhs, (const double*)h->pq, h->rho,
                            (const Flags*)h->fl);
         Flags f2 = run_pcg(h, prec, nullptr, h->rho, sigx, sigA, d, dh, hs, false, tacc);
@@ -512,6 +578,7 @@ void qp_default_settings(qp_settings* s) {
     s->timing = 0;
     s->log_level = 0;
     s->precond = 1;
+    s->spmv_format = 0;
 }
 
 const char* qp_last_error(const qp_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
@@ -560,6 +627,8 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         // host preparation (no device calls yet)
         HostCsr hJ = to_host_csr(J);
         HostCsr hJt = transpose(hJ);
+        LineFormat lf;
+        const bool use_line = (h->set.spmv_format != 1) && build_line_format(hJ, 64, lf);
         HostCsr hA, hAt;
         if (m > 0) {
             hA = to_host_csr(A);
@@ -613,6 +682,18 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->Jtv = h->upload(hJt.val.data(), hJt.val.size());
         h->hJv = std::move(hJ.val);
         h->hJtv = std::move(hJt.val);
+        if (use_line) {
+            h->line = true;
+            h->L = lf.lines;
+            h->lptr = h->upload(lf.ptr.data(), lf.ptr.size());
+            h->lcol = h->upload(lf.col.data(), lf.col.size());
+            h->lval = h->upload(lf.val.data(), lf.val.size());
+            h->sptr = h->upload(lf.sptr.data(), lf.sptr.size());
+            h->sline = h->upload(lf.sline.data(), lf.sline.size());
+            h->sslot = h->upload(lf.sslot.data(), lf.sslot.size());
+            HIPCHK(hipStreamSynchronize(h->stream));
+            h->hlval = std::move(lf.val);
+        }
         h->W = nJ > 0 ? h->upload(W, size_t(nJ)) : h->dalloc<double>(1);
         if (m > 0) {
             h->Ap = h->upload(hA.ptr.data(), hA.ptr.size());
@@ -768,6 +849,7 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
             info->t_solve_ms = ms;
+            info->spmv_format = h->line ? 1 : 0;
             harvest_timing(h, ta, info);
         }
     } catch (const HipError& he) {
@@ -998,6 +1080,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
             info->t_solve_ms = ms;
             info->t_pcg_ms = pcg_ms;
+            info->spmv_format = h->line ? 1 : 0;
             harvest_timing(h, ta, info);
         }
     } catch (const HipError& he) {

@@ -45,7 +45,7 @@ class qp_settings(C.Structure):
                 ("pcg_max_iter", C.c_int32), ("mu0", C.c_double), ("mu_tol", C.c_double),
                 ("tau", C.c_double), ("max_ipm_iter", C.c_int32), ("step_mode", C.c_int32),
                 ("scale_objective", C.c_int32), ("schedule", C.c_int32), ("timing", C.c_int32),
-                ("log_level", C.c_int32), ("precond", C.c_int32)]
+                ("log_level", C.c_int32), ("precond", C.c_int32), ("spmv_format", C.c_int32)]
 
 
 class qp_info(C.Structure):
@@ -54,7 +54,7 @@ class qp_info(C.Structure):
                 ("rnorm", C.c_double), ("zeta", C.c_double), ("objective", C.c_double),
                 ("pcg_relres", C.c_double), ("t_solve_ms", C.c_double), ("t_pcg_ms", C.c_double),
                 ("t_spmv_fwd_ms", C.c_double), ("t_spmv_bwd_ms", C.c_double),
-                ("n_spmv_fwd", C.c_int64), ("n_spmv_bwd", C.c_int64)]
+                ("n_spmv_fwd", C.c_int64), ("n_spmv_bwd", C.c_int64), ("spmv_format", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

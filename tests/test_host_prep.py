@@ -1,0 +1,113 @@
+"""Host preparation code of the library (validation helpers, transposes, value
+rounding, the line format), compiled with g++ for the CPU: no GPU needed."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import qpsynth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2405_03584_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def hp(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("hp") / "libhp.so")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-I", os.path.join(ROOT, "include"),
+                    "-I", CSRC, os.path.join(CSRC, "host_prep.cpp"),
+                    os.path.join(ROOT, "tests", "host_prep_harness.cpp"), "-o", out], check=True)
+    return C.CDLL(out)
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def test_transpose_matches_scipy(hp):
+    M = qpsynth.config1(0).J
+    ptr = M.indptr.astype(np.int32); col = M.indices.astype(np.int32); val = M.data.copy()
+    optr = np.zeros(M.shape[1] + 1, np.int32); ocol = np.zeros(M.nnz, np.int32); oval = np.zeros(M.nnz)
+    hp.hp_transpose(M.shape[0], M.shape[1], _p(ptr, C.c_int), _p(col, C.c_int), _p(val, C.c_double),
+                    _p(optr, C.c_int), _p(ocol, C.c_int), _p(oval, C.c_double))
+    T = M.T.tocsr()
+    T.sort_indices()
+    assert np.array_equal(optr, T.indptr) and np.array_equal(ocol, T.indices)
+    assert np.array_equal(oval, T.data)
+
+
+def _bf16_bruteforce(v):
+    """Nearest bfloat16 by enumeration of the two neighbours (ties to even)."""
+    out = np.empty(v.shape, np.uint16)
+    for i, x in enumerate(v):
+        f = np.float32(x)
+        b = int(np.array([f], np.float32).view(np.uint32)[0]) >> 16
+        cands = [(b - 1) & 0xFFFF, b, (b + 1) & 0xFFFF]
+        best = None
+        for c in cands:
+            val = float(np.array([c << 16], np.uint32).view(np.float32)[0])
+            if not np.isfinite(val):
+                continue
+            d = abs(val - x)
+            key = (d, c & 1)
+            if best is None or key < best[0]:
+                best = (key, c)
+        out[i] = best[1]
+    return out
+
+
+def test_bf16_round_to_nearest_even(hp):
+    rng = np.random.default_rng(3)
+    v = np.concatenate([rng.lognormal(0, 1, 3000), -rng.lognormal(0, 3, 1000),
+                        [1.0, 1.00390625, 1.01171875, 1.0 + 2 ** -8 + 2 ** -40, 0.0, 3.0e38]])
+    out = np.zeros(v.shape, np.uint16)
+    hp.hp_bf16(_p(v, C.c_double), _p(out, C.c_ushort), C.c_long(v.size))
+    ref = _bf16_bruteforce(v)
+    assert np.array_equal(out, ref)
+    # the generator's rounding agrees with the library's
+    gen = qpsynth.round_to_bf16(v[:-1])
+    lib = (out[:-1].astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    assert np.array_equal(gen, lib)
+
+
+def _line_format(hp, M, R=64):
+    ptr = M.indptr.astype(np.int32); col = M.indices.astype(np.int32); val = M.data.copy()
+    L = M.shape[0] // R if M.shape[0] % R == 0 else 0
+    lptr = np.zeros(max(L, 1) + 1, np.int32); lcol = np.zeros(M.nnz, np.int32); lval = np.zeros(M.nnz)
+    sptr = np.zeros(M.shape[1] + 1, np.int32); sline = np.zeros(M.nnz, np.int32)
+    sslot = np.zeros(M.nnz, np.int32); ns = C.c_int(0)
+    ok = hp.hp_line_format(M.shape[0], M.shape[1], _p(ptr, C.c_int), _p(col, C.c_int), _p(val, C.c_double), R,
+                           _p(lptr, C.c_int), _p(lcol, C.c_int), _p(lval, C.c_double), _p(sptr, C.c_int),
+                           _p(sline, C.c_int), _p(sslot, C.c_int), C.byref(ns))
+    return ok, L, lptr, lcol[:ns.value], lval, sptr, sline[:ns.value], sslot[:ns.value]
+
+
+def test_line_format_reconstructs_banded_matrix(hp):
+    M = qpsynth.config2(scale=0.02).J
+    ok, L, lptr, lcol, lval, sptr, sline, sslot = _line_format(hp, M)
+    assert ok == 1
+    rows, cols, vals = [], [], []
+    for l in range(L):
+        for k in range(lptr[l], lptr[l + 1]):
+            for r in range(64):
+                rows.append(64 * l + r); cols.append(lcol[k]); vals.append(lval[k * 64 + r])
+    R = sp.csr_matrix((vals, (rows, cols)), shape=M.shape)
+    assert (R != M).nnz == 0
+    # per-spot (line, slot) lists are the transpose of the line incidence, lines increasing
+    for j in range(0, M.shape[1], 37):
+        ls = sline[sptr[j]:sptr[j + 1]]
+        assert np.all(np.diff(ls) > 0)
+        assert np.all(lcol[sslot[sptr[j]:sptr[j + 1]]] == j)
+        col_rows = M.tocsc()[:, j].indices
+        assert np.array_equal(np.unique(col_rows // 64), ls)
+
+
+def test_line_format_rejects_unstructured(hp):
+    M = qpsynth.config1(0).J   # 2000 rows (not a multiple of 64 -> 2000 = 31*64+16)
+    assert _line_format(hp, M)[0] == 0
+    M2 = qpsynth.config2(scale=0.02).J.tolil()
+    M2[5, 7] = 1.0 if M2[5, 7] == 0 else 0.0
+    assert _line_format(hp, M2.tocsr())[0] == 0
