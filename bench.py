@@ -26,15 +26,23 @@ METRIC = "QP time-to-solution & PCG iters/s; SpMV HBM GB/s vs peak, mixed vs FP6
 HBM_PEAK_GBS = 8000.0
 
 
-def spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes=8):
+def spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes=8, fmt=0):
     """Algorithmic HBM bytes of one operator product, per kernel.
 
-    Each matrix value and int32 index read once, row pointers once, every
-    dense vector read or written once (gathered vectors counted once)."""
-    fwd = (nnzJ * (vbytes + 4) + (nJ + 1) * 4 + n * 8 + nJ * 8 + nJ * 8
-           + nnzA * 12 + (m + 1) * 4 + m * 8 + m * 8)
-    bwd = (nnzJ * (vbytes + 4) + (n + 1) * 4 + nJ * 8
-           + nnzA * 12 + (n + 1) * 4 + m * 8 + n * 8 * 3)
+    Each matrix value and index read once, row pointers once, every dense
+    vector read or written once (gathered vectors counted once).  fmt = 0: CSR
+    (int32 column index per nonzero); fmt = 1: line format (one int32 column id
+    per 64-row line slot, and one (line, slot) int32 pair per slot for J^T)."""
+    if fmt == 1:
+        slots = nnzJ // 64
+        lines = nJ // 64
+        jf = nnzJ * vbytes + slots * 4 + (lines + 1) * 4
+        jb = nnzJ * vbytes + slots * 8 + (n + 1) * 4
+    else:
+        jf = nnzJ * (vbytes + 4) + (nJ + 1) * 4
+        jb = nnzJ * (vbytes + 4) + (n + 1) * 4
+    fwd = jf + n * 8 + nJ * 8 + nJ * 8 + nnzA * 12 + (m + 1) * 4 + m * 8 + m * 8
+    bwd = jb + nJ * 8 + nnzA * 12 + (n + 1) * 4 + m * 8 + n * 8 * 3
     return fwd, bwd
 
 
@@ -79,7 +87,7 @@ def cpu_baseline(prob, ipm_iters):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("device_common.hpp", "ipm_kernels.hpp"):
+    for f in ("device_common.hpp", "ipm_kernels.hpp", "line_kernels.hpp"):
         with open(os.path.join(ROOT, "paper_2405_03584_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -95,7 +103,7 @@ def counter_traffic(kernel_tag, precision):
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     for name, v in rec["kernels"].items():
-        if name.startswith(kernel_tag):
+        if name.split("<")[0] == kernel_tag:
             return v["hbm_bytes"]
     return None
 
@@ -111,12 +119,17 @@ def operator_only(args, prob):
                                       reps=args.reps)
     n, m, nJ = prob.n, prob.m, prob.J.shape[0]
     vbytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
-    bf, bb = spmv_bytes(n, nJ, m, int(prob.J.nnz), int(prob.A.nnz), vbytes)
+    fmt = info["spmv_format"]
+    bf, bb = spmv_bytes(n, nJ, m, int(prob.J.nnz), int(prob.A.nnz), vbytes, fmt)
+    cf, cb = spmv_bytes(n, nJ, m, int(prob.J.nnz), int(prob.A.nnz), vbytes, 0)
     fus = 1e3 * info["t_spmv_fwd_ms"] / max(info["n_spmv_fwd"], 1)
     bus = 1e3 * info["t_spmv_bwd_ms"] / max(info["n_spmv_bwd"], 1)
     print(json.dumps({"mode": "operator", "precision": args.precision, "reps": args.reps,
+                      "format": ["csr", "line"][fmt],
                       "fwd_us": fus, "bwd_us": bus, "fwd_GBs": bf / fus / 1e3, "bwd_GBs": bb / bus / 1e3,
-                      "fwd_bytes": bf, "bwd_bytes": bb, "checksum": float(np.abs(y).sum())}), flush=True)
+                      "fwd_bytes": bf, "bwd_bytes": bb,
+                      "csr_equivalent_fwd_GBs": cf / fus / 1e3, "csr_equivalent_bwd_GBs": cb / bus / 1e3,
+                      "checksum": float(np.abs(y).sum())}), flush=True)
 
 
 def copy_calibration(args):
@@ -196,13 +209,16 @@ def main():
     nf = sum(i["n_spmv_fwd"] for i in infos)
     nb = sum(i["n_spmv_bwd"] for i in infos)
     vbytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
-    bf, bb = spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes)
+    fmt = infos[-1]["spmv_format"]
+    bf, bb = spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes, fmt)
+    cf, cb = spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes, 0)
     fwd_us = 1e3 * fwd_ms / max(nf, 1)
     bwd_us = 1e3 * bwd_ms / max(nb, 1)
     gbs_f = bf / (fwd_us * 1e-6) / 1e9
     gbs_b = bb / (bwd_us * 1e-6) / 1e9
-    dom = ("k_op_bwd (J^T + A^T SpMV, fused epilogue and p.q partials)", bb, bwd_us, gbs_b) \
-        if bwd_us >= fwd_us else ("k_op_fwd (J + A SpMV, fused W / Sigma_A scaling)", bf, fwd_us, gbs_f)
+    sfx = "_line" if fmt == 1 else ""
+    dom = (f"k_op_bwd{sfx} (J^T + A^T SpMV, fused epilogue and p.q partials)", bb, bwd_us, gbs_b) \
+        if bwd_us >= fwd_us else (f"k_op_fwd{sfx} (J + A SpMV, fused W / Sigma_A scaling)", bf, fwd_us, gbs_f)
 
     parity = None
     gold = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")
@@ -235,8 +251,10 @@ def main():
         "pcg_iters_per_qp": pcg_iters / args.steps,
         "pcg_iters_per_s": pcg_iters / (pcg_ms * 1e-3) if pcg_ms > 0 else None,
         "status_ok": status_ok,
-        "spmv": {"fwd_us": fwd_us, "bwd_us": bwd_us, "fwd_GBs": gbs_f, "bwd_GBs": gbs_b,
-                 "fwd_bytes": bf, "bwd_bytes": bb, "timed_launches": nb},
+        "spmv": {"format": ["csr", "line"][fmt], "fwd_us": fwd_us, "bwd_us": bwd_us, "fwd_GBs": gbs_f,
+                 "bwd_GBs": gbs_b, "fwd_bytes": bf, "bwd_bytes": bb, "timed_launches": nb,
+                 "csr_equivalent_fwd_GBs": cf / (fwd_us * 1e-6) / 1e9,
+                 "csr_equivalent_bwd_GBs": cb / (bwd_us * 1e-6) / 1e9},
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": dom[3], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dom[3] / HBM_PEAK_GBS,
                      "traffic": counter_traffic(dom[0].split()[0], args.precision) if args.scale == 1.0 else None,

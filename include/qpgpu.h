@@ -171,6 +171,17 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
                             const double* v, double* y, int32_t precision, int32_t reps,
                             qp_info* info);
 
+/* qp_solve_batch: solve `count` independent QPs (each a handle from
+ * qp_create) together; xs[i] (n_i doubles) receives QP i's minimiser and
+ * infos[i] (may be NULL) its info.  Handles run concurrently, each on its own
+ * stream (create them with hip_stream = NULL for a stream per handle), by up
+ * to 4 host workers (environment QPGPU_BATCH_WORKERS), largest nnz first.
+ * The batch workload of the task (many QPs of uneven size) is the intended
+ * use.  Returns QP_OK when every QP returned QP_OK, else the first failing
+ * status (QP_ERR_DEVICE preferred); QP_ERR_INVALID for NULL or repeated
+ * handles (text in qp_last_error(NULL)). */
+qp_status qp_solve_batch(qp_handle* const* hs, int32_t count, double* const* xs, qp_info* infos);
+
 /* Text of the last error on this handle; h == NULL gives the calling
  * thread's last qp_create error.  Valid until the next call on h. */
 const char* qp_last_error(const qp_handle* h);

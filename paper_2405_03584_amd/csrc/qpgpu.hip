@@ -3,7 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -279,6 +285,14 @@ int apply_op_prec(qp_handle* h, int prec, const double* p, double* q, const doub
     }
 }
 
+// SpMV schedule autotuner for CSR matrices: time each lane-group size for the
+// J pass and the J^T pass (a few launches each, HIP events) and keep the
+// fastest; results are cached per (rows, cols, nnz) for the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int64_t, int, int>, std::pair<int, int>> g_tune_cache;
+
+void autotune_schedule(qp_handle* h);
+
 void ensure_lowp(qp_handle* h, int prec) {
     if (h->line && prec == QP_FP32 && !h->lval32) {
         std::vector<uint32_t> a(h->hlval.size());
@@ -381,6 +395,63 @@ int apply_precond(qp_handle* h, const double* D, const double* sigA, int init) {
                        h->pz, h->pp, h->n, init, h->part_rz, (const Flags*)h->fl);
     HIPCHK(hipGetLastError());
     return grid;
+}
+
+void autotune_schedule(qp_handle* h) {
+    if (h->line || h->set.schedule != 0) return;
+    const auto key = std::make_tuple(h->nJ, h->n, h->nnzJ, h->m, int(h->nnzA > 0));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            h->GJ = it->second.first;
+            h->GJt = it->second.second;
+            return;
+        }
+    }
+    const int cand[] = {8, 16, 32, 64};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_f = 1e30f, best_b = 1e30f;
+    int gf = h->GJ, gb = h->GJt;
+    const int save_f = h->GJ, save_b = h->GJt;
+    for (int g : cand) {
+        h->GJ = g;
+        h->GJt = g;
+        float tf = 0.f, tb = 0.f;
+        for (int rep = 0; rep < 4; ++rep) {   // first repetition warms up
+            FwdArgs<double> f{};
+            f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = h->Jv; f.W = h->W; f.nJ = h->nJ;
+            f.x = h->zero_n; f.t = h->t; f.u = h->u;
+            HIPCHK(hipEventRecord(e0, h->stream));
+            launch_fwd<double, double>(h, g, f, 0);
+            HIPCHK(hipEventRecord(e1, h->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep) tf += ms;
+            BwdArgs<double> b{};
+            b.Jtp = h->Jtp; b.Jtc = h->Jtc; b.Jtv = h->Jtv; b.n = h->n;
+            b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = h->m > 0;
+            b.t = h->t; b.u = h->zero_m; b.p = h->zero_n; b.hs = 1.0; b.q = h->tmp_n;
+            HIPCHK(hipEventRecord(e0, h->stream));
+            launch_bwd<double, double>(h, g, b);
+            HIPCHK(hipEventRecord(e1, h->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep) tb += ms;
+        }
+        if (tf < best_f) { best_f = tf; gf = g; }
+        if (tb < best_b) { best_b = tb; gb = g; }
+    }
+    (void)save_f; (void)save_b;
+    h->GJ = gf;
+    h->GJt = gb;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {gf, gb};
 }
 
 // One PCG solve of K dx = rhs (rhs = mu*rhs_a + rhs_b when rhs_a is given, mu
@@ -799,6 +870,7 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         }
         if (h->set.precision != QP_FP64) ensure_lowp(h, h->set.precision);
         HIPCHK(hipStreamSynchronize(h->stream));
+        autotune_schedule(h);
     } catch (const HipError& he) {
         g_create_error = std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e);
         delete h;
@@ -1089,6 +1161,56 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
     if (st == QP_ERR_NUMERIC) h->err = "PCG breakdown";
     else if (st == QP_ERR_NOT_CONVERGED) h->err = "IPM reached max_ipm_iter";
     return st;
+}
+
+qp_status qp_solve_batch(qp_handle* const* hs, int32_t count, double* const* xs, qp_info* infos) {
+    g_create_error.clear();
+    if (count < 0 || (count > 0 && (!hs || !xs))) {
+        g_create_error = "qp_solve_batch: NULL array or negative count";
+        return QP_ERR_INVALID;
+    }
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i] || !xs[i]) {
+            g_create_error = "qp_solve_batch: NULL handle or output at index " + std::to_string(i);
+            return QP_ERR_INVALID;
+        }
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) {
+                g_create_error = "qp_solve_batch: a handle appears twice";
+                return QP_ERR_INVALID;
+            }
+    }
+    if (count == 0) return QP_OK;
+    // largest problems first, so the tail of the batch is short
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return hs[a]->nnzJ + hs[a]->nnzA > hs[b]->nnzJ + hs[b]->nnzA;
+    });
+    int workers = 4;   // one per hardware queue of the device by default
+    if (const char* e = std::getenv("QPGPU_BATCH_WORKERS")) workers = std::max(1, std::atoi(e));
+    workers = std::min(workers, count);
+    std::vector<qp_status> st(count, QP_OK);
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        while (true) {
+            const int q = next.fetch_add(1);
+            if (q >= count) break;
+            const int i = order[q];
+            (void)hipSetDevice(hs[i]->device);
+            qp_info inf{};
+            st[i] = qp_solve(hs[i], xs[i], nullptr, nullptr, &inf);
+            if (infos) infos[i] = inf;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int w = 1; w < workers; ++w) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+    qp_status worst = QP_OK;
+    for (int i = 0; i < count; ++i)
+        if (st[i] != QP_OK && (worst == QP_OK || st[i] == QP_ERR_DEVICE)) worst = st[i];
+    return worst;
 }
 
 }  // extern "C"

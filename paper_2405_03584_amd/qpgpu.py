@@ -61,7 +61,7 @@ class qp_info(C.Structure):
 
 
 EXPORTS = ["qp_default_settings", "qp_create", "qp_solve", "qp_newton_step", "qp_operator_apply",
-           "qp_last_error", "qp_destroy", "qp_sizes"]
+           "qp_solve_batch", "qp_last_error", "qp_destroy", "qp_sizes"]
 
 _lib = None
 
@@ -87,6 +87,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qp_operator_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int32, C.c_int32,
                                       C.POINTER(qp_info)]
     lib.qp_operator_apply.restype = C.c_int
+    lib.qp_solve_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(_dp), C.POINTER(qp_info)]
+    lib.qp_solve_batch.restype = C.c_int
     lib.qp_last_error.argtypes = [C.c_void_p]
     lib.qp_last_error.restype = C.c_char_p
     lib.qp_destroy.argtypes = [C.c_void_p]
@@ -223,6 +225,21 @@ def qp_solve(h: QPHandle, raise_on_error: bool = False) -> SolveResult:
     if raise_on_error and st not in (QP_OK,):
         raise QPError(st, h.last_error())
     return SolveResult(st, x, lA[:h.m], lx, info.as_dict())
+
+
+def qp_solve_batch(handles, raise_on_error: bool = False):
+    """Solve several handles together (qp_solve_batch).  Returns (status,
+    list of x arrays, list of info dicts)."""
+    lib = load_library()
+    count = len(handles)
+    hs = (C.c_void_p * count)(*[h._h for h in handles])
+    xs_np = [np.zeros(h.n) for h in handles]
+    xs = (_dp * count)(*[_ptr(x) for x in xs_np])
+    infos = (qp_info * count)()
+    st = lib.qp_solve_batch(hs, count, xs, infos)
+    if raise_on_error and st != QP_OK:
+        raise QPError(st, lib.qp_last_error(None).decode())
+    return st, xs_np, [infos[i].as_dict() for i in range(count)]
 
 
 def qp_newton_step(h: QPHandle, sigma_x, sigma_A, rhs):

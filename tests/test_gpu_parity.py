@@ -350,3 +350,88 @@ def test_solve_config5_scaled(prec):
     assert abs(res.info["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
     cert = oracle.kkt_certificate(prob, res.x, res.lam_x, res.lam_A)
     assert cert.worst() <= 1e-9, cert
+
+
+# ----------------------------------------------------------------------------
+# line format of J (64-row lines sharing a column list) vs CSR
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_line_format_operator_matches_csr(prec):
+    prob = qpsynth.config2(scale=0.02)
+    it = qpsynth.random_iterate(prob, 41)
+    hl = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(spmv_format=0))
+    hc = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(spmv_format=1))
+    yl, il = qpgpu.qp_operator_apply(hl, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
+    yc, ic = qpgpu.qp_operator_apply(hc, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
+    assert il["spmv_format"] == 1 and ic["spmv_format"] == 0
+    ref = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"]) @ it["v"]
+    bound = _abs_op(prob, it["sigma_x"], it["sigma_A"]) @ np.abs(it["v"])
+    unit = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16": 2.0 ** -8}[prec]
+    Lj = np.diff(prob.J.indptr).max()
+    Lt = np.diff(prob.J.tocsc().indptr).max()
+    acc = 2.0 ** -53 if prec == "fp64" else 2.0 ** -24
+    c = 2 * unit + (Lj + Lt + 2) * acc + 1e-13
+    assert np.all(np.abs(yl - ref) <= c * bound)
+    assert np.all(np.abs(yc - ref) <= c * bound)
+
+
+def test_config1_uses_csr():
+    prob = qpsynth.config1(0)
+    it = qpsynth.random_iterate(prob, 2)
+    h = qpgpu.qp_create_from_problem(prob)
+    _, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"])
+    assert info["spmv_format"] == 0
+
+
+def test_solve_band_csr_and_line_agree():
+    prob = qpsynth.config2(scale=0.02)
+    hl = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(spmv_format=0))
+    hc = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(spmv_format=1))
+    a, b = qpgpu.qp_solve(hl), qpgpu.qp_solve(hc)
+    assert a.status == b.status == qpgpu.QP_OK
+    assert np.abs(a.x - b.x).max() <= 1e-6 * (1 + np.abs(a.x).max())
+
+
+# ----------------------------------------------------------------------------
+# batched solves (a10): many uneven QPs through qp_solve_batch
+# ----------------------------------------------------------------------------
+
+def _batch_members():
+    sizes = qpsynth.config4_sizes()
+    small = [int(i) for i in np.argsort(sizes)[:2]]
+    return ([qpsynth.config4_instance(i) for i in small]
+            + [qpsynth.config1(i) for i in range(3)]
+            + [qpsynth.config2(scale=0.02), qpsynth.tiny(12)])
+
+
+def test_solve_batch_matches_single_solves():
+    probs = _batch_members()
+    print("batch of", [p.name for p in probs], flush=True)
+    hs = [qpgpu.qp_create_from_problem(p) for p in probs]
+    st, xs, infos = qpgpu.qp_solve_batch(hs)
+    assert st == qpgpu.QP_OK, [i["status"] for i in infos]
+    for p, h, x, inf in zip(probs, hs, xs, infos):
+        single = qpgpu.qp_solve(h)
+        assert single.status == qpgpu.QP_OK
+        assert x.tobytes() == single.x.tobytes(), p.name
+        assert inf["ipm_iters"] == single.info["ipm_iters"]
+
+
+def test_solve_batch_config4_members_vs_oracle():
+    sizes = qpsynth.config4_sizes()
+    idx = [int(i) for i in np.argsort(sizes)[:2]]
+    probs = [qpsynth.config4_instance(i) for i in idx]
+    hs = [qpgpu.qp_create_from_problem(p, settings=qpgpu.qp_default_settings(precision="fp32")) for p in probs]
+    st, xs, infos = qpgpu.qp_solve_batch(hs)
+    assert st == qpgpu.QP_OK
+    for p, x, inf in zip(probs, xs, infos):
+        ref = oracle.solve(p)
+        assert np.abs(x - ref.x).max() <= 1e-5, p.name
+        assert abs(inf["objective"] - ref.objective) <= 1e-6 * abs(ref.objective)
+
+
+def test_solve_batch_rejects_repeated_handle():
+    h = qpgpu.qp_create_from_problem(qpsynth.config1(0))
+    st, _, _ = qpgpu.qp_solve_batch([h, h])
+    assert st == qpgpu.QP_ERR_INVALID
