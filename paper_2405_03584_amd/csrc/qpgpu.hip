@@ -359,22 +359,19 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
                        (const int*)h->rpos, (const int*)h->ridx, k, ld, h->Sm, stop);
     HIPCHK(hipGetLastError());
     for (int b = 0; b < T; ++b) {
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, h->stream, h->Sm, ld, b, h->Linv, stop);
-        const int rest = T - b - 1;
-        if (rest > 0) {
-            hipLaunchKernelGGL(k_chol_panel, dim3(rest), dim3(256), 0, h->stream, h->Sm, ld, b,
-                               (const double*)h->Linv, stop);
-            hipLaunchKernelGGL(k_chol_update, dim3(rest, rest), dim3(256), 0, h->stream, h->Sm, ld, b, stop);
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, h->stream, h->Sm, ld, b, h->Linv, stop);
+        if (T > 1) {
+            hipLaunchKernelGGL(k_gj_row, dim3(T), dim3(256), 0, h->stream, h->Sm, ld, b, (const double*)h->Linv, stop);
+            hipLaunchKernelGGL(k_gj_update, dim3(T, T), dim3(256), 0, h->stream, h->Sm, ld, b, stop);
+            hipLaunchKernelGGL(k_gj_col, dim3(T), dim3(256), 0, h->stream, h->Sm, ld, b, (const double*)h->Linv, stop);
         }
     }
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_trinv_diag, dim3(T), dim3(256), 0, h->stream, (const double*)h->Linv, ld, T, h->Xm,
-                       stop);
-    for (int i = 1; i < T; ++i)
-        hipLaunchKernelGGL(k_trinv_row, dim3(i), dim3(256), 0, h->stream, (const double*)h->Sm, ld, i,
-                           (const double*)h->Linv, h->Xm, stop);
-    hipLaunchKernelGGL(k_inv_product, dim3(T, T), dim3(256), 0, h->stream, (const double*)h->Xm, ld, T, h->Sinv,
-                       stop);
+    {
+        const size_t N = size_t(ld) * ld;
+        const int g = int(std::min<size_t>((N + 255) / 256, 4096));
+        hipLaunchKernelGGL(k_symmetrize, dim3(g), dim3(256), 0, h->stream, (const double*)h->Sm, ld, h->Sinv, stop);
+    }
     HIPCHK(hipGetLastError());
     return true;
 }
@@ -833,9 +830,8 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
             } else {
                 const size_t mm = size_t(h->ld) * h->ld;
                 h->Sm = h->dalloc<double>(mm);
-                h->Xm = h->dalloc<double>(mm);
                 h->Sinv = h->dalloc<double>(mm);
-                h->Linv = h->dalloc<double>(size_t(h->T) * TS * TS);
+                h->Linv = h->dalloc<double>(size_t(TS) * TS);   // pivot tile inverse of the sweep
                 h->wpre = h->dalloc<double>(h->ld);
                 h->vpre = h->dalloc<double>(std::max(h->ld, m));
                 h->Dw = h->dalloc<double>(n);

@@ -11,10 +11,9 @@
 //   P^{-1} r = D^{-1} r - D^{-1} A^T Sigma^{1/2} S^{-1} Sigma^{1/2} A D^{-1} r,
 //   S = I + Sigma^{1/2} A D^{-1} A^T Sigma^{1/2}        (m x m, SPD, eigenvalues >= 1)
 //
-// (Sherman-Morrison-Woodbury).  S is formed densely without atomics, factored
-// by a blocked Cholesky (its pivots cannot drop below 1), inverted through the
-// triangular inverse, and applied as one dense symmetric matrix-vector product
-// per PCG iteration.  Only the "strong" rows of A enter the dense block: a
+// (Sherman-Morrison-Woodbury).  S is formed densely without atomics, inverted
+// in place by a block Gauss-Jordan sweep (its pivots cannot drop below 1), and
+// applied as one dense symmetric matrix-vector product per PCG iteration.  Only the "strong" rows of A enter the dense block: a
 // row i with M_ii = Sigma_i sum_j A_ij^2 / D_j below 1 changes P little and is
 // folded into the Jacobi diagonal instead (D_j += Sigma_i A_ij^2), so the
 // dense block has k <= m rows, about the number of active constraints late in
@@ -136,191 +135,128 @@ __global__ __launch_bounds__(64) void k_schur_form(const int* __restrict__ Ap, c
     }
 }
 
-// ---- blocked Cholesky S = L L^T, L overwriting the lower triangle -------------
+// ---- in-place inverse by a block Gauss-Jordan sweep ------------------------------
+//
+// For each pivot tile b (TS x TS):  S_bb <- S_bb^{-1};  S_bj <- S_bb^{-1} S_bj;
+// S_ij <- S_ij - S_ib S_bj;  S_ib <- -S_ib S_bb^{-1}  (i, j != b).  After the
+// last pivot S holds S^{-1}.  Every pivot is a Schur complement of S, and S has
+// eigenvalues >= 1, so every pivot tile has eigenvalues >= 1: no pivoting is
+// needed.  Each step is one small single-workgroup inversion and three fully
+// parallel tile launches, so the serial depth is T = ld/TS steps.
 
-// Diagonal tile b: unblocked Cholesky in LDS, then its inverse (forward
-// substitution on the identity), stored in Linv[b].
-__global__ __launch_bounds__(256) void k_chol_diag(double* S, int ld, int b, double* Linv, const int* stop) {
-    __shared__ double a[TS][TS + 1];
-    __shared__ double x[TS][TS + 1];
-    if (stop && *stop) return;
+// C (TS x TS, in registers: element e = t + 256q) = A * B for LDS tiles.
+__device__ __forceinline__ void tile_mm(const double (*a)[TS + 1], const double (*b)[TS + 1], double out[4]) {
     const int t = threadIdx.x;
-    const size_t base = size_t(b) * TS * ld + size_t(b) * TS;
-    for (int e = t; e < TS * TS; e += 256) a[e / TS][e % TS] = S[base + size_t(e / TS) * ld + e % TS];
-    __syncthreads();
-    for (int j = 0; j < TS; ++j) {
-        if (t == 0) {
-            const double d = a[j][j];
-            // S has eigenvalues >= 1, so d >= 1 in exact arithmetic; the
-            // guard only keeps a rounding accident from producing NaN.
-            a[j][j] = (d > 0.0 && __builtin_isfinite(d)) ? sqrt(d) : 1.0;
-        }
-        __syncthreads();
-        if (t > j && t < TS) a[t][j] /= a[j][j];
-        __syncthreads();
-        for (int e = t; e < TS * TS; e += 256) {
-            const int r = e / TS, c = e % TS;
-            if (c > j && r >= c) a[r][c] -= a[r][j] * a[c][j];
-        }
-        __syncthreads();
-    }
-    if (t < TS) {
-        const int c = t;
-        for (int r = 0; r < TS; ++r) {
-            if (r < c) {
-                x[r][c] = 0.0;
-            } else {
-                double s = (r == c) ? 1.0 : 0.0;
-                for (int k = c; k < r; ++k) s -= a[r][k] * x[k][c];
-                x[r][c] = s / a[r][r];
-            }
-        }
-    }
-    __syncthreads();
-    for (int e = t; e < TS * TS; e += 256) {
-        const int r = e / TS, c = e % TS;
-        S[base + size_t(r) * ld + c] = (c <= r) ? a[r][c] : 0.0;
-        Linv[size_t(b) * TS * TS + e] = x[r][c];
-    }
-}
-
-// Panel: L_ib = S_ib L_bb^{-T} for row tiles i = b+1+blockIdx.x.
-__global__ __launch_bounds__(256) void k_chol_panel(double* S, int ld, int b, const double* Linv, const int* stop) {
-    __shared__ double a[TS][TS + 1];
-    __shared__ double v[TS][TS + 1];
-    if (stop && *stop) return;
-    const int i = b + 1 + blockIdx.x;
-    const int t = threadIdx.x;
-    const size_t base = size_t(i) * TS * ld + size_t(b) * TS;
-    for (int e = t; e < TS * TS; e += 256) {
-        a[e / TS][e % TS] = S[base + size_t(e / TS) * ld + e % TS];
-        v[e / TS][e % TS] = Linv[size_t(b) * TS * TS + e];
-    }
-    __syncthreads();
-    for (int e = t; e < TS * TS; e += 256) {
-        const int r = e / TS, c = e % TS;
-        double s = 0.0;
-        for (int k = 0; k <= c; ++k) s += a[r][k] * v[c][k];   // (L^-T)_{kc} = Linv_{ck}, zero for k > c
-        S[base + size_t(r) * ld + c] = s;
-    }
-}
-
-// Trailing update S_ij -= L_ib L_jb^T for b < j <= i.
-__global__ __launch_bounds__(256) void k_chol_update(double* S, int ld, int b, const int* stop) {
-    __shared__ double li[TS][TS + 1];
-    __shared__ double lj[TS][TS + 1];
-    if (stop && *stop) return;
-    const int i = b + 1 + blockIdx.x, j = b + 1 + blockIdx.y;
-    if (j > i) return;
-    const int t = threadIdx.x;
-    const size_t bi = size_t(i) * TS * ld + size_t(b) * TS;
-    const size_t bj = size_t(j) * TS * ld + size_t(b) * TS;
-    for (int e = t; e < TS * TS; e += 256) {
-        li[e / TS][e % TS] = S[bi + size_t(e / TS) * ld + e % TS];
-        lj[e / TS][e % TS] = S[bj + size_t(e / TS) * ld + e % TS];
-    }
-    __syncthreads();
-    const size_t out = size_t(i) * TS * ld + size_t(j) * TS;
-    for (int e = t; e < TS * TS; e += 256) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = t + 256 * q;
         const int r = e / TS, c = e % TS;
         double s = 0.0;
 #pragma unroll 8
-        for (int k = 0; k < TS; ++k) s += li[r][k] * lj[c][k];
-        S[out + size_t(r) * ld + c] -= s;
+        for (int k = 0; k < TS; ++k) s += a[r][k] * b[k][c];
+        out[q] = s;
     }
 }
 
-// ---- inverse: X = L^{-1} (lower), then S^{-1} = X^T X ---------------------------
+__device__ __forceinline__ void tile_load(double (*dst)[TS + 1], const double* S, int ld, int ti, int tj) {
+    const size_t base = size_t(ti) * TS * ld + size_t(tj) * TS;
+    for (int e = threadIdx.x; e < TS * TS; e += 256) dst[e / TS][e % TS] = S[base + size_t(e / TS) * ld + e % TS];
+}
 
-// Row tile i of X: X_ib = -L_ii^{-1} sum_{k=b}^{i-1} L_ik X_kb for b = blockIdx.x < i.
-// The diagonal tiles X_bb = L_bb^{-1} are written by k_trinv_diag.
-__global__ __launch_bounds__(256) void k_trinv_row(const double* S, int ld, int i, const double* Linv,
-                                                   double* X, const int* stop) {
-    __shared__ double l[TS][TS + 1];
-    __shared__ double xk[TS][TS + 1];
+// Pivot tile b: Gauss-Jordan inversion of S_bb in LDS (one thread per entry),
+// written back to S_bb and to P.
+__global__ __launch_bounds__(1024) void k_gj_pivot(double* S, int ld, int b, double* P, const int* stop) {
+    __shared__ double a[TS][TS + 1];
     if (stop && *stop) return;
-    const int b = blockIdx.x;
-    const int t = threadIdx.x;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = b; k < i; ++k) {
-        __syncthreads();
-        const size_t sl = size_t(i) * TS * ld + size_t(k) * TS;
-        const size_t sx = size_t(k) * TS * ld + size_t(b) * TS;
-        for (int e = t; e < TS * TS; e += 256) {
-            l[e / TS][e % TS] = S[sl + size_t(e / TS) * ld + e % TS];
-            xk[e / TS][e % TS] = X[sx + size_t(e / TS) * ld + e % TS];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = t + 256 * q;
-            const int r = e / TS, c = e % TS;
-            double s = 0.0;
-            for (int kk = 0; kk < TS; ++kk) s += l[r][kk] * xk[kk][c];
-            acc[q] += s;
-        }
-    }
+    const int r = threadIdx.x / TS, c = threadIdx.x % TS;
+    const size_t base = size_t(b) * TS * ld + size_t(b) * TS;
+    a[r][c] = S[base + size_t(r) * ld + c];
     __syncthreads();
-    // y -> LDS, then X_ib = -Linv_ii * y
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = t + 256 * q;
-        xk[e / TS][e % TS] = acc[q];
-        l[e / TS][e % TS] = Linv[size_t(i) * TS * TS + e];
+    for (int j = 0; j < TS; ++j) {
+        const double pv = a[j][j];
+        const double f = a[r][j];
+        const double ajc = a[j][c];
+        __syncthreads();
+        // pivots are >= 1 in exact arithmetic; the guard keeps a rounding
+        // accident from spreading NaN through the preconditioner
+        const double pinv = (pv > 0.0 && __builtin_isfinite(pv)) ? 1.0 / pv : 1.0;
+        const double rowj = (c == j) ? pinv : ajc * pinv;
+        if (r == j) a[r][c] = rowj;
+        else a[r][c] = (c == j) ? -f * pinv : a[r][c] - f * rowj;
+        __syncthreads();
     }
+    S[base + size_t(r) * ld + c] = a[r][c];
+    P[size_t(r) * TS + c] = a[r][c];
+}
+
+// Row panel: S_bj <- P S_bj for j != b.
+__global__ __launch_bounds__(256) void k_gj_row(double* S, int ld, int b, const double* P, const int* stop) {
+    __shared__ double pa[TS][TS + 1];
+    __shared__ double sb[TS][TS + 1];
+    if (stop && *stop) return;
+    const int j = blockIdx.x;
+    if (j == b) return;
+    for (int e = threadIdx.x; e < TS * TS; e += 256) pa[e / TS][e % TS] = P[e];
+    tile_load(sb, S, ld, b, j);
     __syncthreads();
-    const size_t ox = size_t(i) * TS * ld + size_t(b) * TS;
+    double out[4];
+    tile_mm(pa, sb, out);
+    const size_t base = size_t(b) * TS * ld + size_t(j) * TS;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int e = t + 256 * q;
-        const int r = e / TS, c = e % TS;
-        double s = 0.0;
-        for (int kk = 0; kk <= r; ++kk) s += l[r][kk] * xk[kk][c];
-        X[ox + size_t(r) * ld + c] = -s;
+        const int e = threadIdx.x + 256 * q;
+        S[base + size_t(e / TS) * ld + e % TS] = out[q];
     }
 }
 
-__global__ __launch_bounds__(256) void k_trinv_diag(const double* Linv, int ld, int T, double* X, const int* stop) {
+// Trailing update: S_ij <- S_ij - S_ib S_bj for i, j != b (S_bj already new).
+__global__ __launch_bounds__(256) void k_gj_update(double* S, int ld, int b, const int* stop) {
+    __shared__ double sib[TS][TS + 1];
+    __shared__ double sbj[TS][TS + 1];
     if (stop && *stop) return;
-    const int b = blockIdx.x;
-    if (b >= T) return;
-    for (int e = threadIdx.x; e < TS * TS; e += 256)
-        X[size_t(b) * TS * ld + size_t(b) * TS + size_t(e / TS) * ld + e % TS] = Linv[size_t(b) * TS * TS + e];
-}
-
-// Sinv tile (I, J), J <= I: sum_{K >= I} X_KI^T X_KJ; written to (I,J) and (J,I).
-__global__ __launch_bounds__(256) void k_inv_product(const double* X, int ld, int T, double* Sinv, const int* stop) {
-    __shared__ double xi[TS][TS + 1];
-    __shared__ double xj[TS][TS + 1];
-    if (stop && *stop) return;
-    const int I = blockIdx.x, J = blockIdx.y;
-    if (J > I) return;
-    const int t = threadIdx.x;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int K = I; K < T; ++K) {
-        __syncthreads();
-        const size_t a = size_t(K) * TS * ld + size_t(I) * TS;
-        const size_t c = size_t(K) * TS * ld + size_t(J) * TS;
-        for (int e = t; e < TS * TS; e += 256) {
-            xi[e / TS][e % TS] = X[a + size_t(e / TS) * ld + e % TS];
-            xj[e / TS][e % TS] = X[c + size_t(e / TS) * ld + e % TS];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = t + 256 * q;
-            const int r = e / TS, cc = e % TS;
-            double s = 0.0;
-            for (int k = 0; k < TS; ++k) s += xi[k][r] * xj[k][cc];
-            acc[q] += s;
-        }
-    }
+    const int i = blockIdx.y, j = blockIdx.x;
+    if (i == b || j == b) return;
+    tile_load(sib, S, ld, i, b);
+    tile_load(sbj, S, ld, b, j);
+    __syncthreads();
+    double out[4];
+    tile_mm(sib, sbj, out);
+    const size_t base = size_t(i) * TS * ld + size_t(j) * TS;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int e = t + 256 * q;
-        const int r = e / TS, c = e % TS;
-        Sinv[(size_t(I) * TS + r) * ld + size_t(J) * TS + c] = acc[q];
-        if (I != J) Sinv[(size_t(J) * TS + c) * ld + size_t(I) * TS + r] = acc[q];
+        const int e = threadIdx.x + 256 * q;
+        S[base + size_t(e / TS) * ld + e % TS] -= out[q];
+    }
+}
+
+// Column panel: S_ib <- -S_ib P for i != b (after the trailing update).
+__global__ __launch_bounds__(256) void k_gj_col(double* S, int ld, int b, const double* P, const int* stop) {
+    __shared__ double sib[TS][TS + 1];
+    __shared__ double pa[TS][TS + 1];
+    if (stop && *stop) return;
+    const int i = blockIdx.x;
+    if (i == b) return;
+    tile_load(sib, S, ld, i, b);
+    for (int e = threadIdx.x; e < TS * TS; e += 256) pa[e / TS][e % TS] = P[e];
+    __syncthreads();
+    double out[4];
+    tile_mm(sib, pa, out);
+    const size_t base = size_t(i) * TS * ld + size_t(b) * TS;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        S[base + size_t(e / TS) * ld + e % TS] = -out[q];
+    }
+}
+
+// Sinv = (S + S^T)/2: the sweep's result is symmetric up to rounding; PCG
+// wants an exactly symmetric preconditioner.
+__global__ __launch_bounds__(256) void k_symmetrize(const double* S, int ld, double* Sinv, const int* stop) {
+    if (stop && *stop) return;
+    const size_t N = size_t(ld) * ld;
+    for (size_t e = size_t(blockIdx.x) * 256 + threadIdx.x; e < N; e += size_t(gridDim.x) * 256) {
+        const size_t r = e / ld, c = e % ld;
+        Sinv[e] = 0.5 * (S[e] + S[c * ld + r]);
     }
 }
 
