@@ -132,6 +132,42 @@ def operator_only(args, prob):
                       "checksum": float(np.abs(y).sum())}), flush=True)
 
 
+def batch_bench(args):
+    """The uneven batch: `count` members of the 64-QP set, created once, then
+    solved together (qp_solve_batch) per step."""
+    import qpsynth
+    from paper_2405_03584_amd import qpgpu
+    t0 = time.perf_counter()
+    probs = [qpsynth.config4_instance(i) for i in range(args.count)]
+    nnz = sum(int(p.J.nnz) for p in probs)
+    print(f"[bench] generated {len(probs)} QPs, n in [{min(p.n for p in probs)}, {max(p.n for p in probs)}], "
+          f"{nnz} nnz of J in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    st = qpgpu.qp_default_settings(precision=args.precision)
+    hs = [qpgpu.qp_create_from_problem(p, settings=st) for p in probs]
+    print(f"[bench] created handles", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        s, xs, infos = qpgpu.qp_solve_batch(hs)
+        print(f"[bench] warmup {i}: status={s}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    all_infos = []
+    for i in range(args.steps):
+        s, xs, infos = qpgpu.qp_solve_batch(hs)
+        all_infos += infos
+        print(f"[bench] step {i}: status={s} pcg={sum(f['pcg_iters'] for f in infos)}", file=sys.stderr, flush=True)
+    el = time.perf_counter() - t0
+    ok = all(f["status"] == qpgpu.QP_OK for f in all_infos)
+    print(json.dumps({"metric": METRIC, "value": args.count * args.steps / el, "unit": "QP/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": args.precision, "data": "synthetic",
+                      "config": {"workload": f"batch of {args.count} uneven banded-dose QPs "
+                                             f"(n in [2000, 20000], {nnz} nnz of J in all)",
+                                 "precision": args.precision},
+                      "status_ok": ok,
+                      "ipm_iters_total": sum(f["ipm_iters"] for f in all_infos),
+                      "pcg_iters_total": sum(f["pcg_iters"] for f in all_infos)}), flush=True)
+
+
 def copy_calibration(args):
     """A plain device-to-device copy of a known byte count with torch's copy
     kernel: what the HBM counters read for it calibrates the counter scale."""
@@ -161,6 +197,11 @@ def main():
                          "products only (for counter runs); copy: a plain device copy of the "
                          "J value+index bytes (counter calibration)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--workload", default="config2", choices=["config2", "config5", "batch"],
+                    help="config2: banded-dose QP n=20,000 (default, the benchmark line); config5: "
+                         "n=60,000, BF16-valued J with 200M nnz and a rank-20 term; batch: the 64 "
+                         "uneven QPs (n in [2000, 20000]) solved together by qp_solve_batch")
+    ap.add_argument("--count", type=int, default=64, help="batch size for --workload batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
@@ -172,8 +213,10 @@ def main():
 
     if args.mode == "copy":
         return copy_calibration(args)
+    if args.workload == "batch":
+        return batch_bench(args)
     t0 = time.perf_counter()
-    prob = qpsynth.config2(scale=args.scale)
+    prob = qpsynth.config5(scale=args.scale) if args.workload == "config5" else qpsynth.config2(scale=args.scale)
     if args.mode == "operator":
         return operator_only(args, prob)
     n, m, nJ = prob.n, prob.m, prob.J.shape[0]
@@ -222,7 +265,7 @@ def main():
 
     parity = None
     gold = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")
-    if args.scale == 1.0 and os.path.exists(gold):
+    if args.workload == "config2" and args.scale == 1.0 and os.path.exists(gold):
         g = json.load(open(gold))
         step = g["sample_index_step"]
         xs = np.array(g["x_sample"])
@@ -244,8 +287,9 @@ def main():
                   "bf16": "bf16 values, f32 accum, f64 scalars"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"banded-dose QP n={n} (J {nJ}x{n}, {nnzJ} nnz; A {m}x{n}, {nnzA} nnz; "
-                               f"bounds [0,50]; PCG tol 1e-8)", "precision": args.precision,
-                   "scale": args.scale},
+                               f"bounds [0,50]; PCG tol 1e-8"
+                               + (f"; rank-{prob.k} term; BF16-valued J" if prob.k else "") + ")",
+                   "precision": args.precision, "scale": args.scale},
         "time_to_solution_ms": 1e3 * elapsed / args.steps,
         "ipm_iters": infos[-1]["ipm_iters"],
         "pcg_iters_per_qp": pcg_iters / args.steps,
@@ -257,12 +301,13 @@ def main():
                  "csr_equivalent_bwd_GBs": cb / (bwd_us * 1e-6) / 1e9},
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": dom[3], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dom[3] / HBM_PEAK_GBS,
-                     "traffic": counter_traffic(dom[0].split()[0], args.precision) if args.scale == 1.0 else None,
+                     "traffic": (counter_traffic(dom[0].split()[0], args.precision)
+                                 if args.scale == 1.0 and args.workload == "config2" else None),
                      "bytes_per_launch": dom[1], "avg_launch_us": dom[2]},
         "create_s": t_create,
         "parity": parity,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "config2":
         print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
         iters = infos[-1]["ipm_iters"]
         if args.scale == 1.0 and os.path.exists(gold):

@@ -435,3 +435,21 @@ def test_solve_batch_rejects_repeated_handle():
     h = qpgpu.qp_create_from_problem(qpsynth.config1(0))
     st, _, _ = qpgpu.qp_solve_batch([h, h])
     assert st == qpgpu.QP_ERR_INVALID
+
+
+def test_solve_without_dose_rows_is_clipping():
+    """J with no rows: H = gamma*I, so x = clip(-p/gamma, lo, hi) (closed form)."""
+    import scipy.sparse as sps
+    rng = np.random.default_rng(17)
+    n = 300
+    p = rng.uniform(-0.02, 0.02, size=n)
+    lo = rng.uniform(-5, 0, size=n)
+    hi = lo + rng.uniform(0.5, 10, size=n)
+    lo[:20] = -np.inf
+    hi[20:40] = np.inf
+    prob = qpsynth.QPProblem(gamma=1e-3, p=p, J=sps.csr_matrix((0, n)), W=np.zeros(0), x_lo=lo, x_hi=hi)
+    h = qpgpu.qp_create_from_problem(prob)
+    res = qpgpu.qp_solve(h)
+    ref = np.clip(-p / 1e-3, lo, hi)
+    assert res.status == qpgpu.QP_OK
+    assert np.abs(res.x - ref).max() <= 1e-6 * (1 + np.abs(ref).max())
