@@ -176,21 +176,24 @@ __device__ __forceinline__ AT row_dot_lane(const int* __restrict__ ptr, const in
     AT acc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u] = AT(0);
+    if (b <= a) return AT(0);
+    // Indices past the row end are clamped to its last entry (a valid
+    // address) and their products zeroed, so every load of a pass is issued
+    // unconditionally, without branches between them.
     for (int k = a + lane; k < b; k += U * G) {
         int c[U];
         AT v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int kk = k + u * G;
-            const bool ok = kk < b;
-            c[u] = ok ? col[kk] : 0;
-            v[u] = ok ? cvt<AT>(val[kk]) : AT(0);
+            const int kk = min(k + u * G, b - 1);
+            c[u] = col[kk];
+            v[u] = cvt<AT>(val[kk]);
         }
         double xv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] += v[u] * AT(xv[u]);
+        for (int u = 0; u < U; ++u) acc[u] += (k + u * G < b) ? v[u] * AT(xv[u]) : AT(0);
     }
     AT s = acc[0];
 #pragma unroll

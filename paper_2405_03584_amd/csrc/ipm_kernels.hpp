@@ -803,9 +803,12 @@ __global__ __launch_bounds__(kBlock) void k_lr_partial(const double* U, int n, i
         for (int c = 0; c < 32; ++c)
             if (c < kc) acc[c] += U[j + size_t(n) * (c0 + c)] * pj;
     }
-    for (int c = 0; c < kc; ++c) {
-        const double t = block_sum(acc[c], sh);
-        if (threadIdx.x == 0) part[size_t(blockIdx.x) * k + c0 + c] = t;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {   // static indices keep acc in registers
+        if (c < kc) {                 // kc is uniform over the block
+            const double t = block_sum(acc[c], sh);
+            if (threadIdx.x == 0) part[size_t(blockIdx.x) * k + c0 + c] = t;
+        }
     }
 }
 

@@ -20,37 +20,52 @@ struct LineFwdArgs {
     const int* lptr; const int* lcol; const VT* lval; int L; const double* W;
     const int* Ap; const int* Ac; const double* Av; int m;
     const double* x; double* t; double* u; const double* sigA;
-    int nbL;               // blocks working on lines (4 lines per block)
+    int nbL;               // blocks working on lines (one line per block)
     const Flags* fl;
 };
 
-// t = W .* (J x) (a wavefront per line, lane = row) and u = Sigma_A .* (A x).
+// t = W .* (J x): a block per line, lane = row; the 4 wavefronts of the block
+// take contiguous quarters of the line's slots and their partial row sums are
+// added in a fixed order through LDS.  u = Sigma_A .* (A x): a wavefront per
+// row of A in the remaining blocks.
 template <typename VT, typename AT>
 __global__ __launch_bounds__(kBlock) void k_op_fwd_line(LineFwdArgs<VT> a) {
+    __shared__ AT part[kBlock / 64][64];
     if (pcg_stopped(a.fl)) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     if (b < a.nbL) {
-        const int l = __builtin_amdgcn_readfirstlane(b * (kBlock / 64) + (threadIdx.x >> 6));
-        if (l >= a.L) return;
+        const int l = b;
         const int off = a.lptr[l];
         const int len = a.lptr[l + 1] - off;
+        const int q = (len + 3) >> 2;
+        const int k0 = __builtin_amdgcn_readfirstlane(min(len, w * q));
+        const int k1 = __builtin_amdgcn_readfirstlane(min(len, k0 + q));
         const VT* v = a.lval + size_t(off) * 64 + lane;
         const int* c = a.lcol + off;
         AT acc[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc[u] = AT(0);
-        int k = 0;
-        for (; k + 8 <= len; k += 8) {
+        // passes of 8 slots; slots past k1 are clamped to k1-1 (valid address)
+        // and contribute 0, so each pass issues all its loads without branches
+        for (int k = k0; k < k1; k += 8) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += cvt<AT>(v[size_t(k + u) * 64]) * AT(a.x[c[k + u]]);
+            for (int u = 0; u < 8; ++u) {
+                const int kk = min(k + u, k1 - 1);
+                const AT prod = cvt<AT>(v[size_t(kk) * 64]) * AT(a.x[c[kk]]);
+                acc[u] += (k + u < k1) ? prod : AT(0);
+            }
         }
-        for (; k < len; ++k) acc[0] += cvt<AT>(v[size_t(k) * 64]) * AT(a.x[c[k]]);
-        const AT s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-        const int row = l * 64 + lane;
-        a.t[row] = a.W[row] * double(s);
+        part[w][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        __syncthreads();
+        if (w == 0) {
+            const AT s = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+            const int row = l * 64 + lane;
+            a.t[row] = a.W[row] * double(s);
+        }
     } else {
-        const int row = (b - a.nbL) * (kBlock / 64) + (threadIdx.x >> 6);
+        const int row = (b - a.nbL) * (kBlock / 64) + w;
         if (row < a.m) {
             double s = row_dot_lane<64, double, double>(a.Ap, a.Ac, a.Av, a.x, row, lane);
             s = group_sum<double, 64>(s);
@@ -86,22 +101,22 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd_line(LineBwdArgs<VT> a) {
         const int j = __builtin_amdgcn_readfirstlane(base + (threadIdx.x >> 6));
         if (j < a.n) {
             const int e0 = a.sptr[j], e1 = a.sptr[j + 1];
-            AT acc[8];
+            AT acc[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] = AT(0);
-            int e = e0;
-            for (; e + 8 <= e1; e += 8) {
+            for (int u = 0; u < 16; ++u) acc[u] = AT(0);
+            // passes of 16 pairs, tail clamped to the last pair and zeroed
+            for (int e = e0; e < e1; e += 16) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int l = a.sline[e + u], s = a.sslot[e + u];
-                    acc[u] += cvt<AT>(a.lval[size_t(s) * 64 + lane]) * AT(a.t[size_t(l) * 64 + lane]);
+                for (int u = 0; u < 16; ++u) {
+                    const int ee = min(e + u, e1 - 1);
+                    const int l = a.sline[ee], s = a.sslot[ee];
+                    const AT prod = cvt<AT>(a.lval[size_t(s) * 64 + lane]) * AT(a.t[size_t(l) * 64 + lane]);
+                    acc[u] += (e + u < e1) ? prod : AT(0);
                 }
             }
-            for (; e < e1; ++e) {
-                const int l = a.sline[e], s = a.sslot[e];
-                acc[0] += cvt<AT>(a.lval[size_t(s) * 64 + lane]) * AT(a.t[size_t(l) * 64 + lane]);
-            }
-            const AT sj = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+            AT sj = AT(0);
+#pragma unroll
+            for (int u = 0; u < 16; u += 2) sj += acc[u] + acc[u + 1];
             double s = a.hs * double(sj);
             if (a.hasA) s += row_dot_lane<64, double, double>(a.Atp, a.Atc, a.Atv, a.u, j, lane);
             if (a.lr_k) s += a.hs * lowrank_lane<64>(a.U, a.lr_v, a.lr_k, a.n, j, lane);

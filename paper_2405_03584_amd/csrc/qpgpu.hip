@@ -220,7 +220,7 @@ int apply_op_line(qp_handle* h, const double* p, double* q, const double* sigx, 
     f.lptr = h->lptr; f.lcol = h->lcol; f.lval = line_vals<VT>(h); f.L = h->L; f.W = h->W;
     f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
     f.x = p; f.t = h->t; f.u = h->u; f.sigA = sigA; f.fl = fl;
-    f.nbL = (h->L + 3) / 4;
+    f.nbL = h->L;
     const int nbA = f.m > 0 ? grid_rows(f.m, 64) : 0;
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
     hipLaunchKernelGGL((k_op_fwd_line<VT, AT>), dim3(std::max(1, f.nbL + nbA)), dim3(kBlock), 0, h->stream, f);
