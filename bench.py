@@ -31,16 +31,19 @@ def spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes=8, fmt=0):
 
     Each matrix value and index read once, row pointers once, every dense
     vector read or written once (gathered vectors counted once).  fmt = 0: CSR
-    (int32 column index per nonzero); fmt = 1: line format (one int32 column id
-    per 64-row line slot, and one (line, slot) int32 pair per slot for J^T)."""
+    (int32 column index per nonzero), a J pass and a J^T pass that each read
+    the values.  fmt = 1: line format, a line pass that reads the values once
+    (one int32 column id per 64-row line slot) and writes one double per slot,
+    then a spot pass that reads one int32 slot id and that double per slot."""
     if fmt == 1:
         slots = nnzJ // 64
         lines = nJ // 64
-        jf = nnzJ * vbytes + slots * 4 + (lines + 1) * 4
-        jb = nnzJ * vbytes + slots * 8 + (n + 1) * 4
-    else:
-        jf = nnzJ * (vbytes + 4) + (nJ + 1) * 4
-        jb = nnzJ * (vbytes + 4) + (n + 1) * 4
+        fwd = (nnzJ * vbytes + slots * 4 + (lines + 1) * 4 + nJ * 8 + n * 8 + slots * 8
+               + nnzA * 12 + (m + 1) * 4 + m * 8 + m * 8)
+        bwd = (n + 1) * 4 + slots * 4 + slots * 8 + nnzA * 12 + (n + 1) * 4 + m * 8 + n * 8 * 3
+        return fwd, bwd
+    jf = nnzJ * (vbytes + 4) + (nJ + 1) * 4
+    jb = nnzJ * (vbytes + 4) + (n + 1) * 4
     fwd = jf + n * 8 + nJ * 8 + nJ * 8 + nnzA * 12 + (m + 1) * 4 + m * 8 + m * 8
     bwd = jb + nJ * 8 + nnzA * 12 + (n + 1) * 4 + m * 8 + n * 8 * 3
     return fwd, bwd
@@ -259,9 +262,13 @@ def main():
     bwd_us = 1e3 * bwd_ms / max(nb, 1)
     gbs_f = bf / (fwd_us * 1e-6) / 1e9
     gbs_b = bb / (bwd_us * 1e-6) / 1e9
-    sfx = "_line" if fmt == 1 else ""
-    dom = (f"k_op_bwd{sfx} (J^T + A^T SpMV, fused epilogue and p.q partials)", bb, bwd_us, gbs_b) \
-        if bwd_us >= fwd_us else (f"k_op_fwd{sfx} (J + A SpMV, fused W / Sigma_A scaling)", bf, fwd_us, gbs_f)
+    if fmt == 1:
+        names = ("k_line_pass (J p, W scaling and per-slot J^T contributions from one read of J; A p)",
+                 "k_spot_pass (per-spot J^T sums, A^T u, epilogue and p.q partials)")
+    else:
+        names = ("k_op_fwd (J + A SpMV, fused W / Sigma_A scaling)",
+                 "k_op_bwd (J^T + A^T SpMV, fused epilogue and p.q partials)")
+    dom = (names[1], bb, bwd_us, gbs_b) if bwd_us >= fwd_us else (names[0], bf, fwd_us, gbs_f)
 
     parity = None
     gold = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")

@@ -28,19 +28,18 @@ constexpr int kMaxElemGrid = 2048;  // cap on grid-stride elementwise grids
 // --------------------------------------------------------------------------
 // scalar state shared by kernels (device memory)
 // --------------------------------------------------------------------------
+// PCG scalars.  Each field is written only by the last block of one kernel
+// (see last_block) and read by later kernels, never by the kernel writing it.
 struct PcgScal {
-    double rho;        // r^T z of the current iteration (K3 writes, K4 reads)
-    double rho_next;   // next r^T z (K4/init writes, K3 reads)
+    double rho;        // r^T z of the current z
+    double beta;       // p <- z + beta p, applied on the fly by the next product
+    double alpha;      // rho / p^T q
+    double pq;         // p^T q
     double bnorm2;     // ||rhs||^2
     double tol2;       // pcg_tol^2 * ||rhs||^2
     double rr;         // ||r||^2 after the last update
-    double alpha;
     int32_t iters;
-    int32_t converged;
-    int32_t breakdown;
-    int32_t capped;
     int32_t max_iter;
-    int32_t pad;
 };
 
 struct IpmScal {
@@ -144,11 +143,46 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
     return s;
 }
 
+// Called by every participating block after its thread 0 stored the block's
+// partial(s); `blocks` is the number of participating blocks.  Returns true in
+// exactly one block, the last to arrive, after which every partial is
+// visible to it; that block reduces them in a fixed order (so the result does
+// not depend on arrival order) and must reset the counter to 0 for the next
+// kernel.  The ticket is a device-scope atomic add in global memory.
+__device__ __forceinline__ bool last_block(unsigned* counter, unsigned blocks) {
+    __shared__ int s_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(counter, 1u) == blocks - 1) ? 1 : 0;
+    __syncthreads();
+    const bool last = s_last != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// Gathered vector of a product: x, or (PCG) the search direction z + beta p
+// formed on the fly from the last z and the previous p.
+struct Gather {
+    const double* x;
+    const double* p2;   // null: plain x
+    double beta;
+    __device__ __forceinline__ double operator()(int c) const { return p2 ? x[c] + beta * p2[c] : x[c]; }
+};
+
 // Reduce `count` per-block partials (stride `stride` between them) in a fixed
-// order; every block that calls this gets the identical value.
+// order; every block that calls this gets the identical value.  Thread t adds
+// partials t, t+B, t+2B, ... in increasing order; each pass issues 8 loads at
+// once (indices past the end clamped and their values dropped) so a long
+// list costs one memory latency per 8B partials.
 __device__ __forceinline__ double reduce_partials_sum(const double* part, int count, int stride, double* sh) {
     double v = 0.0;
-    for (int i = threadIdx.x; i < count; i += kBlock) v += part[size_t(i) * stride];
+    for (int i = threadIdx.x; i < count; i += 8 * kBlock) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = part[size_t(min(i + u * kBlock, count - 1)) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += (i + u * kBlock < count) ? t[u] : 0.0;
+    }
     return block_sum(v, sh);
 }
 __device__ __forceinline__ double reduce_partials_max(const double* part, int count, int stride, double* sh) {
@@ -162,16 +196,15 @@ __device__ __forceinline__ double reduce_partials_min(const double* part, int co
     return block_min(v, sh);
 }
 
-// Dot product of CSR row `row` with x by a group of G lanes (lane in [0,G)).
-// Each pass lets every lane issue U index/value loads at once (predicated
+// Dot product of CSR row `row` with a gathered vector by a group of G lanes (lane in [0,G)).
+// Each pass lets every lane issue U index/value loads at once (clamped
 // past the row end), then U gathers, so a row costs about one index latency
 // plus one gather latency per U*G entries instead of one per entry; U
 // independent accumulators are combined in a fixed order.  The group sum is
 // done by the caller.
-template <int G, typename VT, typename AT, int U = 4>
-__device__ __forceinline__ AT row_dot_lane(const int* __restrict__ ptr, const int* __restrict__ col,
-                                           const VT* __restrict__ val, const double* __restrict__ x,
-                                           int row, int lane) {
+template <int G, typename VT, typename AT, int U = 4, typename GV>
+__device__ __forceinline__ AT row_dot_lane_g(const int* __restrict__ ptr, const int* __restrict__ col,
+                                             const VT* __restrict__ val, const GV& x, int row, int lane) {
     const int a = ptr[row], b = ptr[row + 1];
     AT acc[U];
 #pragma unroll
@@ -191,13 +224,116 @@ __device__ __forceinline__ AT row_dot_lane(const int* __restrict__ ptr, const in
         }
         double xv[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+        for (int u = 0; u < U; ++u) xv[u] = x(c[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) acc[u] += (k + u * G < b) ? v[u] * AT(xv[u]) : AT(0);
     }
     AT s = acc[0];
 #pragma unroll
     for (int u = 1; u < U; ++u) s += acc[u];
+    return s;
+}
+
+template <int G, typename VT, typename AT, int U = 4>
+__device__ __forceinline__ AT row_dot_lane(const int* __restrict__ ptr, const int* __restrict__ col,
+                                           const VT* __restrict__ val, const double* __restrict__ x,
+                                           int row, int lane) {
+    const Gather g{x, nullptr, 0.0};
+    return row_dot_lane_g<G, VT, AT, U>(ptr, col, val, g, row, lane);
+}
+
+// Sum of val[idx[e]] over e in [ptr[row], ptr[row+1]) by a group of G lanes,
+// U loads per lane in flight per pass (clamped past the end, as above).
+template <int G, int U = 4>
+__device__ __forceinline__ double index_sum_lane(const int* __restrict__ ptr, const int* __restrict__ idx,
+                                                 const double* __restrict__ val, int row, int lane) {
+    const int a = ptr[row], b = ptr[row + 1];
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+    if (b <= a) return 0.0;
+    for (int k = a + lane; k < b; k += U * G) {
+        int c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = idx[min(k + u * G, b - 1)];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = val[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += (k + u * G < b) ? v[u] : 0.0;
+    }
+    double s = acc[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u) s += acc[u];
+    return s;
+}
+
+// Cross-lane half swaps of CDNA4: permlane32_swap exchanges lanes 32..63 of
+// x with lanes 0..31 of y; permlane16_swap exchanges the odd 16-lane rows of x
+// with the even rows of y.  Doubles move as two 32-bit halves.
+template <int M>
+__device__ __forceinline__ void lane_swap(float& x, float& y) {
+    static_assert(M == 32 || M == 16, "half swaps exist for masks 32 and 16");
+    const auto r = (M == 32) ? __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false)
+                             : __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    x = __uint_as_float(r[0]);
+    y = __uint_as_float(r[1]);
+}
+template <int M>
+__device__ __forceinline__ void lane_swap(double& x, double& y) {
+    float xl = __int_as_float(__double2loint(x)), xh = __int_as_float(__double2hiint(x));
+    float yl = __int_as_float(__double2loint(y)), yh = __int_as_float(__double2hiint(y));
+    lane_swap<M>(xl, yl);
+    lane_swap<M>(xh, yh);
+    x = __hiloint2double(__float_as_int(xh), __float_as_int(xl));
+    y = __hiloint2double(__float_as_int(yh), __float_as_int(yl));
+}
+
+// Reduce-scatter over the 64 lanes of a wavefront: each lane holds N values
+// v[0..N) (N a power of two, N <= 32); on return every lane holds, in the
+// value returned, the sum over all 64 lanes of value index
+// slot(lane) = lane >> (6 - log2 N).  Level by level, lane pairs (L, L^M)
+// split the remaining values in halves and each keeps the sum of one half,
+// so N values cost N-1 exchanges plus 6 - log2 N for the final group sum,
+// instead of 6 per value.  For masks 32 and 16 one half swap of (v[i],
+// v[i+N/2]) leaves each lane its own and its partner's copy of the half it
+// keeps.  The order of additions is fixed.
+template <int N, int M, typename T>
+struct ReduceScatter {
+    template <int NV>
+    static __device__ __forceinline__ void run(T (&v)[NV], int lane) {
+        if constexpr (M == 32 || M == 16) {
+#pragma unroll
+            for (int i = 0; i < N / 2; ++i) {
+                T x = v[i], y = v[i + N / 2];
+                lane_swap<M>(x, y);
+                v[i] = x + y;
+            }
+        } else {
+            const bool hi = (lane & M) != 0;
+#pragma unroll
+            for (int i = 0; i < N / 2; ++i) {
+                const T send = hi ? v[i] : v[i + N / 2];
+                const T keep = hi ? v[i + N / 2] : v[i];
+                v[i] = keep + __shfl_xor(send, M, 64);
+            }
+        }
+        ReduceScatter<N / 2, M / 2, T>::run(v, lane);
+    }
+};
+template <int M, typename T>
+struct ReduceScatter<1, M, T> {
+    template <int NV>
+    static __device__ __forceinline__ void run(T (&)[NV], int) {}
+};
+
+template <int N, typename T>
+__device__ __forceinline__ T wave_reduce_scatter(T (&v)[N], int lane) {
+    static_assert(N >= 1 && N <= 32 && (N & (N - 1)) == 0, "N must be a power of two <= 32");
+    ReduceScatter<N, 32, T>::run(v, lane);
+    T s = v[0];
+#pragma unroll
+    for (int M = 32 / N; M >= 1; M >>= 1) s += __shfl_xor(s, M, 64);
     return s;
 }
 

@@ -53,6 +53,8 @@ struct FwdArgs {
     const int* Jp; const int* Jc; const VT* Jv; const double* W; int nJ;
     const int* Ap; const int* Ac; const double* Av; int m;
     const double* x;       // gathered vector (n)
+    const double* p2;      // PCG: the gathered vector is x + beta*p2 (beta in sc); null: x
+    const PcgScal* sc;
     double* t;             // W .* (J x)        (nJ)
     double* u;             // sigA .* (A x)     (m), or A x when sigA is null
     const double* sigA;
@@ -60,18 +62,23 @@ struct FwdArgs {
     const Flags* fl;
 };
 
+__device__ __forceinline__ Gather make_gather(const double* x, const double* p2, const PcgScal* sc) {
+    return Gather{x, p2, p2 ? sc->beta : 0.0};
+}
+
 // t = W .* (J x) and u = Sigma_A .* (A x).  Rows of J: G lanes per row; rows
 // of A: a full wavefront per row.
 template <int G, typename VT, typename AT>
 __global__ __launch_bounds__(kBlock) void k_op_fwd(FwdArgs<VT> a) {
     if (pcg_stopped(a.fl)) return;
+    const Gather g = make_gather(a.x, a.p2, a.sc);
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     if (b < a.nbJ) {
         constexpr int RPB = kBlock / G;
         const int row = b * RPB + threadIdx.x / G;
         const int lane = threadIdx.x % G;
         if (row < a.nJ) {   // whole groups are uniform: inactive groups skip together
-            AT s = row_dot_lane<G, VT, AT>(a.Jp, a.Jc, a.Jv, a.x, row, lane);
+            AT s = row_dot_lane_g<G, VT, AT>(a.Jp, a.Jc, a.Jv, g, row, lane);
             s = group_sum<AT, G>(s);
             if (lane == 0) a.t[row] = a.W[row] * double(s);
         }
@@ -79,23 +86,34 @@ __global__ __launch_bounds__(kBlock) void k_op_fwd(FwdArgs<VT> a) {
         const int row = (b - a.nbJ) * (kBlock / 64) + (threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
         if (row < a.m) {
-            double s = row_dot_lane<64, double, double>(a.Ap, a.Ac, a.Av, a.x, row, lane);
+            double s = row_dot_lane_g<64, double, double>(a.Ap, a.Ac, a.Av, g, row, lane);
             s = group_sum<double, 64>(s);
             if (lane == 0) a.u[row] = a.sigA ? a.sigA[row] * s : s;
         }
     }
 }
 
+// PCG bookkeeping of an operator product: where the search direction and the
+// scalars live, and the ticket counter of the last-block reductions.
+struct PcgLink {
+    double* p2;            // previous direction p; overwritten with p = x + beta*p
+    PcgScal* sc;
+    Flags* fl;
+    unsigned* ticket;
+};
+
 template <typename VT>
 struct BwdArgs {
     const int* Jtp; const int* Jtc; const VT* Jtv; int n;
     const int* Atp; const int* Atc; const double* Atv; int hasA;
-    const double* t; const double* u; const double* p;
+    const double* t; const double* u;
+    const double* x;       // gathered vector (its own entries only)
     const double* sigx;    // may be null
     double hs, gamma;
     double* q;
     double* part;          // per-block partial p^T q (may be null)
-    const Flags* fl;
+    const Flags* fl;       // stop flags (null: always run)
+    PcgLink pcg;           // pcg.p2 null: plain product
     const double* U;       // n x lr_k column-major low-rank factor (lr_k = 0: none)
     const double* lr_v;    // w .* (U^T p), lr_k entries
     int lr_k;
@@ -110,6 +128,36 @@ __device__ __forceinline__ double lowrank_lane(const double* U, const double* v,
     return s;
 }
 
+// Entry j of the product's output.  In a PCG product the direction entry
+// p_j = x_j + beta*p_j is formed here and stored back (each entry is read and
+// written by the group owning row j only).
+__device__ __forceinline__ double direction_entry(const double* x, const PcgLink& pl, double beta, int j) {
+    if (!pl.p2) return x[j];
+    const double pj = x[j] + beta * pl.p2[j];
+    pl.p2[j] = pj;
+    return pj;
+}
+
+// End of a PCG product: block partials of p^T q; the last block reduces them
+// in a fixed order and sets alpha = rho / p^T q (breakdown flag when p^T q is
+// not positive or alpha is not finite).
+__device__ __forceinline__ void product_tail(double dot, double* part, int b, const PcgLink& pl, double* sh) {
+    if (!part) return;
+    const double tot = block_sum(dot, sh);
+    if (threadIdx.x == 0) part[b] = tot;
+    if (!pl.ticket) return;
+    if (last_block(pl.ticket, gridDim.x)) {
+        const double pq = reduce_partials_sum(part, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) {
+            const double alpha = pl.sc->rho / pq;
+            pl.sc->pq = pq;
+            pl.sc->alpha = alpha;
+            if (!(pq > 0.0) || !finite_d(alpha)) pl.fl->pcg_breakdown = 1;
+            *pl.ticket = 0u;
+        }
+    }
+}
+
 // q_j = hs*(J^T t + gamma p + U(w .* U^T p))_j + Sigma_x,j p_j + (A^T u)_j and per-block
 // partials of p^T q.  Grid-stride over row groups with a capped grid so the
 // partial count stays small.
@@ -120,6 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
     constexpr int RPB = kBlock / G;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x % G;
+    const double beta = a.pcg.p2 ? a.pcg.sc->beta : 0.0;
     double dot = 0.0;
     for (int base = b * RPB; base < a.n; base += gridDim.x * RPB) {
         const int row = base + threadIdx.x / G;
@@ -130,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
             if (a.hasA) s += row_dot_lane<G, double, double>(a.Atp, a.Atc, a.Atv, a.u, row, lane);
             s = group_sum<double, G>(s);
             if (lane == 0) {
-                const double pj = a.p[row];
+                const double pj = direction_entry(a.x, a.pcg, beta, row);
                 double y = s + a.hs * a.gamma * pj;
                 if (a.sigx) y += a.sigx[row] * pj;
                 a.q[row] = y;
@@ -138,45 +187,39 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
             }
         }
     }
-    if (a.part) {
-        const double tot = block_sum(dot, sh);
-        if (threadIdx.x == 0) a.part[b] = tot;
-    }
+    product_tail(dot, a.part, b, a.pcg, sh);
 }
 
 // ==========================================================================
 // PCG vector updates
 // ==========================================================================
+// One iteration: the product kernels form p = z + beta p on the fly and
+// q = K p, and their last block sets alpha; k_pcg_xr updates x and r and
+// applies the diagonal part of the preconditioner; with the constraint block,
+// k_prec_a, k_prec_symv and k_prec_at finish z.  The last block of the kernel
+// that completes z sets beta = r^T z / rho and rho = r^T z.
 // Preconditioner z = P^{-1} r.  Jacobi (the paper, Section 4.1.2): z = r ./ d
 // with d = diag(K).  Constraint block (woodbury = 1): y = r ./ D with
 // D = diag(Hs + Sigma_x), then z = y - D^{-1} A^T Sigma^{1/2} S^{-1}
-// Sigma^{1/2} A y by k_prec_a, k_prec_symv and k_prec_at.
+// Sigma^{1/2} A y.
 struct PcgArgs {
     int n;
-    double* x; double* r; double* z; double* p; const double* q; const double* d;
-    const double* part_pq; int n_pq;     // partials of p^T q from k_op_bwd
-    double* part_rz; int n_rz;           // partials of r^T z
-    double* part_rr; int n_rr;           // partials of r^T r (this grid)
+    double* x; double* r; double* z; const double* p; const double* q; const double* d;
+    double* part_rz;                     // partials of r^T z (Jacobi)
+    double* part_rr;                     // partials of r^T r
     int woodbury;
     PcgScal* sc;
     Flags* fl;
+    unsigned* ticket;
 };
 
-// alpha = rho / p^T q; x += alpha p; r -= alpha q; z (Jacobi) or y = r ./ D
-// (constraint block, stored in z until k_prec_at finishes it); partials.
+// x += alpha p; r -= alpha q; z = r ./ d (Jacobi) or y = r ./ D (constraint
+// block, stored in z until k_prec_at finishes it).  Last block: ||r||^2, the
+// iteration count, convergence and cap flags, and (Jacobi) beta and rho.
 __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped(a.fl)) return;
-    const double pq = reduce_partials_sum(a.part_pq, a.n_pq, 1, sh);
-    const double rho = a.sc->rho_next;
-    const double alpha = rho / pq;
-    const bool bad = !(pq > 0.0) || !finite_d(alpha);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.sc->rho = rho;
-        a.sc->alpha = alpha;
-        if (bad) a.fl->pcg_breakdown = 1;
-    }
-    if (bad) return;
+    const double alpha = a.sc->alpha;
     double rz = 0.0, rr = 0.0;
     for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
         a.x[j] += alpha * a.p[j];
@@ -193,26 +236,24 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
         if (!a.woodbury) a.part_rz[blockIdx.x] = rz;
         a.part_rr[blockIdx.x] = rr;
     }
-}
-
-// beta = rho_new / rho; p = z + beta p; convergence and iteration cap.
-__global__ __launch_bounds__(kBlock) void k_pcg_p(PcgArgs a) {
-    __shared__ double sh[kBlock / 64];
-    if (pcg_stopped(a.fl)) return;
-    const double rz = reduce_partials_sum(a.part_rz, a.n_rz, 1, sh);
-    const double rr = reduce_partials_sum(a.part_rr, a.n_rr, 1, sh);
-    const double beta = rz / a.sc->rho;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.sc->rho_next = rz;
-        a.sc->rr = rr;
-        const int it = a.sc->iters + 1;
-        a.sc->iters = it;
-        a.fl->pcg_iters = it;
-        if (rr <= a.sc->tol2) a.fl->pcg_converged = 1;
-        else if (it >= a.sc->max_iter) a.fl->pcg_capped = 1;
+    if (last_block(a.ticket, gridDim.x)) {
+        const double rr_t = reduce_partials_sum(a.part_rr, gridDim.x, 1, sh);
+        const double rz_t = a.woodbury ? 0.0 : reduce_partials_sum(a.part_rz, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) {
+            PcgScal* sc = a.sc;
+            sc->rr = rr_t;
+            const int it = sc->iters + 1;
+            sc->iters = it;
+            a.fl->pcg_iters = it;
+            if (rr_t <= sc->tol2) a.fl->pcg_converged = 1;
+            else if (it >= sc->max_iter) a.fl->pcg_capped = 1;
+            if (!a.woodbury) {
+                sc->beta = rz_t / sc->rho;
+                sc->rho = rz_t;
+            }
+            *a.ticket = 0u;
+        }
     }
-    for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock)
-        a.p[j] = a.z[j] + beta * a.p[j];
 }
 
 struct PcgInitArgs {
@@ -223,20 +264,20 @@ struct PcgInitArgs {
     double* x; double* r; double* z; double* p; const double* d;
     double* part_rz; double* part_rr;
     int woodbury;
+    double tol;
+    int max_iter;
+    PcgScal* sc;
     Flags* fl;
+    unsigned* ticket;
 };
 
-// x = 0; r = rhs; z = r ./ d (Jacobi: also p = z) ; partials.  Clears the
-// PCG flags of the previous solve (no other block of this kernel reads them;
-// later kernels of this solve see them cleared).
+// x = 0; r = rhs; z = r ./ d; p = 0 with beta = 0 (so the first product's
+// direction is z).  Last block: ||rhs||^2, the stopping threshold, cleared
+// PCG flags of the previous solve (converged at once when rhs = 0) and
+// (Jacobi) rho = r^T z.
 __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
     __shared__ double sh[kBlock / 64];
     if (ipm_finished(a.fl)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.fl->pcg_converged = 0;
-        a.fl->pcg_breakdown = 0;
-        a.fl->pcg_capped = 0;
-    }
     const double mu = a.ipm ? a.ipm->mu : 0.0;
     double rz = 0.0, rr = 0.0;
     for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
@@ -245,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
         a.x[j] = 0.0;
         a.r[j] = rj;
         a.z[j] = zj;
-        if (!a.woodbury) a.p[j] = zj;
+        a.p[j] = 0.0;
         rz += rj * zj;
         rr += rj * rj;
     }
@@ -255,27 +296,26 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
         if (!a.woodbury) a.part_rz[blockIdx.x] = rz;
         a.part_rr[blockIdx.x] = rr;
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_pcg_init1(const double* part_rz, int n_rz, const double* part_rr,
-                                                      int n_rr, double tol, int max_iter, PcgScal* sc,
-                                                      Flags* fl) {
-    __shared__ double sh[kBlock / 64];
-    if (ipm_finished(fl)) return;
-    const double rz = reduce_partials_sum(part_rz, n_rz, 1, sh);
-    const double rr = reduce_partials_sum(part_rr, n_rr, 1, sh);
-    if (threadIdx.x == 0) {
-        sc->rho_next = rz;
-        sc->rho = rz;
-        sc->bnorm2 = rr;
-        sc->rr = rr;
-        sc->tol2 = tol * tol * rr;
-        sc->iters = 0;
-        sc->max_iter = max_iter;
-        fl->pcg_iters = 0;
-        fl->pcg_breakdown = 0;
-        fl->pcg_capped = 0;
-        fl->pcg_converged = (rr == 0.0) ? 1 : 0;
+    if (last_block(a.ticket, gridDim.x)) {
+        const double rr_t = reduce_partials_sum(a.part_rr, gridDim.x, 1, sh);
+        const double rz_t = a.woodbury ? 0.0 : reduce_partials_sum(a.part_rz, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) {
+            PcgScal* sc = a.sc;
+            sc->rho = rz_t;
+            sc->beta = 0.0;
+            sc->alpha = 0.0;
+            sc->pq = 0.0;
+            sc->bnorm2 = rr_t;
+            sc->rr = rr_t;
+            sc->tol2 = a.tol * a.tol * rr_t;
+            sc->iters = 0;
+            sc->max_iter = a.max_iter;
+            a.fl->pcg_iters = 0;
+            a.fl->pcg_breakdown = 0;
+            a.fl->pcg_capped = 0;
+            a.fl->pcg_converged = (rr_t == 0.0) ? 1 : 0;
+            *a.ticket = 0u;
+        }
     }
 }
 
@@ -320,14 +360,14 @@ __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, int ld
     }
 }
 
-// Step 3: z_j = y_j - (A^T v)_j / D_j (y held in z), partials of r^T z; at the
-// start of a solve (init = 1) also p = z.  G lanes per row of A^T, grid-stride
-// with a capped grid.
+// Step 3: z_j = y_j - (A^T v)_j / D_j (y held in z) and partials of r^T z;
+// the last block sets beta = r^T z / rho (0 at the start of a solve, init = 1)
+// and rho = r^T z.  G lanes per row of A^T, grid-stride with a capped grid.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* Atc, const double* Atv,
                                                     const double* v, const double* D, const double* r,
-                                                    double* z, double* p, int n, int init, double* part_rz,
-                                                    const Flags* fl) {
+                                                    double* z, int n, int init, double* part_rz, PcgScal* sc,
+                                                    unsigned* ticket, const Flags* fl) {
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped(fl)) return;
     constexpr int RPB = kBlock / G;
@@ -341,13 +381,20 @@ __global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* A
             if (lane == 0) {
                 const double zj = z[j] - s / D[j];
                 z[j] = zj;
-                if (init) p[j] = zj;
                 rz += r[j] * zj;
             }
         }
     }
     rz = block_sum(rz, sh);
     if (threadIdx.x == 0) part_rz[blockIdx.x] = rz;
+    if (last_block(ticket, gridDim.x)) {
+        const double t = reduce_partials_sum(part_rz, gridDim.x, 1, sh);
+        if (threadIdx.x == 0) {
+            sc->beta = init ? 0.0 : t / sc->rho;
+            sc->rho = t;
+            *ticket = 0u;
+        }
+    }
 }
 
 // ==========================================================================
@@ -785,20 +832,25 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double*
     }
 }
 
-// Low-rank factor product U^T p (eq. (bfgs_hessian) applied matrix-free):
-// per-block partials of up to 32 columns (grid.y walks column groups), then a
-// one-block fixed-order reduction v_c = w_c * sum_b partial[b][c].
-__global__ __launch_bounds__(kBlock) void k_lr_partial(const double* U, int n, int k, const double* p,
-                                                       double* part, const Flags* fl) {
+// Low-rank factor product v = w .* (U^T p) (eq. (bfgs_hessian) applied
+// matrix-free), p the gathered vector: per-block partials of up to 32 columns
+// (grid.y walks column groups); the last block reduces them in a fixed order.
+// Partial layout part[b * k + c] for x-block b and column c.
+__global__ __launch_bounds__(kBlock) void k_lr_partial(const double* U, int n, int k, const double* x,
+                                                       const double* p2, const PcgScal* sc, const double* w,
+                                                       double* part, double* v, unsigned* ticket,
+                                                       const Flags* fl) {
     __shared__ double sh[kBlock / 64];
+    __shared__ double sub[kBlock / 32][32];
     if (pcg_stopped(fl)) return;
+    const Gather g = make_gather(x, p2, sc);
     const int c0 = blockIdx.y * 32;
     const int kc = min(32, k - c0);
     double acc[32];
 #pragma unroll
     for (int c = 0; c < 32; ++c) acc[c] = 0.0;
     for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) {
-        const double pj = p[j];
+        const double pj = g(j);
 #pragma unroll
         for (int c = 0; c < 32; ++c)
             if (c < kc) acc[c] += U[j + size_t(n) * (c0 + c)] * pj;
@@ -810,16 +862,32 @@ __global__ __launch_bounds__(kBlock) void k_lr_partial(const double* U, int n, i
             if (threadIdx.x == 0) part[size_t(blockIdx.x) * k + c0 + c] = t;
         }
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_lr_reduce(const double* part, int nb, int k, const double* w,
-                                                      double* v, const Flags* fl) {
-    __shared__ double sh[kBlock / 64];
-    if (pcg_stopped(fl)) return;
-    for (int c = 0; c < k; ++c) {
-        const double t = reduce_partials_sum(part + c, nb, k, sh);
-        if (threadIdx.x == 0) v[c] = w[c] * t;
+    if (!last_block(ticket, gridDim.x * gridDim.y)) return;
+    // thread (s, c): column c of a 32-column group, x-blocks s, s+8, s+16, ...
+    const int c = threadIdx.x & 31, s8 = threadIdx.x >> 5;
+    constexpr int S = kBlock / 32;
+    for (int cg = 0; cg < k; cg += 32) {
+        const int col = min(cg + c, k - 1);
+        double a = 0.0;
+        for (int bx = s8; bx < int(gridDim.x); bx += 8 * S) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                t[u] = part[size_t(min(bx + u * S, int(gridDim.x) - 1)) * k + col];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a += (bx + u * S < int(gridDim.x)) ? t[u] : 0.0;
+        }
+        sub[s8][c] = a;
+        __syncthreads();
+        if (threadIdx.x < 32 && cg + c < k) {
+            double tot = 0.0;
+#pragma unroll
+            for (int i = 0; i < S; ++i) tot += sub[i][c];
+            v[cg + c] = w[cg + c] * tot;
+        }
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *ticket = 0u;
 }
 
 // Mixed-precision refinement helpers (skipped once the IPM has finished).

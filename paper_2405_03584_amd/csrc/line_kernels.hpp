@@ -2,36 +2,54 @@
 //
 // A dose matrix whose rows come in lines of 64 voxels sharing one column list
 // (the 64-voxel bands of every spot) is stored once: column ids per line and
-// values slot-major with the 64 rows of a slot contiguous.  J p then needs no
-// per-entry index: a wavefront owns a line, lane r owns row r, the column id
-// and p[col] of each slot are wave-uniform (scalar loads) and each slot's 64
-// values are one coalesced load.  J^T t reads the same values: spot j visits
-// the (line, slot) pairs it covers, and both lval[slot*64 + r] and
-// t[line*64 + r] are contiguous in r.  Index traffic falls from 4 bytes per
-// nonzero (CSR) to 4 bytes per (line, slot) pair, 1/64 per nonzero.
+// values slot-major with the 64 rows of a slot contiguous.
+//
+// The product J^T W J p takes two kernels and reads the values of J once:
+//
+//  k_line_pass   a block per line: lane r of each wavefront owns row r, the
+//                four wavefronts take contiguous quarters of the line's
+//                slots and keep their values in registers.  Pass 1 forms
+//                t_r = W_r (J p)_r (the quarters' partial sums combined in a
+//                fixed order through LDS); pass 2 multiplies the held values
+//                by t_r and reduces over the 64 rows of every slot, giving
+//                c[slot] = sum_r J_(r,slot) t_r, the line's contribution to
+//                (J^T t)_col(slot).  Remaining blocks: u = Sigma_A .* (A p).
+//  k_spot_pass   spot j sums c over the slots it covers (its (line, slot)
+//                list), adds gamma p_j, the low-rank term, Sigma_x p_j and
+//                (A^T u)_j, and in a PCG product stores p and the p^T q
+//                partials.
+//
+// Against two SpMV passes (J, then J^T reading the values again) this halves
+// the HBM traffic of J; c is one double per slot (1/64 per nonzero).
 #pragma once
 
 #include "ipm_kernels.hpp"
 
 namespace qpg {
 
+// Slots of a line kept in registers per wavefront; a line with more than
+// 4*kLineHeld slots streams the rest from memory in both passes.
+constexpr int kLineHeld = 32;
+
 template <typename VT>
-struct LineFwdArgs {
+struct LineArgs {
     const int* lptr; const int* lcol; const VT* lval; int L; const double* W;
     const int* Ap; const int* Ac; const double* Av; int m;
-    const double* x; double* t; double* u; const double* sigA;
+    const double* x; const double* p2; const PcgScal* sc;   // gathered vector, as in FwdArgs
+    double* c;             // per slot (lptr[L] entries)
+    double* u; const double* sigA;
     int nbL;               // blocks working on lines (one line per block)
     const Flags* fl;
 };
 
-// t = W .* (J x): a block per line, lane = row; the 4 wavefronts of the block
-// take contiguous quarters of the line's slots and their partial row sums are
-// added in a fixed order through LDS.  u = Sigma_A .* (A x): a wavefront per
-// row of A in the remaining blocks.
 template <typename VT, typename AT>
-__global__ __launch_bounds__(kBlock) void k_op_fwd_line(LineFwdArgs<VT> a) {
-    __shared__ AT part[kBlock / 64][64];
+__global__ __launch_bounds__(kBlock) void k_line_pass(LineArgs<VT> a) {
+    constexpr int NW = kBlock / 64;
+    constexpr int RH = kLineHeld;
+    static_assert(NW == 4, "the pass-1 combine adds four wavefront partials");
+    __shared__ AT part[NW][64];
     if (pcg_stopped(a.fl)) return;
+    const Gather g = make_gather(a.x, a.p2, a.sc);
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -39,90 +57,114 @@ __global__ __launch_bounds__(kBlock) void k_op_fwd_line(LineFwdArgs<VT> a) {
         const int l = b;
         const int off = a.lptr[l];
         const int len = a.lptr[l + 1] - off;
-        const int q = (len + 3) >> 2;
+        const int q = (len + NW - 1) / NW;
         const int k0 = __builtin_amdgcn_readfirstlane(min(len, w * q));
         const int k1 = __builtin_amdgcn_readfirstlane(min(len, k0 + q));
+        const int kh = min(k1, k0 + RH);   // held slots [k0, kh)
         const VT* v = a.lval + size_t(off) * 64 + lane;
-        const int* c = a.lcol + off;
-        AT acc[8];
+        const int* col = a.lcol + off;
+        // pass 1: partial (J p)_r over this wavefront's slots.  Lane i
+        // gathers p at the column of held slot k0+i (one coalesced index load
+        // and one gather per lane instead of RH wave-uniform ones), and the
+        // product loop reads it back with readlane.  Value loads past kh are
+        // clamped to kh-1 (a valid address) and contribute 0, so every load
+        // is issued at once, without branches between them.
+        AT hv[RH];
+        AT acc = AT(0);
+        if (k0 < kh) {
+            const double pl = g(col[min(k0 + (lane & (RH - 1)), kh - 1)]);
+            const int plo = __double2loint(pl), phi = __double2hiint(pl);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] = AT(0);
-        // passes of 8 slots; slots past k1 are clamped to k1-1 (valid address)
-        // and contribute 0, so each pass issues all its loads without branches
-        for (int k = k0; k < k1; k += 8) {
+            for (int i = 0; i < RH; ++i) hv[i] = cvt<AT>(v[size_t(min(k0 + i, kh - 1)) * 64]);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int kk = min(k + u, k1 - 1);
-                const AT prod = cvt<AT>(v[size_t(kk) * 64]) * AT(a.x[c[kk]]);
-                acc[u] += (k + u < k1) ? prod : AT(0);
+            for (int i = 0; i < RH; ++i) {
+                const double xv = __hiloint2double(__builtin_amdgcn_readlane(phi, i),
+                                                   __builtin_amdgcn_readlane(plo, i));
+                acc = (k0 + i < kh) ? fma(hv[i], AT(xv), acc) : acc;   // one chain: no product array
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < RH; ++i) hv[i] = AT(0);
         }
-        part[w][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        for (int k = kh; k < k1; k += 4) {   // only lines longer than NW*RH slots
+            AT s4 = AT(0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kk = min(k + i, k1 - 1);
+                const AT prod = cvt<AT>(v[size_t(kk) * 64]) * AT(g(col[kk]));
+                s4 += (k + i < k1) ? prod : AT(0);
+            }
+            acc += s4;
+        }
+        part[w][lane] = acc;
         __syncthreads();
-        if (w == 0) {
-            const AT s = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-            const int row = l * 64 + lane;
-            a.t[row] = a.W[row] * double(s);
+        const AT s = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+        const AT t = AT(a.W[size_t(l) * 64 + lane] * double(s));
+        // pass 2: c[slot] = sum_r J_(r,slot) t_r, RH slots per reduce-scatter
+        constexpr int SHIFT = RH == 32 ? 1 : RH == 16 ? 2 : RH == 8 ? 3 : RH == 4 ? 4 : RH == 2 ? 5 : 6;
+        const int slot = lane >> SHIFT;
+        const bool writer = (lane & ((1 << SHIFT) - 1)) == 0;
+        if (k0 < kh) {   // held slots (hv is dead afterwards)
+#pragma unroll
+            for (int i = 0; i < RH; ++i) hv[i] = (k0 + i < kh) ? hv[i] * t : AT(0);
+            const AT cs = wave_reduce_scatter<RH>(hv, lane);
+            if (writer && k0 + slot < kh) a.c[off + k0 + slot] = double(cs);
+        }
+        for (int kg = kh; kg < k1; kg += RH) {   // streamed slots of long lines
+            AT pv[RH];
+#pragma unroll
+            for (int i = 0; i < RH; ++i) {
+                const AT val = cvt<AT>(v[size_t(min(kg + i, k1 - 1)) * 64]);
+                pv[i] = (kg + i < k1) ? val * t : AT(0);
+            }
+            const AT cs = wave_reduce_scatter<RH>(pv, lane);
+            if (writer && kg + slot < k1) a.c[off + kg + slot] = double(cs);
         }
     } else {
-        const int row = (b - a.nbL) * (kBlock / 64) + w;
+        const int row = (b - a.nbL) * NW + w;
         if (row < a.m) {
-            double s = row_dot_lane<64, double, double>(a.Ap, a.Ac, a.Av, a.x, row, lane);
+            double s = row_dot_lane_g<64, double, double>(a.Ap, a.Ac, a.Av, g, row, lane);
             s = group_sum<double, 64>(s);
             if (lane == 0) a.u[row] = a.sigA ? a.sigA[row] * s : s;
         }
     }
 }
 
-template <typename VT>
-struct LineBwdArgs {
-    const int* sptr; const int* sline; const int* sslot; const VT* lval; int n;
+struct SpotArgs {
+    const int* sptr; const int* sslot; const double* c; int n;
     const int* Atp; const int* Atc; const double* Atv; int hasA;
-    const double* t; const double* u; const double* p;
+    const double* u;
+    const double* x;       // gathered vector (its own entries only)
     const double* sigx;
     double hs, gamma;
     double* q;
     double* part;
     const Flags* fl;
+    PcgLink pcg;           // as in BwdArgs
     const double* U; const double* lr_v; int lr_k;
 };
 
-// q_j = hs*(J^T t + gamma p + U(w .* U^T p))_j + Sigma_x,j p_j + (A^T u)_j with
-// a wavefront per spot j, and per-block partials of p^T q.
-template <typename VT, typename AT>
-__global__ __launch_bounds__(kBlock) void k_op_bwd_line(LineBwdArgs<VT> a) {
+// q_j = hs*((J^T W J p)_j + gamma p_j + (U(w .* U^T p))_j) + Sigma_x,j p_j + (A^T u)_j
+// with G lanes per spot, per-block partials of p^T q and, in a PCG product,
+// p stored back and alpha set by the last block.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_spot_pass(SpotArgs a) {
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped(a.fl)) return;
+    constexpr int RPB = kBlock / G;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x & 63;
-    constexpr int WPB = kBlock / 64;
+    const int lane = threadIdx.x % G;
+    const double beta = a.pcg.p2 ? a.pcg.sc->beta : 0.0;
     double dot = 0.0;
-    for (int base = b * WPB; base < a.n; base += gridDim.x * WPB) {
-        const int j = __builtin_amdgcn_readfirstlane(base + (threadIdx.x >> 6));
+    for (int base = b * RPB; base < a.n; base += gridDim.x * RPB) {
+        const int j = base + threadIdx.x / G;
         if (j < a.n) {
-            const int e0 = a.sptr[j], e1 = a.sptr[j + 1];
-            AT acc[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) acc[u] = AT(0);
-            // passes of 16 pairs, tail clamped to the last pair and zeroed
-            for (int e = e0; e < e1; e += 16) {
-#pragma unroll
-                for (int u = 0; u < 16; ++u) {
-                    const int ee = min(e + u, e1 - 1);
-                    const int l = a.sline[ee], s = a.sslot[ee];
-                    const AT prod = cvt<AT>(a.lval[size_t(s) * 64 + lane]) * AT(a.t[size_t(l) * 64 + lane]);
-                    acc[u] += (e + u < e1) ? prod : AT(0);
-                }
-            }
-            AT sj = AT(0);
-#pragma unroll
-            for (int u = 0; u < 16; u += 2) sj += acc[u] + acc[u + 1];
-            double s = a.hs * double(sj);
-            if (a.hasA) s += row_dot_lane<64, double, double>(a.Atp, a.Atc, a.Atv, a.u, j, lane);
-            if (a.lr_k) s += a.hs * lowrank_lane<64>(a.U, a.lr_v, a.lr_k, a.n, j, lane);
-            s = group_sum<double, 64>(s);
+            double s = a.hs * index_sum_lane<G>(a.sptr, a.sslot, a.c, j, lane);
+            if (a.lr_k) s += a.hs * lowrank_lane<G>(a.U, a.lr_v, a.lr_k, a.n, j, lane);
+            if (a.hasA) s += row_dot_lane<G, double, double>(a.Atp, a.Atc, a.Atv, a.u, j, lane);
+            s = group_sum<double, G>(s);
             if (lane == 0) {
-                const double pj = a.p[j];
+                const double pj = direction_entry(a.x, a.pcg, beta, j);
                 double y = s + a.hs * a.gamma * pj;
                 if (a.sigx) y += a.sigx[j] * pj;
                 a.q[j] = y;
@@ -130,10 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd_line(LineBwdArgs<VT> a) {
             }
         }
     }
-    if (a.part) {
-        const double tot = block_sum(dot, sh);
-        if (threadIdx.x == 0) a.part[b] = tot;
-    }
+    product_tail(dot, a.part, b, a.pcg, sh);
 }
 
 }  // namespace qpg

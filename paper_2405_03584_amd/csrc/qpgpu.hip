@@ -76,8 +76,9 @@ struct qp_handle {
     // line format of J (64-row lines sharing a column list), used by the PCG operator
     bool line = false;
     int L = 0;
-    int *lptr = nullptr, *lcol = nullptr, *sptr = nullptr, *sline = nullptr, *sslot = nullptr;
+    int *lptr = nullptr, *lcol = nullptr, *sptr = nullptr, *sslot = nullptr;
     double* lval = nullptr;
+    double* lc = nullptr;   // per-slot J^T contributions of the line pass
     float* lval32 = nullptr;
     bf16_t* lval16 = nullptr;
     std::vector<double> hlval;
@@ -102,6 +103,7 @@ struct qp_handle {
     double* log = nullptr;
     IpmScal* isc = nullptr;
     PcgScal* psc = nullptr;
+    unsigned* ticket = nullptr;   // last-block counter of the fused reductions (0 between kernels)
     Flags* fl = nullptr;
     Flags* fl_host = nullptr;   // pinned, 2 slots
 
@@ -143,14 +145,14 @@ namespace {
 
 constexpr int kLrBlocks = 256;   // blocks of the U^T p partial pass
 
-// v = w .* (U^T p) for the low-rank part of H (no-op when k = 0).
-void lowrank_prepare(qp_handle* h, const double* p, const Flags* fl) {
+// v = w .* (U^T p) for the low-rank part of H (no-op when k = 0); p is x, or
+// x + beta*p2 in a PCG product.
+void lowrank_prepare(qp_handle* h, const double* x, const double* p2, const Flags* fl) {
     if (h->k == 0) return;
     const int gy = (h->k + 31) / 32;
     hipLaunchKernelGGL(k_lr_partial, dim3(kLrBlocks, gy), dim3(kBlock), 0, h->stream, (const double*)h->U, h->n,
-                       h->k, p, h->lr_part, fl);
-    hipLaunchKernelGGL(k_lr_reduce, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->lr_part, kLrBlocks,
-                       h->k, (const double*)h->w, h->lr_v, fl);
+                       h->k, x, p2, (const PcgScal*)h->psc, (const double*)h->w, h->lr_part, h->lr_v, h->ticket,
+                       fl);
     HIPCHK(hipGetLastError());
 }
 
@@ -212,56 +214,80 @@ const float* line_vals<float>(qp_handle* h) { return h->lval32; }
 template <>
 const bf16_t* line_vals<bf16_t>(qp_handle* h) { return h->lval16; }
 
-// q = K p on the line format of J (same contract as apply_op).
+// PCG link of a product: in a PCG product (pcg = true) the gathered vector is
+// z + beta*p, p is written back and the last block sets alpha.
+PcgLink pcg_link(qp_handle* h, bool pcg) {
+    PcgLink l{};
+    if (pcg) {
+        l.p2 = h->pp;
+        l.sc = h->psc;
+        l.fl = h->fl;
+        l.ticket = h->ticket;
+    }
+    return l;
+}
+
+// q = K p on the line format of J (same contract as apply_op): the line pass
+// (J and the per-slot J^T contributions, A) and the spot pass.
+constexpr int kSpotLanes = 16;
+
 template <typename VT, typename AT>
-int apply_op_line(qp_handle* h, const double* p, double* q, const double* sigx, const double* sigA, double hs,
-                  double* part, const Flags* fl, bool timed, int tslot) {
-    LineFwdArgs<VT> f{};
+int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, const double* sigA, double hs,
+                  bool pcg, bool timed, int tslot) {
+    const PcgLink pl = pcg_link(h, pcg);
+    const Flags* fl = pcg ? h->fl : nullptr;
+    double* part = pcg ? h->part : nullptr;
+    LineArgs<VT> f{};
     f.lptr = h->lptr; f.lcol = h->lcol; f.lval = line_vals<VT>(h); f.L = h->L; f.W = h->W;
     f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
-    f.x = p; f.t = h->t; f.u = h->u; f.sigA = sigA; f.fl = fl;
+    f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.c = h->lc; f.u = h->u; f.sigA = sigA; f.fl = fl;
     f.nbL = h->L;
     const int nbA = f.m > 0 ? grid_rows(f.m, 64) : 0;
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
-    hipLaunchKernelGGL((k_op_fwd_line<VT, AT>), dim3(std::max(1, f.nbL + nbA)), dim3(kBlock), 0, h->stream, f);
+    hipLaunchKernelGGL((k_line_pass<VT, AT>), dim3(std::max(1, f.nbL + nbA)), dim3(kBlock), 0, h->stream, f);
     HIPCHK(hipGetLastError());
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
-    lowrank_prepare(h, p, fl);
-    LineBwdArgs<VT> b{};
-    b.sptr = h->sptr; b.sline = h->sline; b.sslot = h->sslot; b.lval = line_vals<VT>(h); b.n = h->n;
+    lowrank_prepare(h, x, pl.p2, fl);
+    SpotArgs b{};
+    b.sptr = h->sptr; b.sslot = h->sslot; b.c = h->lc; b.n = h->n;
     b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = f.m > 0;
-    b.t = h->t; b.u = h->u; b.p = p; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
-    b.q = q; b.part = part; b.fl = fl;
+    b.u = h->u; b.x = x; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
+    b.q = q; b.part = part; b.fl = fl; b.pcg = pl;
     b.U = h->U; b.lr_v = h->lr_v; b.lr_k = h->k;
-    const int grid = std::min((h->n + 3) / 4, kMaxPartials);
+    const int grid = grid_rows_capped(h->n, kSpotLanes);
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], h->stream));
-    hipLaunchKernelGGL((k_op_bwd_line<VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, b);
+    hipLaunchKernelGGL(k_spot_pass<kSpotLanes>, dim3(grid), dim3(kBlock), 0, h->stream, b);
     HIPCHK(hipGetLastError());
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], h->stream));
     return part ? grid : 0;
 }
 
-// q = K p with K = hs*H + diag(sigx) + A^T diag(sigA) A; returns the number of
-// p^T q partials written to `part` (0 when part is null).
+// q = K p with K = hs*H + diag(sigx) + A^T diag(sigA) A.  pcg = false: p = x,
+// run unconditionally; pcg = true: p = z + beta*p of the PCG iteration
+// (x = z), skipped once the solve has stopped.  Returns the number of p^T q
+// partials (0 when pcg is false).
 template <typename VT, typename AT>
-int apply_op(qp_handle* h, const double* p, double* q, const double* sigx, const double* sigA, double hs,
-             double* part, const Flags* fl, bool timed, int tslot) {
+int apply_op(qp_handle* h, const double* x, double* q, const double* sigx, const double* sigA, double hs,
+             bool pcg, bool timed, int tslot) {
+    const PcgLink pl = pcg_link(h, pcg);
+    const Flags* fl = pcg ? h->fl : nullptr;
+    double* part = pcg ? h->part : nullptr;
     FwdArgs<VT> f{};
     const VT *jv = nullptr, *jtv = nullptr;
     mat_ptrs<VT>(h, jv, jtv);
     f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = jv; f.W = h->W; f.nJ = h->nJ;
     f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
-    f.x = p; f.t = h->t; f.u = h->u; f.sigA = sigA; f.fl = fl;
+    f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.t = h->t; f.u = h->u; f.sigA = sigA; f.fl = fl;
     const int nbA = f.m > 0 ? grid_rows(f.m, 64) : 0;
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
     launch_fwd<VT, AT>(h, h->GJ, f, nbA);
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
-    lowrank_prepare(h, p, fl);
+    lowrank_prepare(h, x, pl.p2, fl);
     BwdArgs<VT> b{};
     b.Jtp = h->Jtp; b.Jtc = h->Jtc; b.Jtv = jtv; b.n = h->n;
     b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = f.m > 0;
-    b.t = h->t; b.u = h->u; b.p = p; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
-    b.q = q; b.part = part; b.fl = fl;
+    b.t = h->t; b.u = h->u; b.x = x; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
+    b.q = q; b.part = part; b.fl = fl; b.pcg = pl;
     b.U = h->U; b.lr_v = h->lr_v; b.lr_k = h->k;
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], h->stream));
     const int g = launch_bwd<VT, AT>(h, h->GJt, b);
@@ -269,19 +295,19 @@ int apply_op(qp_handle* h, const double* p, double* q, const double* sigx, const
     return part ? g : 0;
 }
 
-int apply_op_prec(qp_handle* h, int prec, const double* p, double* q, const double* sigx, const double* sigA,
-                  double hs, double* part, const Flags* fl, bool timed, int tslot) {
+int apply_op_prec(qp_handle* h, int prec, const double* x, double* q, const double* sigx, const double* sigA,
+                  double hs, bool pcg, bool timed, int tslot) {
     if (h->line) {
         switch (prec) {
-            case QP_FP32: return apply_op_line<float, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
-            case QP_BF16: return apply_op_line<bf16_t, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
-            default: return apply_op_line<double, double>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
+            case QP_FP32: return apply_op_line<float, float>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
+            case QP_BF16: return apply_op_line<bf16_t, float>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
+            default: return apply_op_line<double, double>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
         }
     }
     switch (prec) {
-        case QP_FP32: return apply_op<float, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
-        case QP_BF16: return apply_op<bf16_t, float>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
-        default: return apply_op<double, double>(h, p, q, sigx, sigA, hs, part, fl, timed, tslot);
+        case QP_FP32: return apply_op<float, float>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
+        case QP_BF16: return apply_op<bf16_t, float>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
+        default: return apply_op<double, double>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
     }
 }
 
@@ -376,8 +402,9 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
     return true;
 }
 
-// z = P^{-1} r for the constraint-block preconditioner, given y = r ./ Dw in z.
-int apply_precond(qp_handle* h, const double* D, const double* sigA, int init) {
+// z = P^{-1} r for the constraint-block preconditioner, given y = r ./ Dw in z;
+// sets beta and rho on the device.
+void apply_precond(qp_handle* h, const double* D, const double* sigA, int init) {
     const int ld = h->ldcur, k = h->kcur, m = h->m;
     const int rows_a = std::max(ld, (m + 63) / 64);
     hipLaunchKernelGGL(k_prec_a, dim3((rows_a + 3) / 4), dim3(kBlock), 0, h->stream, (const int*)h->Ap,
@@ -389,9 +416,8 @@ int apply_precond(qp_handle* h, const double* D, const double* sigA, int init) {
     const int grid = grid_rows_capped(h->n, G);
     hipLaunchKernelGGL(k_prec_at<G>, dim3(grid), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
                        (const int*)h->Atc, (const double*)h->Atv, (const double*)h->vpre, D, (const double*)h->pr,
-                       h->pz, h->pp, h->n, init, h->part_rz, (const Flags*)h->fl);
+                       h->pz, h->n, init, h->part_rz, h->psc, h->ticket, (const Flags*)h->fl);
     HIPCHK(hipGetLastError());
-    return grid;
 }
 
 void autotune_schedule(qp_handle* h) {
@@ -431,7 +457,7 @@ void autotune_schedule(qp_handle* h) {
             BwdArgs<double> b{};
             b.Jtp = h->Jtp; b.Jtc = h->Jtc; b.Jtv = h->Jtv; b.n = h->n;
             b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = h->m > 0;
-            b.t = h->t; b.u = h->zero_m; b.p = h->zero_n; b.hs = 1.0; b.q = h->tmp_n;
+            b.t = h->t; b.u = h->zero_m; b.x = h->zero_n; b.hs = 1.0; b.q = h->tmp_n;
             HIPCHK(hipEventRecord(e0, h->stream));
             launch_bwd<double, double>(h, g, b);
             HIPCHK(hipEventRecord(e1, h->stream));
@@ -465,19 +491,17 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     PcgInitArgs ia{};
     ia.n = n; ia.rhs_a = rhs_a; ia.rhs_b = rhs_b; ia.ipm = ipm_mode ? h->isc : nullptr;
     ia.x = h->px; ia.r = h->pr; ia.z = h->pz; ia.p = h->pp; ia.d = dd;
-    ia.part_rz = h->part_rz; ia.part_rr = h->part_rr; ia.woodbury = wb; ia.fl = h->fl;
+    ia.part_rz = h->part_rz; ia.part_rr = h->part_rr; ia.woodbury = wb;
+    ia.tol = h->set.pcg_tol; ia.max_iter = h->set.pcg_max_iter;
+    ia.sc = h->psc; ia.fl = h->fl; ia.ticket = h->ticket;
     hipLaunchKernelGGL(k_pcg_init0, dim3(ge), dim3(kBlock), 0, h->stream, ia);
     HIPCHK(hipGetLastError());
-    int n_rz = ge;
-    if (wb) n_rz = apply_precond(h, dh, sigA, 1);
-    hipLaunchKernelGGL(k_pcg_init1, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
-                       (const double*)h->part_rr, ge, h->set.pcg_tol, h->set.pcg_max_iter, h->psc, h->fl);
-    HIPCHK(hipGetLastError());
+    if (wb) apply_precond(h, dh, sigA, 1);
 
     PcgArgs pa{};
     pa.n = n; pa.x = h->px; pa.r = h->pr; pa.z = h->pz; pa.p = h->pp; pa.q = h->pq; pa.d = dd;
-    pa.part_pq = h->part; pa.part_rz = h->part_rz; pa.n_rz = n_rz; pa.part_rr = h->part_rr; pa.n_rr = ge;
-    pa.woodbury = wb; pa.sc = h->psc; pa.fl = h->fl;
+    pa.part_rz = h->part_rz; pa.part_rr = h->part_rr;
+    pa.woodbury = wb; pa.sc = h->psc; pa.fl = h->fl; pa.ticket = h->ticket;
 
     const bool timing = h->set.timing != 0 && tacc != nullptr;
     const int slot_begin = tacc ? tacc->pairs : 0;
@@ -489,10 +513,9 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
             slot = tacc->pairs++;
             tacc->valid.push_back(1);
         }
-        pa.n_pq = apply_op_prec(h, prec, h->pp, h->pq, sigx, sigA, hs, h->part, h->fl, timed, slot);
+        apply_op_prec(h, prec, h->pz, h->pq, sigx, sigA, hs, true, timed, slot);
         hipLaunchKernelGGL(k_pcg_xr, dim3(ge), dim3(kBlock), 0, h->stream, pa);
         if (wb) apply_precond(h, dh, sigA, 0);
-        hipLaunchKernelGGL(k_pcg_p, dim3(ge), dim3(kBlock), 0, h->stream, pa);
     };
     auto snapshot = [&](int slot) {
         HIPCHK(hipMemcpyAsync(&h->fl_host[slot], h->fl, sizeof(Flags), hipMemcpyDeviceToHost, h->stream));
@@ -565,7 +588,7 @@ Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double
     hipLaunchKernelGGL(k_acc, dim3(ge), dim3(kBlock), 0, h->stream, n, h->dxacc, (const double*)h->px, 1,
                        (const Flags*)h->fl);
     for (int k = 0; k < h->set.refine_steps; ++k) {
-        apply_op_prec(h, QP_FP64, h->dxacc, h->pq, sigx, sigA, hs, nullptr, nullptr, false, 0);
+        apply_op_prec(h, QP_FP64, h->dxacc, h->pq, sigx, sigA, hs, false, false, 0);
         hipLaunchKernelGGL(k_sub, dim3(ge), dim3(kBlock), 0, h->stream, n, rhs, (const double*)h->pq, h->rho,
                            (const Flags*)h->fl);
         Flags f2 = run_pcg(h, prec, nullptr, h->rho, sigx, sigA, d, dh, hs, false, tacc);
@@ -757,8 +780,8 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
             h->lcol = h->upload(lf.col.data(), lf.col.size());
             h->lval = h->upload(lf.val.data(), lf.val.size());
             h->sptr = h->upload(lf.sptr.data(), lf.sptr.size());
-            h->sline = h->upload(lf.sline.data(), lf.sline.size());
             h->sslot = h->upload(lf.sslot.data(), lf.sslot.size());
+            h->lc = h->dalloc<double>(lf.col.size());
             HIPCHK(hipStreamSynchronize(h->stream));
             h->hlval = std::move(lf.val);
         }
@@ -845,6 +868,9 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->log = h->dalloc<double>(4 * size_t(h->set.max_ipm_iter + 1));
         h->isc = h->dalloc<IpmScal>(1);
         h->psc = h->dalloc<PcgScal>(1);
+        h->ticket = h->dalloc<unsigned>(1);
+        HIPCHK(hipMemsetAsync(h->ticket, 0, sizeof(unsigned), h->stream));
+        HIPCHK(hipMemsetAsync(h->psc, 0, sizeof(PcgScal), h->stream));
         h->fl = h->dalloc<Flags>(1);
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->fl_host), 2 * sizeof(Flags), hipHostMallocDefault));
         for (auto& ev : h->ev_chunk) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -907,7 +933,7 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
             const int slot = timed ? ta.pairs++ : 0;
             if (timed) ta.valid.push_back(1);
             apply_op_prec(h, precision, h->tmp_n2, h->pq, h->tmp_n, h->m > 0 ? h->tmp_m : nullptr, 1.0,
-                          nullptr, nullptr, timed, slot);
+                          false, timed, slot);
         }
         HIPCHK(hipEventRecord(h->ev_t1, h->stream));
         HIPCHK(hipMemcpyAsync(y, h->pq, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
@@ -1018,7 +1044,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             HIPCHK(hipGetLastError());
             nps += ga;
         }
-        apply_op<double, double>(h, v.x, h->tmp_n, nullptr, nullptr, 1.0, nullptr, nullptr, false, 0);
+        apply_op<double, double>(h, v.x, h->tmp_n, nullptr, nullptr, 1.0, false, false, 0);
         hipLaunchKernelGGL(k_ipm_scale, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->tmp_n,
                            (const double*)h->p, n, (const double*)h->partA, nps, h->mtot,
                            h->set.scale_objective, h->set.mu0, h->isc);
@@ -1051,7 +1077,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             ba.Atp = h->Atp; ba.Atc = h->Atc; ba.Atv = h->Atv; ba.hasA = m > 0;
             ba.t = h->t; ba.gamma = h->gamma;
             ba.U = h->U; ba.lr_v = h->lr_v; ba.lr_k = h->k;
-            lowrank_prepare(h, v.x, nullptr);
+            lowrank_prepare(h, v.x, nullptr, nullptr);
             const int gb = grid_rows_capped(n, Gt);
             switch (Gt) {
                 case 4: hipLaunchKernelGGL(k_ipm_bwd<4>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;

@@ -356,9 +356,10 @@ def test_solve_config5_scaled(prec):
 # line format of J (64-row lines sharing a column list) vs CSR
 # ----------------------------------------------------------------------------
 
+@pytest.mark.parametrize("scale", [0.02, 0.05])   # 0.05: lines of up to 173 slots (> 4*32 held)
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_line_format_operator_matches_csr(prec):
-    prob = qpsynth.config2(scale=0.02)
+def test_line_format_operator_matches_csr(prec, scale):
+    prob = qpsynth.config2(scale=scale)
     it = qpsynth.random_iterate(prob, 41)
     hl = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(spmv_format=0))
     hc = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(spmv_format=1))
