@@ -95,7 +95,7 @@ struct qp_handle {
     // constraint-block preconditioner (dense m x m, leading dimension ld)
     int woodbury = 0, ld = 0, T = 0;            // allocation sizes (all m rows)
     int kcur = 0, ldcur = 0, Tcur = 0;           // strong rows of the current build
-    double *Sm = nullptr, *Xm = nullptr, *Sinv = nullptr, *Linv = nullptr, *wpre = nullptr, *vpre = nullptr;
+    double *Sm = nullptr, *Sinv = nullptr, *Qf = nullptr, *Cf = nullptr, *wpre = nullptr, *vpre = nullptr;
     double* Dw = nullptr;                        // D plus the weak rows' diagonal
     double *lr_part = nullptr, *lr_v = nullptr;  // low-rank term: U^T p partials and w .* U^T p
     int *rflag = nullptr, *rpos = nullptr, *ridx = nullptr, *kdev = nullptr;
@@ -385,12 +385,10 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
                        (const int*)h->rpos, (const int*)h->ridx, k, ld, h->Sm, stop);
     HIPCHK(hipGetLastError());
     for (int b = 0; b < T; ++b) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, h->stream, h->Sm, ld, b, h->Linv, stop);
-        if (T > 1) {
-            hipLaunchKernelGGL(k_gj_row, dim3(T), dim3(256), 0, h->stream, h->Sm, ld, b, (const double*)h->Linv, stop);
-            hipLaunchKernelGGL(k_gj_update, dim3(T, T), dim3(256), 0, h->stream, h->Sm, ld, b, stop);
-            hipLaunchKernelGGL(k_gj_col, dim3(T), dim3(256), 0, h->stream, h->Sm, ld, b, (const double*)h->Linv, stop);
-        }
+        hipLaunchKernelGGL(k_gj_panel, dim3(T), dim3(256), 0, h->stream, (const double*)h->Sm, ld, b, h->Qf, h->Cf,
+                           stop);
+        hipLaunchKernelGGL(k_gj_apply, dim3((T + 1) / 2, (T + 1) / 2), dim3(256), 0, h->stream, h->Sm, ld, T, b,
+                           (const double*)h->Qf, (const double*)h->Cf, stop);
     }
     HIPCHK(hipGetLastError());
     {
@@ -854,7 +852,8 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
                 const size_t mm = size_t(h->ld) * h->ld;
                 h->Sm = h->dalloc<double>(mm);
                 h->Sinv = h->dalloc<double>(mm);
-                h->Linv = h->dalloc<double>(size_t(TS) * TS);   // pivot tile inverse of the sweep
+                h->Qf = h->dalloc<double>(size_t(h->ld) * TS);   // sweep panels (T tiles each)
+                h->Cf = h->dalloc<double>(size_t(h->ld) * TS);
                 h->wpre = h->dalloc<double>(h->ld);
                 h->vpre = h->dalloc<double>(std::max(h->ld, m));
                 h->Dw = h->dalloc<double>(n);

@@ -137,12 +137,35 @@ __global__ __launch_bounds__(64) void k_schur_form(const int* __restrict__ Ap, c
 
 // ---- in-place inverse by a block Gauss-Jordan sweep ------------------------------
 //
-// For each pivot tile b (TS x TS):  S_bb <- S_bb^{-1};  S_bj <- S_bb^{-1} S_bj;
-// S_ij <- S_ij - S_ib S_bj;  S_ib <- -S_ib S_bb^{-1}  (i, j != b).  After the
-// last pivot S holds S^{-1}.  Every pivot is a Schur complement of S, and S has
-// eigenvalues >= 1, so every pivot tile has eigenvalues >= 1: no pivoting is
-// needed.  Each step is one small single-workgroup inversion and three fully
-// parallel tile launches, so the serial depth is T = ld/TS steps.
+// For each pivot tile b (TS x TS):  P = S_bb^{-1};  S_bj <- P S_bj;
+// S_ij <- S_ij - S_ib (P S_bj);  S_ib <- -S_ib P;  S_bb <- P  (i, j != b).
+// After the last pivot S holds S^{-1}.  Every pivot is a Schur complement of
+// S, and S has eigenvalues >= 1, so every pivot tile has eigenvalues >= 1: no
+// pivoting is needed.  A step is two launches:
+//   k_gj_panel  (T blocks)   block j inverts the pivot tile in LDS (every
+//               block redundantly: no single-workgroup launch on the critical
+//               path), forms Q_j = P S_bj (Q_b = P) and copies the old column
+//               tile C_j = S_jb; both go to panel buffers in the operand
+//               layouts of the matrix cores;
+//   k_gj_apply  (T x T tiles, a wavefront per tile)  S_ij <- S_ij - C_i Q_j,
+//               S_ib <- -C_i Q_b, S_bj <- Q_j, the products on FP64 MFMA
+//               16x16x4.
+// The dense contraction (T^3 tile products per inversion) runs on the matrix
+// cores; the panels make every tile of a step independent of the others.
+
+using f64x4 = double __attribute__((ext_vector_type(4)));
+
+// Operand layouts of v_mfma_f64_16x16x4f64 for a 32 x 32 tile, 1024 doubles:
+//   left operand (A, 16 x 4 per step):  X[16a + l%16][4s + l/16] at ((a*8 + s)*64 + l)
+//   right operand (B, 4 x 16 per step): X[4s + l/16][16c + l%16] at ((c*8 + s)*64 + l)
+// and the result (16 x 16 per block): lane l, element r holds
+//   D[4*(l/16) + r][l%16].
+__device__ __forceinline__ int frag_left(int row, int col) {
+    return ((row >> 4) * 8 + (col >> 2)) * 64 + (row & 15) + 16 * (col & 3);
+}
+__device__ __forceinline__ int frag_right(int row, int col) {
+    return ((col >> 4) * 8 + (row >> 2)) * 64 + (col & 15) + 16 * (row & 3);
+}
 
 // C (TS x TS, in registers: element e = t + 256q) = A * B for LDS tiles.
 __device__ __forceinline__ void tile_mm(const double (*a)[TS + 1], const double (*b)[TS + 1], double out[4]) {
@@ -163,90 +186,106 @@ __device__ __forceinline__ void tile_load(double (*dst)[TS + 1], const double* S
     for (int e = threadIdx.x; e < TS * TS; e += 256) dst[e / TS][e % TS] = S[base + size_t(e / TS) * ld + e % TS];
 }
 
-// Pivot tile b: Gauss-Jordan inversion of S_bb in LDS (one thread per entry),
-// written back to S_bb and to P.
-__global__ __launch_bounds__(1024) void k_gj_pivot(double* S, int ld, int b, double* P, const int* stop) {
+// Step b, panels: block j of T.  Qf, Cf: T tiles of 1024 doubles each.
+__global__ __launch_bounds__(256) void k_gj_panel(const double* S, int ld, int b, double* Qf, double* Cf,
+                                                  const int* stop) {
     __shared__ double a[TS][TS + 1];
+    __shared__ double sb[TS][TS + 1];
     if (stop && *stop) return;
-    const int r = threadIdx.x / TS, c = threadIdx.x % TS;
-    const size_t base = size_t(b) * TS * ld + size_t(b) * TS;
-    a[r][c] = S[base + size_t(r) * ld + c];
+    const int j = blockIdx.x;
+    tile_load(a, S, ld, b, b);
+    if (j != b) tile_load(sb, S, ld, b, j);
     __syncthreads();
-    for (int j = 0; j < TS; ++j) {
-        const double pv = a[j][j];
-        const double f = a[r][j];
-        const double ajc = a[j][c];
+    // Gauss-Jordan inversion of the pivot tile in LDS, four entries per thread
+    for (int jj = 0; jj < TS; ++jj) {
+        const double pv = a[jj][jj];
+        double f[4], ajc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            f[q] = a[e / TS][jj];
+            ajc[q] = a[jj][e % TS];
+        }
         __syncthreads();
         // pivots are >= 1 in exact arithmetic; the guard keeps a rounding
         // accident from spreading NaN through the preconditioner
         const double pinv = (pv > 0.0 && __builtin_isfinite(pv)) ? 1.0 / pv : 1.0;
-        const double rowj = (c == j) ? pinv : ajc * pinv;
-        if (r == j) a[r][c] = rowj;
-        else a[r][c] = (c == j) ? -f * pinv : a[r][c] - f * rowj;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int r = e / TS, c = e % TS;
+            const double rowj = (c == jj) ? pinv : ajc[q] * pinv;
+            if (r == jj) a[r][c] = rowj;
+            else a[r][c] = (c == jj) ? -f[q] * pinv : a[r][c] - f[q] * rowj;
+        }
         __syncthreads();
     }
-    S[base + size_t(r) * ld + c] = a[r][c];
-    P[size_t(r) * TS + c] = a[r][c];
-}
-
-// Row panel: S_bj <- P S_bj for j != b.
-__global__ __launch_bounds__(256) void k_gj_row(double* S, int ld, int b, const double* P, const int* stop) {
-    __shared__ double pa[TS][TS + 1];
-    __shared__ double sb[TS][TS + 1];
-    if (stop && *stop) return;
-    const int j = blockIdx.x;
-    if (j == b) return;
-    for (int e = threadIdx.x; e < TS * TS; e += 256) pa[e / TS][e % TS] = P[e];
-    tile_load(sb, S, ld, b, j);
-    __syncthreads();
-    double out[4];
-    tile_mm(pa, sb, out);
-    const size_t base = size_t(b) * TS * ld + size_t(j) * TS;
+    double* q = Qf + size_t(j) * TS * TS;
+    if (j == b) {
+        for (int e = threadIdx.x; e < TS * TS; e += 256) q[frag_right(e / TS, e % TS)] = a[e / TS][e % TS];
+    } else {
+        double out[4];
+        tile_mm(a, sb, out);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        S[base + size_t(e / TS) * ld + e % TS] = out[q];
+        for (int k = 0; k < 4; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            q[frag_right(e / TS, e % TS)] = out[k];
+        }
+        // old column tile S_jb, left-operand layout
+        double* c = Cf + size_t(j) * TS * TS;
+        const size_t base = size_t(j) * TS * ld + size_t(b) * TS;
+        for (int e = threadIdx.x; e < TS * TS; e += 256)
+            c[frag_left(e / TS, e % TS)] = S[base + size_t(e / TS) * ld + e % TS];
     }
 }
 
-// Trailing update: S_ij <- S_ij - S_ib S_bj for i, j != b (S_bj already new).
-__global__ __launch_bounds__(256) void k_gj_update(double* S, int ld, int b, const int* stop) {
-    __shared__ double sib[TS][TS + 1];
-    __shared__ double sbj[TS][TS + 1];
+// Step b, update: a wavefront per tile (i, j); blocks of four wavefronts take
+// 2 x 2 tiles.  Grid ((T+1)/2, (T+1)/2).
+__global__ __launch_bounds__(256) void k_gj_apply(double* S, int ld, int T, int b, const double* Qf,
+                                                  const double* Cf, const int* stop) {
     if (stop && *stop) return;
-    const int i = blockIdx.y, j = blockIdx.x;
-    if (i == b || j == b) return;
-    tile_load(sib, S, ld, i, b);
-    tile_load(sbj, S, ld, b, j);
-    __syncthreads();
-    double out[4];
-    tile_mm(sib, sbj, out);
-    const size_t base = size_t(i) * TS * ld + size_t(j) * TS;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int i = 2 * blockIdx.y + (w >> 1), j = 2 * blockIdx.x + (w & 1);
+    if (i >= T || j >= T) return;   // whole wavefronts
+    double* tile = S + size_t(i) * TS * ld + size_t(j) * TS;
+    const double* q = Qf + size_t(j) * TS * TS;
+    if (i == b) {   // new pivot row: S_bj = Q_j
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        S[base + size_t(e / TS) * ld + e % TS] -= out[q];
-    }
-}
-
-// Column panel: S_ib <- -S_ib P for i != b (after the trailing update).
-__global__ __launch_bounds__(256) void k_gj_col(double* S, int ld, int b, const double* P, const int* stop) {
-    __shared__ double sib[TS][TS + 1];
-    __shared__ double pa[TS][TS + 1];
-    if (stop && *stop) return;
-    const int i = blockIdx.x;
-    if (i == b) return;
-    tile_load(sib, S, ld, i, b);
-    for (int e = threadIdx.x; e < TS * TS; e += 256) pa[e / TS][e % TS] = P[e];
-    __syncthreads();
-    double out[4];
-    tile_mm(sib, pa, out);
-    const size_t base = size_t(i) * TS * ld + size_t(b) * TS;
+        for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        S[base + size_t(e / TS) * ld + e % TS] = -out[q];
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * ra + 4 * (l >> 4) + r, col = 16 * cb + (l & 15);
+                    tile[size_t(row) * ld + col] = q[frag_right(row, col)];
+                }
+        return;
     }
+    const double* c = Cf + size_t(i) * TS * TS;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[ra][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < TS / 4; ++s) {
+        const double a0 = c[(0 * 8 + s) * 64 + l], a1 = c[(1 * 8 + s) * 64 + l];
+        const double b0 = q[(0 * 8 + s) * 64 + l], b1 = q[(1 * 8 + s) * 64 + l];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * ra + 4 * (l >> 4) + r, col = 16 * cb + (l & 15);
+                double* dst = tile + size_t(row) * ld + col;
+                *dst = (j == b) ? -acc[ra][cb][r] : *dst - acc[ra][cb][r];
+            }
 }
 
 // Sinv = (S + S^T)/2: the sweep's result is symmetric up to rounding; PCG

@@ -249,6 +249,33 @@ def test_newton_step_preconditioners(precond, spread):
         assert info["pcg_iters"] <= 200, info["pcg_iters"]
 
 
+@pytest.mark.parametrize("m", [40, 300])
+def test_constraint_block_is_exact_for_diagonal_h(m):
+    """With no dose rows H = gamma*I is diagonal, so D = diag(H + Sigma_x) is
+    H + Sigma_x itself; when every row of A is strong the constraint-block
+    preconditioner P = D + A^T Sigma_A A equals the operator and PCG stops
+    after one or two iterations.  A wrong entry anywhere in the dense inverse
+    (a tile of the Gauss-Jordan sweep, the symmetric product) costs many more.
+    m = 300 spans 10 pivot tiles."""
+    import scipy.sparse as sps
+    n = 1500
+    rng = np.random.default_rng(77 + m)
+    A = qpsynth.random_sparse(rng, m, n, 30)
+    prob = qpsynth.QPProblem(gamma=1.0, p=np.zeros(n), J=sps.csr_matrix((0, n)), W=np.zeros(0),
+                             x_lo=np.full(n, -np.inf), x_hi=np.full(n, np.inf), A=A,
+                             A_lo=np.full(m, -np.inf), A_hi=np.zeros(m))
+    sx = rng.uniform(0.0, 9.0, size=n)
+    sA = 10.0 ** rng.uniform(2.0, 4.0, size=m)   # M_ii >> 1: every row strong
+    rhs = rng.standard_normal(n)
+    s = qpgpu.qp_default_settings(pcg_tol=1e-10, precond=1)
+    h = qpgpu.qp_create_from_problem(prob, settings=s)
+    st, dx, info = qpgpu.qp_newton_step(h, sx, sA, rhs)
+    assert st == qpgpu.QP_OK, info
+    K = oracle.condensed_operator_dense(prob, sx, sA)
+    assert np.linalg.norm(K @ dx - rhs) <= 1e-10 * np.linalg.norm(rhs)
+    assert info["pcg_iters"] <= 3, info["pcg_iters"]
+
+
 @pytest.mark.parametrize("precond", [0, 1])
 def test_solve_config1_both_preconditioners(precond):
     prob = qpsynth.config1(4)
