@@ -28,8 +28,8 @@ constexpr int kMaxElemGrid = 2048;  // cap on grid-stride elementwise grids
 // --------------------------------------------------------------------------
 // scalar state shared by kernels (device memory)
 // --------------------------------------------------------------------------
-// PCG scalars.  Each field is written only by the last block of one kernel
-// (see last_block) and read by later kernels, never by the kernel writing it.
+// PCG scalars.  Each field is written by one thread of one kernel and read
+// only by later kernels (kernel boundaries order the accesses).
 struct PcgScal {
     double rho;        // r^T z of the current z
     double beta;       // p <- z + beta p, applied on the fly by the next product
@@ -141,23 +141,6 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
 #pragma unroll
     for (int i = 1; i < kBlock / 64; ++i) s = fmin(s, sh[i]);
     return s;
-}
-
-// Called by every participating block after its thread 0 stored the block's
-// partial(s); `blocks` is the number of participating blocks.  Returns true in
-// exactly one block, the last to arrive, after which every partial is
-// visible to it; that block reduces them in a fixed order (so the result does
-// not depend on arrival order) and must reset the counter to 0 for the next
-// kernel.  The ticket is a device-scope atomic add in global memory.
-__device__ __forceinline__ bool last_block(unsigned* counter, unsigned blocks) {
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(counter, 1u) == blocks - 1) ? 1 : 0;
-    __syncthreads();
-    const bool last = s_last != 0;
-    if (last) __threadfence();
-    return last;
 }
 
 // Gathered vector of a product: x, or (PCG) the search direction z + beta p

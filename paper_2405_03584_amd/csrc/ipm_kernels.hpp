@@ -43,6 +43,10 @@ __device__ __forceinline__ bool pcg_stopped(const Flags* fl) {
 __device__ __forceinline__ bool ipm_finished(const Flags* fl) {
     return block_flag(threadIdx.x == 0 && fl->ipm_done);
 }
+// Stop test for kernels that never write the flags: they cannot change while
+// such a kernel runs, so every thread reads them directly (one uniform load,
+// no barrier), and the read overlaps the kernel's first index loads.
+__device__ __forceinline__ bool pcg_stopped_ro(const Flags* fl) { return pcg_stopped_raw(fl); }
 
 // ==========================================================================
 // Operator kernels (one PCG product q = K p)
@@ -70,7 +74,7 @@ __device__ __forceinline__ Gather make_gather(const double* x, const double* p2,
 // of A: a full wavefront per row.
 template <int G, typename VT, typename AT>
 __global__ __launch_bounds__(kBlock) void k_op_fwd(FwdArgs<VT> a) {
-    if (pcg_stopped(a.fl)) return;
+    if (pcg_stopped_ro(a.fl)) return;
     const Gather g = make_gather(a.x, a.p2, a.sc);
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     if (b < a.nbJ) {
@@ -93,13 +97,11 @@ __global__ __launch_bounds__(kBlock) void k_op_fwd(FwdArgs<VT> a) {
     }
 }
 
-// PCG bookkeeping of an operator product: where the search direction and the
-// scalars live, and the ticket counter of the last-block reductions.
+// PCG bookkeeping of an operator product: where the search direction and
+// beta live.
 struct PcgLink {
     double* p2;            // previous direction p; overwritten with p = x + beta*p
-    PcgScal* sc;
-    Flags* fl;
-    unsigned* ticket;
+    const PcgScal* sc;
 };
 
 template <typename VT>
@@ -138,24 +140,11 @@ __device__ __forceinline__ double direction_entry(const double* x, const PcgLink
     return pj;
 }
 
-// End of a PCG product: block partials of p^T q; the last block reduces them
-// in a fixed order and sets alpha = rho / p^T q (breakdown flag when p^T q is
-// not positive or alpha is not finite).
-__device__ __forceinline__ void product_tail(double dot, double* part, int b, const PcgLink& pl, double* sh) {
+// End of a product: block partials of p^T q (k_pcg_xr reduces them).
+__device__ __forceinline__ void product_tail(double dot, double* part, int b, double* sh) {
     if (!part) return;
     const double tot = block_sum(dot, sh);
     if (threadIdx.x == 0) part[b] = tot;
-    if (!pl.ticket) return;
-    if (last_block(pl.ticket, gridDim.x)) {
-        const double pq = reduce_partials_sum(part, gridDim.x, 1, sh);
-        if (threadIdx.x == 0) {
-            const double alpha = pl.sc->rho / pq;
-            pl.sc->pq = pq;
-            pl.sc->alpha = alpha;
-            if (!(pq > 0.0) || !finite_d(alpha)) pl.fl->pcg_breakdown = 1;
-            *pl.ticket = 0u;
-        }
-    }
 }
 
 // q_j = hs*(J^T t + gamma p + U(w .* U^T p))_j + Sigma_x,j p_j + (A^T u)_j and per-block
@@ -164,7 +153,7 @@ __device__ __forceinline__ void product_tail(double dot, double* part, int b, co
 template <int G, typename VT, typename AT>
 __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
     __shared__ double sh[kBlock / 64];
-    if (pcg_stopped(a.fl)) return;
+    if (pcg_stopped_ro(a.fl)) return;
     constexpr int RPB = kBlock / G;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x % G;
@@ -187,17 +176,19 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
             }
         }
     }
-    product_tail(dot, a.part, b, a.pcg, sh);
+    product_tail(dot, a.part, b, sh);
 }
 
 // ==========================================================================
 // PCG vector updates
 // ==========================================================================
 // One iteration: the product kernels form p = z + beta p on the fly and
-// q = K p, and their last block sets alpha; k_pcg_xr updates x and r and
-// applies the diagonal part of the preconditioner; with the constraint block,
-// k_prec_a, k_prec_symv and k_prec_at finish z.  The last block of the kernel
-// that completes z sets beta = r^T z / rho and rho = r^T z.
+// q = K p with partials of p^T q; k_pcg_xr reduces them (every block, in the
+// same fixed order) into alpha, updates x and r and applies the diagonal part
+// of the preconditioner; with the constraint block, k_prec_a, k_prec_symv and
+// k_prec_at finish z; k_pcg_scalars (one block) reduces r^T r and r^T z into
+// the stop test, beta and rho.  Reductions are finished by the consumer:
+// kernel boundaries make the partials visible without device-wide fences.
 // Preconditioner z = P^{-1} r.  Jacobi (the paper, Section 4.1.2): z = r ./ d
 // with d = diag(K).  Constraint block (woodbury = 1): y = r ./ D with
 // D = diag(Hs + Sigma_x), then z = y - D^{-1} A^T Sigma^{1/2} S^{-1}
@@ -205,21 +196,29 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
 struct PcgArgs {
     int n;
     double* x; double* r; double* z; const double* p; const double* q; const double* d;
+    const double* part_pq; int n_pq;     // partials of p^T q from the product
     double* part_rz;                     // partials of r^T z (Jacobi)
     double* part_rr;                     // partials of r^T r
     int woodbury;
     PcgScal* sc;
     Flags* fl;
-    unsigned* ticket;
 };
 
-// x += alpha p; r -= alpha q; z = r ./ d (Jacobi) or y = r ./ D (constraint
-// block, stored in z until k_prec_at finishes it).  Last block: ||r||^2, the
-// iteration count, convergence and cap flags, and (Jacobi) beta and rho.
+// alpha = rho / p^T q; x += alpha p; r -= alpha q; z = r ./ d (Jacobi) or
+// y = r ./ D (constraint block, stored in z until k_prec_at finishes it);
+// partials of r^T r (and r^T z for Jacobi).
 __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped(a.fl)) return;
-    const double alpha = a.sc->alpha;
+    const double pq = reduce_partials_sum(a.part_pq, a.n_pq, 1, sh);
+    const double alpha = a.sc->rho / pq;
+    const bool bad = !(pq > 0.0) || !finite_d(alpha);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.sc->pq = pq;
+        a.sc->alpha = alpha;
+        if (bad) a.fl->pcg_breakdown = 1;
+    }
+    if (bad) return;
     double rz = 0.0, rr = 0.0;
     for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
         a.x[j] += alpha * a.p[j];
@@ -236,24 +235,42 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
         if (!a.woodbury) a.part_rz[blockIdx.x] = rz;
         a.part_rr[blockIdx.x] = rr;
     }
-    if (last_block(a.ticket, gridDim.x)) {
-        const double rr_t = reduce_partials_sum(a.part_rr, gridDim.x, 1, sh);
-        const double rz_t = a.woodbury ? 0.0 : reduce_partials_sum(a.part_rz, gridDim.x, 1, sh);
-        if (threadIdx.x == 0) {
-            PcgScal* sc = a.sc;
-            sc->rr = rr_t;
-            const int it = sc->iters + 1;
-            sc->iters = it;
-            a.fl->pcg_iters = it;
-            if (rr_t <= sc->tol2) a.fl->pcg_converged = 1;
-            else if (it >= sc->max_iter) a.fl->pcg_capped = 1;
-            if (!a.woodbury) {
-                sc->beta = rz_t / sc->rho;
-                sc->rho = rz_t;
-            }
-            *a.ticket = 0u;
-        }
+}
+
+// One block.  init = 0: ||r||^2, iteration count, convergence / cap flags,
+// beta = r^T z / rho, rho = r^T z.  init = 1 (start of a solve): ||rhs||^2,
+// the stopping threshold, rho, beta = 0 (p was zeroed, so the first
+// direction is z), converged at once when rhs = 0.
+__global__ __launch_bounds__(kBlock) void k_pcg_scalars(const double* part_rz, int n_rz, const double* part_rr,
+                                                        int n_rr, int init, double tol, int max_iter,
+                                                        PcgScal* sc, Flags* fl) {
+    __shared__ double sh[kBlock / 64];
+    if (init ? ipm_finished(fl) : pcg_stopped(fl)) return;
+    const double rz = reduce_partials_sum(part_rz, n_rz, 1, sh);
+    const double rr = reduce_partials_sum(part_rr, n_rr, 1, sh);
+    if (threadIdx.x != 0) return;
+    if (init) {
+        sc->rho = rz;
+        sc->beta = 0.0;
+        sc->alpha = 0.0;
+        sc->pq = 0.0;
+        sc->bnorm2 = rr;
+        sc->rr = rr;
+        sc->tol2 = tol * tol * rr;
+        sc->iters = 0;
+        sc->max_iter = max_iter;
+        fl->pcg_iters = 0;
+        fl->pcg_converged = (rr == 0.0) ? 1 : 0;
+        return;
     }
+    sc->rr = rr;
+    const int it = sc->iters + 1;
+    sc->iters = it;
+    fl->pcg_iters = it;
+    if (rr <= sc->tol2) fl->pcg_converged = 1;
+    else if (it >= sc->max_iter) fl->pcg_capped = 1;
+    sc->beta = rz / sc->rho;
+    sc->rho = rz;
 }
 
 struct PcgInitArgs {
@@ -264,20 +281,20 @@ struct PcgInitArgs {
     double* x; double* r; double* z; double* p; const double* d;
     double* part_rz; double* part_rr;
     int woodbury;
-    double tol;
-    int max_iter;
-    PcgScal* sc;
     Flags* fl;
-    unsigned* ticket;
 };
 
-// x = 0; r = rhs; z = r ./ d; p = 0 with beta = 0 (so the first product's
-// direction is z).  Last block: ||rhs||^2, the stopping threshold, cleared
-// PCG flags of the previous solve (converged at once when rhs = 0) and
-// (Jacobi) rho = r^T z.
+// x = 0; r = rhs; z = r ./ d; p = 0; partials.  Clears the PCG flags of the
+// previous solve (no other block of this kernel reads them; later kernels of
+// this solve see them cleared).
 __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
     __shared__ double sh[kBlock / 64];
     if (ipm_finished(a.fl)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.fl->pcg_converged = 0;
+        a.fl->pcg_breakdown = 0;
+        a.fl->pcg_capped = 0;
+    }
     const double mu = a.ipm ? a.ipm->mu : 0.0;
     double rz = 0.0, rr = 0.0;
     for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
@@ -296,27 +313,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
         if (!a.woodbury) a.part_rz[blockIdx.x] = rz;
         a.part_rr[blockIdx.x] = rr;
     }
-    if (last_block(a.ticket, gridDim.x)) {
-        const double rr_t = reduce_partials_sum(a.part_rr, gridDim.x, 1, sh);
-        const double rz_t = a.woodbury ? 0.0 : reduce_partials_sum(a.part_rz, gridDim.x, 1, sh);
-        if (threadIdx.x == 0) {
-            PcgScal* sc = a.sc;
-            sc->rho = rz_t;
-            sc->beta = 0.0;
-            sc->alpha = 0.0;
-            sc->pq = 0.0;
-            sc->bnorm2 = rr_t;
-            sc->rr = rr_t;
-            sc->tol2 = a.tol * a.tol * rr_t;
-            sc->iters = 0;
-            sc->max_iter = a.max_iter;
-            a.fl->pcg_iters = 0;
-            a.fl->pcg_breakdown = 0;
-            a.fl->pcg_capped = 0;
-            a.fl->pcg_converged = (rr_t == 0.0) ? 1 : 0;
-            *a.ticket = 0u;
-        }
-    }
 }
 
 // Constraint-block preconditioner, step 1: w_r = sqrt(Sigma_i) (A y)_i for the
@@ -325,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
 __global__ __launch_bounds__(kBlock) void k_prec_a(const int* Ap, const int* Ac, const double* Av,
                                                    const double* y, const double* sigA, const int* idx, int k,
                                                    int ld, int m, double* w, double* vm, const Flags* fl) {
-    if (pcg_stopped(fl)) return;
+    if (pcg_stopped_ro(fl)) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     for (int q = row * 64 + lane; q < m && q < (row + 1) * 64; q += 64) vm[q] = 0.0;
@@ -341,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_prec_a(const int* Ap, const int* Ac,
 __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, int ld, const double* w,
                                                       const double* sigA, const int* idx, int k, double* vm,
                                                       const Flags* fl) {
-    if (pcg_stopped(fl)) return;
+    if (pcg_stopped_ro(fl)) return;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= k) return;
@@ -360,16 +356,14 @@ __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, int ld
     }
 }
 
-// Step 3: z_j = y_j - (A^T v)_j / D_j (y held in z) and partials of r^T z;
-// the last block sets beta = r^T z / rho (0 at the start of a solve, init = 1)
-// and rho = r^T z.  G lanes per row of A^T, grid-stride with a capped grid.
+// Step 3: z_j = y_j - (A^T v)_j / D_j (y held in z) and partials of r^T z.
+// G lanes per row of A^T, grid-stride with a capped grid.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* Atc, const double* Atv,
                                                     const double* v, const double* D, const double* r,
-                                                    double* z, int n, int init, double* part_rz, PcgScal* sc,
-                                                    unsigned* ticket, const Flags* fl) {
+                                                    double* z, int n, double* part_rz, const Flags* fl) {
     __shared__ double sh[kBlock / 64];
-    if (pcg_stopped(fl)) return;
+    if (pcg_stopped_ro(fl)) return;
     constexpr int RPB = kBlock / G;
     const int lane = threadIdx.x % G;
     double rz = 0.0;
@@ -387,14 +381,6 @@ __global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* A
     }
     rz = block_sum(rz, sh);
     if (threadIdx.x == 0) part_rz[blockIdx.x] = rz;
-    if (last_block(ticket, gridDim.x)) {
-        const double t = reduce_partials_sum(part_rz, gridDim.x, 1, sh);
-        if (threadIdx.x == 0) {
-            sc->beta = init ? 0.0 : t / sc->rho;
-            sc->rho = t;
-            *ticket = 0u;
-        }
-    }
 }
 
 // ==========================================================================
@@ -834,15 +820,13 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double*
 
 // Low-rank factor product v = w .* (U^T p) (eq. (bfgs_hessian) applied
 // matrix-free), p the gathered vector: per-block partials of up to 32 columns
-// (grid.y walks column groups); the last block reduces them in a fixed order.
+// (grid.y walks column groups), then a one-block fixed-order reduction.
 // Partial layout part[b * k + c] for x-block b and column c.
 __global__ __launch_bounds__(kBlock) void k_lr_partial(const double* U, int n, int k, const double* x,
-                                                       const double* p2, const PcgScal* sc, const double* w,
-                                                       double* part, double* v, unsigned* ticket,
+                                                       const double* p2, const PcgScal* sc, double* part,
                                                        const Flags* fl) {
     __shared__ double sh[kBlock / 64];
-    __shared__ double sub[kBlock / 32][32];
-    if (pcg_stopped(fl)) return;
+    if (pcg_stopped_ro(fl)) return;
     const Gather g = make_gather(x, p2, sc);
     const int c0 = blockIdx.y * 32;
     const int kc = min(32, k - c0);
@@ -862,20 +846,25 @@ __global__ __launch_bounds__(kBlock) void k_lr_partial(const double* U, int n, i
             if (threadIdx.x == 0) part[size_t(blockIdx.x) * k + c0 + c] = t;
         }
     }
-    if (!last_block(ticket, gridDim.x * gridDim.y)) return;
-    // thread (s, c): column c of a 32-column group, x-blocks s, s+8, s+16, ...
+}
+
+// v_c = w_c * sum_b part[b][c]: thread (s, c) adds x-blocks s, s+8, ... of
+// column c of a 32-column group, then the 8 sums are added in order.
+__global__ __launch_bounds__(kBlock) void k_lr_reduce(const double* part, int nb, int k, const double* w,
+                                                      double* v, const Flags* fl) {
+    __shared__ double sub[kBlock / 32][32];
+    if (pcg_stopped_ro(fl)) return;
     const int c = threadIdx.x & 31, s8 = threadIdx.x >> 5;
     constexpr int S = kBlock / 32;
     for (int cg = 0; cg < k; cg += 32) {
         const int col = min(cg + c, k - 1);
         double a = 0.0;
-        for (int bx = s8; bx < int(gridDim.x); bx += 8 * S) {
+        for (int bx = s8; bx < nb; bx += 8 * S) {
             double t[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                t[u] = part[size_t(min(bx + u * S, int(gridDim.x) - 1)) * k + col];
+            for (int u = 0; u < 8; ++u) t[u] = part[size_t(min(bx + u * S, nb - 1)) * k + col];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a += (bx + u * S < int(gridDim.x)) ? t[u] : 0.0;
+            for (int u = 0; u < 8; ++u) a += (bx + u * S < nb) ? t[u] : 0.0;
         }
         sub[s8][c] = a;
         __syncthreads();
@@ -887,7 +876,6 @@ __global__ __launch_bounds__(kBlock) void k_lr_partial(const double* U, int n, i
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *ticket = 0u;
 }
 
 // Mixed-precision refinement helpers (skipped once the IPM has finished).

@@ -39,6 +39,7 @@ struct LineArgs {
     double* c;             // per slot (lptr[L] entries)
     double* u; const double* sigA;
     int nbL;               // blocks working on lines (one line per block)
+    int nbA;               // blocks working on rows of A (first in the grid)
     const Flags* fl;
 };
 
@@ -48,15 +49,24 @@ __global__ __launch_bounds__(kBlock) void k_line_pass(LineArgs<VT> a) {
     constexpr int RH = kLineHeld;
     static_assert(NW == 4, "the pass-1 combine adds four wavefront partials");
     __shared__ AT part[NW][64];
-    if (pcg_stopped(a.fl)) return;
-    const Gather g = make_gather(a.x, a.p2, a.sc);
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    // Rows of A come first in the grid, so their longer dependent chains run
+    // beside the line blocks instead of trailing them; the line blocks are
+    // remapped so each XCD streams one contiguous range of lines.
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
+    const bool arow = int(blockIdx.x) < a.nbA;
+    const int b = arow ? a.nbL : xcd_remap(int(blockIdx.x) - a.nbA, int(gridDim.x) - a.nbA);
+    // the line's extent is loaded before the stop test so both loads overlap
+    // (blocks past the lines read the last line's extent, unused; L = 0 reads
+    // nothing)
+    const int lb = max(0, min(b, a.L - 1));
+    const int off = a.L > 0 ? a.lptr[lb] : 0;
+    const int end = a.L > 0 ? a.lptr[lb + 1] : 0;
+    if (pcg_stopped_ro(a.fl)) return;
+    const Gather g = make_gather(a.x, a.p2, a.sc);
     if (b < a.nbL) {
         const int l = b;
-        const int off = a.lptr[l];
-        const int len = a.lptr[l + 1] - off;
+        const int len = end - off;
         const int q = (len + NW - 1) / NW;
         const int k0 = __builtin_amdgcn_readfirstlane(min(len, w * q));
         const int k1 = __builtin_amdgcn_readfirstlane(min(len, k0 + q));
@@ -121,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_line_pass(LineArgs<VT> a) {
             if (writer && kg + slot < k1) a.c[off + kg + slot] = double(cs);
         }
     } else {
-        const int row = (b - a.nbL) * NW + w;
+        const int row = int(blockIdx.x) * NW + w;
         if (row < a.m) {
             double s = row_dot_lane_g<64, double, double>(a.Ap, a.Ac, a.Av, g, row, lane);
             s = group_sum<double, 64>(s);
@@ -146,11 +156,11 @@ struct SpotArgs {
 
 // q_j = hs*((J^T W J p)_j + gamma p_j + (U(w .* U^T p))_j) + Sigma_x,j p_j + (A^T u)_j
 // with G lanes per spot, per-block partials of p^T q and, in a PCG product,
-// p stored back and alpha set by the last block.
+// p stored back.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_spot_pass(SpotArgs a) {
     __shared__ double sh[kBlock / 64];
-    if (pcg_stopped(a.fl)) return;
+    if (pcg_stopped_ro(a.fl)) return;
     constexpr int RPB = kBlock / G;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x % G;
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_spot_pass(SpotArgs a) {
             }
         }
     }
-    product_tail(dot, a.part, b, a.pcg, sh);
+    product_tail(dot, a.part, b, sh);
 }
 
 }  // namespace qpg

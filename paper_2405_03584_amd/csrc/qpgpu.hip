@@ -103,7 +103,6 @@ struct qp_handle {
     double* log = nullptr;
     IpmScal* isc = nullptr;
     PcgScal* psc = nullptr;
-    unsigned* ticket = nullptr;   // last-block counter of the fused reductions (0 between kernels)
     Flags* fl = nullptr;
     Flags* fl_host = nullptr;   // pinned, 2 slots
 
@@ -151,8 +150,9 @@ void lowrank_prepare(qp_handle* h, const double* x, const double* p2, const Flag
     if (h->k == 0) return;
     const int gy = (h->k + 31) / 32;
     hipLaunchKernelGGL(k_lr_partial, dim3(kLrBlocks, gy), dim3(kBlock), 0, h->stream, (const double*)h->U, h->n,
-                       h->k, x, p2, (const PcgScal*)h->psc, (const double*)h->w, h->lr_part, h->lr_v, h->ticket,
-                       fl);
+                       h->k, x, p2, (const PcgScal*)h->psc, h->lr_part, fl);
+    hipLaunchKernelGGL(k_lr_reduce, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->lr_part, kLrBlocks,
+                       h->k, (const double*)h->w, h->lr_v, fl);
     HIPCHK(hipGetLastError());
 }
 
@@ -215,14 +215,12 @@ template <>
 const bf16_t* line_vals<bf16_t>(qp_handle* h) { return h->lval16; }
 
 // PCG link of a product: in a PCG product (pcg = true) the gathered vector is
-// z + beta*p, p is written back and the last block sets alpha.
+// z + beta*p and p is written back.
 PcgLink pcg_link(qp_handle* h, bool pcg) {
     PcgLink l{};
     if (pcg) {
         l.p2 = h->pp;
         l.sc = h->psc;
-        l.fl = h->fl;
-        l.ticket = h->ticket;
     }
     return l;
 }
@@ -243,6 +241,7 @@ int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, 
     f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.c = h->lc; f.u = h->u; f.sigA = sigA; f.fl = fl;
     f.nbL = h->L;
     const int nbA = f.m > 0 ? grid_rows(f.m, 64) : 0;
+    f.nbA = nbA;
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
     hipLaunchKernelGGL((k_line_pass<VT, AT>), dim3(std::max(1, f.nbL + nbA)), dim3(kBlock), 0, h->stream, f);
     HIPCHK(hipGetLastError());
@@ -401,8 +400,8 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
 }
 
 // z = P^{-1} r for the constraint-block preconditioner, given y = r ./ Dw in z;
-// sets beta and rho on the device.
-void apply_precond(qp_handle* h, const double* D, const double* sigA, int init) {
+// returns the number of r^T z partials.
+int apply_precond(qp_handle* h, const double* D, const double* sigA) {
     const int ld = h->ldcur, k = h->kcur, m = h->m;
     const int rows_a = std::max(ld, (m + 63) / 64);
     hipLaunchKernelGGL(k_prec_a, dim3((rows_a + 3) / 4), dim3(kBlock), 0, h->stream, (const int*)h->Ap,
@@ -414,8 +413,9 @@ void apply_precond(qp_handle* h, const double* D, const double* sigA, int init) 
     const int grid = grid_rows_capped(h->n, G);
     hipLaunchKernelGGL(k_prec_at<G>, dim3(grid), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
                        (const int*)h->Atc, (const double*)h->Atv, (const double*)h->vpre, D, (const double*)h->pr,
-                       h->pz, h->n, init, h->part_rz, h->psc, h->ticket, (const Flags*)h->fl);
+                       h->pz, h->n, h->part_rz, (const Flags*)h->fl);
     HIPCHK(hipGetLastError());
+    return grid;
 }
 
 void autotune_schedule(qp_handle* h) {
@@ -489,17 +489,18 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     PcgInitArgs ia{};
     ia.n = n; ia.rhs_a = rhs_a; ia.rhs_b = rhs_b; ia.ipm = ipm_mode ? h->isc : nullptr;
     ia.x = h->px; ia.r = h->pr; ia.z = h->pz; ia.p = h->pp; ia.d = dd;
-    ia.part_rz = h->part_rz; ia.part_rr = h->part_rr; ia.woodbury = wb;
-    ia.tol = h->set.pcg_tol; ia.max_iter = h->set.pcg_max_iter;
-    ia.sc = h->psc; ia.fl = h->fl; ia.ticket = h->ticket;
+    ia.part_rz = h->part_rz; ia.part_rr = h->part_rr; ia.woodbury = wb; ia.fl = h->fl;
     hipLaunchKernelGGL(k_pcg_init0, dim3(ge), dim3(kBlock), 0, h->stream, ia);
     HIPCHK(hipGetLastError());
-    if (wb) apply_precond(h, dh, sigA, 1);
+    const int n_rz = wb ? apply_precond(h, dh, sigA) : ge;
+    hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
+                       (const double*)h->part_rr, ge, 1, h->set.pcg_tol, h->set.pcg_max_iter, h->psc, h->fl);
+    HIPCHK(hipGetLastError());
 
     PcgArgs pa{};
     pa.n = n; pa.x = h->px; pa.r = h->pr; pa.z = h->pz; pa.p = h->pp; pa.q = h->pq; pa.d = dd;
-    pa.part_rz = h->part_rz; pa.part_rr = h->part_rr;
-    pa.woodbury = wb; pa.sc = h->psc; pa.fl = h->fl; pa.ticket = h->ticket;
+    pa.part_pq = h->part; pa.part_rz = h->part_rz; pa.part_rr = h->part_rr;
+    pa.woodbury = wb; pa.sc = h->psc; pa.fl = h->fl;
 
     const bool timing = h->set.timing != 0 && tacc != nullptr;
     const int slot_begin = tacc ? tacc->pairs : 0;
@@ -511,9 +512,11 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
             slot = tacc->pairs++;
             tacc->valid.push_back(1);
         }
-        apply_op_prec(h, prec, h->pz, h->pq, sigx, sigA, hs, true, timed, slot);
+        pa.n_pq = apply_op_prec(h, prec, h->pz, h->pq, sigx, sigA, hs, true, timed, slot);
         hipLaunchKernelGGL(k_pcg_xr, dim3(ge), dim3(kBlock), 0, h->stream, pa);
-        if (wb) apply_precond(h, dh, sigA, 0);
+        if (wb) apply_precond(h, dh, sigA);
+        hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
+                           (const double*)h->part_rr, ge, 0, 0.0, 0, h->psc, h->fl);
     };
     auto snapshot = [&](int slot) {
         HIPCHK(hipMemcpyAsync(&h->fl_host[slot], h->fl, sizeof(Flags), hipMemcpyDeviceToHost, h->stream));
@@ -867,8 +870,6 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->log = h->dalloc<double>(4 * size_t(h->set.max_ipm_iter + 1));
         h->isc = h->dalloc<IpmScal>(1);
         h->psc = h->dalloc<PcgScal>(1);
-        h->ticket = h->dalloc<unsigned>(1);
-        HIPCHK(hipMemsetAsync(h->ticket, 0, sizeof(unsigned), h->stream));
         HIPCHK(hipMemsetAsync(h->psc, 0, sizeof(PcgScal), h->stream));
         h->fl = h->dalloc<Flags>(1);
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->fl_host), 2 * sizeof(Flags), hipHostMallocDefault));

@@ -159,7 +159,7 @@ using f64x4 = double __attribute__((ext_vector_type(4)));
 //   left operand (A, 16 x 4 per step):  X[16a + l%16][4s + l/16] at ((a*8 + s)*64 + l)
 //   right operand (B, 4 x 16 per step): X[4s + l/16][16c + l%16] at ((c*8 + s)*64 + l)
 // and the result (16 x 16 per block): lane l, element r holds
-//   D[4*(l/16) + r][l%16].
+//   D[l/16 + 4r][l%16].
 __device__ __forceinline__ int frag_left(int row, int col) {
     return ((row >> 4) * 8 + (col >> 2)) * 64 + (row & 15) + 16 * (col & 3);
 }
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void k_gj_apply(double* S, int ld, int T, int 
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * ra + 4 * (l >> 4) + r, col = 16 * cb + (l & 15);
+                    const int row = 16 * ra + (l >> 4) + 4 * r, col = 16 * cb + (l & 15);
                     tile[size_t(row) * ld + col] = q[frag_right(row, col)];
                 }
         return;
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_gj_apply(double* S, int ld, int T, int 
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = 16 * ra + 4 * (l >> 4) + r, col = 16 * cb + (l & 15);
+                const int row = 16 * ra + (l >> 4) + 4 * r, col = 16 * cb + (l & 15);
                 double* dst = tile + size_t(row) * ld + col;
                 *dst = (j == b) ? -acc[ra][cb][r] : *dst - acc[ra][cb][r];
             }
