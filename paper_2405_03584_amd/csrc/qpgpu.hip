@@ -95,7 +95,7 @@ struct qp_handle {
     // constraint-block preconditioner (dense m x m, leading dimension ld)
     int woodbury = 0, ld = 0, T = 0;            // allocation sizes (all m rows)
     int kcur = 0, ldcur = 0, Tcur = 0;           // strong rows of the current build
-    double *Sm = nullptr, *Sinv = nullptr, *Qf = nullptr, *Cf = nullptr, *wpre = nullptr, *vpre = nullptr;
+    double *Sm = nullptr, *Sm2 = nullptr, *Sinv = nullptr, *Pbuf = nullptr, *wpre = nullptr, *vpre = nullptr;
     double* Dw = nullptr;                        // D plus the weak rows' diagonal
     double *lr_part = nullptr, *lr_v = nullptr;  // low-rank term: U^T p partials and w .* U^T p
     int *rflag = nullptr, *rpos = nullptr, *ridx = nullptr, *kdev = nullptr;
@@ -383,17 +383,21 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
                        (const int*)h->Atc, (const double*)h->Atv, (const double*)h->Dw, sigA,
                        (const int*)h->rpos, (const int*)h->ridx, k, ld, h->Sm, stop);
     HIPCHK(hipGetLastError());
-    for (int b = 0; b < T; ++b) {
-        hipLaunchKernelGGL(k_gj_panel, dim3(T), dim3(256), 0, h->stream, (const double*)h->Sm, ld, b, h->Qf, h->Cf,
-                           stop);
-        hipLaunchKernelGGL(k_gj_apply, dim3((T + 1) / 2, (T + 1) / 2), dim3(256), 0, h->stream, h->Sm, ld, T, b,
-                           (const double*)h->Qf, (const double*)h->Cf, stop);
-    }
+    // sweep: S alternates between Sm and Sm2; P between the two halves of Pbuf
+    double* Sb[2] = {h->Sm, h->Sm2};
+    double* Pb[2] = {h->Pbuf, h->Pbuf + 2 * TS * TS};
+    hipLaunchKernelGGL(k_gj_pivot0, dim3(1), dim3(256), 0, h->stream, (const double*)h->Sm, ld, Pb[0], stop);
+    const int gx = (T + 1) / 2;
+    for (int b = 0; b < T; ++b)
+        hipLaunchKernelGGL(k_gj_step, dim3(gx * gx + (b + 1 < T ? 1 : 0)), dim3(256), 0, h->stream,
+                           (const double*)Sb[b & 1],
+                           Sb[(b + 1) & 1], ld, T, b, (const double*)Pb[b & 1], Pb[(b + 1) & 1], stop);
+    const double* Sfin = Sb[T & 1];
     HIPCHK(hipGetLastError());
     {
         const size_t N = size_t(ld) * ld;
         const int g = int(std::min<size_t>((N + 255) / 256, 4096));
-        hipLaunchKernelGGL(k_symmetrize, dim3(g), dim3(256), 0, h->stream, (const double*)h->Sm, ld, h->Sinv, stop);
+        hipLaunchKernelGGL(k_symmetrize, dim3(g), dim3(256), 0, h->stream, Sfin, ld, h->Sinv, stop);
     }
     HIPCHK(hipGetLastError());
     return true;
@@ -855,8 +859,8 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
                 const size_t mm = size_t(h->ld) * h->ld;
                 h->Sm = h->dalloc<double>(mm);
                 h->Sinv = h->dalloc<double>(mm);
-                h->Qf = h->dalloc<double>(size_t(h->ld) * TS);   // sweep panels (T tiles each)
-                h->Cf = h->dalloc<double>(size_t(h->ld) * TS);
+                h->Sm2 = h->dalloc<double>(mm);                       // second matrix of the sweep
+                h->Pbuf = h->dalloc<double>(4 * size_t(TS) * TS);      // two pivot inverses, both layouts
                 h->wpre = h->dalloc<double>(h->ld);
                 h->vpre = h->dalloc<double>(std::max(h->ld, m));
                 h->Dw = h->dalloc<double>(n);

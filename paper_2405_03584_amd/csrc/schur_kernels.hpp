@@ -135,23 +135,21 @@ __global__ __launch_bounds__(64) void k_schur_form(const int* __restrict__ Ap, c
     }
 }
 
-// ---- in-place inverse by a block Gauss-Jordan sweep ------------------------------
+// ---- inverse by a block Gauss-Jordan sweep --------------------------------------
 //
 // For each pivot tile b (TS x TS):  P = S_bb^{-1};  S_bj <- P S_bj;
 // S_ij <- S_ij - S_ib (P S_bj);  S_ib <- -S_ib P;  S_bb <- P  (i, j != b).
 // After the last pivot S holds S^{-1}.  Every pivot is a Schur complement of
 // S, and S has eigenvalues >= 1, so every pivot tile has eigenvalues >= 1: no
-// pivoting is needed.  A step is two launches:
-//   k_gj_panel  (T blocks)   block j inverts the pivot tile in LDS (every
-//               block redundantly: no single-workgroup launch on the critical
-//               path), forms Q_j = P S_bj (Q_b = P) and copies the old column
-//               tile C_j = S_jb; both go to panel buffers in the operand
-//               layouts of the matrix cores;
-//   k_gj_apply  (T x T tiles, a wavefront per tile)  S_ij <- S_ij - C_i Q_j,
-//               S_ib <- -C_i Q_b, S_bj <- Q_j, the products on FP64 MFMA
-//               16x16x4.
-// The dense contraction (T^3 tile products per inversion) runs on the matrix
-// cores; the panels make every tile of a step independent of the others.
+// pivoting is needed.
+//
+// One launch per pivot (k_gj_step), reading the matrix of the previous step
+// and writing the next one (two buffers, so no tile waits for another): a
+// wavefront per 32 x 32 tile forms Q_j = P S_bj and its update on FP64 MFMA
+// 16x16x4, and the workgroup holding tile (b+1, b+1) -- dispatched first --
+// inverts that tile once it is final, so P for the next step is ready when
+// the launch ends.  The step is latency-bound at these sizes (~10^9 flops per
+// inversion); one launch per pivot keeps the serial chain at T launches.
 
 using f64x4 = double __attribute__((ext_vector_type(4)));
 
@@ -166,126 +164,225 @@ __device__ __forceinline__ int frag_left(int row, int col) {
 __device__ __forceinline__ int frag_right(int row, int col) {
     return ((col >> 4) * 8 + (row >> 2)) * 64 + (col & 15) + 16 * (row & 3);
 }
+// Row / column of element r of 16 x 16 block (ra, cb) in lane l.
+__device__ __forceinline__ int res_row(int ra, int l, int r) { return 16 * ra + (l >> 4) + 4 * r; }
+__device__ __forceinline__ int res_col(int cb, int l) { return 16 * cb + (l & 15); }
 
-// C (TS x TS, in registers: element e = t + 256q) = A * B for LDS tiles.
-__device__ __forceinline__ void tile_mm(const double (*a)[TS + 1], const double (*b)[TS + 1], double out[4]) {
-    const int t = threadIdx.x;
+// 1/v for v >= 1 (pivots of S): hardware reciprocal estimate refined by two
+// Newton steps (r <- r + r(1 - v r)), accurate to about one ulp; a pivot that
+// is not a finite number >= some tiny positive value maps to 1 so a rounding
+// accident cannot spread NaN through the preconditioner.
+__device__ __forceinline__ double pivot_recip(double v) {
+    if (!(v > 0.0 && __builtin_isfinite(v))) return 1.0;
+    double r = __builtin_amdgcn_rcp(v);
+    r = fma(r, fma(-v, r, 1.0), r);
+    r = fma(r, fma(-v, r, 1.0), r);
+    return r;
+}
+
+// Gauss-Jordan inversion of a TS x TS tile in LDS by the whole workgroup
+// (256 threads).  Thread t keeps entries (t/TS + 8q, t%TS), q < 4, in
+// registers; each elimination step needs only the current pivot row and
+// pivot column, which their owners publish in double-buffered LDS arrays, so
+// a step is one barrier.  The step is branch-free: all its LDS reads are
+// issued together and selects replace the special cases (pivot row, pivot
+// column).
+__device__ __forceinline__ void lds_gj_invert(double (*a)[TS + 1]) {
+    __shared__ double rowbuf[2][TS], colbuf[2][TS];
+    const int c = threadIdx.x % TS, r0 = threadIdx.x / TS;
+    double v[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = t + 256 * q;
-        const int r = e / TS, c = e % TS;
-        double s = 0.0;
-#pragma unroll 8
-        for (int k = 0; k < TS; ++k) s += a[r][k] * b[k][c];
-        out[q] = s;
-    }
-}
-
-__device__ __forceinline__ void tile_load(double (*dst)[TS + 1], const double* S, int ld, int ti, int tj) {
-    const size_t base = size_t(ti) * TS * ld + size_t(tj) * TS;
-    for (int e = threadIdx.x; e < TS * TS; e += 256) dst[e / TS][e % TS] = S[base + size_t(e / TS) * ld + e % TS];
-}
-
-// Step b, panels: block j of T.  Qf, Cf: T tiles of 1024 doubles each.
-__global__ __launch_bounds__(256) void k_gj_panel(const double* S, int ld, int b, double* Qf, double* Cf,
-                                                  const int* stop) {
-    __shared__ double a[TS][TS + 1];
-    __shared__ double sb[TS][TS + 1];
-    if (stop && *stop) return;
-    const int j = blockIdx.x;
-    tile_load(a, S, ld, b, b);
-    if (j != b) tile_load(sb, S, ld, b, j);
+    for (int q = 0; q < 4; ++q) v[q] = a[r0 + 8 * q][c];
+    if (r0 == 0) rowbuf[0][c] = v[0];
+    if (c == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) colbuf[0][r0 + 8 * q] = v[q];
     __syncthreads();
-    // Gauss-Jordan inversion of the pivot tile in LDS, four entries per thread
+#pragma unroll
     for (int jj = 0; jj < TS; ++jj) {
-        const double pv = a[jj][jj];
-        double f[4], ajc[4];
+        const int cur = jj & 1, nxt = cur ^ 1;
+        const double pv = rowbuf[cur][jj];
+        const double rc = rowbuf[cur][c];
+        double f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) f[q] = colbuf[cur][r0 + 8 * q];
+        const double pinv = pivot_recip(pv);
+        const double rowj = (c == jj) ? pinv : rc * pinv;
+        // new entry: rowj on the pivot row; -f*pinv on the pivot column;
+        // v - f*rowj elsewhere
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int e = threadIdx.x + 256 * q;
-            f[q] = a[e / TS][jj];
-            ajc[q] = a[jj][e % TS];
+            const double base = (c == jj) ? 0.0 : v[q];
+            const double nv = fma(-f[q], rowj, base);
+            v[q] = (r0 + 8 * q == jj) ? rowj : nv;
         }
-        __syncthreads();
-        // pivots are >= 1 in exact arithmetic; the guard keeps a rounding
-        // accident from spreading NaN through the preconditioner
-        const double pinv = (pv > 0.0 && __builtin_isfinite(pv)) ? 1.0 / pv : 1.0;
+        if (jj + 1 < TS) {   // publish row and column jj+1 of the updated tile
+            if (r0 == ((jj + 1) & 7)) rowbuf[nxt][c] = v[(jj + 1) >> 3];
+            if (c == jj + 1)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = threadIdx.x + 256 * q;
-            const int r = e / TS, c = e % TS;
-            const double rowj = (c == jj) ? pinv : ajc[q] * pinv;
-            if (r == jj) a[r][c] = rowj;
-            else a[r][c] = (c == jj) ? -f[q] * pinv : a[r][c] - f[q] * rowj;
+                for (int q = 0; q < 4; ++q) colbuf[nxt][r0 + 8 * q] = v[q];
         }
         __syncthreads();
     }
-    double* q = Qf + size_t(j) * TS * TS;
-    if (j == b) {
-        for (int e = threadIdx.x; e < TS * TS; e += 256) q[frag_right(e / TS, e % TS)] = a[e / TS][e % TS];
-    } else {
-        double out[4];
-        tile_mm(a, sb, out);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = threadIdx.x + 256 * k;
-            q[frag_right(e / TS, e % TS)] = out[k];
-        }
-        // old column tile S_jb, left-operand layout
-        double* c = Cf + size_t(j) * TS * TS;
-        const size_t base = size_t(j) * TS * ld + size_t(b) * TS;
-        for (int e = threadIdx.x; e < TS * TS; e += 256)
-            c[frag_left(e / TS, e % TS)] = S[base + size_t(e / TS) * ld + e % TS];
+    for (int q = 0; q < 4; ++q) a[r0 + 8 * q][c] = v[q];
+    __syncthreads();
+}
+
+// P (in LDS) to both operand layouts: P[0..1024) left, P[1024..2048) right.
+__device__ __forceinline__ void store_pivot(const double (*a)[TS + 1], double* P) {
+    for (int e = threadIdx.x; e < TS * TS; e += 256) {
+        const int r = e / TS, c = e % TS;
+        P[frag_left(r, c)] = a[r][c];
+        P[TS * TS + frag_right(r, c)] = a[r][c];
     }
 }
 
-// Step b, update: a wavefront per tile (i, j); blocks of four wavefronts take
-// 2 x 2 tiles.  Grid ((T+1)/2, (T+1)/2).
-__global__ __launch_bounds__(256) void k_gj_apply(double* S, int ld, int T, int b, const double* Qf,
-                                                  const double* Cf, const int* stop) {
+// Inverse of the first pivot tile S_00 into P (one workgroup).
+__global__ __launch_bounds__(256) void k_gj_pivot0(const double* S, int ld, double* P, const int* stop) {
+    __shared__ double a[TS][TS + 1];
     if (stop && *stop) return;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int i = 2 * blockIdx.y + (w >> 1), j = 2 * blockIdx.x + (w & 1);
-    if (i >= T || j >= T) return;   // whole wavefronts
-    double* tile = S + size_t(i) * TS * ld + size_t(j) * TS;
-    const double* q = Qf + size_t(j) * TS * TS;
-    if (i == b) {   // new pivot row: S_bj = Q_j
+    for (int e = threadIdx.x; e < TS * TS; e += 256) a[e / TS][e % TS] = S[size_t(e / TS) * ld + e % TS];
+    __syncthreads();
+    lds_gj_invert(a);
+    store_pivot(a, P);
+}
+
+// New value of tile (i, j) at pivot step b, in the result layout (o[ra][cb]
+// element r is entry (res_row(ra, l, r), res_col(cb, l))); x: this
+// wavefront's LDS exchange buffer (TS*TS doubles).
+__device__ __forceinline__ void tile_step(const double* __restrict__ So, int ld, int b, int i, int j,
+                                          const double* __restrict__ Pin, double* x, int l, f64x4 (&o)[2][2]) {
+    const double* P_left = Pin;
+    const double* P_right = Pin + TS * TS;
+    if (i == b && j == b) {          // S_bb <- P
 #pragma unroll
         for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * ra + (l >> 4) + 4 * r, col = 16 * cb + (l & 15);
-                    tile[size_t(row) * ld + col] = q[frag_right(row, col)];
-                }
+                for (int r = 0; r < 4; ++r) o[ra][cb][r] = P_left[frag_left(res_row(ra, l, r), res_col(cb, l))];
         return;
     }
-    const double* c = Cf + size_t(i) * TS * TS;
     f64x4 acc[2][2];
 #pragma unroll
     for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) acc[ra][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const double* c = So + size_t(i) * TS * ld + size_t(b) * TS;   // C_i = S_ib (left operand)
+    if (j == b) {                    // S_ib <- -C_i P
+#pragma unroll
+        for (int s = 0; s < TS / 4; ++s) {
+            const double a0 = c[size_t(l & 15) * ld + 4 * s + (l >> 4)];
+            const double a1 = c[size_t(16 + (l & 15)) * ld + 4 * s + (l >> 4)];
+            const double b0 = P_right[(0 * 8 + s) * 64 + l], b1 = P_right[(1 * 8 + s) * 64 + l];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+#pragma unroll
+        for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) o[ra][cb] = -acc[ra][cb];
+        return;
+    }
+    // Q_j = P S_bj
+    const double* sbj = So + size_t(b) * TS * ld + size_t(j) * TS;
 #pragma unroll
     for (int s = 0; s < TS / 4; ++s) {
-        const double a0 = c[(0 * 8 + s) * 64 + l], a1 = c[(1 * 8 + s) * 64 + l];
-        const double b0 = q[(0 * 8 + s) * 64 + l], b1 = q[(1 * 8 + s) * 64 + l];
+        const double a0 = P_left[(0 * 8 + s) * 64 + l], a1 = P_left[(1 * 8 + s) * 64 + l];
+        const double b0 = sbj[size_t(4 * s + (l >> 4)) * ld + (l & 15)];
+        const double b1 = sbj[size_t(4 * s + (l >> 4)) * ld + 16 + (l & 15)];
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
+    if (i == b) {                    // S_bj <- Q_j
+#pragma unroll
+        for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) o[ra][cb] = acc[ra][cb];
+        return;
+    }
+    // S_ij <- S_ij - C_i Q_j, Q_j to right-operand order through LDS (the
+    // wavefront's own LDS writes precede its reads in order)
 #pragma unroll
     for (int ra = 0; ra < 2; ++ra)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * ra + (l >> 4) + 4 * r, col = 16 * cb + (l & 15);
-                double* dst = tile + size_t(row) * ld + col;
-                *dst = (j == b) ? -acc[ra][cb][r] : *dst - acc[ra][cb][r];
-            }
+            for (int r = 0; r < 4; ++r) x[res_row(ra, l, r) * TS + res_col(cb, l)] = acc[ra][cb][r];
+    f64x4 u[2][2];
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) u[ra][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < TS / 4; ++s) {
+        const double a0 = c[size_t(l & 15) * ld + 4 * s + (l >> 4)];
+        const double a1 = c[size_t(16 + (l & 15)) * ld + 4 * s + (l >> 4)];
+        const double b0 = x[(4 * s + (l >> 4)) * TS + (l & 15)];
+        const double b1 = x[(4 * s + (l >> 4)) * TS + 16 + (l & 15)];
+        u[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, u[0][0], 0, 0, 0);
+        u[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, u[0][1], 0, 0, 0);
+        u[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, u[1][0], 0, 0, 0);
+        u[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, u[1][1], 0, 0, 0);
+    }
+    const double* sij = So + size_t(i) * TS * ld + size_t(j) * TS;
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                o[ra][cb][r] = sij[size_t(res_row(ra, l, r)) * ld + res_col(cb, l)] - u[ra][cb][r];
+}
+
+// Pivot step b: So (matrix after step b-1) -> Sn; Pin = S_bb^{-1} in both
+// operand layouts.  When b+1 < T, workgroup 0 (dispatched first) recomputes
+// only tile (b+1, b+1) and writes its inverse to Pout; workgroups 1.. each
+// update a 2 x 2 group of tiles, a wavefront per tile.
+__global__ __launch_bounds__(256) void k_gj_step(const double* __restrict__ So, double* __restrict__ Sn, int ld,
+                                                 int T, int b, const double* __restrict__ Pin,
+                                                 double* __restrict__ Pout, const int* stop) {
+    __shared__ double xch[4][TS * TS];    // per wavefront: Q_j from result to right-operand order
+    __shared__ double piv[TS][TS + 1];
+    if (stop && *stop) return;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int nb = b + 1;
+    const int lead = nb < T ? 1 : 0;
+    if (lead && blockIdx.x == 0) {   // next pivot: tile (nb, nb) after this step, inverted
+        if (w == 0) {
+            f64x4 o[2][2];
+            tile_step(So, ld, b, nb, nb, Pin, xch[0], l, o);
+#pragma unroll
+            for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) piv[res_row(ra, l, r)][res_col(cb, l)] = o[ra][cb][r];
+        }
+        __syncthreads();
+        lds_gj_invert(piv);
+        store_pivot(piv, Pout);
+        return;
+    }
+    const int gx = (T + 1) / 2;
+    const int L = int(blockIdx.x) - lead;
+    const int by = L / gx, bx = L % gx;
+    const int i = 2 * by + (w >> 1), j = 2 * bx + (w & 1);
+    if (i >= T || j >= T) return;    // whole wavefronts; no barrier follows
+    f64x4 o[2][2];
+    tile_step(So, ld, b, i, j, Pin, xch[w], l, o);
+    double* dst = Sn + size_t(i) * TS * ld + size_t(j) * TS;
+#pragma unroll
+    for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[size_t(res_row(ra, l, r)) * ld + res_col(cb, l)] = o[ra][cb][r];
 }
 
 // Sinv = (S + S^T)/2: the sweep's result is symmetric up to rounding; PCG
