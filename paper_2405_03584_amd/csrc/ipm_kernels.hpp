@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_prec_a(const int* Ap, const int* Ac,
     for (int q = row * 64 + lane; q < m && q < (row + 1) * 64; q += 64) vm[q] = 0.0;
     if (row >= ld) return;
     double s = 0.0;
-    if (row < k) s = row_dot_lane<64, double, double>(Ap, Ac, Av, y, idx[row], lane);
+    if (row < k) s = row_dot_lane<64, double, double, 8>(Ap, Ac, Av, y, idx[row], lane);
     s = group_sum<double, 64>(s);
     if (lane == 0) w[row] = row < k ? sqrt(sigA[idx[row]]) * s : 0.0;
 }
@@ -342,14 +342,22 @@ __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, int ld
     const int lane = threadIdx.x & 63;
     if (row >= k) return;
     const double* srow = Sinv + size_t(row) * ld;
-    double s0 = 0.0, s1 = 0.0;
-    int c = lane;
-    for (; c + 64 < ld; c += 128) {
-        s0 += srow[c] * w[c];
-        s1 += srow[c + 64] * w[c + 64];
+    // passes of 8 loads per lane in flight (indices past ld clamped, zeroed)
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    for (int c = lane; c < ld; c += 512) {
+        double sv[8], wv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int cc = min(c + 64 * u, ld - 1);
+            sv[u] = srow[cc];
+            wv[u] = w[cc];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += (c + 64 * u < ld) ? sv[u] * wv[u] : 0.0;
     }
-    if (c < ld) s0 += srow[c] * w[c];
-    double s = group_sum<double, 64>(s0 + s1);
+    double s = group_sum<double, 64>(((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
     if (lane == 0) {
         const int i = idx[row];
         vm[i] = sqrt(sigA[i]) * s;

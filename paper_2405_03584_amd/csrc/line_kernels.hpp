@@ -86,12 +86,14 @@ __global__ __launch_bounds__(kBlock) void k_line_pass(LineArgs<VT> a) {
             const int plo = __double2loint(pl), phi = __double2hiint(pl);
 #pragma unroll
             for (int i = 0; i < RH; ++i) hv[i] = cvt<AT>(v[size_t(min(k0 + i, kh - 1)) * 64]);
+            AT a4[4] = {AT(0), AT(0), AT(0), AT(0)};   // four short chains, no product array
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
                 const double xv = __hiloint2double(__builtin_amdgcn_readlane(phi, i),
                                                    __builtin_amdgcn_readlane(plo, i));
-                acc = (k0 + i < kh) ? fma(hv[i], AT(xv), acc) : acc;   // one chain: no product array
+                a4[i & 3] = (k0 + i < kh) ? fma(hv[i], AT(xv), a4[i & 3]) : a4[i & 3];
             }
+            acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         } else {
 #pragma unroll
             for (int i = 0; i < RH; ++i) hv[i] = AT(0);

@@ -72,7 +72,7 @@ struct qp_handle {
     double* W = nullptr;
     int *Ap = nullptr, *Ac = nullptr, *Atp = nullptr, *Atc = nullptr;
     double *Av = nullptr, *Atv = nullptr;
-    int last_pcg_iters = 0;   // iterations of the previous PCG solve (chunk size predictor)
+    int last_pcg_iters = 0, last_pcg_iters2 = 0;   // iterations of the two previous PCG solves (chunk sizes)
     // line format of J (64-row lines sharing a column list), used by the PCG operator
     bool line = false;
     int L = 0;
@@ -531,9 +531,12 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     };
     // Chunks of iterations are queued ahead of the host check: kernels of a
     // finished solve return at once, so the GPU never waits on the host.  The
-    // first chunk covers most of the previous solve's iteration count; later
-    // chunks are short, so few no-op launches trail the converged iteration.
-    int chunk = std::max(4, std::min(512, (h->last_pcg_iters * 3) / 4));
+    // first chunk covers most of the smaller of the two previous solves'
+    // iteration counts (consecutive IPM directions alternate between short and
+    // long solves); later chunks are four iterations, so few no-op launches
+    // trail the converged iteration.
+    const int pred = std::min(h->last_pcg_iters, h->last_pcg_iters2);
+    int chunk = std::max(4, std::min(512, (pred * 3) / 4));
     int64_t launched = 0;
     const int64_t guard = int64_t(h->set.pcg_max_iter) + 4096;
     int cur = 0;
@@ -542,7 +545,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     snapshot(cur);
     Flags f{};
     while (true) {
-        chunk = std::min(std::max(8, chunk / 4), 32);
+        chunk = 4;
         for (int i = 0; i < chunk; ++i) one_iter();
         launched += chunk;
         snapshot(cur ^ 1);
@@ -555,7 +558,10 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         }
         cur ^= 1;
     }
-    if (!f.ipm_done) h->last_pcg_iters = f.pcg_iters;
+    if (!f.ipm_done) {
+        h->last_pcg_iters2 = h->last_pcg_iters;
+        h->last_pcg_iters = f.pcg_iters;
+    }
     if (timing) {
         // launches past the last executed iteration returned at once: drop them
         for (int sl = slot_begin + std::max(f.pcg_iters, 0); sl < tacc->pairs; ++sl) tacc->valid[sl] = 0;
