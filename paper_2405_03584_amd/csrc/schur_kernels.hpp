@@ -117,12 +117,37 @@ __global__ __launch_bounds__(64) void k_schur_form(const int* __restrict__ Ap, c
     if (r < k) {
         const int i = idx[r];
         const int e0 = Ap[i], e1 = Ap[i + 1];
-        for (int e = e0; e < e1; ++e) {
-            const int j = Ac[e];
-            const double c = Av[e] / D[j];
-            for (int f = Atp[j] + lane; f < Atp[j + 1]; f += 64) {
-                const int q = pos[Atc[f]];
-                if (q >= 0) acc[q] += c * Atv[f];
+        // Batches of 8 nonzeros: every load of a batch (column ids, weights,
+        // the first 64 entries of each column and their strong-row ranks) is
+        // issued before the adds, which then run in the original order, so
+        // the sums are those of the one-at-a-time loop.
+        constexpr int B = 8;
+        for (int e = e0; e < e1; e += B) {
+            int jv[B], f0[B], f1[B], q[B];
+            double c[B], av[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int ee = min(e + u, e1 - 1);
+                jv[u] = Ac[ee];
+                c[u] = (e + u < e1) ? Av[ee] / D[jv[u]] : 0.0;
+                f0[u] = Atp[jv[u]];
+                f1[u] = (e + u < e1) ? Atp[jv[u] + 1] : f0[u];
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int f = f0[u] + lane;
+                const bool in = f < f1[u];
+                const int ff = in ? f : 0;   // a valid index when idle (A has nonzeros when k > 0)
+                av[u] = in ? Atv[ff] : 0.0;
+                q[u] = in ? pos[Atc[ff]] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                if (q[u] >= 0) acc[q[u]] += c[u] * av[u];
+                for (int f = f0[u] + 64 + lane; f < f1[u]; f += 64) {   // columns longer than 64
+                    const int qq = pos[Atc[f]];
+                    if (qq >= 0) acc[qq] += c[u] * Atv[f];
+                }
             }
         }
     }
