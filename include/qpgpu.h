@@ -58,7 +58,10 @@ typedef enum {
 /* Storage of the J values inside the PCG operator (Section 4.1 keeps FP64).
  * FP32/BF16 keep a rounded copy (round to nearest even) with FP32
  * accumulation; residuals, PCG scalars and dot products stay FP64, and the
- * direction is refined against the FP64 operator (refine_steps). */
+ * direction is refined against the FP64 operator: each low-precision PCG
+ * solve stops at refine_tol times its own right-hand side, and refinement
+ * passes (at most refine_steps) go on until the FP64 residual is below
+ * pcg_tol times the original right-hand side. */
 typedef enum { QP_FP64 = 0, QP_FP32 = 1, QP_BF16 = 2 } qp_precision;
 
 typedef struct {
@@ -86,7 +89,8 @@ typedef struct {
 
 typedef struct {
     int32_t precision;        /* qp_precision, default QP_FP64 */
-    int32_t refine_steps;     /* FP64 refinement passes of each low-precision direction, default 2 */
+    int32_t refine_steps;     /* at most this many FP64 refinement passes per low-precision direction,
+                                 default 6 (they stop once the FP64 residual meets pcg_tol) */
     double  pcg_tol;          /* stop at ||r||_2 <= pcg_tol*||rhs||_2, default 1e-8 */
     int32_t pcg_max_iter;     /* per PCG solve, default 20000 */
     double  mu0;              /* <= 0: average complementarity of the start point (default) */
@@ -104,6 +108,8 @@ typedef struct {
                                  falls back to 0 when m = 0 or m > 8192 */
     int32_t spmv_format;      /* 0 (default): line format for J when its rows come in lines of 64
                                  sharing one column list (the 64-voxel bands), else CSR; 1: CSR */
+    double  refine_tol;       /* relative residual target of each low-precision PCG solve when
+                                 refine_steps > 0, in [pcg_tol, 1); default 1e-3 */
 } qp_settings;
 
 typedef struct {

@@ -38,6 +38,7 @@ struct PcgScal {
     double bnorm2;     // ||rhs||^2
     double tol2;       // pcg_tol^2 * ||rhs||^2
     double rr;         // ||r||^2 after the last update
+    double bnorm2_outer;   // ||rhs||^2 of the first solve of a refined direction
     int32_t iters;
     int32_t max_iter;
 };

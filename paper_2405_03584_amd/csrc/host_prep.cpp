@@ -163,6 +163,8 @@ std::string validate_settings(const qp_settings* s) {
     if (s->precision < QP_FP64 || s->precision > QP_BF16) return "settings.precision out of range";
     if (s->refine_steps < 0 || s->refine_steps > 16) return "settings.refine_steps must be in [0, 16]";
     if (!(s->pcg_tol > 0.0) || !(s->pcg_tol < 1.0)) return "settings.pcg_tol must be in (0, 1)";
+    if (!(s->refine_tol >= s->pcg_tol) || !(s->refine_tol < 1.0))
+        return "settings.refine_tol must be in [pcg_tol, 1)";
     if (s->pcg_max_iter < 1) return "settings.pcg_max_iter must be >= 1";
     if (!std::isfinite(s->mu0)) return "settings.mu0 must be finite";
     if (!(s->mu_tol > 0.0)) return "settings.mu_tol must be > 0";

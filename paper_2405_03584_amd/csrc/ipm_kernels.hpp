@@ -237,30 +237,34 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
     }
 }
 
-// One block.  init = 0: ||r||^2, iteration count, convergence / cap flags,
-// beta = r^T z / rho, rho = r^T z.  init = 1 (start of a solve): ||rhs||^2,
-// the stopping threshold, rho, beta = 0 (p was zeroed, so the first
-// direction is z), converged at once when rhs = 0.
+// One block.  mode 0: ||r||^2, iteration count, convergence / cap flags,
+// beta = r^T z / rho, rho = r^T z.  Start of a solve (p was zeroed, so the
+// first direction is z; beta = 0): mode 1 stops at rel_tol * ||rhs|| and
+// records ||rhs||^2 as the outer norm; mode 2 (a refinement solve) stops at
+// max(rel_tol * ||rhs||, tol * outer norm), and at once when rhs already
+// meets tol * outer norm.
 __global__ __launch_bounds__(kBlock) void k_pcg_scalars(const double* part_rz, int n_rz, const double* part_rr,
-                                                        int n_rr, int init, double tol, int max_iter,
-                                                        PcgScal* sc, Flags* fl) {
+                                                        int n_rr, int mode, double rel_tol, double tol,
+                                                        int max_iter, PcgScal* sc, Flags* fl) {
     __shared__ double sh[kBlock / 64];
-    if (init ? ipm_finished(fl) : pcg_stopped(fl)) return;
+    if (mode ? ipm_finished(fl) : pcg_stopped(fl)) return;
     const double rz = reduce_partials_sum(part_rz, n_rz, 1, sh);
     const double rr = reduce_partials_sum(part_rr, n_rr, 1, sh);
     if (threadIdx.x != 0) return;
-    if (init) {
+    if (mode) {
+        if (mode == 1) sc->bnorm2_outer = rr;
+        const double floor2 = tol * tol * sc->bnorm2_outer;
         sc->rho = rz;
         sc->beta = 0.0;
         sc->alpha = 0.0;
         sc->pq = 0.0;
         sc->bnorm2 = rr;
         sc->rr = rr;
-        sc->tol2 = tol * tol * rr;
+        sc->tol2 = fmax(rel_tol * rel_tol * rr, mode == 2 ? floor2 : 0.0);
         sc->iters = 0;
         sc->max_iter = max_iter;
         fl->pcg_iters = 0;
-        fl->pcg_converged = (rr == 0.0) ? 1 : 0;
+        fl->pcg_converged = (rr == 0.0 || (mode == 2 && rr <= floor2)) ? 1 : 0;
         return;
     }
     sc->rr = rr;

@@ -484,7 +484,8 @@ void autotune_schedule(qp_handle* h) {
 // sigA given) the constraint block with D = dh.  dx is written to h->px.
 // Returns the flags after the solve.
 Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, const double* sigx,
-              const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode, TimingAcc* tacc) {
+              const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode, TimingAcc* tacc,
+              double rel_tol, bool refine) {
     const int n = h->n;
     const int ge = grid_elems(n);
     // dh != null selects the constraint-block preconditioner (built for this Sigma)
@@ -498,7 +499,8 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     HIPCHK(hipGetLastError());
     const int n_rz = wb ? apply_precond(h, dh, sigA) : ge;
     hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
-                       (const double*)h->part_rr, ge, 1, h->set.pcg_tol, h->set.pcg_max_iter, h->psc, h->fl);
+                       (const double*)h->part_rr, ge, refine ? 2 : 1, rel_tol, h->set.pcg_tol,
+                       h->set.pcg_max_iter, h->psc, h->fl);
     HIPCHK(hipGetLastError());
 
     PcgArgs pa{};
@@ -520,7 +522,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         hipLaunchKernelGGL(k_pcg_xr, dim3(ge), dim3(kBlock), 0, h->stream, pa);
         if (wb) apply_precond(h, dh, sigA);
         hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
-                           (const double*)h->part_rr, ge, 0, 0.0, 0, h->psc, h->fl);
+                           (const double*)h->part_rr, ge, 0, 0.0, 0.0, 0, h->psc, h->fl);
     };
     auto snapshot = [&](int slot) {
         HIPCHK(hipMemcpyAsync(&h->fl_host[slot], h->fl, sizeof(Flags), hipMemcpyDeviceToHost, h->stream));
@@ -571,17 +573,21 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     return f;
 }
 
-// One Newton direction into h->px.  FP64: one PCG solve.  FP32/BF16: PCG on
-// the low-precision operator, then `refine_steps` passes of
-// rho = rhs - K_64 dx (FP64 operator), delta = PCG_lo(rho), dx += delta.
-// rhs = mu*rhs_a + rhs_b (ipm_mode) or rhs_b.  The returned flags carry the
-// PCG iteration count summed over the solves; `solves` counts them.
+// One Newton direction into h->px.  FP64: one PCG solve to pcg_tol.
+// FP32/BF16: PCG on the low-precision operator to refine_tol, then up to
+// `refine_steps` passes of rho = rhs - K_64 dx (FP64 operator),
+// delta = PCG_lo(rho) (to refine_tol of rho, but never below pcg_tol of the
+// original rhs), dx += delta; a pass whose rho already meets pcg_tol * ||rhs||
+// takes no iteration and ends the refinement.  rhs = mu*rhs_a + rhs_b
+// (ipm_mode) or rhs_b.  The returned flags carry the PCG iteration count
+// summed over the solves; `solves` counts them.
 Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, const double* sigx,
                        const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode,
                        TimingAcc* tacc, int* solves) {
+    const double tol = h->set.pcg_tol;
     if (prec == QP_FP64) {
         *solves = 1;
-        return run_pcg(h, QP_FP64, rhs_a, rhs_b, sigx, sigA, d, dh, hs, ipm_mode, tacc);
+        return run_pcg(h, QP_FP64, rhs_a, rhs_b, sigx, sigA, d, dh, hs, ipm_mode, tacc, tol, false);
     }
     const int n = h->n;
     const int ge = grid_elems(n);
@@ -592,7 +598,8 @@ Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double
         HIPCHK(hipGetLastError());
         rhs = h->rhs_full;
     }
-    Flags f = run_pcg(h, prec, nullptr, rhs, sigx, sigA, d, dh, hs, false, tacc);
+    const double inner = h->set.refine_steps > 0 ? std::max(h->set.refine_tol, tol) : tol;
+    Flags f = run_pcg(h, prec, nullptr, rhs, sigx, sigA, d, dh, hs, false, tacc, inner, false);
     *solves = 1;
     int total = f.pcg_iters;
     if (f.ipm_done || f.pcg_breakdown) return f;
@@ -602,15 +609,17 @@ Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double
         apply_op_prec(h, QP_FP64, h->dxacc, h->pq, sigx, sigA, hs, false, false, 0);
         hipLaunchKernelGGL(k_sub, dim3(ge), dim3(kBlock), 0, h->stream, n, rhs, (const double*)h->pq, h->rho,
                            (const Flags*)h->fl);
-        Flags f2 = run_pcg(h, prec, nullptr, h->rho, sigx, sigA, d, dh, hs, false, tacc);
+        Flags f2 = run_pcg(h, prec, nullptr, h->rho, sigx, sigA, d, dh, hs, false, tacc, inner, true);
         *solves += 1;
         total += f2.pcg_iters;
         f.pcg_capped |= f2.pcg_capped;
+        f.pcg_converged = f2.pcg_converged;
         if (f2.pcg_breakdown) {
             // a zero residual (exact direction) is not a breakdown; rr == 0 stops at init
             f.pcg_breakdown = 1;
             break;
         }
+        if (f2.pcg_iters == 0) break;   // the FP64 residual already meets pcg_tol
         hipLaunchKernelGGL(k_acc, dim3(ge), dim3(kBlock), 0, h->stream, n, h->dxacc, (const double*)h->px, 0,
                            (const Flags*)h->fl);
     }
@@ -667,7 +676,7 @@ void qp_default_settings(qp_settings* s) {
     if (!s) return;
     std::memset(s, 0, sizeof(*s));
     s->precision = QP_FP64;
-    s->refine_steps = 2;
+    s->refine_steps = 6;
     s->pcg_tol = 1e-8;
     s->pcg_max_iter = 20000;
     s->mu0 = -1.0;
@@ -681,6 +690,7 @@ void qp_default_settings(qp_settings* s) {
     s->log_level = 0;
     s->precond = 1;
     s->spmv_format = 0;
+    s->refine_tol = 1e-3;
 }
 
 const char* qp_last_error(const qp_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }

@@ -301,18 +301,28 @@ def test_solve_band_medium():
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_newton_step_mixed_precision_refined(prec):
-    """After refinement the direction solves the FP64 system to about the PCG
-    tolerance times the contraction of the low-precision operator."""
+    """Refinement passes against the FP64 operator bring the direction's FP64
+    residual to about the PCG tolerance although every low-precision solve
+    stops at refine_tol; the passes end by themselves once the FP64 residual
+    meets pcg_tol."""
     prob = qpsynth.config2(scale=0.02)
     it = qpsynth.random_iterate(prob, 31)
-    s = qpgpu.qp_default_settings(precision=prec, refine_steps=3, pcg_tol=1e-10)
+    s = qpgpu.qp_default_settings(precision=prec, refine_steps=8, pcg_tol=1e-10)
     h = qpgpu.qp_create_from_problem(prob, settings=s)
     st, dx, info = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], it["rhs"])
     assert st == qpgpu.QP_OK, info
-    assert info["pcg_solves"] == 4
+    assert 2 <= info["pcg_solves"] <= 9, info
     K = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"])
     res = np.linalg.norm(K @ dx - it["rhs"]) / np.linalg.norm(it["rhs"])
-    assert res <= 1e-8, res
+    assert res <= 1e-9, res
+    # the same direction with inner solves at pcg_tol (the slow schedule)
+    s2 = qpgpu.qp_default_settings(precision=prec, refine_steps=8, pcg_tol=1e-10, refine_tol=1e-10)
+    h2 = qpgpu.qp_create_from_problem(prob, settings=s2)
+    st2, dx2, info2 = qpgpu.qp_newton_step(h2, it["sigma_x"], it["sigma_A"], it["rhs"])
+    assert st2 == qpgpu.QP_OK
+    res2 = np.linalg.norm(K @ dx2 - it["rhs"]) / np.linalg.norm(it["rhs"])
+    assert res2 <= 1e-9, res2
+    assert info["pcg_iters"] < info2["pcg_iters"], (info["pcg_iters"], info2["pcg_iters"])
     # without refinement the low-precision operator leaves a visible residual
     s0 = qpgpu.qp_default_settings(precision=prec, refine_steps=0, pcg_tol=1e-10)
     h0 = qpgpu.qp_create_from_problem(prob, settings=s0)
