@@ -39,12 +39,12 @@ struct LineArgs {
     double* c;             // per slot (lptr[L] entries)
     double* u; const double* sigA;
     int nbL;               // blocks working on lines (one line per block)
-    int nbA;               // blocks working on rows of A (first in the grid)
+    int nbA;               // blocks working on rows of A (first in the grid, one row each)
     const Flags* fl;
 };
 
 template <typename VT, typename AT>
-__global__ __launch_bounds__(kBlock) void k_line_pass(LineArgs<VT> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_line_pass(LineArgs<VT> a) {
     constexpr int NW = kBlock / 64;
     constexpr int RH = kLineHeld;
     static_assert(NW == 4, "the pass-1 combine adds four wavefront partials");
@@ -70,43 +70,49 @@ __global__ __launch_bounds__(kBlock) void k_line_pass(LineArgs<VT> a) {
         const int q = (len + NW - 1) / NW;
         const int k0 = __builtin_amdgcn_readfirstlane(min(len, w * q));
         const int k1 = __builtin_amdgcn_readfirstlane(min(len, k0 + q));
-        const int kh = min(k1, k0 + RH);   // held slots [k0, kh)
+        // held slots [kh, k1): the last RH of the wavefront's range; the
+        // slots before them (only in lines longer than NW*RH slots) are
+        // streamed first, so their registers are free before the held loads
+        const int kh = max(k0, k1 - RH);
         const VT* v = a.lval + size_t(off) * 64 + lane;
         const int* col = a.lcol + off;
-        // pass 1: partial (J p)_r over this wavefront's slots.  Lane i
-        // gathers p at the column of held slot k0+i (one coalesced index load
-        // and one gather per lane instead of RH wave-uniform ones), and the
-        // product loop reads it back with readlane.  Value loads past kh are
-        // clamped to kh-1 (a valid address) and contribute 0, so every load
-        // is issued at once, without branches between them.
-        AT hv[RH];
         AT acc = AT(0);
-        if (k0 < kh) {
-            const double pl = g(col[min(k0 + (lane & (RH - 1)), kh - 1)]);
+        for (int k = k0; k < kh; k += 4) {
+            AT s4 = AT(0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int kk = min(k + i, kh - 1);
+                const AT prod = cvt<AT>(v[size_t(kk) * 64]) * AT(g(col[kk]));
+                s4 += (k + i < kh) ? prod : AT(0);
+            }
+            acc += s4;
+        }
+        // pass 1: partial (J p)_r over this wavefront's held slots.  Lane i
+        // gathers p at the column of held slot kh+i (one coalesced index load
+        // and one gather per lane instead of RH wave-uniform ones), and the
+        // product loop reads it back with readlane.  Value loads past k1 are
+        // clamped to k1-1 (a valid address) and zeroed, so every load is
+        // issued at once, without branches between them.
+        AT hv[RH];
+        if (kh < k1) {
+            const double pl = g(col[min(kh + (lane & (RH - 1)), k1 - 1)]);
             const int plo = __double2loint(pl), phi = __double2hiint(pl);
 #pragma unroll
-            for (int i = 0; i < RH; ++i) hv[i] = cvt<AT>(v[size_t(min(k0 + i, kh - 1)) * 64]);
-            AT a4[4] = {AT(0), AT(0), AT(0), AT(0)};   // four short chains, no product array
+            for (int i = 0; i < RH; ++i) {
+                const AT val = cvt<AT>(v[size_t(min(kh + i, k1 - 1)) * 64]);
+                hv[i] = (kh + i < k1) ? val : AT(0);
+            }
+            AT a2[2] = {AT(0), AT(0)};   // two chains, no product array
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
                 const double xv = __hiloint2double(__builtin_amdgcn_readlane(phi, i),
                                                    __builtin_amdgcn_readlane(plo, i));
-                a4[i & 3] = (k0 + i < kh) ? fma(hv[i], AT(xv), a4[i & 3]) : a4[i & 3];
+                a2[i & 1] = fma(hv[i], AT(xv), a2[i & 1]);
             }
-            acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+            acc += a2[0] + a2[1];
         } else {
 #pragma unroll
             for (int i = 0; i < RH; ++i) hv[i] = AT(0);
-        }
-        for (int k = kh; k < k1; k += 4) {   // only lines longer than NW*RH slots
-            AT s4 = AT(0);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int kk = min(k + i, k1 - 1);
-                const AT prod = cvt<AT>(v[size_t(kk) * 64]) * AT(g(col[kk]));
-                s4 += (k + i < k1) ? prod : AT(0);
-            }
-            acc += s4;
         }
         part[w][lane] = acc;
         __syncthreads();
@@ -116,28 +122,36 @@ __global__ __launch_bounds__(kBlock) void k_line_pass(LineArgs<VT> a) {
         constexpr int SHIFT = RH == 32 ? 1 : RH == 16 ? 2 : RH == 8 ? 3 : RH == 4 ? 4 : RH == 2 ? 5 : 6;
         const int slot = lane >> SHIFT;
         const bool writer = (lane & ((1 << SHIFT) - 1)) == 0;
-        if (k0 < kh) {   // held slots (hv is dead afterwards)
+        if (kh < k1) {   // held slots (hv is dead afterwards)
 #pragma unroll
-            for (int i = 0; i < RH; ++i) hv[i] = (k0 + i < kh) ? hv[i] * t : AT(0);
+            for (int i = 0; i < RH; ++i) hv[i] *= t;
             const AT cs = wave_reduce_scatter<RH>(hv, lane);
-            if (writer && k0 + slot < kh) a.c[off + k0 + slot] = double(cs);
+            if (writer && kh + slot < k1) a.c[off + kh + slot] = double(cs);
         }
-        for (int kg = kh; kg < k1; kg += RH) {   // streamed slots of long lines
-            AT pv[RH];
+        for (int kg = k0; kg < kh; kg += 8) {   // streamed slots of long lines, 8 at a time
+            AT pv[8];
 #pragma unroll
-            for (int i = 0; i < RH; ++i) {
-                const AT val = cvt<AT>(v[size_t(min(kg + i, k1 - 1)) * 64]);
-                pv[i] = (kg + i < k1) ? val * t : AT(0);
+            for (int i = 0; i < 8; ++i) {
+                const AT val = cvt<AT>(v[size_t(min(kg + i, kh - 1)) * 64]);
+                pv[i] = (kg + i < kh) ? val * t : AT(0);
             }
-            const AT cs = wave_reduce_scatter<RH>(pv, lane);
-            if (writer && kg + slot < k1) a.c[off + kg + slot] = double(cs);
+            const AT cs = wave_reduce_scatter<8>(pv, lane);
+            if ((lane & 7) == 0 && kg + (lane >> 3) < kh) a.c[off + kg + (lane >> 3)] = double(cs);
         }
     } else {
-        const int row = int(blockIdx.x) * NW + w;
-        if (row < a.m) {
-            double s = row_dot_lane_g<64, double, double>(a.Ap, a.Ac, a.Av, g, row, lane);
-            s = group_sum<double, 64>(s);
-            if (lane == 0) a.u[row] = a.sigA ? a.sigA[row] * s : s;
+        // a row of A per workgroup: 256 lanes with two loads each cover up to
+        // 512 nonzeros in one round of gathers; wavefront sums combined in
+        // a fixed order through LDS
+        const int row = int(blockIdx.x);
+        double s = 0.0;
+        if (row < a.m) s = row_dot_lane_g<kBlock, double, double, 2>(a.Ap, a.Ac, a.Av, g, row, threadIdx.x);
+        s = group_sum<double, 64>(s);
+        __shared__ double rs[NW];
+        if (lane == 0) rs[w] = s;
+        __syncthreads();
+        if (threadIdx.x == 0 && row < a.m) {
+            const double tot = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+            a.u[row] = a.sigA ? a.sigA[row] * tot : tot;
         }
     }
 }

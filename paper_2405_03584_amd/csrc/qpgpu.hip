@@ -240,7 +240,7 @@ int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, 
     f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
     f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.c = h->lc; f.u = h->u; f.sigA = sigA; f.fl = fl;
     f.nbL = h->L;
-    const int nbA = f.m > 0 ? grid_rows(f.m, 64) : 0;
+    const int nbA = f.m;
     f.nbA = nbA;
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
     hipLaunchKernelGGL((k_line_pass<VT, AT>), dim3(std::max(1, f.nbL + nbA)), dim3(kBlock), 0, h->stream, f);
