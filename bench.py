@@ -1,10 +1,13 @@
 """Benchmark: QP time-to-solution, PCG iterations/s and SpMV HBM GB/s vs peak.
 
-One step = one whole QP solve (qp_solve: start point, residuals, every Jacobi
-PCG direction, recovery, ratio test, update, barrier rule) of the banded-dose
-QP with n = 20,000 spots, J 400,000 x 20,000 (40M nnz), A 2,000 x 20,000 at 2%,
-bounds [0, 50], PCG tolerance 1e-8.  Problem data are resident in HBM (created
-once by qp_create) before the timed region.
+One step = one whole QP solve (qp_solve: start point, residuals, every PCG
+direction, recovery, ratio test, update, barrier rule) of the banded-dose QP
+with n = 20,000 spots, J 400,000 x 20,000 (40M nnz), A 2,000 x 20,000 at 2%,
+bounds [0, 50], PCG tolerance 1e-8, with the library's default settings
+(captured PCG graphs).  Problem data are resident in HBM (created once by
+qp_create) before the timed region.  One more solve on a second handle with
+per-kernel HIP events gives the SpMV kernel durations of the roofline; a
+child process measures the streaming-read ceiling with torch.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
                     [--scale 1.0] [--no-cpu-baseline]
@@ -159,6 +162,12 @@ def batch_bench(args):
         print(f"[bench] step {i}: status={s} pcg={sum(f['pcg_iters'] for f in infos)}", file=sys.stderr, flush=True)
     el = time.perf_counter() - t0
     ok = all(f["status"] == qpgpu.QP_OK for f in all_infos)
+    # the same handles solved one after another (one stream busy at a time)
+    t1 = time.perf_counter()
+    for h in hs:
+        qpgpu.qp_solve(h)
+    seq = time.perf_counter() - t1
+    print(f"[bench] sequential: {1e3 * seq:.1f} ms", file=sys.stderr, flush=True)
     print(json.dumps({"metric": METRIC, "value": args.count * args.steps / el, "unit": "QP/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -167,8 +176,43 @@ def batch_bench(args):
                                              f"(n in [2000, 20000], {nnz} nnz of J in all)",
                                  "precision": args.precision},
                       "status_ok": ok,
+                      "sequential_ms": 1e3 * seq,
+                      "batch_speedup_vs_sequential": seq / (el / args.steps),
                       "ipm_iters_total": sum(f["ipm_iters"] for f in all_infos),
                       "pcg_iters_total": sum(f["pcg_iters"] for f in all_infos)}), flush=True)
+
+
+def stream_ceiling():
+    """Measured streaming-read ceiling in GB/s, from `--mode stream` run in a
+    child process (torch brings its own HIP runtime, which must not share a
+    process with the library's)."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--mode", "stream"], capture_output=True,
+                       text=True, timeout=300)
+    if r.returncode != 0:
+        print(f"[bench] stream ceiling failed: {r.stderr[-400:]}", file=sys.stderr, flush=True)
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])["read_GBs"]
+
+
+def stream_read(args):
+    """A 1 GiB FP64 tensor summed by torch (each byte read once), best of 5
+    after a warm-up: the streaming-read ceiling the kernels are compared to."""
+    import torch
+    x = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    x.sum()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        x.sum()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    print(json.dumps({"mode": "stream", "bytes": 1 << 30, "ms": best, "read_GBs": (1 << 30) / (best * 1e-3) / 1e9}),
+          flush=True)
 
 
 def copy_calibration(args):
@@ -195,7 +239,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--log", type=int, default=1, help="per-IPM-iteration progress on stderr")
-    ap.add_argument("--mode", default="solve", choices=["solve", "operator", "copy"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "operator", "copy", "stream"],
                     help="solve: whole QP solves (the benchmark); operator: repeated operator "
                          "products only (for counter runs); copy: a plain device copy of the "
                          "J value+index bytes (counter calibration)")
@@ -216,8 +260,11 @@ def main():
 
     if args.mode == "copy":
         return copy_calibration(args)
+    if args.mode == "stream":
+        return stream_read(args)
     if args.workload == "batch":
         return batch_bench(args)
+    ceiling = stream_ceiling() if args.mode == "solve" else None   # before this process touches the GPU
     t0 = time.perf_counter()
     prob = qpsynth.config5(scale=args.scale) if args.workload == "config5" else qpsynth.config2(scale=args.scale)
     if args.mode == "operator":
@@ -226,7 +273,10 @@ def main():
     nnzJ, nnzA = int(prob.J.nnz), int(prob.A.nnz)
     print(f"[bench] generated n={n} nJ={nJ} nnzJ={nnzJ} m={m} nnzA={nnzA} in "
           f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    settings = qpgpu.qp_default_settings(precision=args.precision, timing=1, log_level=args.log)
+    # the timed solves use the production settings (captured PCG graphs, no
+    # per-kernel events); one extra solve on a second handle with timing = 1
+    # gives the SpMV kernel durations for the roofline
+    settings = qpgpu.qp_default_settings(precision=args.precision, log_level=args.log)
     t0 = time.perf_counter()
     h = qpgpu.qp_create_from_problem(prob, settings=settings)
     t_create = time.perf_counter() - t0
@@ -250,10 +300,16 @@ def main():
 
     pcg_iters = sum(i["pcg_iters"] for i in infos)
     pcg_ms = sum(i["t_pcg_ms"] for i in infos)
-    fwd_ms = sum(i["t_spmv_fwd_ms"] for i in infos)
-    bwd_ms = sum(i["t_spmv_bwd_ms"] for i in infos)
-    nf = sum(i["n_spmv_fwd"] for i in infos)
-    nb = sum(i["n_spmv_bwd"] for i in infos)
+    ht = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=args.precision,
+                                                                              timing=1))
+    rt = qpgpu.qp_solve(ht)
+    print(f"[bench] timing solve: status={rt.status} pcg={rt.info['pcg_iters']} {rt.info['t_solve_ms']:.1f} ms",
+          file=sys.stderr, flush=True)
+    tinfo = [rt.info]
+    fwd_ms = sum(i["t_spmv_fwd_ms"] for i in tinfo)
+    bwd_ms = sum(i["t_spmv_bwd_ms"] for i in tinfo)
+    nf = sum(i["n_spmv_fwd"] for i in tinfo)
+    nb = sum(i["n_spmv_bwd"] for i in tinfo)
     vbytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
     fmt = infos[-1]["spmv_format"]
     bf, bb = spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes, fmt)
@@ -310,7 +366,9 @@ def main():
                      "unit": "GB/s", "frac": dom[3] / HBM_PEAK_GBS,
                      "traffic": (counter_traffic(dom[0].split()[0], args.precision)
                                  if args.scale == 1.0 and args.workload == "config2" else None),
-                     "bytes_per_launch": dom[1], "avg_launch_us": dom[2]},
+                     "bytes_per_launch": dom[1], "avg_launch_us": dom[2],
+                     "stream_read_ceiling_GBs": ceiling,
+                     "frac_of_stream_ceiling": dom[3] / ceiling if ceiling else None},
         "create_s": t_create,
         "parity": parity,
     }

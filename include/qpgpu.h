@@ -110,6 +110,9 @@ typedef struct {
                                  sharing one column list (the 64-voxel bands), else CSR; 1: CSR */
     double  refine_tol;       /* relative residual target of each low-precision PCG solve when
                                  refine_steps > 0, in [pcg_tol, 1); default 1e-3 */
+    int32_t graphs;           /* 1 (default): PCG iterations are launched as HIP graphs of four
+                                 iterations, captured once per operator and replayed; 0: one launch
+                                 per kernel.  Results are identical.  timing = 1 launches directly. */
 } qp_settings;
 
 typedef struct {

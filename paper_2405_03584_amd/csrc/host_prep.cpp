@@ -175,6 +175,7 @@ std::string validate_settings(const qp_settings* s) {
         s->schedule != 32 && s->schedule != 64)
         return "settings.schedule must be 0, 4, 8, 16, 32 or 64";
     if (s->precond != 0 && s->precond != 1) return "settings.precond must be 0 or 1";
+    if (s->graphs != 0 && s->graphs != 1) return "settings.graphs must be 0 or 1";
     if (s->spmv_format != 0 && s->spmv_format != 1) return "settings.spmv_format must be 0 or 1";
     return "";
 }

@@ -321,11 +321,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
 
 // Constraint-block preconditioner, step 1: w_r = sqrt(Sigma_i) (A y)_i for the
 // strong rows i = idx[r] (a wavefront per row; padding rows k..ld-1 get 0),
-// and vm = 0 on all m rows (step 2 fills the strong ones).
+// and vm = 0 on all m rows (step 2 fills the strong ones).  k (strong rows)
+// is read from the device, ld = k rounded up to TS_PREC; the grid covers the
+// largest possible ld, so launch shapes do not depend on the current k.
+constexpr int TS_PREC = 32;   // tile edge of the dense block (schur_kernels.hpp: TS)
 __global__ __launch_bounds__(kBlock) void k_prec_a(const int* Ap, const int* Ac, const double* Av,
-                                                   const double* y, const double* sigA, const int* idx, int k,
-                                                   int ld, int m, double* w, double* vm, const Flags* fl) {
+                                                   const double* y, const double* sigA, const int* idx,
+                                                   const int* kdev, int m, double* w, double* vm, const Flags* fl) {
     if (pcg_stopped_ro(fl)) return;
+    const int k = *kdev;
+    const int ld = ((k + TS_PREC - 1) / TS_PREC) * TS_PREC;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     for (int q = row * 64 + lane; q < m && q < (row + 1) * 64; q += 64) vm[q] = 0.0;
@@ -337,11 +342,13 @@ __global__ __launch_bounds__(kBlock) void k_prec_a(const int* Ap, const int* Ac,
 }
 
 // Step 2: vm[idx[r]] = sqrt(Sigma) (S^{-1} w)_r, a wavefront per row of the
-// dense symmetric inverse (row-major, leading dimension ld).
-__global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, int ld, const double* w,
-                                                      const double* sigA, const int* idx, int k, double* vm,
+// dense symmetric inverse (row-major, leading dimension ld); k from the device.
+__global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, const double* w, const double* sigA,
+                                                      const int* idx, const int* kdev, double* vm,
                                                       const Flags* fl) {
     if (pcg_stopped_ro(fl)) return;
+    const int k = *kdev;
+    const int ld = ((k + TS_PREC - 1) / TS_PREC) * TS_PREC;
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= k) return;

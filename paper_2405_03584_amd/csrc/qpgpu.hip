@@ -106,6 +106,16 @@ struct qp_handle {
     Flags* fl = nullptr;
     Flags* fl_host = nullptr;   // pinned, 2 slots
 
+    // captured PCG iteration graphs, one per operator (precision, preconditioner, operands)
+    struct PcgGraph {
+        int prec = 0, wb = 0, n_rz = 0;
+        const void* ops[4] = {nullptr, nullptr, nullptr, nullptr};   // sigx, sigA, d, dh
+        double hs = 0.0;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<PcgGraph> graphs;
+    bool graphs_failed = false;
+
     std::vector<hipEvent_t> tev;  // timing events, pairs
     hipEvent_t ev_chunk[2] = {nullptr, nullptr};
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_p0 = nullptr, ev_p1 = nullptr;
@@ -130,6 +140,8 @@ struct qp_handle {
         if (stream) (void)hipStreamSynchronize(stream);
         for (void* a : allocs) (void)hipFree(a);
         if (fl_host) (void)hipHostFree(fl_host);
+        for (auto& g : graphs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
         for (auto e : tev) (void)hipEventDestroy(e);
         for (auto e : {ev_chunk[0], ev_chunk[1], ev_t0, ev_t1, ev_p0, ev_p1})
             if (e) (void)hipEventDestroy(e);
@@ -143,6 +155,7 @@ struct qp_handle {
 namespace {
 
 constexpr int kLrBlocks = 256;   // blocks of the U^T p partial pass
+constexpr int kGraphIters = 4;   // PCG iterations per captured graph (and per trailing chunk)
 
 // v = w .* (U^T p) for the low-rank part of H (no-op when k = 0); p is x, or
 // x + beta*p2 in a PCG product.
@@ -404,15 +417,17 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
 }
 
 // z = P^{-1} r for the constraint-block preconditioner, given y = r ./ Dw in z;
-// returns the number of r^T z partials.
+// returns the number of r^T z partials.  Launch shapes cover the largest
+// dense block (all m rows strong); the kernels read the current k.
 int apply_precond(qp_handle* h, const double* D, const double* sigA) {
-    const int ld = h->ldcur, k = h->kcur, m = h->m;
-    const int rows_a = std::max(ld, (m + 63) / 64);
+    const int m = h->m;
+    const int rows_a = std::max(h->ld, (m + 63) / 64);
     hipLaunchKernelGGL(k_prec_a, dim3((rows_a + 3) / 4), dim3(kBlock), 0, h->stream, (const int*)h->Ap,
                        (const int*)h->Ac, (const double*)h->Av, (const double*)h->pz, sigA, (const int*)h->ridx,
-                       k, ld, m, h->wpre, h->vpre, (const Flags*)h->fl);
-    hipLaunchKernelGGL(k_prec_symv, dim3((k + 3) / 4), dim3(kBlock), 0, h->stream, (const double*)h->Sinv, ld,
-                       (const double*)h->wpre, sigA, (const int*)h->ridx, k, h->vpre, (const Flags*)h->fl);
+                       (const int*)h->kdev, m, h->wpre, h->vpre, (const Flags*)h->fl);
+    hipLaunchKernelGGL(k_prec_symv, dim3((m + 3) / 4), dim3(kBlock), 0, h->stream, (const double*)h->Sinv,
+                       (const double*)h->wpre, sigA, (const int*)h->ridx, (const int*)h->kdev, h->vpre,
+                       (const Flags*)h->fl);
     const int G = 16;
     const int grid = grid_rows_capped(h->n, G);
     hipLaunchKernelGGL(k_prec_at<G>, dim3(grid), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
@@ -503,6 +518,15 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
                        h->set.pcg_max_iter, h->psc, h->fl);
     HIPCHK(hipGetLastError());
 
+    if (refine) {
+        // A refinement solve is often converged at its start (the FP64
+        // residual already meets pcg_tol): find out before queuing iterations.
+        HIPCHK(hipMemcpyAsync(&h->fl_host[0], h->fl, sizeof(Flags), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        const Flags f0 = h->fl_host[0];
+        if (f0.pcg_converged || f0.pcg_breakdown || f0.pcg_capped || f0.ipm_done) return f0;
+    }
+
     PcgArgs pa{};
     pa.n = n; pa.x = h->px; pa.r = h->pr; pa.z = h->pz; pa.p = h->pp; pa.q = h->pq; pa.d = dd;
     pa.part_pq = h->part; pa.part_rz = h->part_rz; pa.part_rr = h->part_rr;
@@ -524,6 +548,56 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
                            (const double*)h->part_rr, ge, 0, 0.0, 0.0, 0, h->psc, h->fl);
     };
+    // Graph mode: the iterations of this operator are captured once as a graph
+    // of kGraphIters iterations and replayed (one launch call per four
+    // iterations instead of one per kernel).  Every dynamic quantity of an
+    // iteration lives in device memory, so replays are exact repeats of the
+    // direct launches.
+    hipGraphExec_t gexec = nullptr;
+    if (h->set.graphs && !timing && !h->graphs_failed) {
+        const void* ops[4] = {sigx, sigA, d, dh};
+        for (auto& g : h->graphs)
+            if (g.prec == prec && g.wb == wb && g.n_rz == n_rz && g.hs == hs && g.ops[0] == ops[0] &&
+                g.ops[1] == ops[1] && g.ops[2] == ops[2] && g.ops[3] == ops[3])
+                gexec = g.exec;
+        if (!gexec) {
+            hipGraph_t graph = nullptr;
+            bool ok = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                try {
+                    for (int i = 0; i < kGraphIters; ++i) one_iter();
+                } catch (...) {
+                    (void)hipStreamEndCapture(h->stream, &graph);
+                    if (graph) (void)hipGraphDestroy(graph);
+                    throw;
+                }
+                ok = hipStreamEndCapture(h->stream, &graph) == hipSuccess && graph != nullptr;
+                if (ok) ok = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+                if (graph) (void)hipGraphDestroy(graph);
+            }
+            if (ok) {
+                if (h->graphs.size() >= 8) {   // keep a few operators per handle
+                    (void)hipGraphExecDestroy(h->graphs.front().exec);
+                    h->graphs.erase(h->graphs.begin());
+                }
+                qp_handle::PcgGraph g;
+                g.prec = prec; g.wb = wb; g.n_rz = n_rz; g.hs = hs;
+                for (int i = 0; i < 4; ++i) g.ops[i] = ops[i];
+                g.exec = gexec;
+                h->graphs.push_back(g);
+            } else {
+                (void)hipGetLastError();   // capture unsupported here: launch directly from now on
+                h->graphs_failed = true;
+                gexec = nullptr;
+            }
+        }
+    }
+    auto queue = [&](int iters) {   // iters is a multiple of kGraphIters in graph mode
+        if (gexec)
+            for (int i = 0; i < iters; i += kGraphIters) HIPCHK(hipGraphLaunch(gexec, h->stream));
+        else
+            for (int i = 0; i < iters; ++i) one_iter();
+    };
     auto snapshot = [&](int slot) {
         HIPCHK(hipMemcpyAsync(&h->fl_host[slot], h->fl, sizeof(Flags), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipEventRecord(h->ev_chunk[slot], h->stream));
@@ -538,17 +612,18 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     // long solves); later chunks are four iterations, so few no-op launches
     // trail the converged iteration.
     const int pred = std::min(h->last_pcg_iters, h->last_pcg_iters2);
-    int chunk = std::max(4, std::min(512, (pred * 3) / 4));
+    int chunk = std::max(kGraphIters, std::min(512, (pred * 3) / 4));
+    chunk = ((chunk + kGraphIters - 1) / kGraphIters) * kGraphIters;
     int64_t launched = 0;
     const int64_t guard = int64_t(h->set.pcg_max_iter) + 4096;
     int cur = 0;
-    for (int i = 0; i < chunk; ++i) one_iter();
+    queue(chunk);
     launched += chunk;
     snapshot(cur);
     Flags f{};
     while (true) {
-        chunk = 4;
-        for (int i = 0; i < chunk; ++i) one_iter();
+        chunk = kGraphIters;
+        queue(chunk);
         launched += chunk;
         snapshot(cur ^ 1);
         HIPCHK(hipEventSynchronize(h->ev_chunk[cur]));
@@ -691,6 +766,7 @@ void qp_default_settings(qp_settings* s) {
     s->precond = 1;
     s->spmv_format = 0;
     s->refine_tol = 1e-3;
+    s->graphs = 1;
 }
 
 const char* qp_last_error(const qp_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }

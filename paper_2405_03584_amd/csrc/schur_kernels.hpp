@@ -21,11 +21,11 @@
 // rounded up to 32; padding rows/columns hold the identity.
 #pragma once
 
-#include "device_common.hpp"
+#include "ipm_kernels.hpp"
 
 namespace qpg {
 
-constexpr int TS = 32;   // tile edge of the dense kernels
+constexpr int TS = TS_PREC;   // tile edge of the dense kernels (the preconditioner kernels use the same)
 
 constexpr double kStrongRow = 1.0;   // M_ii threshold for the dense block
 

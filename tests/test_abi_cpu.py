@@ -32,7 +32,7 @@ def test_default_settings():
     s = qpgpu.qp_default_settings()
     assert s.pcg_tol == 1e-8 and s.mu_tol == 1e-10 and s.tau == 0.995
     assert s.precision == qpgpu.QP_FP64 and s.refine_steps == 6 and s.max_ipm_iter == 200
-    assert s.refine_tol == 1e-3
+    assert s.refine_tol == 1e-3 and s.graphs == 1
 
 
 def _expect_invalid(**kw):
@@ -70,6 +70,8 @@ def test_invalid_inputs_rejected_before_device():
     assert "schedule" in _expect_invalid(settings=s)
     s = qpgpu.qp_default_settings(refine_tol=1e-9)   # below pcg_tol
     assert "refine_tol" in _expect_invalid(settings=s)
+    s = qpgpu.qp_default_settings(graphs=2)
+    assert "graphs" in _expect_invalid(settings=s)
 
 
 def test_no_gpu_gives_device_error_not_crash():

@@ -432,6 +432,34 @@ def test_solve_band_csr_and_line_agree():
 
 
 # ----------------------------------------------------------------------------
+# captured PCG graphs (a10): replays are exact repeats of the direct launches
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which,prec", [("band", "fp64"), ("band", "bf16"), ("cfg1", "fp64")])
+def test_graph_replays_match_direct_launches(which, prec):
+    """Three solves and a Newton step on a handle that replays captured graphs,
+    with direct (uncaptured) work between them, against the same calls on a
+    handle that launches every kernel directly: identical bits every time."""
+    prob = qpsynth.config2(scale=0.02) if which == "band" else qpsynth.config1(3)
+    it = qpsynth.random_iterate(prob, 13)
+    hg = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec, graphs=1))
+    hd = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec, graphs=0))
+    for rep in range(3):
+        a, b = qpgpu.qp_solve(hg), qpgpu.qp_solve(hd)
+        assert a.status == b.status == qpgpu.QP_OK
+        assert np.array_equal(a.x, b.x), (rep, np.abs(a.x - b.x).max())
+        assert a.info["pcg_iters"] == b.info["pcg_iters"]
+        # direct work on the graph handle between replays
+        ya, _ = qpgpu.qp_operator_apply(hg, it["sigma_x"], it["sigma_A"], it["v"])
+        yb, _ = qpgpu.qp_operator_apply(hd, it["sigma_x"], it["sigma_A"], it["v"])
+        assert np.array_equal(ya, yb)
+    sa, dxa, ia = qpgpu.qp_newton_step(hg, it["sigma_x"], it["sigma_A"], it["rhs"])
+    sb, dxb, ib = qpgpu.qp_newton_step(hd, it["sigma_x"], it["sigma_A"], it["rhs"])
+    assert sa == sb == qpgpu.QP_OK
+    assert np.array_equal(dxa, dxb) and ia["pcg_iters"] == ib["pcg_iters"]
+
+
+# ----------------------------------------------------------------------------
 # batched solves (a10): many uneven QPs through qp_solve_batch
 # ----------------------------------------------------------------------------
 
