@@ -559,6 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_ipm_fwd(FwdArgs<double> a, IpmVec v,
 
 struct IpmBwdArgs {
     const int* Jtp; const int* Jtc; const double* Jtv;
+    const int* sptr; const int* sslot; const double* lc;   // line format: per-spot slot ids, per-slot J^T W J x shares
     const int* Atp; const int* Atc; const double* Atv; int hasA;
     const double* t;
     double gamma;
@@ -583,7 +584,8 @@ __global__ __launch_bounds__(kBlock) void k_ipm_bwd(IpmBwdArgs a, IpmVec v, cons
     for (int base = b * RPB; base < v.n; base += gridDim.x * RPB) {
         const int j = base + threadIdx.x / G;
         if (j < v.n) {
-            double hj = hs * row_dot_lane<G, double, double>(a.Jtp, a.Jtc, a.Jtv, a.t, j, lane);
+            double hj = hs * (a.lc ? index_sum_lane<G>(a.sptr, a.sslot, a.lc, j, lane)
+                                   : row_dot_lane<G, double, double>(a.Jtp, a.Jtc, a.Jtv, a.t, j, lane));
             if (a.lr_k) hj += hs * lowrank_lane<G>(a.U, a.lr_v, a.lr_k, v.n, j, lane);
             double aty = 0.0, ava = 0.0, avb = 0.0, a2s = 0.0;
             if (a.hasA) {

@@ -40,7 +40,8 @@ struct LineArgs {
     double* u; const double* sigA;
     int nbL;               // blocks working on lines (one line per block)
     int nbA;               // blocks working on rows of A (first in the grid, one row each)
-    const Flags* fl;
+    const Flags* fl;       // PCG product: skipped once the PCG solve has stopped
+    const Flags* fl_ipm;   // residual pass: skipped once the IPM has finished
 };
 
 template <typename VT, typename AT>
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const int lb = max(0, min(b, a.L - 1));
     const int off = a.L > 0 ? a.lptr[lb] : 0;
     const int end = a.L > 0 ? a.lptr[lb + 1] : 0;
-    if (pcg_stopped_ro(a.fl)) return;
+    if (pcg_stopped_ro(a.fl) || (a.fl_ipm && a.fl_ipm->ipm_done)) return;
     const Gather g = make_gather(a.x, a.p2, a.sc);
     if (b < a.nbL) {
         const int l = b;

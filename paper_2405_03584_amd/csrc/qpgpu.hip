@@ -1157,8 +1157,18 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = h->Jv; f.W = h->W; f.nJ = h->nJ;
             f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = m;
             f.x = v.x; f.t = h->t; f.u = h->u; f.sigA = nullptr; f.fl = nullptr;
-            f.nbJ = h->nJ > 0 ? grid_rows(h->nJ, G) : 0;
+            // line format: J x and the per-slot shares of J^T W J x come from
+            // one read of J in the line pass; k_ipm_fwd keeps the rows of A
+            f.nbJ = (h->nJ > 0 && !h->line) ? grid_rows(h->nJ, G) : 0;
             const int nbA = m > 0 ? grid_rows(m, 64) : 0;
+            if (h->line) {
+                LineArgs<double> la{};
+                la.lptr = h->lptr; la.lcol = h->lcol; la.lval = h->lval; la.L = h->L; la.W = h->W;
+                la.x = v.x; la.c = h->lc; la.u = h->u; la.nbL = h->L; la.nbA = 0; la.fl_ipm = h->fl;
+                hipLaunchKernelGGL((k_line_pass<double, double>), dim3(std::max(1, h->L)), dim3(kBlock), 0,
+                                   h->stream, la);
+                HIPCHK(hipGetLastError());
+            }
             const int grid = std::max(1, f.nbJ + nbA);
             switch (G) {
                 case 4: hipLaunchKernelGGL(k_ipm_fwd<4>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
@@ -1170,6 +1180,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             HIPCHK(hipGetLastError());
             IpmBwdArgs ba{};
             ba.Jtp = h->Jtp; ba.Jtc = h->Jtc; ba.Jtv = h->Jtv;
+            if (h->line) { ba.sptr = h->sptr; ba.sslot = h->sslot; ba.lc = h->lc; }
             ba.Atp = h->Atp; ba.Atc = h->Atc; ba.Atv = h->Atv; ba.hasA = m > 0;
             ba.t = h->t; ba.gamma = h->gamma;
             ba.U = h->U; ba.lr_v = h->lr_v; ba.lr_k = h->k;
