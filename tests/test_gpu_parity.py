@@ -432,6 +432,66 @@ def test_solve_band_csr_and_line_agree():
 
 
 # ----------------------------------------------------------------------------
+# full size: the n = 20,000 band QP in the launch configuration bench.py times
+# (default settings: line format, constraint block, captured graphs)
+# ----------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def band_full():
+    print("generating the n=20000 band QP", flush=True)
+    return qpsynth.config2()
+
+
+def _golden_config2():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config2_oracle.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_full_size_solve_matches_oracle_sample(band_full, prec):
+    """x at every 50th spot against the oracle's stored solution (written by
+    tests/golden/make_config2_golden.py from oracle/ only), the objective
+    within the gap the stopping rule allows, and the KKT certificate of the
+    whole GPU solution."""
+    prob, g = band_full, _golden_config2()
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
+    res = qpgpu.qp_solve(h)
+    assert res.status == qpgpu.QP_OK, res.info
+    step = g["sample_index_step"]
+    assert np.abs(res.x[::step] - np.array(g["x_sample"])).max() <= 1e-6 * (1 + g["x_inf_norm"])
+    m_tot = int(np.isfinite(prob.x_lo).sum() + np.isfinite(prob.x_hi).sum()
+                + np.isfinite(prob.A_lo).sum() + np.isfinite(prob.A_hi).sum())
+    gap = 2.0 * m_tot * 1e-10 * g["zeta"]
+    assert abs(res.info["objective"] - g["objective"]) <= 1e-8 * (1 + abs(g["objective"])) + gap
+    cert = oracle.kkt_certificate(prob, res.x, res.lam_x, res.lam_A)
+    assert cert.worst() <= 1e-9, cert
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_full_size_operator(band_full, prec):
+    """K v at full size against the oracle's factor-form H product plus the
+    Sigma and A terms, within the rounding bound of the line test (doubled:
+    the reference is rounded too)."""
+    prob = band_full
+    it = qpsynth.random_iterate(prob, 5)
+    h = qpgpu.qp_create_from_problem(prob)
+    y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
+    assert info["spmv_format"] == 1
+    v, sx, sA = it["v"], it["sigma_x"], it["sigma_A"]
+    ref = oracle.hessian_apply(prob, v) + sx * v + prob.A.T @ (sA * (prob.A @ v))
+    aJ, aA, av = abs(prob.J), abs(prob.A), np.abs(v)
+    bound = prob.gamma * av + aJ.T @ (prob.W * (aJ @ av)) + sx * av + aA.T @ (sA * (aA @ av))
+    unit = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16": 2.0 ** -8}[prec]
+    acc = 2.0 ** -53 if prec == "fp64" else 2.0 ** -24
+    Lj = np.diff(prob.J.indptr).max()
+    Lt = np.diff(prob.J.tocsc().indptr).max()
+    c = 2 * (2 * unit + (Lj + Lt + 2) * acc) + 1e-13
+    assert np.all(np.abs(y - ref) <= c * bound)
+
+
+# ----------------------------------------------------------------------------
 # captured PCG graphs (a10): replays are exact repeats of the direct launches
 # ----------------------------------------------------------------------------
 
