@@ -273,6 +273,68 @@ __device__ __forceinline__ void lane_swap(double& x, double& y) {
     y = __hiloint2double(__float_as_int(yh), __float_as_int(yl));
 }
 
+// h1 * index_sum_lane (ptr/idx/val) plus row_dot_lane (ptr2/col2/val2
+// against x2; ptr2 null: none) for the same row, by a group of G lanes with U
+// loads per lane and term: the
+// loads of both sums are issued level by level together (row bounds, then
+// indices and values, then the gathers), so the two three-level chains
+// overlap.  Each covers up to U*G entries in one pass; longer rows loop.
+template <int G, int U = 4>
+__device__ __forceinline__ double index_sum_plus_row_dot(const int* __restrict__ ptr, const int* __restrict__ idx,
+                                                         const double* __restrict__ val,
+                                                         const int* __restrict__ ptr2, const int* __restrict__ col2,
+                                                         const double* __restrict__ val2,
+                                                         const double* __restrict__ x2, double h1, int row,
+                                                         int lane) {
+    const int a = ptr[row], b = ptr[row + 1];
+    const int a2 = ptr2 ? ptr2[row] : 0, b2 = ptr2 ? ptr2[row + 1] : 0;
+    const bool has1 = b > a, has2 = b2 > a2;   // uniform over the group
+    double s1 = 0.0, s2 = 0.0;
+    int k = a + lane, k2 = a2 + lane;
+    while (k < b || k2 < b2) {
+        int c[U], c2[U];
+        double w2[U], g1[U], g2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = 0;
+            c2[u] = 0;
+            w2[u] = 0.0;
+        }
+        if (has1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) c[u] = idx[min(k + u * G, b - 1)];
+        }
+        if (has2) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c2[u] = col2[min(k2 + u * G, b2 - 1)];
+                w2[u] = val2[min(k2 + u * G, b2 - 1)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            g1[u] = 0.0;
+            g2[u] = 0.0;
+        }
+        if (has1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) g1[u] = val[c[u]];
+        }
+        if (has2) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) g2[u] = x2[c2[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s1 += (k + u * G < b) ? g1[u] : 0.0;
+            s2 += (k2 + u * G < b2) ? w2[u] * g2[u] : 0.0;
+        }
+        k += U * G;
+        k2 += U * G;
+    }
+    return h1 * s1 + s2;
+}
+
 // Reduce-scatter over the 64 lanes of a wavefront: each lane holds N values
 // v[0..N) (N a power of two, N <= 32); on return every lane holds, in the
 // value returned, the sum over all 64 lanes of value index

@@ -186,9 +186,9 @@ __global__ __launch_bounds__(kBlock) void k_spot_pass(SpotArgs a) {
     for (int base = b * RPB; base < a.n; base += gridDim.x * RPB) {
         const int j = base + threadIdx.x / G;
         if (j < a.n) {
-            double s = a.hs * index_sum_lane<G>(a.sptr, a.sslot, a.c, j, lane);
+            double s = index_sum_plus_row_dot<G>(a.sptr, a.sslot, a.c, a.hasA ? a.Atp : nullptr, a.Atc, a.Atv,
+                                                 a.u, a.hs, j, lane);
             if (a.lr_k) s += a.hs * lowrank_lane<G>(a.U, a.lr_v, a.lr_k, a.n, j, lane);
-            if (a.hasA) s += row_dot_lane<G, double, double>(a.Atp, a.Atc, a.Atv, a.u, j, lane);
             s = group_sum<double, G>(s);
             if (lane == 0) {
                 const double pj = direction_entry(a.x, a.pcg, beta, j);
