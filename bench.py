@@ -35,15 +35,18 @@ def spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes=8, fmt=0):
     Each matrix value and index read once, row pointers once, every dense
     vector read or written once (gathered vectors counted once).  fmt = 0: CSR
     (int32 column index per nonzero), a J pass and a J^T pass that each read
-    the values.  fmt = 1: line format, a line pass that reads the values once
-    (one int32 column id per 64-row line slot) and writes one double per slot,
-    then a spot pass that reads one int32 slot id and that double per slot."""
+    the values.  fmt = 1: line format in a PCG product, a line pass that reads
+    the values once (one int32 column id per 64-row line slot), gathers z and
+    p, and writes one double per slot, and forms u from A z and A p (five
+    m-vectors: A z, A p read and written, Sigma_A, u); then a spot pass that
+    reads one int32 slot id and that double per slot, A^T, u, z, p and
+    Sigma_x, and writes p and q."""
     if fmt == 1:
         slots = nnzJ // 64
         lines = nJ // 64
-        fwd = (nnzJ * vbytes + slots * 4 + (lines + 1) * 4 + nJ * 8 + n * 8 + slots * 8
-               + nnzA * 12 + (m + 1) * 4 + m * 8 + m * 8)
-        bwd = (n + 1) * 4 + slots * 4 + slots * 8 + nnzA * 12 + (n + 1) * 4 + m * 8 + n * 8 * 3
+        fwd = (nnzJ * vbytes + slots * 4 + (lines + 1) * 4 + nJ * 8 + 2 * n * 8 + slots * 8
+               + 5 * m * 8)
+        bwd = (n + 1) * 4 + slots * 4 + slots * 8 + nnzA * 12 + (n + 1) * 4 + m * 8 + n * 8 * 5
         return fwd, bwd
     jf = nnzJ * (vbytes + 4) + (nJ + 1) * 4
     jb = nnzJ * (vbytes + 4) + (n + 1) * 4

@@ -185,14 +185,48 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
 // One iteration: the product kernels form p = z + beta p on the fly and
 // q = K p with partials of p^T q; k_pcg_xr reduces them (every block, in the
 // same fixed order) into alpha, updates x and r and applies the diagonal part
-// of the preconditioner; with the constraint block, k_prec_a, k_prec_symv and
-// k_prec_at finish z; k_pcg_scalars (one block) reduces r^T r and r^T z into
-// the stop test, beta and rho.  Reductions are finished by the consumer:
-// kernel boundaries make the partials visible without device-wide fences.
+// of the preconditioner; with the constraint block, k_pcg_xr also runs step 1
+// of z = P^{-1} r (on r - alpha q, before r is stored), and k_prec_symv and
+// k_prec_at finish z and store r; k_pcg_scalars (one block) reduces r^T r and
+// r^T z into the stop test, beta and rho.  Reductions are finished by the
+// consumer: kernel boundaries make the partials visible without device-wide
+// fences.
 // Preconditioner z = P^{-1} r.  Jacobi (the paper, Section 4.1.2): z = r ./ d
 // with d = diag(K).  Constraint block (woodbury = 1): y = r ./ D with
 // D = diag(Hs + Sigma_x), then z = y - D^{-1} A^T Sigma^{1/2} S^{-1}
 // Sigma^{1/2} A y.
+
+// Constraint-block preconditioner, step 1: w_r = sqrt(Sigma_i) (A y)_i for the
+// strong rows i = idx[r] (a wavefront per row; padding rows k..ld-1 get 0),
+// and vm = 0 on all m rows (step 2 fills the strong ones).  k (strong rows)
+// is read from the device, ld = k rounded up to TS_PREC; grids cover the
+// largest possible ld, so launch shapes do not depend on the current k.
+struct PrecRows {
+    const int* Ap; const int* Ac; const double* Av;
+    const double* sigA; const int* idx; const int* kdev; int m;
+    double* w; double* vm;
+};
+constexpr int TS_PREC = 32;   // tile edge of the dense block (schur_kernels.hpp: TS)
+template <typename GV>
+__device__ __forceinline__ void prec_rows(const PrecRows& a, const GV& y, int blk) {
+    const int k = *a.kdev;
+    const int ld = ((k + TS_PREC - 1) / TS_PREC) * TS_PREC;
+    const int row = blk * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int q = row * 64 + lane; q < a.m && q < (row + 1) * 64; q += 64) a.vm[q] = 0.0;
+    if (row >= ld) return;
+    double s = 0.0;
+    if (row < k) s = row_dot_lane_g<64, double, double, 8>(a.Ap, a.Ac, a.Av, y, a.idx[row], lane);
+    s = group_sum<double, 64>(s);
+    if (lane == 0) a.w[row] = row < k ? sqrt(a.sigA[a.idx[row]]) * s : 0.0;
+}
+
+// Step 1 at the start of a solve: y = r ./ D is held in z.
+__global__ __launch_bounds__(kBlock) void k_prec_a(PrecRows a, const double* y, const Flags* fl) {
+    if (pcg_stopped_ro(fl)) return;
+    prec_rows(a, Gather{y, nullptr, 0.0}, blockIdx.x);
+}
+
 struct PcgArgs {
     int n;
     double* x; double* r; double* z; const double* p; const double* q; const double* d;
@@ -202,11 +236,21 @@ struct PcgArgs {
     int woodbury;
     PcgScal* sc;
     Flags* fl;
+    PrecRows pa;                         // constraint block: step 1 of z = P^{-1} r
+    int nbA;                             // blocks of the grid (the first ones) working on pa
 };
 
-// alpha = rho / p^T q; x += alpha p; r -= alpha q; z = r ./ d (Jacobi) or
-// y = r ./ D (constraint block, stored in z until k_prec_at finishes it);
-// partials of r^T r (and r^T z for Jacobi).
+// y_c = (r_c - alpha q_c) / D_c: the preconditioner's first vector, read from
+// the residual before it is updated (the update is stored by k_prec_at).
+struct ScaledResidual {
+    const double* r; const double* q; const double* D; double alpha;
+    __device__ __forceinline__ double operator()(int c) const { return fma(-alpha, q[c], r[c]) / D[c]; }
+};
+
+// alpha = rho / p^T q; x += alpha p; partials of r^T r for r - alpha q.
+// Jacobi: r -= alpha q and z = r ./ d stored, with partials of r^T z.
+// Constraint block: the first nbA blocks run step 1 of the preconditioner on
+// y = (r - alpha q) ./ D, so r is left for k_prec_at to update.
 __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped(a.fl)) return;
@@ -219,35 +263,60 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
         if (bad) a.fl->pcg_breakdown = 1;
     }
     if (bad) return;
+    if (int(blockIdx.x) < a.nbA) {
+        prec_rows(a.pa, ScaledResidual{a.r, a.q, a.d, alpha}, blockIdx.x);
+        return;
+    }
+    const int eb = int(blockIdx.x) - a.nbA;
+    const int ne = int(gridDim.x) - a.nbA;
     double rz = 0.0, rr = 0.0;
-    for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+    for (int j = eb * kBlock + threadIdx.x; j < a.n; j += ne * kBlock) {
         a.x[j] += alpha * a.p[j];
-        const double rj = a.r[j] - alpha * a.q[j];
-        const double zj = rj / a.d[j];
-        a.r[j] = rj;
-        a.z[j] = zj;
-        rz += rj * zj;
+        const double rj = fma(-alpha, a.q[j], a.r[j]);
+        if (!a.woodbury) {
+            const double zj = rj / a.d[j];
+            a.r[j] = rj;
+            a.z[j] = zj;
+            rz += rj * zj;
+        }
         rr += rj * rj;
     }
     rz = block_sum(rz, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        if (!a.woodbury) a.part_rz[blockIdx.x] = rz;
-        a.part_rr[blockIdx.x] = rr;
+        if (!a.woodbury) a.part_rz[eb] = rz;
+        a.part_rr[eb] = rr;
     }
 }
 
-// One block.  mode 0: ||r||^2, iteration count, convergence / cap flags,
+// A z for the line-format PCG product, which forms A p of the new direction
+// p = z + beta p as A z + beta (A p) (k_line_pass): the rows of A, a
+// wavefront per row.
+struct AzArgs {
+    const int* Ap; const int* Ac; const double* Av; const double* z; int m;
+    double* az;
+};
+
+// Block 0.  mode 0: ||r||^2, iteration count, convergence / cap flags,
 // beta = r^T z / rho, rho = r^T z.  Start of a solve (p was zeroed, so the
 // first direction is z; beta = 0): mode 1 stops at rel_tol * ||rhs|| and
 // records ||rhs||^2 as the outer norm; mode 2 (a refinement solve) stops at
 // max(rel_tol * ||rhs||, tol * outer norm), and at once when rhs already
-// meets tol * outer norm.
+// meets tol * outer norm.  Blocks 1.. (when az.m > 0): A z, four rows each.
 __global__ __launch_bounds__(kBlock) void k_pcg_scalars(const double* part_rz, int n_rz, const double* part_rr,
                                                         int n_rr, int mode, double rel_tol, double tol,
-                                                        int max_iter, PcgScal* sc, Flags* fl) {
+                                                        int max_iter, PcgScal* sc, Flags* fl, AzArgs az) {
     __shared__ double sh[kBlock / 64];
     if (mode ? ipm_finished(fl) : pcg_stopped(fl)) return;
+    if (blockIdx.x > 0) {
+        const int row = (int(blockIdx.x) - 1) * (kBlock / 64) + (threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        if (row >= az.m) return;
+        double s = row_dot_lane<64, double, double, 8>(az.Ap, az.Ac, az.Av, az.z, row, lane);
+        s = group_sum<double, 64>(s);
+        if (lane == 0) az.az[row] = s;
+        return;
+    }
     const double rz = reduce_partials_sum(part_rz, n_rz, 1, sh);
     const double rr = reduce_partials_sum(part_rr, n_rr, 1, sh);
     if (threadIdx.x != 0) return;
@@ -286,6 +355,7 @@ struct PcgInitArgs {
     double* part_rz; double* part_rr;
     int woodbury;
     Flags* fl;
+    double* apv; int m;    // A p of the line-format product (may be null): zeroed with p
 };
 
 // x = 0; r = rhs; z = r ./ d; p = 0; partials.  Clears the PCG flags of the
@@ -311,34 +381,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
         rz += rj * zj;
         rr += rj * rj;
     }
+    if (a.apv)
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.m; i += gridDim.x * kBlock) a.apv[i] = 0.0;
     rz = block_sum(rz, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
         if (!a.woodbury) a.part_rz[blockIdx.x] = rz;
         a.part_rr[blockIdx.x] = rr;
     }
-}
-
-// Constraint-block preconditioner, step 1: w_r = sqrt(Sigma_i) (A y)_i for the
-// strong rows i = idx[r] (a wavefront per row; padding rows k..ld-1 get 0),
-// and vm = 0 on all m rows (step 2 fills the strong ones).  k (strong rows)
-// is read from the device, ld = k rounded up to TS_PREC; the grid covers the
-// largest possible ld, so launch shapes do not depend on the current k.
-constexpr int TS_PREC = 32;   // tile edge of the dense block (schur_kernels.hpp: TS)
-__global__ __launch_bounds__(kBlock) void k_prec_a(const int* Ap, const int* Ac, const double* Av,
-                                                   const double* y, const double* sigA, const int* idx,
-                                                   const int* kdev, int m, double* w, double* vm, const Flags* fl) {
-    if (pcg_stopped_ro(fl)) return;
-    const int k = *kdev;
-    const int ld = ((k + TS_PREC - 1) / TS_PREC) * TS_PREC;
-    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    for (int q = row * 64 + lane; q < m && q < (row + 1) * 64; q += 64) vm[q] = 0.0;
-    if (row >= ld) return;
-    double s = 0.0;
-    if (row < k) s = row_dot_lane<64, double, double, 8>(Ap, Ac, Av, y, idx[row], lane);
-    s = group_sum<double, 64>(s);
-    if (lane == 0) w[row] = row < k ? sqrt(sigA[idx[row]]) * s : 0.0;
 }
 
 // Step 2: vm[idx[r]] = sqrt(Sigma) (S^{-1} w)_r, a wavefront per row of the
@@ -375,16 +425,20 @@ __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, const 
     }
 }
 
-// Step 3: z_j = y_j - (A^T v)_j / D_j (y held in z) and partials of r^T z.
-// G lanes per row of A^T, grid-stride with a capped grid.
+// Step 3: z_j = y_j - (A^T v)_j / D_j and partials of r^T z.  Start of a
+// solve (q null): y is held in z and r is final.  In an iteration: r_j -=
+// alpha q_j is stored here and y_j = r_j / D_j.  G lanes per row of A^T,
+// grid-stride with a capped grid.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* Atc, const double* Atv,
-                                                    const double* v, const double* D, const double* r,
-                                                    double* z, int n, double* part_rz, const Flags* fl) {
+                                                    const double* v, const double* D, double* r,
+                                                    const double* q, const PcgScal* sc, double* z, int n,
+                                                    double* part_rz, const Flags* fl) {
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped_ro(fl)) return;
     constexpr int RPB = kBlock / G;
     const int lane = threadIdx.x % G;
+    const double alpha = q ? sc->alpha : 0.0;
     double rz = 0.0;
     for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
         const int j = base + threadIdx.x / G;
@@ -392,9 +446,18 @@ __global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* A
             double s = row_dot_lane<G, double, double>(Atp, Atc, Atv, v, j, lane);
             s = group_sum<double, G>(s);
             if (lane == 0) {
-                const double zj = z[j] - s / D[j];
+                double rj, yj;
+                if (q) {
+                    rj = fma(-alpha, q[j], r[j]);
+                    yj = rj / D[j];
+                    r[j] = rj;
+                } else {
+                    rj = r[j];
+                    yj = z[j];
+                }
+                const double zj = yj - s / D[j];
                 z[j] = zj;
-                rz += r[j] * zj;
+                rz += rj * zj;
             }
         }
     }

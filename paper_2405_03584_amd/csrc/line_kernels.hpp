@@ -13,7 +13,9 @@
 //                fixed order through LDS); pass 2 multiplies the held values
 //                by t_r and reduces over the 64 rows of every slot, giving
 //                c[slot] = sum_r J_(r,slot) t_r, the line's contribution to
-//                (J^T t)_col(slot).  Remaining blocks: u = Sigma_A .* (A p).
+//                (J^T t)_col(slot).  Other blocks: u = Sigma_A .* (A p), by
+//                rows of A, or in a PCG product from A z (left by the
+//                previous iteration's k_pcg_scalars) as A p = A z + beta A p.
 //  k_spot_pass   spot j sums c over the slots it covers (its (line, slot)
 //                list), adds gamma p_j, the low-rank term, Sigma_x p_j and
 //                (A^T u)_j, and in a PCG product stores p and the p^T q
@@ -38,8 +40,11 @@ struct LineArgs {
     const double* x; const double* p2; const PcgScal* sc;   // gathered vector, as in FwdArgs
     double* c;             // per slot (lptr[L] entries)
     double* u; const double* sigA;
+    const double* az;      // A z of the new direction's z (nbU > 0)
+    double* apv;           // A p: the previous direction's on entry, the new one's on exit (nbU > 0)
     int nbL;               // blocks working on lines (one line per block)
-    int nbA;               // blocks working on rows of A (first in the grid, one row each)
+    int nbA;               // blocks working on rows of A (after the nbU blocks, one row each)
+    int nbU;               // blocks forming u from A z and A p (first in the grid)
     const Flags* fl;       // PCG product: skipped once the PCG solve has stopped
     const Flags* fl_ipm;   // residual pass: skipped once the IPM has finished
 };
@@ -55,8 +60,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     // remapped so each XCD streams one contiguous range of lines.
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const bool arow = int(blockIdx.x) < a.nbA;
-    const int b = arow ? a.nbL : xcd_remap(int(blockIdx.x) - a.nbA, int(gridDim.x) - a.nbA);
+    const int bi = int(blockIdx.x);
+    const int first = a.nbU + a.nbA;
+    const bool side = bi < first;   // a u block or an A-row block
+    const int b = side ? a.nbL : xcd_remap(bi - first, int(gridDim.x) - first);
     // the line's extent is loaded before the stop test so both loads overlap
     // (blocks past the lines read the last line's extent, unused; L = 0 reads
     // nothing)
@@ -65,6 +72,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const int end = a.L > 0 ? a.lptr[lb + 1] : 0;
     if (pcg_stopped_ro(a.fl) || (a.fl_ipm && a.fl_ipm->ipm_done)) return;
     const Gather g = make_gather(a.x, a.p2, a.sc);
+    if (bi < a.nbU) {
+        // A p of the new direction p = z + beta p from the two m-vectors
+        for (int i = bi * kBlock + threadIdx.x; i < a.m; i += a.nbU * kBlock) {
+            const double v = fma(g.beta, a.apv[i], a.az[i]);
+            a.apv[i] = v;
+            a.u[i] = a.sigA ? a.sigA[i] * v : v;
+        }
+        return;
+    }
     if (b < a.nbL) {
         const int l = b;
         const int len = end - off;
@@ -143,7 +159,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         // a row of A per workgroup: 256 lanes with two loads each cover up to
         // 512 nonzeros in one round of gathers; wavefront sums combined in
         // a fixed order through LDS
-        const int row = int(blockIdx.x);
+        const int row = bi - a.nbU;
         double s = 0.0;
         if (row < a.m) s = row_dot_lane_g<kBlock, double, double, 2>(a.Ap, a.Ac, a.Av, g, row, threadIdx.x);
         s = group_sum<double, 64>(s);

@@ -88,6 +88,7 @@ struct qp_handle {
     // work
     IpmVec iv{};
     double *t = nullptr, *u = nullptr;
+    double *az = nullptr, *apv = nullptr;   // A z and A p of the line-format PCG product
     double *px = nullptr, *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;
     double *zero_n = nullptr, *zero_m = nullptr, *tmp_n = nullptr, *tmp_n2 = nullptr, *tmp_m = nullptr;
     double *rhs_full = nullptr, *rho = nullptr, *dxacc = nullptr;   // refinement of low-precision directions
@@ -253,10 +254,16 @@ int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, 
     f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
     f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.c = h->lc; f.u = h->u; f.sigA = sigA; f.fl = fl;
     f.nbL = h->L;
-    const int nbA = f.m;
-    f.nbA = nbA;
+    if (pcg && f.m > 0) {   // A p from A z (k_pcg_scalars) and the previous A p
+        f.az = h->az;
+        f.apv = h->apv;
+        f.nbU = std::min((f.m + kBlock - 1) / kBlock, 64);
+    } else {
+        f.nbA = f.m;
+    }
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
-    hipLaunchKernelGGL((k_line_pass<VT, AT>), dim3(std::max(1, f.nbL + nbA)), dim3(kBlock), 0, h->stream, f);
+    hipLaunchKernelGGL((k_line_pass<VT, AT>), dim3(std::max(1, f.nbL + f.nbA + f.nbU)), dim3(kBlock), 0,
+                       h->stream, f);
     HIPCHK(hipGetLastError());
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
     lowrank_prepare(h, x, pl.p2, fl);
@@ -416,25 +423,44 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
     return true;
 }
 
-// z = P^{-1} r for the constraint-block preconditioner, given y = r ./ Dw in z;
-// returns the number of r^T z partials.  Launch shapes cover the largest
-// dense block (all m rows strong); the kernels read the current k.
-int apply_precond(qp_handle* h, const double* D, const double* sigA) {
+// Step 1 of the constraint-block preconditioner on the strong rows of A; the
+// grid covers the largest dense block (all m rows strong), kernels read the
+// current k.
+PrecRows prec_rows_args(qp_handle* h, const double* sigA) {
+    PrecRows pa{};
+    pa.Ap = h->Ap; pa.Ac = h->Ac; pa.Av = h->Av; pa.sigA = sigA;
+    pa.idx = h->ridx; pa.kdev = h->kdev; pa.m = h->m;
+    pa.w = h->wpre; pa.vm = h->vpre;
+    return pa;
+}
+int prec_rows_blocks(const qp_handle* h) {
+    const int rows_a = std::max(h->ld, (h->m + 63) / 64);
+    return (rows_a + 3) / 4;
+}
+
+// Steps 2 and 3 of z = P^{-1} r for the constraint-block preconditioner
+// (step 1 ran before: k_prec_a at the start of a solve, k_pcg_xr in an
+// iteration, where q != null makes step 3 store r -= alpha q); returns the
+// number of r^T z partials.
+int apply_precond_23(qp_handle* h, const double* D, const double* sigA, const double* q) {
     const int m = h->m;
-    const int rows_a = std::max(h->ld, (m + 63) / 64);
-    hipLaunchKernelGGL(k_prec_a, dim3((rows_a + 3) / 4), dim3(kBlock), 0, h->stream, (const int*)h->Ap,
-                       (const int*)h->Ac, (const double*)h->Av, (const double*)h->pz, sigA, (const int*)h->ridx,
-                       (const int*)h->kdev, m, h->wpre, h->vpre, (const Flags*)h->fl);
     hipLaunchKernelGGL(k_prec_symv, dim3((m + 3) / 4), dim3(kBlock), 0, h->stream, (const double*)h->Sinv,
                        (const double*)h->wpre, sigA, (const int*)h->ridx, (const int*)h->kdev, h->vpre,
                        (const Flags*)h->fl);
     const int G = 16;
     const int grid = grid_rows_capped(h->n, G);
     hipLaunchKernelGGL(k_prec_at<G>, dim3(grid), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
-                       (const int*)h->Atc, (const double*)h->Atv, (const double*)h->vpre, D, (const double*)h->pr,
-                       h->pz, h->n, h->part_rz, (const Flags*)h->fl);
+                       (const int*)h->Atc, (const double*)h->Atv, (const double*)h->vpre, D, h->pr, q,
+                       (const PcgScal*)h->psc, h->pz, h->n, h->part_rz, (const Flags*)h->fl);
     HIPCHK(hipGetLastError());
     return grid;
+}
+
+// z = P^{-1} r at the start of a solve, given y = r ./ D in z.
+int apply_precond(qp_handle* h, const double* D, const double* sigA) {
+    hipLaunchKernelGGL(k_prec_a, dim3(prec_rows_blocks(h)), dim3(kBlock), 0, h->stream,
+                       prec_rows_args(h, sigA), (const double*)h->pz, (const Flags*)h->fl);
+    return apply_precond_23(h, D, sigA, nullptr);
 }
 
 void autotune_schedule(qp_handle* h) {
@@ -510,12 +536,20 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     ia.n = n; ia.rhs_a = rhs_a; ia.rhs_b = rhs_b; ia.ipm = ipm_mode ? h->isc : nullptr;
     ia.x = h->px; ia.r = h->pr; ia.z = h->pz; ia.p = h->pp; ia.d = dd;
     ia.part_rz = h->part_rz; ia.part_rr = h->part_rr; ia.woodbury = wb; ia.fl = h->fl;
+    // line format: the product forms A p = A z + beta A p, with A z from the
+    // scalar kernel's other blocks
+    AzArgs az{};
+    if (h->line && sigA && h->m > 0) {
+        az.Ap = h->Ap; az.Ac = h->Ac; az.Av = h->Av; az.z = h->pz; az.m = h->m; az.az = h->az;
+        ia.apv = h->apv; ia.m = h->m;
+    }
+    const int gs = 1 + (az.m + kBlock / 64 - 1) / (kBlock / 64);
     hipLaunchKernelGGL(k_pcg_init0, dim3(ge), dim3(kBlock), 0, h->stream, ia);
     HIPCHK(hipGetLastError());
     const int n_rz = wb ? apply_precond(h, dh, sigA) : ge;
-    hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
+    hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
                        (const double*)h->part_rr, ge, refine ? 2 : 1, rel_tol, h->set.pcg_tol,
-                       h->set.pcg_max_iter, h->psc, h->fl);
+                       h->set.pcg_max_iter, h->psc, h->fl, az);
     HIPCHK(hipGetLastError());
 
     if (refine) {
@@ -531,6 +565,10 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     pa.n = n; pa.x = h->px; pa.r = h->pr; pa.z = h->pz; pa.p = h->pp; pa.q = h->pq; pa.d = dd;
     pa.part_pq = h->part; pa.part_rz = h->part_rz; pa.part_rr = h->part_rr;
     pa.woodbury = wb; pa.sc = h->psc; pa.fl = h->fl;
+    if (wb) {
+        pa.pa = prec_rows_args(h, sigA);
+        pa.nbA = prec_rows_blocks(h);
+    }
 
     const bool timing = h->set.timing != 0 && tacc != nullptr;
     const int slot_begin = tacc ? tacc->pairs : 0;
@@ -543,10 +581,10 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
             tacc->valid.push_back(1);
         }
         pa.n_pq = apply_op_prec(h, prec, h->pz, h->pq, sigx, sigA, hs, true, timed, slot);
-        hipLaunchKernelGGL(k_pcg_xr, dim3(ge), dim3(kBlock), 0, h->stream, pa);
-        if (wb) apply_precond(h, dh, sigA);
-        hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
-                           (const double*)h->part_rr, ge, 0, 0.0, 0.0, 0, h->psc, h->fl);
+        hipLaunchKernelGGL(k_pcg_xr, dim3(pa.nbA + ge), dim3(kBlock), 0, h->stream, pa);
+        if (wb) apply_precond_23(h, dh, sigA, h->pq);
+        hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
+                           (const double*)h->part_rr, ge, 0, 0.0, 0.0, 0, h->psc, h->fl, az);
     };
     // Graph mode: the iterations of this operator are captured once as a graph
     // of kGraphIters iterations and replayed (one launch call per four
@@ -914,6 +952,8 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         for (double** pv : mvec) *pv = h->dalloc<double>(std::max(m, 1));
         h->t = h->dalloc<double>(std::max(nJ, 1));
         h->u = h->dalloc<double>(std::max(m, 1));
+        h->az = h->dalloc<double>(std::max(m, 1));
+        h->apv = h->dalloc<double>(std::max(m, 1));
         h->px = h->dalloc<double>(n);
         h->pr = h->dalloc<double>(n);
         h->pz = h->dalloc<double>(n);
