@@ -200,25 +200,28 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
 // strong rows i = idx[r] (a wavefront per row; padding rows k..ld-1 get 0),
 // and vm = 0 on all m rows (step 2 fills the strong ones).  k (strong rows)
 // is read from the device, ld = k rounded up to TS_PREC; grids cover the
-// largest possible ld, so launch shapes do not depend on the current k.
+// largest possible ld, so launch shapes do not depend on the current k.  The
+// row's range in A and sqrt(Sigma_i) come from one load of the per-row table
+// (k_strong_rows), which holds empty ranges past k.
 struct PrecRows {
-    const int* Ap; const int* Ac; const double* Av;
-    const double* sigA; const int* idx; const int* kdev; int m;
+    const int* Ac; const double* Av;
+    const int* ext; const double* sq;   // per strong row: range in A, sqrt(Sigma)
+    const int* kdev; int m;
     double* w; double* vm;
 };
 constexpr int TS_PREC = 32;   // tile edge of the dense block (schur_kernels.hpp: TS)
 template <typename GV>
 __device__ __forceinline__ void prec_rows(const PrecRows& a, const GV& y, int blk) {
-    const int k = *a.kdev;
-    const int ld = ((k + TS_PREC - 1) / TS_PREC) * TS_PREC;
     const int row = blk * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    const int k = *a.kdev;
+    const int ld = ((k + TS_PREC - 1) / TS_PREC) * TS_PREC;
     for (int q = row * 64 + lane; q < a.m && q < (row + 1) * 64; q += 64) a.vm[q] = 0.0;
     if (row >= ld) return;
-    double s = 0.0;
-    if (row < k) s = row_dot_lane_g<64, double, double, 8>(a.Ap, a.Ac, a.Av, y, a.idx[row], lane);
+    const double sq = a.sq[row];
+    double s = row_dot_lane_g<64, double, double, 8>(a.ext + 2 * row, a.Ac, a.Av, y, 0, lane);
     s = group_sum<double, 64>(s);
-    if (lane == 0) a.w[row] = row < k ? sqrt(a.sigA[a.idx[row]]) * s : 0.0;
+    if (lane == 0) a.w[row] = sq * s;
 }
 
 // Step 1 at the start of a solve: y = r ./ D is held in z.
@@ -393,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
 
 // Step 2: vm[idx[r]] = sqrt(Sigma) (S^{-1} w)_r, a wavefront per row of the
 // dense symmetric inverse (row-major, leading dimension ld); k from the device.
-__global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, const double* w, const double* sigA,
+__global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, const double* w, const double* sq,
                                                       const int* idx, const int* kdev, double* vm,
                                                       const Flags* fl) {
     if (pcg_stopped_ro(fl)) return;
@@ -402,6 +405,8 @@ __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, const 
     const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= k) return;
+    const int i = idx[row];       // the output's place and scale, loaded beside the row
+    const double sqi = sq[row];
     const double* srow = Sinv + size_t(row) * ld;
     // passes of 8 loads per lane in flight (indices past ld clamped, zeroed)
     double acc[8];
@@ -419,10 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, const 
         for (int u = 0; u < 8; ++u) acc[u] += (c + 64 * u < ld) ? sv[u] * wv[u] : 0.0;
     }
     double s = group_sum<double, 64>(((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
-    if (lane == 0) {
-        const int i = idx[row];
-        vm[i] = sqrt(sigA[i]) * s;
-    }
+    if (lane == 0) vm[i] = sqi * s;
 }
 
 // Step 3: z_j = y_j - (A^T v)_j / D_j and partials of r^T z.  Start of a
@@ -443,19 +445,23 @@ __global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* A
     for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
         const int j = base + threadIdx.x / G;
         if (j < n) {
+            // the column's own entries are loaded first, beside the sum's loads
+            const double r0 = r[j], dj = D[j];
+            const double q0 = q ? q[j] : 0.0;
+            const double z0 = q ? 0.0 : z[j];
             double s = row_dot_lane<G, double, double>(Atp, Atc, Atv, v, j, lane);
             s = group_sum<double, G>(s);
             if (lane == 0) {
                 double rj, yj;
                 if (q) {
-                    rj = fma(-alpha, q[j], r[j]);
-                    yj = rj / D[j];
+                    rj = fma(-alpha, q0, r0);
+                    yj = rj / dj;
                     r[j] = rj;
                 } else {
-                    rj = r[j];
-                    yj = z[j];
+                    rj = r0;
+                    yj = z0;
                 }
-                const double zj = yj - s / D[j];
+                const double zj = yj - s / dj;
                 z[j] = zj;
                 rz += rj * zj;
             }

@@ -66,10 +66,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     const int b = side ? a.nbL : xcd_remap(bi - first, int(gridDim.x) - first);
     // the line's extent is loaded before the stop test so both loads overlap
     // (blocks past the lines read the last line's extent, unused; L = 0 reads
-    // nothing)
+    // nothing).  With 2- and 4-byte values, where a line is short work and
+    // the block's chain of dependent loads sets its time, the rows' weights
+    // are loaded here too; with doubles they are loaded after pass 1, where
+    // no register is free for them earlier.
+    constexpr bool kEarlyW = sizeof(VT) < 8;
     const int lb = max(0, min(b, a.L - 1));
     const int off = a.L > 0 ? a.lptr[lb] : 0;
     const int end = a.L > 0 ? a.lptr[lb + 1] : 0;
+    const double wrow = (kEarlyW && a.L > 0) ? a.W[size_t(lb) * 64 + lane] : 0.0;
     if (pcg_stopped_ro(a.fl) || (a.fl_ipm && a.fl_ipm->ipm_done)) return;
     const Gather g = make_gather(a.x, a.p2, a.sc);
     if (bi < a.nbU) {
@@ -134,7 +139,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         part[w][lane] = acc;
         __syncthreads();
         const AT s = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-        const AT t = AT(a.W[size_t(l) * 64 + lane] * double(s));
+        const AT t = AT((kEarlyW ? wrow : a.W[size_t(l) * 64 + lane]) * double(s));
         // pass 2: c[slot] = sum_r J_(r,slot) t_r, RH slots per reduce-scatter
         constexpr int SHIFT = RH == 32 ? 1 : RH == 16 ? 2 : RH == 8 ? 3 : RH == 4 ? 4 : RH == 2 ? 5 : 6;
         const int slot = lane >> SHIFT;
@@ -202,14 +207,20 @@ __global__ __launch_bounds__(kBlock) void k_spot_pass(SpotArgs a) {
     for (int base = b * RPB; base < a.n; base += gridDim.x * RPB) {
         const int j = base + threadIdx.x / G;
         if (j < a.n) {
+            // the spot's own entries are loaded first, beside the sums' loads
+            const double xj = a.x[j];
+            const double p2j = a.pcg.p2 ? a.pcg.p2[j] : 0.0;
+            const double sxj = a.sigx ? a.sigx[j] : 0.0;
             double s = index_sum_plus_row_dot<G>(a.sptr, a.sslot, a.c, a.hasA ? a.Atp : nullptr, a.Atc, a.Atv,
                                                  a.u, a.hs, j, lane);
             if (a.lr_k) s += a.hs * lowrank_lane<G>(a.U, a.lr_v, a.lr_k, a.n, j, lane);
             s = group_sum<double, G>(s);
             if (lane == 0) {
-                const double pj = direction_entry(a.x, a.pcg, beta, j);
+                // direction entry p_j = z_j + beta p_j, stored back in a PCG product
+                const double pj = a.pcg.p2 ? xj + beta * p2j : xj;
+                if (a.pcg.p2) a.pcg.p2[j] = pj;
                 double y = s + a.hs * a.gamma * pj;
-                if (a.sigx) y += a.sigx[j] * pj;
+                if (a.sigx) y += sxj * pj;
                 a.q[j] = y;
                 dot += pj * y;
             }

@@ -100,6 +100,9 @@ struct qp_handle {
     double* Dw = nullptr;                        // D plus the weak rows' diagonal
     double *lr_part = nullptr, *lr_v = nullptr;  // low-rank term: U^T p partials and w .* U^T p
     int *rflag = nullptr, *rpos = nullptr, *ridx = nullptr, *kdev = nullptr;
+    int* sext = nullptr;        // per strong row: range in A (k_strong_rows)
+    double* ssq = nullptr;      // per strong row: sqrt(Sigma)
+    int srows = 0;              // rows of that table (covers every step-1 grid)
     size_t part_len = 0;
     double* log = nullptr;
     IpmScal* isc = nullptr;
@@ -386,6 +389,8 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
                        (const int*)h->Ac, (const double*)h->Av, D, sigA, m, h->rflag, stop);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, h->stream, (const int*)h->rflag, m, h->rpos, h->ridx,
                        h->kdev, stop);
+    hipLaunchKernelGGL(k_strong_rows, dim3((h->srows + 255) / 256), dim3(256), 0, h->stream, (const int*)h->Ap,
+                       (const int*)h->ridx, sigA, (const int*)h->kdev, h->srows, h->sext, h->ssq, stop);
     hipLaunchKernelGGL(k_fold_weak, dim3((n + 15) / 16), dim3(256), 0, h->stream, (const int*)h->Atp,
                        (const int*)h->Atc, (const double*)h->Atv, sigA, (const int*)h->rpos, D, n, h->Dw, stop);
     HIPCHK(hipGetLastError());
@@ -426,10 +431,10 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
 // Step 1 of the constraint-block preconditioner on the strong rows of A; the
 // grid covers the largest dense block (all m rows strong), kernels read the
 // current k.
-PrecRows prec_rows_args(qp_handle* h, const double* sigA) {
+PrecRows prec_rows_args(qp_handle* h) {
     PrecRows pa{};
-    pa.Ap = h->Ap; pa.Ac = h->Ac; pa.Av = h->Av; pa.sigA = sigA;
-    pa.idx = h->ridx; pa.kdev = h->kdev; pa.m = h->m;
+    pa.Ac = h->Ac; pa.Av = h->Av; pa.ext = h->sext; pa.sq = h->ssq;
+    pa.kdev = h->kdev; pa.m = h->m;
     pa.w = h->wpre; pa.vm = h->vpre;
     return pa;
 }
@@ -445,8 +450,8 @@ int prec_rows_blocks(const qp_handle* h) {
 int apply_precond_23(qp_handle* h, const double* D, const double* sigA, const double* q) {
     const int m = h->m;
     hipLaunchKernelGGL(k_prec_symv, dim3((m + 3) / 4), dim3(kBlock), 0, h->stream, (const double*)h->Sinv,
-                       (const double*)h->wpre, sigA, (const int*)h->ridx, (const int*)h->kdev, h->vpre,
-                       (const Flags*)h->fl);
+                       (const double*)h->wpre, (const double*)h->ssq, (const int*)h->ridx, (const int*)h->kdev,
+                       h->vpre, (const Flags*)h->fl);
     const int G = 16;
     const int grid = grid_rows_capped(h->n, G);
     hipLaunchKernelGGL(k_prec_at<G>, dim3(grid), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
@@ -459,7 +464,7 @@ int apply_precond_23(qp_handle* h, const double* D, const double* sigA, const do
 // z = P^{-1} r at the start of a solve, given y = r ./ D in z.
 int apply_precond(qp_handle* h, const double* D, const double* sigA) {
     hipLaunchKernelGGL(k_prec_a, dim3(prec_rows_blocks(h)), dim3(kBlock), 0, h->stream,
-                       prec_rows_args(h, sigA), (const double*)h->pz, (const Flags*)h->fl);
+                       prec_rows_args(h), (const double*)h->pz, (const Flags*)h->fl);
     return apply_precond_23(h, D, sigA, nullptr);
 }
 
@@ -566,7 +571,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     pa.part_pq = h->part; pa.part_rz = h->part_rz; pa.part_rr = h->part_rr;
     pa.woodbury = wb; pa.sc = h->psc; pa.fl = h->fl;
     if (wb) {
-        pa.pa = prec_rows_args(h, sigA);
+        pa.pa = prec_rows_args(h);
         pa.nbA = prec_rows_blocks(h);
     }
 
@@ -1001,6 +1006,9 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
                 h->ridx = h->dalloc<int>(m);
                 h->kdev = h->dalloc<int>(1);
                 HIPCHK(hipMemsetAsync(h->kdev, 0, sizeof(int), h->stream));
+                h->srows = 4 * prec_rows_blocks(h);
+                h->sext = h->dalloc<int>(2 * size_t(h->srows));
+                h->ssq = h->dalloc<double>(h->srows);
             }
         }
         h->log = h->dalloc<double>(4 * size_t(h->set.max_ipm_iter + 1));

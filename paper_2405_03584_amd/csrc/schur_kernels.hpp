@@ -76,6 +76,29 @@ __global__ __launch_bounds__(1024) void k_compact(const int* flag, int m, int* p
     if (threadIdx.x == 0) *k_out = base;
 }
 
+// Per strong row r, what the per-iteration kernels read in one load: the
+// range of row idx[r] in A (ext[2r], ext[2r+1]) and sqrt(Sigma) of it (sq[r]);
+// rows r in [k, rows) get an empty range and 0.
+__global__ __launch_bounds__(256) void k_strong_rows(const int* Ap, const int* idx, const double* sigA,
+                                                     const int* kdev, int rows, int* ext, double* sq,
+                                                     const int* stop) {
+    if (stop && *stop) return;
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= rows) return;
+    const int k = *kdev;
+    int e0 = 0, e1 = 0;
+    double q = 0.0;
+    if (r < k) {
+        const int i = idx[r];
+        e0 = Ap[i];
+        e1 = Ap[i + 1];
+        q = sqrt(sigA[i]);
+    }
+    ext[2 * r] = e0;
+    ext[2 * r + 1] = e1;
+    sq[r] = q;
+}
+
 // Dw_j = dh_j + sum over weak rows i of Sigma_i A_ij^2 (rows of A^T, G = 16).
 __global__ __launch_bounds__(256) void k_fold_weak(const int* Atp, const int* Atc, const double* Atv,
                                                    const double* sigA, const int* pos, const double* dh,
