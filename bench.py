@@ -247,6 +247,9 @@ def main():
                          "products only (for counter runs); copy: a plain device copy of the "
                          "J value+index bytes (counter calibration)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
+                    help="1: PCG iterations replayed as captured HIP graphs (the production setting); "
+                         "0: direct launches (for kernel-trace and counter runs)")
     ap.add_argument("--workload", default="config2", choices=["config2", "config5", "batch"],
                     help="config2: banded-dose QP n=20,000 (default, the benchmark line); config5: "
                          "n=60,000, BF16-valued J with 200M nnz and a rank-20 term; batch: the 64 "
@@ -279,7 +282,7 @@ def main():
     # the timed solves use the production settings (captured PCG graphs, no
     # per-kernel events); one extra solve on a second handle with timing = 1
     # gives the SpMV kernel durations for the roofline
-    settings = qpgpu.qp_default_settings(precision=args.precision, log_level=args.log)
+    settings = qpgpu.qp_default_settings(precision=args.precision, log_level=args.log, graphs=args.graphs)
     t0 = time.perf_counter()
     h = qpgpu.qp_create_from_problem(prob, settings=settings)
     t_create = time.perf_counter() - t0

@@ -310,8 +310,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalars(const double* part_rz, i
                                                         int n_rr, int mode, double rel_tol, double tol,
                                                         int max_iter, PcgScal* sc, Flags* fl, AzArgs az) {
     __shared__ double sh[kBlock / 64];
-    if (mode ? ipm_finished(fl) : pcg_stopped(fl)) return;
     if (blockIdx.x > 0) {
+        // A z needs no block barrier: each wavefront reads the flags with one
+        // uniform load beside its first index load (block 0 may set a flag
+        // meanwhile; either reading leaves a valid state, since later kernels
+        // test the flags themselves)
+        if (mode ? fl->ipm_done : pcg_stopped_raw(fl)) return;
         const int row = (int(blockIdx.x) - 1) * (kBlock / 64) + (threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
         if (row >= az.m) return;
@@ -320,6 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalars(const double* part_rz, i
         if (lane == 0) az.az[row] = s;
         return;
     }
+    if (mode ? ipm_finished(fl) : pcg_stopped(fl)) return;
     const double rz = reduce_partials_sum(part_rz, n_rz, 1, sh);
     const double rr = reduce_partials_sum(part_rr, n_rr, 1, sh);
     if (threadIdx.x != 0) return;

@@ -403,10 +403,15 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
     h->Tcur = h->ldcur / TS;
     if (k == 0) return false;
     const int ld = h->ldcur, T = h->Tcur;
-    hipLaunchKernelGGL(k_schur_form, dim3(ld), dim3(64), size_t(ld) * sizeof(double), h->stream,
-                       (const int*)h->Ap, (const int*)h->Ac, (const double*)h->Av, (const int*)h->Atp,
-                       (const int*)h->Atc, (const double*)h->Atv, (const double*)h->Dw, sigA,
-                       (const int*)h->rpos, (const int*)h->ridx, k, ld, h->Sm, stop);
+    {   // wavefronts per row: as many as fit their LDS row copies in 64 KiB, at most 4
+        const size_t row_bytes = size_t(ld) * sizeof(double);
+        const int nw = row_bytes * 4 <= 64 * 1024 ? 4 : row_bytes * 2 <= 64 * 1024 ? 2 : 1;
+        auto kern = nw == 4 ? k_schur_form<4> : nw == 2 ? k_schur_form<2> : k_schur_form<1>;
+        hipLaunchKernelGGL(kern, dim3(ld), dim3(64 * nw), row_bytes * nw, h->stream, (const int*)h->Ap,
+                           (const int*)h->Ac, (const double*)h->Av, (const int*)h->Atp, (const int*)h->Atc,
+                           (const double*)h->Atv, (const double*)h->Dw, sigA, (const int*)h->rpos,
+                           (const int*)h->ridx, k, ld, h->Sm, stop);
+    }
     HIPCHK(hipGetLastError());
     // sweep: S alternates between Sm and Sm2; P between the two halves of Pbuf
     double* Sb[2] = {h->Sm, h->Sm2};

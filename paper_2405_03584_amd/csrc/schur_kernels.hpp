@@ -120,30 +120,35 @@ __global__ __launch_bounds__(256) void k_fold_weak(const int* Atp, const int* At
 }
 
 // S = I + Sigma^{1/2} A_s D^{-1} A_s^T Sigma^{1/2} over the k strong rows: one
-// wavefront per strong row r (row i = idx[r] of A), the row accumulated in
-// LDS.  For each nonzero A_ij of row i (in column order), the strong entries
-// of column j of A (row j of the stored A^T) are added with weight A_ij/D_j;
-// within one column all row indices differ, so no two lanes touch the same
-// LDS word in a step, and steps of one wavefront execute in order.
-__global__ __launch_bounds__(64) void k_schur_form(const int* __restrict__ Ap, const int* __restrict__ Ac,
-                                                  const double* __restrict__ Av, const int* __restrict__ Atp,
-                                                  const int* __restrict__ Atc, const double* __restrict__ Atv,
-                                                  const double* __restrict__ D, const double* __restrict__ sigA,
-                                                  const int* __restrict__ pos, const int* __restrict__ idx, int k,
-                                                  int ld, double* __restrict__ S, const int* stop) {
-    extern __shared__ double acc[];
+// workgroup of NW wavefronts per strong row r (row i = idx[r] of A), the
+// wavefronts taking contiguous parts of the row's nonzeros, each with its own
+// copy of the output row in LDS.  For each nonzero A_ij (in column order), the
+// strong entries of column j of A (row j of the stored A^T) are added with
+// weight A_ij/D_j; within one column all row indices differ, so no two lanes
+// touch the same LDS word in a step, and steps of one wavefront execute in
+// order.  The NW copies are summed in a fixed order at the end.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_schur_form(const int* __restrict__ Ap, const int* __restrict__ Ac,
+                                                       const double* __restrict__ Av, const int* __restrict__ Atp,
+                                                       const int* __restrict__ Atc, const double* __restrict__ Atv,
+                                                       const double* __restrict__ D, const double* __restrict__ sigA,
+                                                       const int* __restrict__ pos, const int* __restrict__ idx,
+                                                       int k, int ld, double* __restrict__ S, const int* stop) {
+    extern __shared__ double acc_all[];
     if (stop && *stop) return;
     const int r = blockIdx.x;
-    const int lane = threadIdx.x;
-    for (int c = lane; c < ld; c += 64) acc[c] = 0.0;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double* acc = acc_all + size_t(w) * ld;
+    for (int c = threadIdx.x; c < NW * ld; c += NW * 64) acc_all[c] = 0.0;
     __syncthreads();
     if (r < k) {
         const int i = idx[r];
-        const int e0 = Ap[i], e1 = Ap[i + 1];
+        const int a0 = Ap[i], len = Ap[i + 1] - a0;
+        const int per = (len + NW - 1) / NW;
+        const int e0 = a0 + min(len, w * per), e1 = a0 + min(len, (w + 1) * per);
         // Batches of 8 nonzeros: every load of a batch (column ids, weights,
         // the first 64 entries of each column and their strong-row ranks) is
-        // issued before the adds, which then run in the original order, so
-        // the sums are those of the one-at-a-time loop.
+        // issued before the adds, which then run in the original order.
         constexpr int B = 8;
         for (int e = e0; e < e1; e += B) {
             int jv[B], f0[B], f1[B], q[B];
@@ -176,8 +181,11 @@ __global__ __launch_bounds__(64) void k_schur_form(const int* __restrict__ Ap, c
     }
     __syncthreads();
     const double si = (r < k) ? sqrt(sigA[idx[r]]) : 0.0;
-    for (int c = lane; c < ld; c += 64) {
-        double v = (r < k && c < k) ? si * sqrt(sigA[idx[c]]) * acc[c] : 0.0;
+    for (int c = threadIdx.x; c < ld; c += NW * 64) {
+        double t = acc_all[c];
+#pragma unroll
+        for (int w2 = 1; w2 < NW; ++w2) t += acc_all[size_t(w2) * ld + c];
+        double v = (r < k && c < k) ? si * sqrt(sigA[idx[c]]) * t : 0.0;
         if (c == r) v += 1.0;
         S[size_t(r) * ld + c] = v;
     }
