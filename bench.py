@@ -325,7 +325,7 @@ def main():
     gbs_f = bf / (fwd_us * 1e-6) / 1e9
     gbs_b = bb / (bwd_us * 1e-6) / 1e9
     if fmt == 1:
-        names = ("k_line_pass (J p, W scaling and per-slot J^T contributions from one read of J; A p)",
+        names = ("k_line_pass (J p, W scaling and per-slot J^T contributions from one read of J; u from A z and A p)",
                  "k_spot_pass (per-spot J^T sums, A^T u, epilogue and p.q partials)")
     else:
         names = ("k_op_fwd (J + A SpMV, fused W / Sigma_A scaling)",
