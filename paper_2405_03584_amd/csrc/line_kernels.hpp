@@ -33,6 +33,23 @@ namespace qpg {
 // 4*kLineHeld slots streams the rest from memory in both passes.
 constexpr int kLineHeld = 32;
 
+// Value loads of the line pass.  Every value is read once per product; when
+// the value array is larger than the last-level cache (MI355X: 256 MB
+// Infinity Cache), cycling it through the caches only evicts what is reused
+// (the gathered vectors, W, the per-slot sums), so such arrays are read with
+// non-temporal loads (NT = true); smaller arrays stay cacheable, and then
+// stay resident between products.
+template <bool NT, typename T>
+__device__ __forceinline__ T load_val(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ bf16_t load_val(const bf16_t* p) {
+    if constexpr (NT) return bf16_t{__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p))};
+    else return *p;
+}
+
 template <typename VT>
 struct LineArgs {
     const int* lptr; const int* lcol; const VT* lval; int L; const double* W;
@@ -49,7 +66,7 @@ struct LineArgs {
     const Flags* fl_ipm;   // residual pass: skipped once the IPM has finished
 };
 
-template <typename VT, typename AT>
+template <typename VT, typename AT, bool NT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_line_pass(LineArgs<VT> a) {
     constexpr int NW = kBlock / 64;
     constexpr int RH = kLineHeld;
@@ -104,7 +121,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int kk = min(k + i, kh - 1);
-                const AT prod = cvt<AT>(v[size_t(kk) * 64]) * AT(g(col[kk]));
+                const AT prod = cvt<AT>(load_val<NT>(&v[size_t(kk) * 64])) * AT(g(col[kk]));
                 s4 += (k + i < kh) ? prod : AT(0);
             }
             acc += s4;
@@ -121,7 +138,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
             const int plo = __double2loint(pl), phi = __double2hiint(pl);
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
-                const AT val = cvt<AT>(v[size_t(min(kh + i, k1 - 1)) * 64]);
+                const AT val = cvt<AT>(load_val<NT>(&v[size_t(min(kh + i, k1 - 1)) * 64]));
                 hv[i] = (kh + i < k1) ? val : AT(0);
             }
             AT a2[2] = {AT(0), AT(0)};   // two chains, no product array
@@ -154,7 +171,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
             AT pv[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const AT val = cvt<AT>(v[size_t(min(kg + i, kh - 1)) * 64]);
+                const AT val = cvt<AT>(load_val<NT>(&v[size_t(min(kg + i, kh - 1)) * 64]));
                 pv[i] = (kg + i < kh) ? val * t : AT(0);
             }
             const AT cs = wave_reduce_scatter<8>(pv, lane);

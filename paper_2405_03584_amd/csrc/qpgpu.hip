@@ -231,6 +231,14 @@ const float* line_vals<float>(qp_handle* h) { return h->lval32; }
 template <>
 const bf16_t* line_vals<bf16_t>(qp_handle* h) { return h->lval16; }
 
+// Value arrays above this size are read with non-temporal loads
+// (line_kernels.hpp: load_val): three quarters of the 256 MB last-level cache.
+constexpr size_t kStreamedValueBytes = size_t(192) << 20;
+template <typename VT>
+bool line_vals_streamed(const qp_handle* h) {
+    return size_t(h->nnzJ) * sizeof(VT) > kStreamedValueBytes;
+}
+
 // PCG link of a product: in a PCG product (pcg = true) the gathered vector is
 // z + beta*p and p is written back.
 PcgLink pcg_link(qp_handle* h, bool pcg) {
@@ -265,8 +273,11 @@ int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, 
         f.nbA = f.m;
     }
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
-    hipLaunchKernelGGL((k_line_pass<VT, AT>), dim3(std::max(1, f.nbL + f.nbA + f.nbU)), dim3(kBlock), 0,
-                       h->stream, f);
+    const dim3 lgrid(std::max(1, f.nbL + f.nbA + f.nbU));
+    if (line_vals_streamed<VT>(h))
+        hipLaunchKernelGGL((k_line_pass<VT, AT, true>), lgrid, dim3(kBlock), 0, h->stream, f);
+    else
+        hipLaunchKernelGGL((k_line_pass<VT, AT, false>), lgrid, dim3(kBlock), 0, h->stream, f);
     HIPCHK(hipGetLastError());
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
     lowrank_prepare(h, x, pl.p2, fl);
@@ -1218,8 +1229,12 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
                 LineArgs<double> la{};
                 la.lptr = h->lptr; la.lcol = h->lcol; la.lval = h->lval; la.L = h->L; la.W = h->W;
                 la.x = v.x; la.c = h->lc; la.u = h->u; la.nbL = h->L; la.nbA = 0; la.fl_ipm = h->fl;
-                hipLaunchKernelGGL((k_line_pass<double, double>), dim3(std::max(1, h->L)), dim3(kBlock), 0,
-                                   h->stream, la);
+                if (line_vals_streamed<double>(h))
+                    hipLaunchKernelGGL((k_line_pass<double, double, true>), dim3(std::max(1, h->L)), dim3(kBlock),
+                                       0, h->stream, la);
+                else
+                    hipLaunchKernelGGL((k_line_pass<double, double, false>), dim3(std::max(1, h->L)),
+                                       dim3(kBlock), 0, h->stream, la);
                 HIPCHK(hipGetLastError());
             }
             const int grid = std::max(1, f.nbJ + nbA);
