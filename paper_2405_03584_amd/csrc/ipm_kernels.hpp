@@ -254,9 +254,56 @@ struct ScaledResidual {
 // Jacobi: r -= alpha q and z = r ./ d stored, with partials of r^T z.
 // Constraint block: the first nbA blocks run step 1 of the preconditioner on
 // y = (r - alpha q) ./ D, so r is left for k_prec_at to update.
+// What does not depend on alpha is loaded before the p^T q reduction, so the
+// two overlap: a strong row's range, scale and first pass of entries (column
+// ids, values and the gathered r, q and D), an element block's first entries.
 __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
+    constexpr int U = 8;
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped(a.fl)) return;
+    const int lane = threadIdx.x & 63;
+    const bool arow = int(blockIdx.x) < a.nbA;
+    // strong-row blocks: a wavefront per row
+    const int row = int(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    int e0 = 0, e1 = 0, ld = 0;
+    double sqr = 0.0;
+    double av[U], rv[U], qv[U], dv[U];
+    // element blocks: the first entry of the grid-stride loop
+    const int eb = int(blockIdx.x) - a.nbA;
+    const int ne = int(gridDim.x) - a.nbA;
+    const int j0 = eb * kBlock + threadIdx.x;
+    double x0 = 0.0, p0 = 0.0, q0 = 0.0, r0 = 0.0, d0 = 1.0;
+    if (arow) {
+        const int k = *a.pa.kdev;
+        ld = ((k + TS_PREC - 1) / TS_PREC) * TS_PREC;
+        for (int t = row * 64 + lane; t < a.pa.m && t < (row + 1) * 64; t += 64) a.pa.vm[t] = 0.0;
+        if (row < ld) {
+            e0 = a.pa.ext[2 * row];
+            e1 = a.pa.ext[2 * row + 1];
+            sqr = a.pa.sq[row];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            av[u] = 0.0; rv[u] = 0.0; qv[u] = 0.0; dv[u] = 1.0;
+        }
+        if (e1 > e0) {   // wavefront-uniform; indices past the row end clamped, zeroed below
+            int c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int kk = min(e0 + lane + 64 * u, e1 - 1);
+                c[u] = a.pa.Ac[kk];
+                av[u] = (e0 + lane + 64 * u < e1) ? a.pa.Av[kk] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                rv[u] = a.r[c[u]];
+                qv[u] = a.q[c[u]];
+                dv[u] = a.d[c[u]];
+            }
+        }
+    } else if (j0 < a.n) {
+        x0 = a.x[j0]; p0 = a.p[j0]; q0 = a.q[j0]; r0 = a.r[j0]; d0 = a.d[j0];
+    }
     const double pq = reduce_partials_sum(a.part_pq, a.n_pq, 1, sh);
     const double alpha = a.sc->rho / pq;
     const bool bad = !(pq > 0.0) || !finite_d(alpha);
@@ -266,18 +313,29 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
         if (bad) a.fl->pcg_breakdown = 1;
     }
     if (bad) return;
-    if (int(blockIdx.x) < a.nbA) {
-        prec_rows(a.pa, ScaledResidual{a.r, a.q, a.d, alpha}, blockIdx.x);
+    if (arow) {
+        if (row >= ld) return;
+        double acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = av[u] * (fma(-alpha, qv[u], rv[u]) / dv[u]);
+        double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        // rows longer than U*64 entries: the rest, one gather round per pass
+        const ScaledResidual y{a.r, a.q, a.d, alpha};
+        for (int kk = e0 + U * 64 + lane; kk < e1; kk += 64) s += a.pa.Av[kk] * y(a.pa.Ac[kk]);
+        s = group_sum<double, 64>(s);
+        if (lane == 0) a.pa.w[row] = sqr * s;
         return;
     }
-    const int eb = int(blockIdx.x) - a.nbA;
-    const int ne = int(gridDim.x) - a.nbA;
     double rz = 0.0, rr = 0.0;
-    for (int j = eb * kBlock + threadIdx.x; j < a.n; j += ne * kBlock) {
-        a.x[j] += alpha * a.p[j];
-        const double rj = fma(-alpha, a.q[j], a.r[j]);
+    for (int j = j0; j < a.n; j += ne * kBlock) {
+        double xj = x0, pj = p0, qj = q0, rj0 = r0, dj = d0;
+        if (j != j0) {
+            xj = a.x[j]; pj = a.p[j]; qj = a.q[j]; rj0 = a.r[j]; dj = a.d[j];
+        }
+        a.x[j] = xj + alpha * pj;
+        const double rj = fma(-alpha, qj, rj0);
         if (!a.woodbury) {
-            const double zj = rj / a.d[j];
+            const double zj = rj / dj;
             a.r[j] = rj;
             a.z[j] = zj;
             rz += rj * zj;
