@@ -414,10 +414,16 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
     h->Tcur = h->ldcur / TS;
     if (k == 0) return false;
     const int ld = h->ldcur, T = h->Tcur;
-    {   // wavefronts per row: as many as fit their LDS row copies in 64 KiB, at most 4
+    {   // wavefronts per row: as many as fit their LDS row copies in 64 KiB, at most 8
         const size_t row_bytes = size_t(ld) * sizeof(double);
-        const int nw = row_bytes * 4 <= 64 * 1024 ? 4 : row_bytes * 2 <= 64 * 1024 ? 2 : 1;
-        auto kern = nw == 4 ? k_schur_form<4> : nw == 2 ? k_schur_form<2> : k_schur_form<1>;
+        const int nw = row_bytes * 8 <= 64 * 1024   ? 8
+                       : row_bytes * 4 <= 64 * 1024 ? 4
+                       : row_bytes * 2 <= 64 * 1024 ? 2
+                                                    : 1;
+        auto kern = nw == 8   ? k_schur_form<8>
+                    : nw == 4 ? k_schur_form<4>
+                    : nw == 2 ? k_schur_form<2>
+                              : k_schur_form<1>;
         hipLaunchKernelGGL(kern, dim3(ld), dim3(64 * nw), row_bytes * nw, h->stream, (const int*)h->Ap,
                            (const int*)h->Ac, (const double*)h->Av, (const int*)h->Atp, (const int*)h->Atc,
                            (const double*)h->Atv, (const double*)h->Dw, sigA, (const int*)h->rpos,
@@ -1253,8 +1259,11 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             ba.t = h->t; ba.gamma = h->gamma;
             ba.U = h->U; ba.lr_v = h->lr_v; ba.lr_k = h->k;
             lowrank_prepare(h, v.x, nullptr, nullptr);
-            const int gb = grid_rows_capped(n, Gt);
-            switch (Gt) {
+            // lanes per variable: with the line format a variable sums one
+            // double per slot of its spot, not one term per nonzero of J
+            const int Gb = h->line ? pick_lanes(h->nnzJ / 64 + h->nnzA, n) : Gt;
+            const int gb = grid_rows_capped(n, Gb);
+            switch (Gb) {
                 case 4: hipLaunchKernelGGL(k_ipm_bwd<4>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
                 case 8: hipLaunchKernelGGL(k_ipm_bwd<8>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
                 case 16: hipLaunchKernelGGL(k_ipm_bwd<16>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
