@@ -61,7 +61,11 @@ typedef enum {
  * direction is refined against the FP64 operator: each low-precision PCG
  * solve stops at refine_tol times its own right-hand side, and refinement
  * passes (at most refine_steps) go on until the FP64 residual is below
- * pcg_tol times the original right-hand side. */
+ * pcg_tol times the original right-hand side.  When it is still above after
+ * refine_steps passes (the rounded operator too far from K for refinement to
+ * converge, e.g. J without full column rank and a small gamma), the direction
+ * is solved again by FP64 PCG.  refine_steps = 0: the low-precision solve to
+ * pcg_tol is the direction, unrefined. */
 typedef enum { QP_FP64 = 0, QP_FP32 = 1, QP_BF16 = 2 } qp_precision;
 
 typedef struct {

@@ -553,7 +553,7 @@ void autotune_schedule(qp_handle* h) {
 // Returns the flags after the solve.
 Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, const double* sigx,
               const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode, TimingAcc* tacc,
-              double rel_tol, bool refine) {
+              double rel_tol, bool refine, bool check_only = false) {
     const int n = h->n;
     const int ge = grid_elems(n);
     // dh != null selects the constraint-block preconditioner (built for this Sigma)
@@ -585,7 +585,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         HIPCHK(hipMemcpyAsync(&h->fl_host[0], h->fl, sizeof(Flags), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         const Flags f0 = h->fl_host[0];
-        if (f0.pcg_converged || f0.pcg_breakdown || f0.pcg_capped || f0.ipm_done) return f0;
+        if (f0.pcg_converged || f0.pcg_breakdown || f0.pcg_capped || f0.ipm_done || check_only) return f0;
     }
 
     PcgArgs pa{};
@@ -742,14 +742,21 @@ Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double
     Flags f = run_pcg(h, prec, nullptr, rhs, sigx, sigA, d, dh, hs, false, tacc, inner, false);
     *solves = 1;
     int total = f.pcg_iters;
-    if (f.ipm_done || f.pcg_breakdown) return f;
+    if (f.ipm_done || f.pcg_breakdown || h->set.refine_steps == 0) return f;   // 0: no refinement
     hipLaunchKernelGGL(k_acc, dim3(ge), dim3(kBlock), 0, h->stream, n, h->dxacc, (const double*)h->px, 1,
                        (const Flags*)h->fl);
-    for (int k = 0; k < h->set.refine_steps; ++k) {
+    // Passes k < refine_steps correct dx; the pass after the last correction
+    // only checks its FP64 residual.
+    bool met = false;
+    for (int k = 0; k <= h->set.refine_steps; ++k) {
         apply_op_prec(h, QP_FP64, h->dxacc, h->pq, sigx, sigA, hs, false, false, 0);
         hipLaunchKernelGGL(k_sub, dim3(ge), dim3(kBlock), 0, h->stream, n, rhs, (const double*)h->pq, h->rho,
                            (const Flags*)h->fl);
-        Flags f2 = run_pcg(h, prec, nullptr, h->rho, sigx, sigA, d, dh, hs, false, tacc, inner, true);
+        const bool check = k == h->set.refine_steps;
+        Flags f2 = run_pcg(h, prec, nullptr, h->rho, sigx, sigA, d, dh, hs, false, tacc, inner, true, check);
+        if (f2.ipm_done) return f2;
+        met = f2.pcg_iters == 0 && f2.pcg_converged;   // the FP64 residual already meets pcg_tol
+        if (check) break;
         *solves += 1;
         total += f2.pcg_iters;
         f.pcg_capped |= f2.pcg_capped;
@@ -759,9 +766,21 @@ Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double
             f.pcg_breakdown = 1;
             break;
         }
-        if (f2.pcg_iters == 0) break;   // the FP64 residual already meets pcg_tol
+        if (met) break;
         hipLaunchKernelGGL(k_acc, dim3(ge), dim3(kBlock), 0, h->stream, n, h->dxacc, (const double*)h->px, 0,
                            (const Flags*)h->fl);
+    }
+    if (!met && !f.pcg_breakdown) {
+        // Refinement converges only while the low-precision operator is close
+        // enough to K (spectral radius of I - K_lo^-1 K below 1).  Where it is
+        // not -- e.g. J without full column rank and a small gamma, where
+        // rounding J moves the eigenvalues near gamma by far more than
+        // gamma -- the direction is solved in FP64 instead.
+        Flags f3 = run_pcg(h, QP_FP64, nullptr, rhs, sigx, sigA, d, dh, hs, false, tacc, tol, false);
+        *solves += 1;
+        f3.pcg_iters += total;
+        f3.pcg_capped |= f.pcg_capped;
+        return f3;
     }
     HIPCHK(hipMemcpyAsync(h->px, h->dxacc, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipGetLastError());

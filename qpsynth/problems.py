@@ -405,6 +405,40 @@ def tiny(instance: int) -> QPProblem:
                      name=f"tiny[{instance}]", meta={"seed": seed})
 
 
+def ragged_lines(seed: int = 95000) -> QPProblem:
+    """Line-format edge cases: n = 400 spots, eight 64-row lines with 0, 1, 5,
+    130, 300, 64, 3 and 0 slots (empty lines, the first and the last included;
+    lines longer than four wavefronts of 32 held slots, with remainders); W
+    uniform [0.5, 2]; A 20 x 400 with 40 normal entries per row, b feasible at
+    x0; bounds [0, 50].
+
+    Draw order: per line, its spots (without replacement, sorted); J values;
+    W; A; x0; slacks; x_t.
+    """
+    rng = np.random.default_rng(seed)
+    n, X = 400, 64
+    lens = [0, 1, 5, 130, 300, 64, 3, 0]
+    cols = [np.sort(rng.choice(n, size=L, replace=False)) for L in lens]
+    rows = X * len(lens)
+    indptr = np.zeros(rows + 1, dtype=np.int64)
+    for ell, L in enumerate(lens):
+        for r in range(X):
+            indptr[ell * X + r + 1] = indptr[ell * X + r] + L
+    indices = np.concatenate([np.tile(c, X) for c in cols]).astype(np.int32)
+    data = rng.lognormal(0.0, 1.0, size=int(indptr[-1]))
+    J = _csr(indptr, indices, data, (rows, n))
+    W = rng.uniform(0.5, 2.0, size=rows)
+    m = 20
+    A = random_sparse(rng, m, n, 40)
+    x0 = rng.uniform(0.0, 1.0, size=n)
+    s0 = rng.uniform(0.1, 1.0, size=m)
+    x_t = rng.uniform(-10.0, 60.0, size=n)
+    return QPProblem(gamma=GAMMA, p=_linear_term(J, W, x_t), J=J, W=W,
+                     x_lo=np.zeros(n), x_hi=np.full(n, 50.0),
+                     A=A, A_lo=np.full(m, -np.inf), A_hi=_feasible_rhs(A, x0, s0),
+                     name="ragged_lines", meta={"seed": seed})
+
+
 def random_iterate(prob: QPProblem, seed: int):
     """Random positive slacks/multipliers and a random x, mu for operator and
     Newton-system checks.  Returns dict with x, mu and per-row sigma values."""

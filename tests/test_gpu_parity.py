@@ -414,6 +414,71 @@ def test_line_format_operator_matches_csr(prec, scale):
     assert np.all(np.abs(yc - ref) <= c * bound)
 
 
+# Line-format edge cases: empty lines (first and last), one-slot lines, lines
+# longer than the 4 x 32 held slots with remainders in both streamed loops.
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_ragged_lines_operator(prec):
+    prob = qpsynth.ragged_lines()
+    it = qpsynth.random_iterate(prob, 43)
+    print(f"ragged lines operator {prec}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob)
+    y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
+    assert info["spmv_format"] == 1
+    ref = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"]) @ it["v"]
+    bound = _abs_op(prob, it["sigma_x"], it["sigma_A"]) @ np.abs(it["v"])
+    unit = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16": 2.0 ** -8}[prec]
+    Lj = np.diff(prob.J.indptr).max()
+    Lt = np.diff(prob.J.tocsc().indptr).max()
+    acc = 2.0 ** -53 if prec == "fp64" else 2.0 ** -24
+    c = 2 * unit + (Lj + Lt + 2) * acc + 1e-13
+    assert np.all(np.abs(y - ref) <= c * bound)
+
+
+def test_ragged_lines_newton_step():
+    prob = qpsynth.ragged_lines()
+    it = qpsynth.random_iterate(prob, 44)
+    print("ragged lines newton step", flush=True)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(pcg_tol=1e-10,
+                                                                            pcg_max_iter=50000))
+    st, dx, info = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], it["rhs"])
+    assert st == qpgpu.QP_OK, info
+    K = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"])
+    ref = oracle.newton_solve_dense(K, it["rhs"])
+    assert np.linalg.norm(K @ dx - it["rhs"]) <= 1e-9 * np.linalg.norm(it["rhs"])
+    assert np.abs(dx - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_ragged_lines_newton_step_low_precision(prec):
+    """J here has rank below n and gamma is small, so rounding J moves the
+    operator's eigenvalues near gamma by far more than gamma and refinement
+    alone cannot reach pcg_tol; the direction must still meet it (by FP64
+    PCG once refinement stops short)."""
+    prob = qpsynth.ragged_lines()
+    it = qpsynth.random_iterate(prob, 44)
+    print(f"ragged lines newton step {prec}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec, pcg_tol=1e-10,
+                                                                            pcg_max_iter=50000))
+    st, dx, info = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], it["rhs"])
+    assert st == qpgpu.QP_OK, info
+    K = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"])
+    assert np.linalg.norm(K @ dx - it["rhs"]) <= 1e-9 * np.linalg.norm(it["rhs"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_ragged_lines_solve(prec):
+    prob = qpsynth.ragged_lines()
+    print(f"ragged lines solve {prec}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    assert res.status == qpgpu.QP_OK, res.info
+    tol = 1e-6 * (1 + np.abs(ref.x).max()) if prec == "fp64" else 1e-5
+    assert np.abs(res.x - ref.x).max() <= tol
+    cert = oracle.kkt_certificate(prob, res.x, res.lam_x, res.lam_A)
+    assert cert.worst() <= 1e-9, cert
+
+
 def test_config1_uses_csr():
     prob = qpsynth.config1(0)
     it = qpsynth.random_iterate(prob, 2)
