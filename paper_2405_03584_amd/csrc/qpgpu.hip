@@ -72,7 +72,9 @@ struct qp_handle {
     double* W = nullptr;
     int *Ap = nullptr, *Ac = nullptr, *Atp = nullptr, *Atc = nullptr;
     double *Av = nullptr, *Atv = nullptr;
-    int last_pcg_iters = 0, last_pcg_iters2 = 0;   // iterations of the two previous PCG solves (chunk sizes)
+    // iterations of the two previous PCG solves of each kind (first solve of
+    // a direction, refinement solve), for the chunk sizes
+    int last_pcg_iters[2][2] = {{0, 0}, {0, 0}};
     // line format of J (64-row lines sharing a column list), used by the PCG operator
     bool line = false;
     int L = 0;
@@ -614,7 +616,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
                            (const double*)h->part_rr, ge, 0, 0.0, 0.0, 0, h->psc, h->fl, az);
     };
     // Graph mode: the iterations of this operator are captured once as a graph
-    // of kGraphIters iterations and replayed (one launch call per four
+    // of kGraphIters iterations and replayed (one launch call per kGraphIters
     // iterations instead of one per kernel).  Every dynamic quantity of an
     // iteration lives in device memory, so replays are exact repeats of the
     // direct launches.
@@ -673,10 +675,12 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     // Chunks of iterations are queued ahead of the host check: kernels of a
     // finished solve return at once, so the GPU never waits on the host.  The
     // first chunk covers most of the smaller of the two previous solves'
-    // iteration counts (consecutive IPM directions alternate between short and
-    // long solves); later chunks are four iterations, so few no-op launches
-    // trail the converged iteration.
-    const int pred = std::min(h->last_pcg_iters, h->last_pcg_iters2);
+    // iteration counts of the same kind (consecutive IPM directions alternate
+    // between short and long solves; refinement solves are shorter than
+    // first solves); later chunks are kGraphIters iterations, so few no-op
+    // launches trail the converged iteration.
+    int* hist = h->last_pcg_iters[refine ? 1 : 0];
+    const int pred = std::min(hist[0], hist[1]);
     int chunk = std::max(kGraphIters, std::min(512, (pred * 3) / 4));
     chunk = ((chunk + kGraphIters - 1) / kGraphIters) * kGraphIters;
     int64_t launched = 0;
@@ -701,8 +705,8 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         cur ^= 1;
     }
     if (!f.ipm_done) {
-        h->last_pcg_iters2 = h->last_pcg_iters;
-        h->last_pcg_iters = f.pcg_iters;
+        hist[1] = hist[0];
+        hist[0] = f.pcg_iters;
     }
     if (timing) {
         // launches past the last executed iteration returned at once: drop them
