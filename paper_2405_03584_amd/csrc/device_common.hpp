@@ -218,6 +218,70 @@ __device__ __forceinline__ AT row_dot_lane_g(const int* __restrict__ ptr, const 
     return s;
 }
 
+// Sum of term(e) over e in [a, b) by a group of G lanes (G divides 64) with
+// the same bits for every G: it is the sum 64 virtual lanes would form, where
+// virtual lane v adds the terms e = a + v, a + v + 64, ... in order and the 64
+// partial sums are combined by the butterfly with offsets 32, 16, ..., 1.
+// Lane p of the group keeps virtual lanes p + G*j (j < 64/G); butterfly
+// offsets >= G combine them inside the lane, smaller ones across lanes.  Each
+// pass issues about 8 term loads per lane before adding (indices past b
+// clamped to b-1 and not added).  Every lane of the group returns the sum.
+// Used where the lane count is a tunable schedule, so that the schedule
+// never changes results.
+template <int G, typename AT, typename Term>
+__device__ __forceinline__ AT canon_sum(int a, int b, int lane, const Term& term) {
+    static_assert(G >= 1 && G <= 64 && 64 % G == 0, "G must divide 64");
+    constexpr int NJ = 64 / G;
+    constexpr int UT = NJ >= 8 ? 1 : 8 / NJ;
+    AT vs[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) vs[j] = AT(0);
+    for (int base = a; base < b; base += 64 * UT) {
+        AT tv[UT][NJ];
+#pragma unroll
+        for (int u = 0; u < UT; ++u)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) tv[u][j] = term(min(base + 64 * u + lane + G * j, b - 1));
+#pragma unroll
+        for (int u = 0; u < UT; ++u)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) vs[j] = (base + 64 * u + lane + G * j < b) ? vs[j] + tv[u][j] : vs[j];
+    }
+#pragma unroll
+    for (int off = 32; off >= G; off >>= 1) {
+        AT nv[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) nv[j] = vs[j] + vs[j ^ (off / G)];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) vs[j] = nv[j];
+    }
+    AT s = vs[0];
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+    return s;
+}
+
+// Partials of per-row values over fixed chunks of kChunkRows consecutive rows
+// (chunk c = rows 4c..4c+3): the chunk structure follows the row numbers
+// only, not the rows per workgroup, so sums built from these partials do not
+// depend on the lane count per row.  vals[k * ld + r] holds value k of row
+// base + r of the pass (r < RPB, rows past n hold 0); values k < NV - 2 are
+// maxima (when NV > 1), the last two (or the only one) sums in row order.
+// One thread per chunk writes out[NV * chunk + k].
+constexpr int kChunkRows = 4;
+template <int RPB, int NV>
+__device__ __forceinline__ void chunk_partials(const double* vals, int ld, int base, int n, double* out) {
+    const int c = threadIdx.x;
+    if (c >= RPB / kChunkRows || base + kChunkRows * c >= n) return;
+    const size_t chunk = size_t(base / kChunkRows + c);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double* r = vals + size_t(k) * ld + kChunkRows * c;
+        const bool is_max = NV > 1 && k < NV - 2;
+        out[NV * chunk + k] = is_max ? fmax(fmax(r[0], r[1]), fmax(r[2], r[3])) : ((r[0] + r[1]) + r[2]) + r[3];
+    }
+}
+
 template <int G, typename VT, typename AT, int U = 4>
 __device__ __forceinline__ AT row_dot_lane(const int* __restrict__ ptr, const int* __restrict__ col,
                                            const VT* __restrict__ val, const double* __restrict__ x,

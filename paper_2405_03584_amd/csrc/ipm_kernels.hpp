@@ -82,8 +82,8 @@ __global__ __launch_bounds__(kBlock) void k_op_fwd(FwdArgs<VT> a) {
         const int row = b * RPB + threadIdx.x / G;
         const int lane = threadIdx.x % G;
         if (row < a.nJ) {   // whole groups are uniform: inactive groups skip together
-            AT s = row_dot_lane_g<G, VT, AT>(a.Jp, a.Jc, a.Jv, g, row, lane);
-            s = group_sum<AT, G>(s);
+            const AT s = canon_sum<G, AT>(a.Jp[row], a.Jp[row + 1], lane,
+                                          [&](int e) { return cvt<AT>(a.Jv[e]) * AT(g(a.Jc[e])); });
             if (lane == 0) a.t[row] = a.W[row] * double(s);
         }
     } else {
@@ -152,31 +152,44 @@ __device__ __forceinline__ void product_tail(double dot, double* part, int b, do
 // partial count stays small.
 template <int G, typename VT, typename AT>
 __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double rowv[kBlock / 4];   // per row of one pass (RPB <= 64)
     if (pcg_stopped_ro(a.fl)) return;
     constexpr int RPB = kBlock / G;
+    static_assert(RPB % kChunkRows == 0, "whole chunks per pass");
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x % G;
+    const int rib = threadIdx.x / G;
     const double beta = a.pcg.p2 ? a.pcg.sc->beta : 0.0;
-    double dot = 0.0;
     for (int base = b * RPB; base < a.n; base += gridDim.x * RPB) {
-        const int row = base + threadIdx.x / G;
+        const int row = base + rib;
+        double dv = 0.0;
         if (row < a.n) {
-            AT sj = row_dot_lane<G, VT, AT, 8>(a.Jtp, a.Jtc, a.Jtv, a.t, row, lane);
+            // each part summed in the schedule-independent order, then added
+            const AT sj = canon_sum<G, AT>(a.Jtp[row], a.Jtp[row + 1], lane,
+                                           [&](int e) { return cvt<AT>(a.Jtv[e]) * AT(a.t[a.Jtc[e]]); });
             double s = a.hs * double(sj);
-            if (a.lr_k) s += a.hs * lowrank_lane<G>(a.U, a.lr_v, a.lr_k, a.n, row, lane);
-            if (a.hasA) s += row_dot_lane<G, double, double>(a.Atp, a.Atc, a.Atv, a.u, row, lane);
-            s = group_sum<double, G>(s);
+            if (a.lr_k)
+                s += a.hs * canon_sum<G, double>(0, a.lr_k, lane, [&](int c) {
+                    return a.U[row + size_t(a.n) * c] * a.lr_v[c];
+                });
+            if (a.hasA)
+                s += canon_sum<G, double>(a.Atp[row], a.Atp[row + 1], lane,
+                                          [&](int e) { return a.Atv[e] * a.u[a.Atc[e]]; });
             if (lane == 0) {
                 const double pj = direction_entry(a.x, a.pcg, beta, row);
                 double y = s + a.hs * a.gamma * pj;
                 if (a.sigx) y += a.sigx[row] * pj;
                 a.q[row] = y;
-                dot += pj * y;
+                dv = pj * y;
             }
         }
+        if (a.part) {   // partials of p^T q per chunk of four rows
+            if (lane == 0) rowv[rib] = dv;
+            __syncthreads();
+            chunk_partials<RPB, 1>(rowv, RPB, base, a.n, a.part);
+            __syncthreads();
+        }
     }
-    product_tail(dot, a.part, b, sh);
 }
 
 // ==========================================================================
@@ -649,8 +662,8 @@ __global__ __launch_bounds__(kBlock) void k_ipm_fwd(FwdArgs<double> a, IpmVec v,
         const int row = b * RPB + threadIdx.x / G;
         const int lane = threadIdx.x % G;
         if (row < a.nJ) {
-            double s = row_dot_lane<G, double, double>(a.Jp, a.Jc, a.Jv, a.x, row, lane);
-            s = group_sum<double, G>(s);
+            const double s = canon_sum<G, double>(a.Jp[row], a.Jp[row + 1], lane,
+                                                  [&](int e) { return a.Jv[e] * a.x[a.Jc[e]]; });
             if (lane == 0) a.t[row] = a.W[row] * s;
         }
         return;
@@ -701,41 +714,40 @@ struct IpmBwdArgs {
 // Residual pass, part 2, per variable j: H x (scaled), the A^T products of
 // ya, va, vb and of the squared values with Sigma_A (Jacobi diagonal of
 // A^T Sigma_A A), then r_H, the bound residuals, Sigma_x, the Jacobi diagonal
-// d, and the two rhs parts.  Partials (6 per block): max|r_H|, max|Hx|,
-// max|r_g| and max|r_c| of the bounds, sum x.Hx, sum p.x.
+// d, and the two rhs parts.  Partials (6 per chunk of four variables):
+// max|r_H|, max|Hx|, max|r_g| and max|r_c| of the bounds, sum x.Hx, sum p.x.
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_ipm_bwd(IpmBwdArgs a, IpmVec v, const IpmScal* sc,
                                                     double* part, const Flags* fl) {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double rowv[6][kBlock / 4];   // per row of one pass (RPB <= 64)
     if (ipm_finished(fl)) return;
     constexpr int RPB = kBlock / G;
+    static_assert(RPB % kChunkRows == 0, "whole chunks per pass");
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x % G;
+    const int rib = threadIdx.x / G;
     const double hs = sc->hs, mu = sc->mu;
-    double mrH = 0.0, mHx = 0.0, mrg = 0.0, mrc = 0.0, sxh = 0.0, spx = 0.0;
     for (int base = b * RPB; base < v.n; base += gridDim.x * RPB) {
-        const int j = base + threadIdx.x / G;
+        const int j = base + rib;
+        double mrH = 0.0, mHx = 0.0, mrg = 0.0, mrc = 0.0, sxh = 0.0, spx = 0.0;
         if (j < v.n) {
-            double hj = hs * (a.lc ? index_sum_lane<G>(a.sptr, a.sslot, a.lc, j, lane)
-                                   : row_dot_lane<G, double, double>(a.Jtp, a.Jtc, a.Jtv, a.t, j, lane));
-            if (a.lr_k) hj += hs * lowrank_lane<G>(a.U, a.lr_v, a.lr_k, v.n, j, lane);
+            // every sum in the schedule-independent order
+            double hj = hs * (a.lc ? canon_sum<G, double>(a.sptr[j], a.sptr[j + 1], lane,
+                                                          [&](int e) { return a.lc[a.sslot[e]]; })
+                                   : canon_sum<G, double>(a.Jtp[j], a.Jtp[j + 1], lane,
+                                                          [&](int e) { return a.Jtv[e] * a.t[a.Jtc[e]]; }));
+            if (a.lr_k)
+                hj += hs * canon_sum<G, double>(0, a.lr_k, lane,
+                                                [&](int c) { return a.U[j + size_t(v.n) * c] * a.lr_v[c]; });
             double aty = 0.0, ava = 0.0, avb = 0.0, a2s = 0.0;
             if (a.hasA) {
                 const int s0 = a.Atp[j], s1 = a.Atp[j + 1];
-                for (int k = s0 + lane; k < s1; k += G) {
-                    const int i = a.Atc[k];
-                    const double av = a.Atv[k];
-                    aty += av * v.ya[i];
-                    ava += av * v.va[i];
-                    avb += av * v.vb[i];
-                    a2s += av * av * v.sigA[i];
-                }
+                aty = canon_sum<G, double>(s0, s1, lane, [&](int e) { return a.Atv[e] * v.ya[a.Atc[e]]; });
+                ava = canon_sum<G, double>(s0, s1, lane, [&](int e) { return a.Atv[e] * v.va[a.Atc[e]]; });
+                avb = canon_sum<G, double>(s0, s1, lane, [&](int e) { return a.Atv[e] * v.vb[a.Atc[e]]; });
+                a2s = canon_sum<G, double>(s0, s1, lane,
+                                           [&](int e) { return a.Atv[e] * a.Atv[e] * v.sigA[a.Atc[e]]; });
             }
-            hj = group_sum<double, G>(hj);
-            aty = group_sum<double, G>(aty);
-            ava = group_sum<double, G>(ava);
-            avb = group_sum<double, G>(avb);
-            a2s = group_sum<double, G>(a2s);
             if (lane == 0) {
                 const double xj = v.x[j];
                 const double hx = hj + hs * a.gamma * xj;
@@ -755,24 +767,22 @@ __global__ __launch_bounds__(kBlock) void k_ipm_bwd(IpmBwdArgs a, IpmVec v, cons
                 v.d[j] = v.dh[j] + a2s;
                 v.rhs_a[j] = (hl ? 1.0 / sl : 0.0) - (hu ? 1.0 / su : 0.0) + ava;
                 v.rhs_b[j] = -(hx + pj) - gl * rl + gu * ru + avb;
-                mrH = fmax(mrH, fabs(rH));
-                mHx = fmax(mHx, fabs(hx));
-                mrg = fmax(mrg, fmax(fabs(rl), fabs(ru)));
-                mrc = fmax(mrc, fmax(hl ? fabs(ll * sl - mu) : 0.0, hu ? fabs(lu * su - mu) : 0.0));
-                sxh += xj * hx;
-                spx += pj * xj;
+                mrH = fabs(rH);
+                mHx = fabs(hx);
+                mrg = fmax(fabs(rl), fabs(ru));
+                mrc = fmax(hl ? fabs(ll * sl - mu) : 0.0, hu ? fabs(lu * su - mu) : 0.0);
+                sxh = xj * hx;
+                spx = pj * xj;
             }
         }
-    }
-    mrH = block_max(mrH, sh);
-    mHx = block_max(mHx, sh);
-    mrg = block_max(mrg, sh);
-    mrc = block_max(mrc, sh);
-    sxh = block_sum(sxh, sh);
-    spx = block_sum(spx, sh);
-    if (threadIdx.x == 0) {
-        double* o = part + 6 * size_t(b);
-        o[0] = mrH; o[1] = mHx; o[2] = mrg; o[3] = mrc; o[4] = sxh; o[5] = spx;
+        // partials per chunk of four rows: four maxima, two sums
+        if (lane == 0) {
+            rowv[0][rib] = mrH; rowv[1][rib] = mHx; rowv[2][rib] = mrg;
+            rowv[3][rib] = mrc; rowv[4][rib] = sxh; rowv[5][rib] = spx;
+        }
+        __syncthreads();
+        chunk_partials<RPB, 6>(&rowv[0][0], kBlock / 4, base, v.n, part);
+        __syncthreads();
     }
 }
 

@@ -212,7 +212,7 @@ int launch_bwd(qp_handle* h, int G, const BwdArgs<VT>& a) {
         default: hipLaunchKernelGGL((k_op_bwd<64, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
     }
     HIPCHK(hipGetLastError());
-    return grid;
+    return (a.n + kChunkRows - 1) / kChunkRows;   // p^T q partials: one per chunk of rows
 }
 
 template <typename VT>
@@ -1023,7 +1023,9 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->rho = h->dalloc<double>(n);
         h->dxacc = h->dalloc<double>(n);
         const size_t nbA = size_t((m + 3) / 4) + 1;
-        h->part_len = 8 * (size_t(kMaxPartials) + nbA + 64);
+        // per-block partials, and six per chunk of four variables (residual pass)
+        h->part_len = std::max(8 * (size_t(kMaxPartials) + nbA + 64),
+                               6 * (size_t(n) / kChunkRows + 1) + 64);
         h->part = h->dalloc<double>(h->part_len);
         h->part2 = h->dalloc<double>(h->part_len);
         h->partA = h->dalloc<double>(h->part_len);
@@ -1295,7 +1297,8 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
             }
             HIPCHK(hipGetLastError());
             hipLaunchKernelGGL(k_ipm_check, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->partA, nbA,
-                               (const double*)h->part, gb, apply, h->isc, h->fl, h->log);
+                               (const double*)h->part, (n + kChunkRows - 1) / kChunkRows, apply, h->isc, h->fl,
+                               h->log);
             HIPCHK(hipGetLastError());
         };
         const int* ipm_stop = reinterpret_cast<const int*>(&h->fl->ipm_done);

@@ -99,6 +99,29 @@ def test_operator_every_schedule(sched):
     assert np.all(np.abs(y - ref) <= 1e-12 * bound)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_schedules_give_identical_bits(prec):
+    """The lane count per row is a tunable schedule (autotuned for CSR
+    matrices); every sum it touches is formed in a schedule-independent
+    order, so the operator, a Newton step and a whole solve are bitwise the
+    same for every schedule."""
+    prob = qpsynth.config1(2)
+    it = qpsynth.random_iterate(prob, 5)
+    outs = []
+    for sched in [4, 8, 16, 32, 64]:
+        print(f"schedule {sched} {prec}", flush=True)
+        h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(schedule=sched, precision=prec))
+        y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
+        assert info["spmv_format"] == 0
+        st, dx, _ = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], it["rhs"])
+        assert st == qpgpu.QP_OK
+        res = qpgpu.qp_solve(h)
+        assert res.status == qpgpu.QP_OK
+        outs.append((y.tobytes(), dx.tobytes(), res.x.tobytes()))
+    for o in outs[1:]:
+        assert o == outs[0]
+
+
 # ----------------------------------------------------------------------------
 # one Newton direction (a3-a5): Jacobi PCG vs dense Cholesky
 # ----------------------------------------------------------------------------
