@@ -94,11 +94,17 @@ def cpu_baseline(prob, ipm_iters):
 
 
 def kernel_source_hash():
+    """Hash of the operator kernels' code (comments and blank lines left out,
+    so that a comment edit does not void the committed counter summary)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("device_common.hpp", "ipm_kernels.hpp", "line_kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_2405_03584_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2405_03584_amd", "csrc", f), encoding="utf-8") as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -72,9 +72,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     constexpr int RH = kLineHeld;
     static_assert(NW == 4, "the pass-1 combine adds four wavefront partials");
     __shared__ AT part[NW][64];
-    // Rows of A come first in the grid, so their longer dependent chains run
-    // beside the line blocks instead of trailing them; the line blocks are
-    // remapped so each XCD streams one contiguous range of lines.
+    // The u blocks and the rows of A come first in the grid, so their longer
+    // dependent chains run beside the line blocks instead of trailing them;
+    // the line blocks are remapped so each XCD streams one contiguous range
+    // of lines.
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int bi = int(blockIdx.x);
