@@ -188,9 +188,8 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
  * qp_create) together; xs[i] (n_i doubles) receives QP i's minimiser and
  * infos[i] (may be NULL) its info.  Handles run concurrently, each on its own
  * stream (create them with hip_stream = NULL for a stream per handle), by up
- * to 4 host workers (environment QPGPU_BATCH_WORKERS), largest nnz first.
- * The batch workload of the task (many QPs of uneven size) is the intended
- * use.  Returns QP_OK when every QP returned QP_OK, else the first failing
+ * to 6 host workers (environment QPGPU_BATCH_WORKERS), largest nnz first.
+ * Many QPs of uneven size are the intended use.  Returns QP_OK when every QP returned QP_OK, else the first failing
  * status (QP_ERR_DEVICE preferred); QP_ERR_INVALID for NULL or repeated
  * handles (text in qp_last_error(NULL)). */
 qp_status qp_solve_batch(qp_handle* const* hs, int32_t count, double* const* xs, qp_info* infos);

@@ -357,7 +357,7 @@ def test_newton_step_mixed_precision_refined(prec):
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("inst", [0, 2])
 def test_solve_mixed_precision_config1(prec, inst):
-    """Spec bars for the low-precision J: x within 1e-5 (inf-norm) and
+    """Bars for the low-precision J: x within 1e-5 (inf-norm) and
     objective within 1e-6 (relative) of the FP64 oracle; certificate 1e-9."""
     prob = qpsynth.config1(inst)
     h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
