@@ -239,6 +239,23 @@ def test_solve_without_constraints_or_bounds():
     assert np.abs(res.x - x_ref).max() <= 1e-6 * (1 + np.abs(x_ref).max())
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_line_format_without_constraint_rows(prec):
+    """Line format, bounds only (m = 0): no u blocks, no constraint block."""
+    band = qpsynth.config2(scale=0.02)
+    prob = qpsynth.QPProblem(gamma=band.gamma, p=band.p, J=band.J, W=band.W, x_lo=band.x_lo, x_hi=band.x_hi)
+    print(f"line format without A, n={prob.n}, {prec}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
+    res = qpgpu.qp_solve(h)
+    ref = oracle.solve(prob)
+    assert res.status == qpgpu.QP_OK, res.info
+    assert res.info["spmv_format"] == 1
+    tol = 1e-6 * (1 + np.abs(ref.x).max()) if prec == "fp64" else 1e-5
+    assert np.abs(res.x - ref.x).max() <= tol
+    cert = oracle.kkt_certificate(prob, res.x, res.lam_x, None)
+    assert cert.worst() <= 1e-9, cert
+
+
 def test_solve_iteration_limit_returns_not_converged():
     prob = qpsynth.config1(0)
     h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(max_ipm_iter=2))
