@@ -103,6 +103,8 @@ struct qp_handle {
     double *lr_part = nullptr, *lr_v = nullptr;  // low-rank term: U^T p partials and w .* U^T p
     int *rflag = nullptr, *rpos = nullptr, *ridx = nullptr, *kdev = nullptr;
     int* sext = nullptr;        // per strong row: range in A (k_strong_rows)
+    int *scr = nullptr, *scnt = nullptr;   // per column of A: strong entries' ranks, count (k_fold_weak)
+    double* scv = nullptr;                 // and their values
     double* ssq = nullptr;      // per strong row: sqrt(Sigma)
     int srows = 0;              // rows of that table (covers every step-1 grid)
     size_t part_len = 0;
@@ -405,7 +407,8 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
     hipLaunchKernelGGL(k_strong_rows, dim3((h->srows + 255) / 256), dim3(256), 0, h->stream, (const int*)h->Ap,
                        (const int*)h->ridx, sigA, (const int*)h->kdev, h->srows, h->sext, h->ssq, stop);
     hipLaunchKernelGGL(k_fold_weak, dim3((n + 15) / 16), dim3(256), 0, h->stream, (const int*)h->Atp,
-                       (const int*)h->Atc, (const double*)h->Atv, sigA, (const int*)h->rpos, D, n, h->Dw, stop);
+                       (const int*)h->Atc, (const double*)h->Atv, sigA, (const int*)h->rpos, D, n, h->Dw, h->scr,
+                       h->scv, h->scnt, stop);
     HIPCHK(hipGetLastError());
     int k = 0;
     HIPCHK(hipMemcpyAsync(&k, h->kdev, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -427,8 +430,8 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
                     : nw == 2 ? k_schur_form<2>
                               : k_schur_form<1>;
         hipLaunchKernelGGL(kern, dim3(ld), dim3(64 * nw), row_bytes * nw, h->stream, (const int*)h->Ap,
-                           (const int*)h->Ac, (const double*)h->Av, (const int*)h->Atp, (const int*)h->Atc,
-                           (const double*)h->Atv, (const double*)h->Dw, sigA, (const int*)h->rpos,
+                           (const int*)h->Ac, (const double*)h->Av, (const int*)h->Atp, (const int*)h->scr,
+                           (const double*)h->scv, (const int*)h->scnt, (const double*)h->Dw, sigA,
                            (const int*)h->ridx, k, ld, h->Sm, stop);
     }
     HIPCHK(hipGetLastError());
@@ -1048,6 +1051,9 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
                 h->wpre = h->dalloc<double>(h->ld);
                 h->vpre = h->dalloc<double>(std::max(h->ld, m));
                 h->Dw = h->dalloc<double>(n);
+                h->scr = h->dalloc<int>(std::max<int64_t>(h->nnzA, 1));
+                h->scv = h->dalloc<double>(std::max<int64_t>(h->nnzA, 1));
+                h->scnt = h->dalloc<int>(n);
                 h->rflag = h->dalloc<int>(m);
                 h->rpos = h->dalloc<int>(m);
                 h->ridx = h->dalloc<int>(m);

@@ -99,40 +99,58 @@ __global__ __launch_bounds__(256) void k_strong_rows(const int* Ap, const int* i
     sq[r] = q;
 }
 
-// Dw_j = dh_j + sum over weak rows i of Sigma_i A_ij^2 (rows of A^T, G = 16).
+// Dw_j = dh_j + sum over weak rows i of Sigma_i A_ij^2 (rows of A^T, G = 16),
+// and column j's strong entries compacted in row order: their ranks and
+// values at scr/scv[Atp[j] ...], their count in scnt[j] (for k_schur_form).
 __global__ __launch_bounds__(256) void k_fold_weak(const int* Atp, const int* Atc, const double* Atv,
                                                    const double* sigA, const int* pos, const double* dh,
-                                                   int n, double* Dw, const int* stop) {
+                                                   int n, double* Dw, int* scr, double* scv, int* scnt,
+                                                   const int* stop) {
     if (stop && *stop) return;
     const int j = blockIdx.x * 16 + (threadIdx.x >> 4);
     const int lane = threadIdx.x & 15;
-    if (j >= n) return;
+    const int gshift = threadIdx.x & 48;   // this group's first lane in the wavefront
+    if (j >= n) return;                    // whole groups
+    const int e0 = Atp[j], e1 = Atp[j + 1];
     double s = 0.0;
-    for (int e = Atp[j] + lane; e < Atp[j + 1]; e += 16) {
-        const int i = Atc[e];
-        if (pos[i] < 0) {
-            const double a = Atv[e];
-            s += a * a * sigA[i];
+    int cnt = 0;
+    for (int base = e0; base < e1; base += 16) {   // trip count uniform over the group
+        const int e = base + lane;
+        const bool in = e < e1;
+        const int i = in ? Atc[e] : 0;
+        const int r = in ? pos[i] : -1;
+        const double a = in ? Atv[e] : 0.0;
+        if (in && r < 0) s += a * a * sigA[i];
+        const unsigned mask = unsigned(__ballot(in && r >= 0) >> gshift) & 0xFFFFu;
+        if (in && r >= 0) {
+            const int at = e0 + cnt + __popc(mask & ((1u << lane) - 1u));
+            scr[at] = r;
+            scv[at] = a;
         }
+        cnt += __popc(mask);
     }
     s = group_sum<double, 16>(s);
-    if (lane == 0) Dw[j] = dh[j] + s;
+    if (lane == 0) {
+        Dw[j] = dh[j] + s;
+        scnt[j] = cnt;
+    }
 }
 
 // S = I + Sigma^{1/2} A_s D^{-1} A_s^T Sigma^{1/2} over the k strong rows: one
 // workgroup of NW wavefronts per strong row r (row i = idx[r] of A), the
 // wavefronts taking contiguous parts of the row's nonzeros, each with its own
 // copy of the output row in LDS.  For each nonzero A_ij (in column order), the
-// strong entries of column j of A (row j of the stored A^T) are added with
+// strong entries of column j of A (compacted by k_fold_weak) are added with
 // weight A_ij/D_j; within one column all row indices differ, so no two lanes
 // touch the same LDS word in a step, and steps of one wavefront execute in
 // order.  The NW copies are summed in a fixed order at the end.
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_schur_form(const int* __restrict__ Ap, const int* __restrict__ Ac,
                                                        const double* __restrict__ Av, const int* __restrict__ Atp,
-                                                       const int* __restrict__ Atc, const double* __restrict__ Atv,
+                                                       const int* __restrict__ scr, const double* __restrict__ scv,
+                                                       const int* __restrict__ scnt,
                                                        const double* __restrict__ D, const double* __restrict__ sigA,
-                                                       const int* __restrict__ pos, const int* __restrict__ idx,
+                                                       const int* __restrict__ idx,
                                                        int k, int ld, double* __restrict__ S, const int* stop) {
     extern __shared__ double acc_all[];
     if (stop && *stop) return;
@@ -147,8 +165,9 @@ __global__ __launch_bounds__(NW * 64) void k_schur_form(const int* __restrict__ 
         const int per = (len + NW - 1) / NW;
         const int e0 = a0 + min(len, w * per), e1 = a0 + min(len, (w + 1) * per);
         // Batches of 8 nonzeros: every load of a batch (column ids, weights,
-        // the first 64 entries of each column and their strong-row ranks) is
-        // issued before the adds, which then run in the original order.
+        // the first 64 strong entries of each column, compacted by
+        // k_fold_weak: ranks and values) is issued before the adds, which then
+        // run in the original order.
         constexpr int B = 8;
         for (int e = e0; e < e1; e += B) {
             int jv[B], f0[B], f1[B], q[B];
@@ -159,23 +178,20 @@ __global__ __launch_bounds__(NW * 64) void k_schur_form(const int* __restrict__ 
                 jv[u] = Ac[ee];
                 c[u] = (e + u < e1) ? Av[ee] / D[jv[u]] : 0.0;
                 f0[u] = Atp[jv[u]];
-                f1[u] = (e + u < e1) ? Atp[jv[u] + 1] : f0[u];
+                f1[u] = (e + u < e1) ? f0[u] + scnt[jv[u]] : f0[u];
             }
 #pragma unroll
             for (int u = 0; u < B; ++u) {
                 const int f = f0[u] + lane;
                 const bool in = f < f1[u];
                 const int ff = in ? f : 0;   // a valid index when idle (A has nonzeros when k > 0)
-                av[u] = in ? Atv[ff] : 0.0;
-                q[u] = in ? pos[Atc[ff]] : -1;
+                av[u] = in ? scv[ff] : 0.0;
+                q[u] = in ? scr[ff] : -1;
             }
 #pragma unroll
             for (int u = 0; u < B; ++u) {
                 if (q[u] >= 0) acc[q[u]] += c[u] * av[u];
-                for (int f = f0[u] + 64 + lane; f < f1[u]; f += 64) {   // columns longer than 64
-                    const int qq = pos[Atc[f]];
-                    if (qq >= 0) acc[qq] += c[u] * Atv[f];
-                }
+                for (int f = f0[u] + 64 + lane; f < f1[u]; f += 64) acc[scr[f]] += c[u] * scv[f];   // columns with > 64
             }
         }
     }
