@@ -431,8 +431,8 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
                               : k_schur_form<1>;
         hipLaunchKernelGGL(kern, dim3(ld), dim3(64 * nw), row_bytes * nw, h->stream, (const int*)h->Ap,
                            (const int*)h->Ac, (const double*)h->Av, (const int*)h->Atp, (const int*)h->scr,
-                           (const double*)h->scv, (const int*)h->scnt, (const double*)h->Dw, sigA,
-                           (const int*)h->ridx, k, ld, h->Sm, stop);
+                           (const double*)h->scv, (const int*)h->scnt, (const double*)h->Dw,
+                           (const double*)h->ssq, (const int*)h->ridx, k, ld, h->Sm, stop);
     }
     HIPCHK(hipGetLastError());
     // sweep: S alternates between Sm and Sm2; P between the two halves of Pbuf

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(NW * 64) void k_schur_form(const int* __restrict__ 
                                                        const double* __restrict__ Av, const int* __restrict__ Atp,
                                                        const int* __restrict__ scr, const double* __restrict__ scv,
                                                        const int* __restrict__ scnt,
-                                                       const double* __restrict__ D, const double* __restrict__ sigA,
+                                                       const double* __restrict__ D, const double* __restrict__ sq,
                                                        const int* __restrict__ idx,
                                                        int k, int ld, double* __restrict__ S, const int* stop) {
     extern __shared__ double acc_all[];
@@ -196,12 +196,14 @@ __global__ __launch_bounds__(NW * 64) void k_schur_form(const int* __restrict__ 
         }
     }
     __syncthreads();
-    const double si = (r < k) ? sqrt(sigA[idx[r]]) : 0.0;
+    // sqrt(Sigma) of the strong rows from the per-row table (k_strong_rows,
+    // the same sqrt of the same value)
+    const double si = (r < k) ? sq[r] : 0.0;
     for (int c = threadIdx.x; c < ld; c += NW * 64) {
         double t = acc_all[c];
 #pragma unroll
         for (int w2 = 1; w2 < NW; ++w2) t += acc_all[size_t(w2) * ld + c];
-        double v = (r < k && c < k) ? si * sqrt(sigA[idx[c]]) * t : 0.0;
+        double v = (r < k && c < k) ? si * sq[c] * t : 0.0;
         if (c == r) v += 1.0;
         S[size_t(r) * ld + c] = v;
     }
