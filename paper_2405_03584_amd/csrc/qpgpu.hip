@@ -113,6 +113,8 @@ struct qp_handle {
     PcgScal* psc = nullptr;
     Flags* fl = nullptr;
     Flags* fl_host = nullptr;   // pinned, 2 slots
+    int* k_host = nullptr;      // pinned: the strong-row count read back by build_precond
+    hipEvent_t ev_k = nullptr;
 
     // captured PCG iteration graphs, one per operator (precision, preconditioner, operands)
     struct PcgGraph {
@@ -148,6 +150,8 @@ struct qp_handle {
         if (stream) (void)hipStreamSynchronize(stream);
         for (void* a : allocs) (void)hipFree(a);
         if (fl_host) (void)hipHostFree(fl_host);
+        if (k_host) (void)hipHostFree(k_host);
+        if (ev_k) (void)hipEventDestroy(ev_k);
         for (auto& g : graphs)
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
         for (auto e : tev) (void)hipEventDestroy(e);
@@ -404,15 +408,18 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
                        (const int*)h->Ac, (const double*)h->Av, D, sigA, m, h->rflag, stop);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, h->stream, (const int*)h->rflag, m, h->rpos, h->ridx,
                        h->kdev, stop);
+    // k goes to the host as soon as it is known; the two kernels below keep
+    // the device busy while the host waits for it
+    HIPCHK(hipMemcpyAsync(h->k_host, h->kdev, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipEventRecord(h->ev_k, h->stream));
     hipLaunchKernelGGL(k_strong_rows, dim3((h->srows + 255) / 256), dim3(256), 0, h->stream, (const int*)h->Ap,
                        (const int*)h->ridx, sigA, (const int*)h->kdev, h->srows, h->sext, h->ssq, stop);
     hipLaunchKernelGGL(k_fold_weak, dim3((n + 15) / 16), dim3(256), 0, h->stream, (const int*)h->Atp,
                        (const int*)h->Atc, (const double*)h->Atv, sigA, (const int*)h->rpos, D, n, h->Dw, h->scr,
                        h->scv, h->scnt, stop);
     HIPCHK(hipGetLastError());
-    int k = 0;
-    HIPCHK(hipMemcpyAsync(&k, h->kdev, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipEventSynchronize(h->ev_k));
+    int k = *h->k_host;
     if (k < 0 || k > m) k = 0;   // never happens; keeps launch shapes in range
     h->kcur = k;
     h->ldcur = ((k + TS - 1) / TS) * TS;
@@ -1070,6 +1077,8 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         HIPCHK(hipMemsetAsync(h->psc, 0, sizeof(PcgScal), h->stream));
         h->fl = h->dalloc<Flags>(1);
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->fl_host), 2 * sizeof(Flags), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->k_host), sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_k, hipEventDisableTiming));
         for (auto& ev : h->ev_chunk) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         HIPCHK(hipEventCreate(&h->ev_t0));
         HIPCHK(hipEventCreate(&h->ev_t1));
