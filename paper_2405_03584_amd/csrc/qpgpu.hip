@@ -128,7 +128,8 @@ struct qp_handle {
 
     std::vector<hipEvent_t> tev;  // timing events, pairs
     hipEvent_t ev_chunk[2] = {nullptr, nullptr};
-    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_p0 = nullptr, ev_p1 = nullptr;
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+    hipEvent_t ev_p0[2] = {nullptr, nullptr}, ev_p1[2] = {nullptr, nullptr};   // PCG time, two IPM iterations in flight
 
     template <typename T>
     T* dalloc(size_t count) {
@@ -155,7 +156,7 @@ struct qp_handle {
         for (auto& g : graphs)
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
         for (auto e : tev) (void)hipEventDestroy(e);
-        for (auto e : {ev_chunk[0], ev_chunk[1], ev_t0, ev_t1, ev_p0, ev_p1})
+        for (auto e : {ev_chunk[0], ev_chunk[1], ev_t0, ev_t1, ev_p0[0], ev_p0[1], ev_p1[0], ev_p1[1]})
             if (e) (void)hipEventDestroy(e);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -707,7 +708,10 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         snapshot(cur ^ 1);
         HIPCHK(hipEventSynchronize(h->ev_chunk[cur]));
         f = h->fl_host[cur];
-        if (stop(f) || launched > guard) {
+        // A stopped solve's flags no longer change: the chunk queued behind
+        // this snapshot runs as no-ops while the host queues what follows.
+        if (stop(f)) break;
+        if (launched > guard) {
             HIPCHK(hipEventSynchronize(h->ev_chunk[cur ^ 1]));
             f = h->fl_host[cur ^ 1];
             break;
@@ -1082,8 +1086,10 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         for (auto& ev : h->ev_chunk) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         HIPCHK(hipEventCreate(&h->ev_t0));
         HIPCHK(hipEventCreate(&h->ev_t1));
-        HIPCHK(hipEventCreate(&h->ev_p0));
-        HIPCHK(hipEventCreate(&h->ev_p1));
+        for (int i = 0; i < 2; ++i) {
+            HIPCHK(hipEventCreate(&h->ev_p0[i]));
+            HIPCHK(hipEventCreate(&h->ev_p1[i]));
+        }
         HIPCHK(hipMemsetAsync(h->zero_n, 0, sizeof(double) * n, h->stream));
         HIPCHK(hipMemsetAsync(h->zero_m, 0, sizeof(double) * std::max(m, 1), h->stream));
 
@@ -1325,20 +1331,29 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
         int pcg_solves = 0, capped = 0;
         double last_relres = 0.0;
         float pcg_ms = 0.f;
+        // The PCG time of an IPM iteration is read two iterations later (its
+        // events are long complete by then), so the host never waits for the
+        // device just to time it.
+        bool pcg_timed[2] = {false, false};
+        auto harvest_pcg_ms = [&](int slot) {
+            if (!pcg_timed[slot]) return;
+            HIPCHK(hipEventSynchronize(h->ev_p1[slot]));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, h->ev_p0[slot], h->ev_p1[slot]));
+            pcg_ms += ms;
+            pcg_timed[slot] = false;
+        };
         Flags f{};
         for (int it = 0; it < h->set.max_ipm_iter; ++it) {
-            HIPCHK(hipEventRecord(h->ev_p0, h->stream));
+            const int ps = it & 1;
+            harvest_pcg_ms(ps);
+            HIPCHK(hipEventRecord(h->ev_p0[ps], h->stream));
             int nsolves = 0;
             f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
                                  wbp ? h->Dw : nullptr, hs, true, &ta, &nsolves);
-            HIPCHK(hipEventRecord(h->ev_p1, h->stream));
+            HIPCHK(hipEventRecord(h->ev_p1[ps], h->stream));
             if (f.ipm_done) break;
-            {
-                HIPCHK(hipEventSynchronize(h->ev_p1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, h->ev_p0, h->ev_p1));
-                pcg_ms += ms;
-            }
+            pcg_timed[ps] = true;
             pcg_total += f.pcg_iters;
             pcg_solves += nsolves;
             capped += f.pcg_capped;
@@ -1381,6 +1396,8 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
         PcgScal ps{};
         HIPCHK(hipMemcpyAsync(&ps, h->psc, sizeof(PcgScal), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
+        harvest_pcg_ms(0);
+        harvest_pcg_ms(1);
         if (st == QP_OK && !sc.done) st = QP_ERR_NOT_CONVERGED;
         last_relres = ps.bnorm2 > 0 ? std::sqrt(ps.rr / ps.bnorm2) : 0.0;
         if (info) {
