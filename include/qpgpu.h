@@ -167,6 +167,29 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
  * QP_ERR_NUMERIC or QP_ERR_DEVICE. */
 qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_info* info);
 
+/* qp_solve_from: qp_solve started at the caller's primal point x0 (n finite
+ * doubles, host memory; NULL = the default start).  Meant for a sequence of
+ * related QPs (Section 3: SQP sub-problems), x0 being the previous QP's
+ * minimiser.  The paper gives no warm-start rule: x0 replaces the default x
+ * of the start point and the slacks (max(x0 - lo, 1), max(hi - x0, 1) and
+ * the same for A x0), multipliers (1) and mu0 follow the default rule, so x0
+ * need not be feasible.  Outputs and errors as qp_solve; QP_ERR_INVALID for
+ * a non-finite x0 (no device work). */
+qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A, double* lam_x,
+                        qp_info* info);
+
+/* qp_update_hessian: replace the objective of a handle (gamma, p, U, w, k;
+ * see qp_hessian) and keep J, W, A and the bounds resident.  In SQP
+ * (Section 3) the quasi-Newton term U w U^T gains columns from one QP
+ * sub-problem to the next (Section 4.1.1); the J and A preparation of
+ * qp_create is not repeated.  Recomputes the cached diag(H) and drops the
+ * handle's captured PCG graphs.  k may grow or shrink (storage grows to
+ * max(k, 2 * capacity) when k exceeds it).  Waits for the handle's queued
+ * work first; H's arrays are copied before return.  Errors: QP_ERR_INVALID
+ * (as qp_create's checks of H: gamma < 0, w < 0, non-finite entries, NULL
+ * arrays; the handle is unchanged), QP_ERR_DEVICE. */
+qp_status qp_update_hessian(qp_handle* h, const qp_hessian* H);
+
 /* qp_newton_step: one PCG solve of (H + diag(sigma_x) + A^T diag(sigma_A) A) dx = rhs
  * (the system of Algorithm 1's second line in condensed form) with the
  * handle's precision and refinement settings and no objective scaling.

@@ -191,15 +191,8 @@ static std::string check_range(const double* lo, const double* hi, int64_t len, 
     return "";
 }
 
-std::string validate_problem(const qp_hessian* H, const qp_csr* J, const double* W,
-                             const qp_csr* A, const qp_range* b, const qp_range* bounds,
-                             const qp_settings* s) {
+std::string validate_hessian(const qp_hessian* H, int32_t n) {
     if (!H) return "H is NULL";
-    if (!J) return "J is NULL";
-    std::string e = check_csr(J, "J", -1);
-    if (!e.empty()) return e;
-    const int32_t n = J->cols;
-    if (n <= 0) return "the problem needs at least one variable (J->cols > 0)";
     if (!(H->gamma >= 0.0) || !std::isfinite(H->gamma)) return "H.gamma must be finite and >= 0";
     if (!H->p) return "H.p is NULL";
     for (int32_t j = 0; j < n; ++j)
@@ -212,6 +205,20 @@ std::string validate_problem(const qp_hessian* H, const qp_csr* J, const double*
         for (int32_t c = 0; c < H->k; ++c)
             if (!(H->w[c] >= 0.0) || !std::isfinite(H->w[c])) return "H.w must be finite and >= 0";
     }
+    return "";
+}
+
+std::string validate_problem(const qp_hessian* H, const qp_csr* J, const double* W,
+                             const qp_csr* A, const qp_range* b, const qp_range* bounds,
+                             const qp_settings* s) {
+    if (!H) return "H is NULL";
+    if (!J) return "J is NULL";
+    std::string e = check_csr(J, "J", -1);
+    if (!e.empty()) return e;
+    const int32_t n = J->cols;
+    if (n <= 0) return "the problem needs at least one variable (J->cols > 0)";
+    e = validate_hessian(H, n);
+    if (!e.empty()) return e;
     if (J->rows > 0 && !W) return "W is NULL";
     for (int32_t i = 0; i < J->rows; ++i)
         if (!(W[i] >= 0.0) || !std::isfinite(W[i])) return "W must be finite and >= 0";

@@ -62,4 +62,7 @@ std::string validate_problem(const qp_hessian* H, const qp_csr* J, const double*
 
 std::string validate_settings(const qp_settings* s);
 
+// Validation of the objective terms (gamma, p, U, w) for n variables; "" when valid.
+std::string validate_hessian(const qp_hessian* H, int32_t n);
+
 }  // namespace qpg

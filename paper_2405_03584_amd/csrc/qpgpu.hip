@@ -19,6 +19,7 @@
 #include "ipm_kernels.hpp"
 #include "schur_kernels.hpp"
 #include "line_kernels.hpp"
+#include "sequence_kernels.hpp"
 #include "qpgpu.h"
 
 using namespace qpg;
@@ -59,6 +60,8 @@ struct qp_handle {
     int32_t n = 0, m = 0, nJ = 0, k = 0;
     int64_t nnzJ = 0, nnzA = 0;
     double gamma = 0.0, cscale = 1.0, mtot = 0.0;
+    int k_cap = 0;              // columns U, w, lr_part, lr_v have room for
+    double* x0d = nullptr;      // caller's start point (qp_solve_from), allocated on first use
     int GJ = 16, GJt = 64;   // lanes per row of J and of J^T (and A^T)
 
     std::vector<void*> allocs;
@@ -139,6 +142,15 @@ struct qp_handle {
         if (e != hipSuccess) throw HipError{e, "hipMalloc"};
         allocs.push_back(ptr);
         return static_cast<T*>(ptr);
+    }
+    void dfree(void* ptr) {
+        if (!ptr) return;
+        for (auto it = allocs.begin(); it != allocs.end(); ++it)
+            if (*it == ptr) {
+                allocs.erase(it);
+                (void)hipFree(ptr);
+                return;
+            }
     }
     template <typename T>
     T* upload(const T* src, size_t count) {
@@ -837,6 +849,22 @@ void ensure_timing_events(qp_handle* h) {
     }
 }
 
+// diag(H) = gamma + sum_i W_i J_ij^2 + sum_c w_c U_jc^2 into h->diagH.
+void compute_diag_h(qp_handle* h) {
+    const int G = 64;
+    hipLaunchKernelGGL(k_diag_h<G>, dim3(grid_rows(h->n, G)), dim3(kBlock), 0, h->stream, (const int*)h->Jtp,
+                       (const int*)h->Jtc, (const double*)h->Jtv, (const double*)h->W, h->n, h->gamma,
+                       (const double*)h->U, (const double*)h->w, h->k, h->diagH);
+    HIPCHK(hipGetLastError());
+}
+
+// Captured PCG graphs hold gamma, U and k by value: a new objective drops them.
+void drop_graphs(qp_handle* h) {
+    for (auto& g : h->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
+
 qp_status fail(qp_handle* h, qp_status st, const std::string& msg) {
     if (h) h->err = msg;
     return st;
@@ -1001,6 +1029,7 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         if (h->k > 0) {
             h->U = h->upload(H->U, size_t(n) * h->k);
             h->w = h->upload(H->w, size_t(h->k));
+            h->k_cap = h->k;
         }
         h->diagH = h->dalloc<double>(n);
 
@@ -1093,15 +1122,8 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         HIPCHK(hipMemsetAsync(h->zero_n, 0, sizeof(double) * n, h->stream));
         HIPCHK(hipMemsetAsync(h->zero_m, 0, sizeof(double) * std::max(m, 1), h->stream));
 
-        // cached diag(H) (Section 4.1.2: computed once, H does not change)
-        {
-            const int G = 64;
-            hipLaunchKernelGGL(k_diag_h<G>, dim3(grid_rows(n, G)), dim3(kBlock), 0, h->stream,
-                               (const int*)h->Jtp, (const int*)h->Jtc, (const double*)h->Jtv,
-                               (const double*)h->W, n, h->gamma, (const double*)h->U, (const double*)h->w,
-                               h->k, h->diagH);
-            HIPCHK(hipGetLastError());
-        }
+        // cached diag(H) (Section 4.1.2: computed once per objective)
+        compute_diag_h(h);
         if (h->set.precision != QP_FP64) ensure_lowp(h, h->set.precision);
         HIPCHK(hipStreamSynchronize(h->stream));
         autotune_schedule(h);
@@ -1225,10 +1247,14 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
     return st;
 }
 
-qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_info* info) {
+qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A, double* lam_x,
+                        qp_info* info) {
     if (!h) return QP_ERR_INVALID;
     (void)hipGetLastError();  // drop an error left by an earlier, unrelated call
     if (!x) return fail(h, QP_ERR_INVALID, "x is NULL");
+    if (x0)
+        for (int j = 0; j < h->n; ++j)
+            if (!std::isfinite(x0[j])) return fail(h, QP_ERR_INVALID, "x0 has a non-finite entry");
     qp_status st = QP_OK;
     try {
         ensure_timing_events(h);
@@ -1246,7 +1272,14 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
         HIPCHK(hipEventRecord(h->ev_t0, h->stream));
         // start point, objective scale, mu0
         const int gx = grid_elems(n);
-        hipLaunchKernelGGL(k_ipm_init_x, dim3(gx), dim3(kBlock), 0, h->stream, v, h->partA);
+        if (x0) {
+            if (!h->x0d) h->x0d = h->dalloc<double>(n);
+            HIPCHK(hipMemcpyAsync(h->x0d, x0, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+            hipLaunchKernelGGL(k_ipm_init_x_from, dim3(gx), dim3(kBlock), 0, h->stream, v,
+                               (const double*)h->x0d, h->partA);
+        } else {
+            hipLaunchKernelGGL(k_ipm_init_x, dim3(gx), dim3(kBlock), 0, h->stream, v, h->partA);
+        }
         HIPCHK(hipGetLastError());
         int nps = gx;
         if (m > 0) {
@@ -1425,6 +1458,48 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
     if (st == QP_ERR_NUMERIC) h->err = "PCG breakdown";
     else if (st == QP_ERR_NOT_CONVERGED) h->err = "IPM reached max_ipm_iter";
     return st;
+}
+
+qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_info* info) {
+    return qp_solve_from(h, nullptr, x, lam_A, lam_x, info);
+}
+
+qp_status qp_update_hessian(qp_handle* h, const qp_hessian* H) {
+    if (!h) return QP_ERR_INVALID;
+    (void)hipGetLastError();  // drop an error left by an earlier, unrelated call
+    const std::string e = validate_hessian(H, h->n);
+    if (!e.empty()) return fail(h, QP_ERR_INVALID, e);
+    try {
+        const int n = h->n, k = H->k;
+        // queued work may still read the old objective
+        HIPCHK(hipStreamSynchronize(h->stream));
+        drop_graphs(h);
+        if (k > h->k_cap) {
+            h->dfree(h->U); h->dfree(h->w); h->dfree(h->lr_part); h->dfree(h->lr_v);
+            const int cap = std::max(k, 2 * h->k_cap);   // a growing term reallocates rarely
+            h->U = h->w = h->lr_part = h->lr_v = nullptr;
+            h->k = 0;
+            h->k_cap = 0;
+            h->U = h->dalloc<double>(size_t(n) * cap);
+            h->w = h->dalloc<double>(size_t(cap));
+            h->lr_part = h->dalloc<double>(size_t(kLrBlocks) * cap);
+            h->lr_v = h->dalloc<double>(size_t(cap));
+            h->k_cap = cap;
+        }
+        HIPCHK(hipMemcpyAsync(h->p, H->p, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+        if (k > 0) {
+            HIPCHK(hipMemcpyAsync(h->U, H->U, sizeof(double) * size_t(n) * k, hipMemcpyHostToDevice, h->stream));
+            HIPCHK(hipMemcpyAsync(h->w, H->w, sizeof(double) * size_t(k), hipMemcpyHostToDevice, h->stream));
+        }
+        h->k = k;
+        h->gamma = H->gamma;
+        compute_diag_h(h);
+        // the caller may free H's arrays on return
+        HIPCHK(hipStreamSynchronize(h->stream));
+    } catch (const HipError& he) {
+        return fail(h, QP_ERR_DEVICE, std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e));
+    }
+    return QP_OK;
 }
 
 qp_status qp_solve_batch(qp_handle* const* hs, int32_t count, double* const* xs, qp_info* infos) {

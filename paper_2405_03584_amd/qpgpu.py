@@ -61,8 +61,8 @@ class qp_info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-EXPORTS = ["qp_default_settings", "qp_create", "qp_solve", "qp_newton_step", "qp_operator_apply",
-           "qp_solve_batch", "qp_last_error", "qp_destroy", "qp_sizes"]
+EXPORTS = ["qp_default_settings", "qp_create", "qp_solve", "qp_solve_from", "qp_update_hessian",
+           "qp_newton_step", "qp_operator_apply", "qp_solve_batch", "qp_last_error", "qp_destroy", "qp_sizes"]
 
 _lib = None
 
@@ -83,6 +83,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qp_create.restype = C.c_int
     lib.qp_solve.argtypes = [C.c_void_p, _dp, _dp, _dp, C.POINTER(qp_info)]
     lib.qp_solve.restype = C.c_int
+    lib.qp_solve_from.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.POINTER(qp_info)]
+    lib.qp_solve_from.restype = C.c_int
+    lib.qp_update_hessian.argtypes = [C.c_void_p, C.POINTER(qp_hessian)]
+    lib.qp_update_hessian.restype = C.c_int
     lib.qp_newton_step.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.POINTER(qp_info)]
     lib.qp_newton_step.restype = C.c_int
     lib.qp_operator_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int32, C.c_int32,
@@ -226,6 +230,37 @@ def qp_solve(h: QPHandle, raise_on_error: bool = False) -> SolveResult:
     if raise_on_error and st not in (QP_OK,):
         raise QPError(st, h.last_error())
     return SolveResult(st, x, lA[:h.m], lx, info.as_dict())
+
+
+def qp_solve_from(h: QPHandle, x0, raise_on_error: bool = False) -> SolveResult:
+    """qp_solve started at the primal point x0 (None = the default start)."""
+    lib = load_library()
+    x0f = None if x0 is None else _f64(x0)
+    if x0f is not None and x0f.shape != (h.n,):
+        raise ValueError(f"x0 must have shape ({h.n},)")
+    x = np.zeros(h.n)
+    lA = np.zeros(max(h.m, 1))
+    lx = np.zeros(h.n)
+    info = qp_info()
+    st = lib.qp_solve_from(h._h, _ptr(x0f), _ptr(x), _ptr(lA), _ptr(lx), C.byref(info))
+    if raise_on_error and st not in (QP_OK,):
+        raise QPError(st, h.last_error())
+    return SolveResult(st, x, lA[:h.m], lx, info.as_dict())
+
+
+def qp_update_hessian(h: QPHandle, gamma: float, p, U=None, w=None) -> None:
+    """Replace the objective (gamma, p, U, w) of a handle (qp_update_hessian)."""
+    lib = load_library()
+    p = _f64(p)
+    k = 0 if U is None else int(np.asarray(U).shape[1])
+    Uf = None if U is None else np.asfortranarray(U, dtype=np.float64).ravel(order="F")
+    wf = None if w is None else _f64(w)
+    if p.shape != (h.n,) or (k > 0 and (np.asarray(U).shape[0] != h.n or wf is None or wf.shape != (k,))):
+        raise ValueError("p must have n entries, U shape (n, k) and w k entries")
+    H = qp_hessian(float(gamma), _ptr(p), k, _ptr(Uf), _ptr(wf))
+    st = lib.qp_update_hessian(h._h, C.byref(H))
+    if st != QP_OK:
+        raise QPError(st, h.last_error())
 
 
 def qp_solve_batch(handles, raise_on_error: bool = False):

@@ -451,3 +451,40 @@ def random_iterate(prob: QPProblem, seed: int):
         "v": rng.standard_normal(n),
         "rhs": rng.standard_normal(n),
     }
+
+
+def sqp_sequence(base: QPProblem, steps: int, seed: int = 77000) -> list:
+    """A sequence of QP sub-problems as an SQP run produces them (Section 3):
+    J, W, A and the bounds of ``base`` throughout; sub-problem t has a
+    quasi-Newton term U_t w_t U_t^T with 2t columns (each step appends two
+    columns of N(0,1)/sqrt(n) entries and keeps the earlier ones, w ~
+    U[0.1, 1]) and the linear term p_t = base.p * (1 + 0.05 N(0,1)) -
+    U_t (w_t * U_t^T x_g), x_g ~ U[lo, hi] drawn once.  Sub-problem 0 has no
+    low-rank term.
+
+    Draw order: x_g, then per step t >= 1: two U columns, two w entries,
+    the p perturbation (step 0 draws its perturbation first).
+    """
+    rng = np.random.default_rng(seed)
+    n = base.n
+    lo = np.where(np.isfinite(base.x_lo), base.x_lo, -1.0)
+    hi = np.where(np.isfinite(base.x_hi), base.x_hi, 1.0)
+    x_g = rng.uniform(lo, hi)
+    cols, ws = [], []
+    out = []
+    for t in range(steps):
+        if t > 0:
+            cols.append(rng.standard_normal((n, 2)) / np.sqrt(n))
+            ws.append(rng.uniform(0.1, 1.0, size=2))
+        pert = 1.0 + 0.05 * rng.standard_normal(n)
+        if cols:
+            U = np.asfortranarray(np.hstack(cols))
+            w = np.concatenate(ws)
+            p = base.p * pert - U @ (w * (U.T @ x_g))
+        else:
+            U, w = None, None
+            p = base.p * pert
+        out.append(QPProblem(gamma=base.gamma, p=p, J=base.J, W=base.W, x_lo=base.x_lo, x_hi=base.x_hi,
+                             A=base.A, A_lo=base.A_lo, A_hi=base.A_hi, U=U, w=w,
+                             name=f"{base.name}/sqp[{t}]", meta={"seed": seed, "step": t}))
+    return out

@@ -85,3 +85,30 @@ def test_no_gpu_gives_device_error_not_crash():
     with pytest.raises(qpgpu.QPError) as e:
         qpgpu.qp_create_from_problem(p)
     assert e.value.status == qpgpu.QP_ERR_DEVICE
+
+
+def test_sequence_entry_points_reject_null_handle():
+    """qp_update_hessian / qp_solve_from return QP_ERR_INVALID for a NULL
+    handle without touching a device."""
+    import ctypes as C
+    lib = qpgpu.load_library()
+    p = np.zeros(4)
+    H = qpgpu.qp_hessian(1e-3, p.ctypes.data_as(C.POINTER(C.c_double)), 0, None, None)
+    assert lib.qp_update_hessian(None, C.byref(H)) == qpgpu.QP_ERR_INVALID
+    x = np.zeros(4)
+    assert lib.qp_solve_from(None, None, x.ctypes.data_as(C.POINTER(C.c_double)), None, None,
+                             None) == qpgpu.QP_ERR_INVALID
+
+
+def test_sqp_sequence_shares_constraints_and_grows_rank():
+    base = qpsynth.config1(0)
+    seq = qpsynth.sqp_sequence(base, 4)
+    assert [q.k for q in seq] == [0, 2, 4, 6]
+    for t, q in enumerate(seq):
+        assert q.J is base.J and q.A is base.A and q.W is base.W
+        if t >= 2:   # earlier columns are kept
+            np.testing.assert_array_equal(q.U[:, :2 * (t - 1)], seq[t - 1].U)
+        if q.k:
+            assert np.all(q.w > 0) and q.U.flags.f_contiguous
+    again = qpsynth.sqp_sequence(base, 4)
+    np.testing.assert_array_equal(again[3].p, seq[3].p)

@@ -1,0 +1,115 @@
+"""GPU parity for sequences of QPs (SQP sub-problems, Section 3): a handle
+whose objective is replaced by qp_update_hessian, solved cold (qp_solve) and
+warm (qp_solve_from the previous minimiser), against the FP64 oracle and
+against a handle created afresh for the same QP."""
+import numpy as np
+import pytest
+
+import oracle
+import qpsynth
+from paper_2405_03584_amd import qpgpu
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 4
+
+
+def _bases():
+    # ragged_lines is left out: 55 of its variables have no dose (curvature
+    # gamma = 1e-3 only) and p = 0; the sequence's perturbed p moves them off
+    # their bounds to where the objective is flat, and there x is fixed only
+    # to about tolerance * |p| / gamma (1e-4), not to the 1e-6 checked here.
+    return {"cfg1": lambda: qpsynth.config1(2),
+            "band": lambda: qpsynth.config2(scale=0.02)}
+
+
+def _check(prob, res, ref):
+    assert res.status == qpgpu.QP_OK, (qpgpu.STATUS_NAMES[res.status], res.info)
+    xs = 1 + np.abs(ref.x).max()
+    dx = np.abs(res.x - ref.x).max()
+    assert dx <= 1e-6 * xs, dx
+    m_tot = sum(len(v) for v in ref.lam.values())
+    gap = 2.0 * m_tot * 1e-10 * ref.zeta
+    dobj = abs(res.info["objective"] - ref.objective)
+    assert dobj <= 1e-8 * (1 + abs(ref.objective)) + gap, dobj
+    cert = oracle.kkt_certificate(prob, res.x, res.lam_x, res.lam_A if prob.m else None)
+    assert cert.worst() <= 1e-9, cert
+
+
+def _update(h, q):
+    qpgpu.qp_update_hessian(h, q.gamma, q.p, q.U, q.w)
+
+
+@pytest.mark.parametrize("which,prec", [("cfg1", "fp64"), ("band", "fp64"), ("band", "bf16")])
+def test_updated_handle_equals_fresh_handle(which, prec):
+    """Each sub-problem solved on one updated handle gives the bits a handle
+    created for that sub-problem gives, and the oracle's minimiser."""
+    seq = qpsynth.sqp_sequence(_bases()[which](), STEPS)
+    s = qpgpu.qp_default_settings(precision=prec)
+    print(f"sequence {seq[0].name} {prec}", flush=True)
+    h = qpgpu.qp_create_from_problem(seq[0], settings=s)
+    for t, q in enumerate(seq):
+        if t > 0:
+            _update(h, q)
+        res = qpgpu.qp_solve(h)
+        fresh = qpgpu.qp_create_from_problem(q, settings=s)
+        ref_res = qpgpu.qp_solve(fresh)
+        fresh.close()
+        print(f"  step {t} k={q.k} ipm={res.info['ipm_iters']} pcg={res.info['pcg_iters']}", flush=True)
+        assert np.array_equal(res.x, ref_res.x), t
+        assert res.info["ipm_iters"] == ref_res.info["ipm_iters"], t
+        _check(q, res, oracle.solve(q))
+
+
+@pytest.mark.parametrize("which", ["cfg1", "band"])
+def test_warm_start_sequence(which):
+    """qp_solve_from the previous minimiser reaches the oracle's minimiser of
+    every sub-problem."""
+    seq = qpsynth.sqp_sequence(_bases()[which](), STEPS)
+    print(f"warm sequence {seq[0].name}", flush=True)
+    h = qpgpu.qp_create_from_problem(seq[0])
+    x_prev = None
+    for t, q in enumerate(seq):
+        if t > 0:
+            _update(h, q)
+        cold = qpgpu.qp_solve(h)
+        warm = qpgpu.qp_solve_from(h, x_prev)
+        print(f"  step {t} ipm cold {cold.info['ipm_iters']} warm {warm.info['ipm_iters']} "
+              f"pcg cold {cold.info['pcg_iters']} warm {warm.info['pcg_iters']}", flush=True)
+        ref = oracle.solve(q)
+        _check(q, cold, ref)
+        _check(q, warm, ref)
+        x_prev = warm.x
+
+
+def test_solve_from_none_is_solve():
+    prob = qpsynth.config1(3)
+    h = qpgpu.qp_create_from_problem(prob)
+    a = qpgpu.qp_solve(h)
+    b = qpgpu.qp_solve_from(h, None)
+    assert np.array_equal(a.x, b.x)
+
+
+def test_update_hessian_shrinks_and_rejects():
+    """k back to 0 after growth; an invalid objective leaves the handle as it was."""
+    seq = qpsynth.sqp_sequence(qpsynth.config1(4), 3)
+    h = qpgpu.qp_create_from_problem(seq[2])           # k = 4
+    _update(h, seq[0])                                 # k = 0
+    res = qpgpu.qp_solve(h)
+    _check(seq[0], res, oracle.solve(seq[0]))
+    _update(h, seq[1])                                 # k = 2, within capacity
+    before = qpgpu.qp_solve(h)
+    bad_w = seq[2].w.copy()
+    bad_w[0] = -1.0
+    with pytest.raises(qpgpu.QPError) as e:
+        qpgpu.qp_update_hessian(h, seq[2].gamma, seq[2].p, seq[2].U, bad_w)
+    assert e.value.status == qpgpu.QP_ERR_INVALID
+    with pytest.raises(qpgpu.QPError):
+        qpgpu.qp_update_hessian(h, -1.0, seq[2].p)
+    after = qpgpu.qp_solve(h)
+    assert np.array_equal(before.x, after.x)
+    _check(seq[1], after, oracle.solve(seq[1]))
+    x0 = np.zeros(prob_n := seq[1].n)
+    x0[prob_n // 2] = np.nan
+    with pytest.raises(qpgpu.QPError):
+        qpgpu.qp_solve_from(h, x0, raise_on_error=True)
