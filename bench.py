@@ -191,6 +191,59 @@ def batch_bench(args):
                       "pcg_iters_total": sum(f["pcg_iters"] for f in all_infos)}), flush=True)
 
 
+def sqp_bench(args):
+    """A sequence of `seq_len` SQP sub-problems on the n = 20,000 banded-dose
+    QP (rank-2 growth of the quasi-Newton term per step): one handle, per
+    step qp_update_hessian + qp_solve (or qp_solve_from the previous
+    minimiser with --warm 1).  For comparison, one sub-problem through
+    qp_create + qp_solve, the cost without a resident handle."""
+    import qpsynth
+    from paper_2405_03584_amd import qpgpu
+    base = qpsynth.config2(scale=args.scale)
+    seq = qpsynth.sqp_sequence(base, args.seq_len + args.warmup)
+    st = qpgpu.qp_default_settings(precision=args.precision)
+    h = qpgpu.qp_create_from_problem(seq[0], settings=st)
+    x_prev = None
+
+    def step(q, first):
+        nonlocal x_prev
+        if not first:
+            qpgpu.qp_update_hessian(h, q.gamma, q.p, q.U, q.w)
+        r = qpgpu.qp_solve_from(h, x_prev) if args.warm else qpgpu.qp_solve(h)
+        x_prev = r.x
+        return r
+
+    for i in range(args.warmup):
+        r = step(seq[i], i == 0)
+        print(f"[bench] warmup {i}: status={r.status} ipm={r.info['ipm_iters']}", file=sys.stderr, flush=True)
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.seq_len):
+        r = step(seq[i], i == 0)
+        infos.append(r.info)
+        print(f"[bench] sub-problem {i} k={seq[i].k}: status={r.status} ipm={r.info['ipm_iters']} "
+              f"pcg={r.info['pcg_iters']}", file=sys.stderr, flush=True)
+    el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    h2 = qpgpu.qp_create_from_problem(seq[-1], settings=st)
+    qpgpu.qp_solve(h2)
+    fresh = time.perf_counter() - t1
+    h2.close()
+    ok = all(f["status"] == qpgpu.QP_OK for f in infos)
+    print(json.dumps({"metric": METRIC, "value": args.seq_len / el, "unit": "QP/s", "n_gpus": 1,
+                      "steps": args.seq_len, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.seq_len,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": args.precision, "data": "synthetic",
+                      "config": {"workload": f"SQP sequence of {args.seq_len} sub-problems on the banded-dose "
+                                             f"QP n={base.n} (quasi-Newton rank +2 per step, "
+                                             f"{'warm' if args.warm else 'cold'} start)",
+                                 "precision": args.precision},
+                      "status_ok": ok,
+                      "create_plus_solve_ms": 1e3 * fresh,
+                      "ipm_iters": [f["ipm_iters"] for f in infos],
+                      "pcg_iters": [f["pcg_iters"] for f in infos]}), flush=True)
+
+
 def stream_ceiling():
     """Measured streaming-read ceiling in GB/s, from `--mode stream` run in a
     child process (torch brings its own HIP runtime, which must not share a
@@ -256,11 +309,14 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
                     help="1: PCG iterations replayed as captured HIP graphs (the production setting); "
                          "0: direct launches (for kernel-trace and counter runs)")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config5", "batch"],
+    ap.add_argument("--workload", default="config2", choices=["config2", "config5", "batch", "sqp"],
                     help="config2: banded-dose QP n=20,000 (default, the benchmark line); config5: "
                          "n=60,000, BF16-valued J with 200M nnz and a rank-20 term; batch: the 64 "
                          "uneven QPs (n in [2000, 20000]) solved together by qp_solve_batch")
     ap.add_argument("--count", type=int, default=64, help="batch size for --workload batch")
+    ap.add_argument("--seq-len", type=int, default=6, help="sub-problems timed for --workload sqp")
+    ap.add_argument("--warm", type=int, default=0, choices=[0, 1],
+                    help="--workload sqp: start each solve at the previous minimiser")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (single-GPU build)",
@@ -276,6 +332,8 @@ def main():
         return stream_read(args)
     if args.workload == "batch":
         return batch_bench(args)
+    if args.workload == "sqp":
+        return sqp_bench(args)
     ceiling = stream_ceiling() if args.mode == "solve" else None   # before this process touches the GPU
     t0 = time.perf_counter()
     prob = qpsynth.config5(scale=args.scale) if args.workload == "config5" else qpsynth.config2(scale=args.scale)
