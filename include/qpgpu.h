@@ -187,7 +187,9 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
  * max(k, 2 * capacity) when k exceeds it).  Waits for the handle's queued
  * work first; H's arrays are copied before return.  Errors: QP_ERR_INVALID
  * (as qp_create's checks of H: gamma < 0, w < 0, non-finite entries, NULL
- * arrays; the handle is unchanged), QP_ERR_DEVICE. */
+ * arrays; the handle is unchanged), QP_ERR_NOMEM (a larger U did not fit),
+ * QP_ERR_DEVICE; after these two the handle's objective is unspecified until
+ * a later call succeeds. */
 qp_status qp_update_hessian(qp_handle* h, const qp_hessian* H);
 
 /* qp_newton_step: one PCG solve of (H + diag(sigma_x) + A^T diag(sigma_A) A) dx = rhs

@@ -1497,7 +1497,9 @@ qp_status qp_update_hessian(qp_handle* h, const qp_hessian* H) {
         // the caller may free H's arrays on return
         HIPCHK(hipStreamSynchronize(h->stream));
     } catch (const HipError& he) {
-        return fail(h, QP_ERR_DEVICE, std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e));
+        // the objective is left unspecified (k = 0 if the larger U could not be allocated)
+        return fail(h, he.e == hipErrorOutOfMemory ? QP_ERR_NOMEM : QP_ERR_DEVICE,
+                    std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e));
     }
     return QP_OK;
 }
