@@ -61,6 +61,7 @@ struct qp_handle {
     int64_t nnzJ = 0, nnzA = 0;
     double gamma = 0.0, cscale = 1.0, mtot = 0.0;
     int k_cap = 0;              // columns U, w, lr_part, lr_v have room for
+    int wb_attempt_cap = 0;     // > 0: iteration cap of constraint-block-preconditioned solves
     double* x0d = nullptr;      // caller's start point (qp_solve_from), allocated on first use
     int GJ = 16, GJt = 64;   // lanes per row of J and of J^T (and A^T)
 
@@ -180,6 +181,9 @@ struct qp_handle {
 namespace {
 
 constexpr int kLrBlocks = 256;   // blocks of the U^T p partial pass
+// iteration cap of a constraint-block-preconditioned solve inside qp_solve
+// (its solves take tens of iterations when the preconditioner is sound)
+constexpr int kPrecAttemptIters = 2000;
 constexpr int kGraphIters = 4;   // PCG iterations per captured graph (and per trailing chunk)
 
 // v = w .* (U^T p) for the low-rank part of H (no-op when k = 0); p is x, or
@@ -599,9 +603,11 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     hipLaunchKernelGGL(k_pcg_init0, dim3(ge), dim3(kBlock), 0, h->stream, ia);
     HIPCHK(hipGetLastError());
     const int n_rz = wb ? apply_precond(h, dh, sigA) : ge;
+    const int cap = (wb && h->wb_attempt_cap > 0) ? std::min(h->set.pcg_max_iter, h->wb_attempt_cap)
+                                                  : h->set.pcg_max_iter;
     hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
-                       (const double*)h->part_rr, ge, refine ? 2 : 1, rel_tol, h->set.pcg_tol,
-                       h->set.pcg_max_iter, h->psc, h->fl, az);
+                       (const double*)h->part_rr, ge, refine ? 2 : 1, rel_tol, h->set.pcg_tol, cap,
+                       h->psc, h->fl, az);
     HIPCHK(hipGetLastError());
 
     if (refine) {
@@ -1377,6 +1383,19 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
             pcg_timed[slot] = false;
         };
         Flags f{};
+        // The constraint-block preconditioner subtracts from D^-1 a Woodbury
+        // correction that nearly cancels it in the row space of the active
+        // rows of A; late in the IPM (Sigma_A -> infinity) its rounding can
+        // leave a preconditioner too far from K for PCG to converge.  Its
+        // solves therefore get a short iteration cap; a solve that hits it
+        // (or breaks down) is repeated with the Jacobi diagonal, which then
+        // serves the rest of this QP.
+        struct CapGuard {
+            qp_handle* h;
+            ~CapGuard() { h->wb_attempt_cap = 0; }
+        } cap_guard{h};
+        h->wb_attempt_cap = kPrecAttemptIters;
+        bool jacobi_only = false;
         for (int it = 0; it < h->set.max_ipm_iter; ++it) {
             const int ps = it & 1;
             harvest_pcg_ms(ps);
@@ -1384,6 +1403,17 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
             int nsolves = 0;
             f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
                                  wbp ? h->Dw : nullptr, hs, true, &ta, &nsolves);
+            if (!f.ipm_done && wbp && (f.pcg_capped || f.pcg_breakdown)) {
+                pcg_total += f.pcg_iters;
+                pcg_solves += nsolves;
+                jacobi_only = true;
+                wbp = false;
+                if (h->set.log_level > 0)
+                    std::fprintf(stderr, "[qpgpu] constraint-block PCG stopped after %d iterations: Jacobi from here\n",
+                                 f.pcg_iters);
+                f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr,
+                                     v.d, nullptr, hs, true, &ta, &nsolves);
+            }
             HIPCHK(hipEventRecord(h->ev_p1[ps], h->stream));
             if (f.ipm_done) break;
             pcg_timed[ps] = true;
@@ -1413,7 +1443,7 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
                                (const double*)h->part2, nbA + nbx, h->isc, (const Flags*)h->fl);
             HIPCHK(hipGetLastError());
             residuals(1);
-            wbp = (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop);
+            wbp = !jacobi_only && (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop);
         }
         // outputs
         HIPCHK(hipEventRecord(h->ev_t1, h->stream));
