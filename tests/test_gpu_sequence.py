@@ -113,3 +113,21 @@ def test_update_hessian_shrinks_and_rejects():
     x0[prob_n // 2] = np.nan
     with pytest.raises(qpgpu.QPError):
         qpgpu.qp_solve_from(h, x0, raise_on_error=True)
+
+
+def test_stalled_constraint_block_solve_falls_back_to_jacobi():
+    """Second sub-problem of the ragged-lines sequence: late in the IPM the
+    constraint-block preconditioner stops converging (its Woodbury
+    correction cancels D^-1 to rounding); the capped solve is repeated with
+    the Jacobi diagonal.  Without the fallback this QP took 38 IPM and
+    244,174 PCG iterations."""
+    q = qpsynth.sqp_sequence(qpsynth.ragged_lines(), 2)[1]
+    h = qpgpu.qp_create_from_problem(q)
+    res = qpgpu.qp_solve(h)
+    print(f"ipm {res.info['ipm_iters']} pcg {res.info['pcg_iters']}", flush=True)
+    assert res.status == qpgpu.QP_OK
+    assert res.info["pcg_iters"] < 20000
+    ref = oracle.solve(q)
+    assert np.abs(res.x - ref.x).max() <= 1e-5 * (1 + np.abs(ref.x).max())
+    cert = oracle.kkt_certificate(q, res.x, res.lam_x, res.lam_A)
+    assert cert.worst() <= 1e-9, cert
