@@ -108,8 +108,12 @@ typedef struct {
     int32_t log_level;        /* 0: quiet; 1: one line per IPM iteration on stderr */
     int32_t precond;          /* 0: Jacobi, diag(K) (Section 4.1.2); 1 (default): Jacobi on the H
                                  part, diag(H + Sigma_x), with the constraint block A^T Sigma_A A
-                                 applied exactly through a dense m x m Cholesky (Woodbury identity);
-                                 falls back to 0 when m = 0 or m > 8192 */
+                                 applied exactly (Woodbury identity) for the rows with
+                                 Sigma_i sum_j A_ij^2 / D_j >= 1 through the dense inverse of their
+                                 Schur complement, the other rows folded into the diagonal;
+                                 falls back to 0 when m = 0 or m > 8192.  A solve with it that
+                                 reaches 2000 PCG iterations or breaks down is repeated with 0
+                                 (qp_solve then keeps 0 for the rest of the QP) */
     int32_t spmv_format;      /* 0 (default): line format for J when its rows come in lines of 64
                                  sharing one column list (the 64-voxel bands), else CSR; 1: CSR */
     double  refine_tol;       /* relative residual target of each low-precision PCG solve when

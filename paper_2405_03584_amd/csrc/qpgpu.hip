@@ -184,6 +184,19 @@ constexpr int kLrBlocks = 256;   // blocks of the U^T p partial pass
 // iteration cap of a constraint-block-preconditioned solve inside qp_solve
 // (its solves take tens of iterations when the preconditioner is sound)
 constexpr int kPrecAttemptIters = 2000;
+
+// The constraint-block preconditioner subtracts from D^-1 a Woodbury
+// correction that nearly cancels it in the row space of the active rows of
+// A; late in the IPM (Sigma_A -> infinity) its rounding can leave a
+// preconditioner too far from K for PCG to converge.  While an entry point
+// holds this guard its constraint-block solves stop at kPrecAttemptIters;
+// the caller repeats a solve that hits the cap (or breaks down) with the
+// Jacobi diagonal.
+struct PrecAttemptCap {
+    qp_handle* h;
+    explicit PrecAttemptCap(qp_handle* hh) : h(hh) { h->wb_attempt_cap = kPrecAttemptIters; }
+    ~PrecAttemptCap() { h->wb_attempt_cap = 0; }
+};
 constexpr int kGraphIters = 4;   // PCG iterations per captured graph (and per trailing chunk)
 
 // v = w .* (U^T p) for the low-rank part of H (no-op when k = 0); p is x, or
@@ -1224,8 +1237,18 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         HIPCHK(hipEventRecord(h->ev_t0, h->stream));
         const bool wbp = (m > 0) && build_precond(h, dh, sigA, nullptr);
         int nsolves = 0;
+        PrecAttemptCap cap_guard(h);
         Flags f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d,
                                    wbp ? h->Dw : nullptr, 1.0, false, &ta, &nsolves);
+        if (wbp && (f.pcg_capped || f.pcg_breakdown)) {
+            // stalled constraint-block solve: again with the Jacobi diagonal
+            int more = 0;
+            const int spent = f.pcg_iters;
+            f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d, nullptr, 1.0,
+                                 false, &ta, &more);
+            f.pcg_iters += spent;
+            nsolves += more;
+        }
         HIPCHK(hipEventRecord(h->ev_t1, h->stream));
         HIPCHK(hipMemcpyAsync(dx, h->px, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
         PcgScal ps{};
@@ -1383,18 +1406,9 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
             pcg_timed[slot] = false;
         };
         Flags f{};
-        // The constraint-block preconditioner subtracts from D^-1 a Woodbury
-        // correction that nearly cancels it in the row space of the active
-        // rows of A; late in the IPM (Sigma_A -> infinity) its rounding can
-        // leave a preconditioner too far from K for PCG to converge.  Its
-        // solves therefore get a short iteration cap; a solve that hits it
-        // (or breaks down) is repeated with the Jacobi diagonal, which then
-        // serves the rest of this QP.
-        struct CapGuard {
-            qp_handle* h;
-            ~CapGuard() { h->wb_attempt_cap = 0; }
-        } cap_guard{h};
-        h->wb_attempt_cap = kPrecAttemptIters;
+        // a stalled constraint-block solve is repeated with the Jacobi
+        // diagonal, which then serves the rest of this QP
+        PrecAttemptCap cap_guard(h);
         bool jacobi_only = false;
         for (int it = 0; it < h->set.max_ipm_iter; ++it) {
             const int ps = it & 1;
