@@ -196,6 +196,11 @@ struct PrecAttemptCap {
     qp_handle* h;
     explicit PrecAttemptCap(qp_handle* hh) : h(hh) { h->wb_attempt_cap = kPrecAttemptIters; }
     ~PrecAttemptCap() { h->wb_attempt_cap = 0; }
+    // a constraint-block solve ended in a way that calls for the Jacobi repeat
+    // (a cap of pcg_max_iter itself, when not above the attempt cap, is final)
+    bool stalled(const Flags& f) const {
+        return f.pcg_breakdown || (f.pcg_capped && h->set.pcg_max_iter > kPrecAttemptIters);
+    }
 };
 constexpr int kGraphIters = 4;   // PCG iterations per captured graph (and per trailing chunk)
 
@@ -1240,7 +1245,7 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         PrecAttemptCap cap_guard(h);
         Flags f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d,
                                    wbp ? h->Dw : nullptr, 1.0, false, &ta, &nsolves);
-        if (wbp && (f.pcg_capped || f.pcg_breakdown)) {
+        if (wbp && cap_guard.stalled(f)) {
             // stalled constraint-block solve: again with the Jacobi diagonal
             int more = 0;
             const int spent = f.pcg_iters;
@@ -1417,7 +1422,7 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
             int nsolves = 0;
             f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
                                  wbp ? h->Dw : nullptr, hs, true, &ta, &nsolves);
-            if (!f.ipm_done && wbp && (f.pcg_capped || f.pcg_breakdown)) {
+            if (!f.ipm_done && wbp && cap_guard.stalled(f)) {
                 pcg_total += f.pcg_iters;
                 pcg_solves += nsolves;
                 jacobi_only = true;
