@@ -131,3 +131,19 @@ def test_stalled_constraint_block_solve_falls_back_to_jacobi():
     assert np.abs(res.x - ref.x).max() <= 1e-5 * (1 + np.abs(ref.x).max())
     cert = oracle.kkt_certificate(q, res.x, res.lam_x, res.lam_A)
     assert cert.worst() <= 1e-9, cert
+
+
+def test_batch_of_updated_handles():
+    """qp_solve_batch over handles whose objectives were replaced: each QP's
+    bits equal its own qp_solve's, and its minimiser is the oracle's."""
+    seqs = [qpsynth.sqp_sequence(qpsynth.config1(i), 3, seed=77000 + i) for i in (0, 1, 3)]
+    hs = [qpgpu.qp_create_from_problem(s[0]) for s in seqs]
+    for h, s in zip(hs, seqs):
+        _update(h, s[2])
+    st, xs, infos = qpgpu.qp_solve_batch(hs)
+    assert st == qpgpu.QP_OK, [f["status"] for f in infos]
+    for h, s, x in zip(hs, seqs, xs):
+        single = qpgpu.qp_solve(h)
+        assert np.array_equal(x, single.x)
+        ref = oracle.solve(s[2])
+        assert np.abs(x - ref.x).max() <= 1e-6 * (1 + np.abs(ref.x).max())
