@@ -61,13 +61,13 @@ def test_updated_handle_equals_fresh_handle(which, prec):
         _check(q, res, oracle.solve(q))
 
 
-@pytest.mark.parametrize("which", ["cfg1", "band"])
-def test_warm_start_sequence(which):
+@pytest.mark.parametrize("which,prec", [("cfg1", "fp64"), ("band", "fp64"), ("band", "bf16")])
+def test_warm_start_sequence(which, prec):
     """qp_solve_from the previous minimiser reaches the oracle's minimiser of
     every sub-problem."""
     seq = qpsynth.sqp_sequence(_bases()[which](), STEPS)
-    print(f"warm sequence {seq[0].name}", flush=True)
-    h = qpgpu.qp_create_from_problem(seq[0])
+    print(f"warm sequence {seq[0].name} {prec}", flush=True)
+    h = qpgpu.qp_create_from_problem(seq[0], settings=qpgpu.qp_default_settings(precision=prec))
     x_prev = None
     for t, q in enumerate(seq):
         if t > 0:
