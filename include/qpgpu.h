@@ -173,7 +173,7 @@ qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_inf
 
 /* qp_solve_from: qp_solve started at the caller's primal point x0 (n finite
  * doubles, host memory; NULL = the default start).  Meant for a sequence of
- * related QPs (Section 3: SQP sub-problems), x0 being the previous QP's
+ * related QPs (SQP sub-problems, Section 3.2), x0 being the previous QP's
  * minimiser.  The paper gives no warm-start rule: x0 replaces the default x
  * of the start point and the slacks (max(x0 - lo, 1), max(hi - x0, 1) and
  * the same for A x0), multipliers (1) and mu0 follow the default rule, so x0
@@ -184,9 +184,9 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
 
 /* qp_update_hessian: replace the objective of a handle (gamma, p, U, w, k;
  * see qp_hessian) and keep J, W, A and the bounds resident.  In SQP
- * (Section 3) the quasi-Newton term U w U^T gains columns from one QP
- * sub-problem to the next (Section 4.1.1); the J and A preparation of
- * qp_create is not repeated.  Recomputes the cached diag(H) and drops the
+ * (Section 3.2) the quasi-Newton term U w U^T of eq. (bfgs_hessian) gains
+ * two columns from one QP sub-problem to the next (Section 5.2); the J and A
+ * preparation of qp_create is not repeated.  Recomputes the cached diag(H) and drops the
  * handle's captured PCG graphs.  k may grow or shrink (storage grows to
  * max(k, 2 * capacity) when k exceeds it).  Waits for the handle's queued
  * work first; H's arrays are copied before return.  Errors: QP_ERR_INVALID

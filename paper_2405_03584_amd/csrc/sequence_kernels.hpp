@@ -1,10 +1,11 @@
 // Kernels for sequences of related QPs.
 //
-// In SQP (Section 3) consecutive QP sub-problems share J, A and the bounds and
-// differ in the objective: the quasi-Newton term U w U^T gains columns and p
-// changes (Section 4.1.1).  A handle keeps the constraint data resident; a new
-// objective only replaces gamma, p, U, w and the cached diag(H), and a solve may
-// start from the previous QP's minimiser.  The paper gives no warm-start rule:
+// In SQP (Section 3.2) consecutive QP sub-problems share J, A and the bounds
+// and differ in the objective: the quasi-Newton term U w U^T of
+// eq. (bfgs_hessian) (Section 4) gains two columns per SQP iteration
+// (Section 5.2) and p changes.  A handle keeps the constraint data resident; a
+// new objective only replaces gamma, p, U, w and the cached diag(H), and a
+// solve may start from the previous QP's minimiser.  The paper gives no warm-start rule:
 // here the given x0 replaces the default start point and every other part of
 // the start (slacks, multipliers, mu0) follows the default rule.
 #pragma once

@@ -454,7 +454,7 @@ def random_iterate(prob: QPProblem, seed: int):
 
 
 def sqp_sequence(base: QPProblem, steps: int, seed: int = 77000) -> list:
-    """A sequence of QP sub-problems as an SQP run produces them (Section 3):
+    """A sequence of QP sub-problems as an SQP run produces them (Section 3.2):
     J, W, A and the bounds of ``base`` throughout; sub-problem t has a
     quasi-Newton term U_t w_t U_t^T with 2t columns (each step appends two
     columns of N(0,1)/sqrt(n) entries and keeps the earlier ones, w ~

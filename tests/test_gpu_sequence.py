@@ -1,4 +1,4 @@
-"""GPU parity for sequences of QPs (SQP sub-problems, Section 3): a handle
+"""GPU parity for sequences of QPs (SQP sub-problems, Section 3.2): a handle
 whose objective is replaced by qp_update_hessian, solved cold (qp_solve) and
 warm (qp_solve_from the previous minimiser), against the FP64 oracle and
 against a handle created afresh for the same QP."""
