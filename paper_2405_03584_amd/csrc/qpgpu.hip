@@ -187,8 +187,9 @@ constexpr int kPrecAttemptIters = 2000;
 
 // The constraint-block preconditioner subtracts from D^-1 a Woodbury
 // correction that nearly cancels it in the row space of the active rows of
-// A; late in the IPM (Sigma_A -> infinity) its rounding can leave a
-// preconditioner too far from K for PCG to converge.  While an entry point
+// A; late in the IPM (Sigma_A -> infinity, cond(S) beyond about 1e8) its
+// rounding can make the computed preconditioner indefinite, and PCG then
+// cannot converge.  While an entry point
 // holds this guard its constraint-block solves stop at kPrecAttemptIters;
 // the caller repeats a solve that hits the cap (or breaks down) with the
 // Jacobi diagonal.
