@@ -1,16 +1,22 @@
-"""Benchmark: QP time-to-solution, PCG iterations/s and SpMV HBM GB/s vs peak.
+"""Benchmark: QP time-to-solution, PCG iterations/s and SpMV HBM GB/s vs peak,
+mixed precision vs FP64.
 
 One step = one whole QP solve (qp_solve: start point, residuals, every PCG
 direction, recovery, ratio test, update, barrier rule) of the banded-dose QP
 with n = 20,000 spots, J 400,000 x 20,000 (40M nnz), A 2,000 x 20,000 at 2%,
 bounds [0, 50], PCG tolerance 1e-8, with the library's default settings
 (captured PCG graphs).  Problem data are resident in HBM (created once by
-qp_create) before the timed region.  One more solve on a second handle with
-per-kernel HIP events gives the SpMV kernel durations of the roofline; a
-child process measures the streaming-read ceiling with torch.
+qp_create) before the timed region.  `value` is the FP64 (or --precision)
+rate; the same QP is then timed with BF16 and FP32 values of J
+(`by_precision`, `mixed_vs_fp64`).  One more solve per precision on a handle
+with per-kernel HIP events gives the operator kernels' durations for the
+roofline, the general CSR path's operator is timed on the same QP
+(`csr_operator`), a child process measures the streaming-read ceiling with
+torch, and the FP64 dense-Cholesky oracle solves the same QP on the host
+cores (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
-                    [--scale 1.0] [--no-cpu-baseline]
+                    [--scale 1.0] [--cpu-baseline full|sample|none] [--mixed 1] [--csr 1]
 
 Prints one JSON line.
 """
@@ -55,11 +61,12 @@ def spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes=8, fmt=0):
     return fwd, bwd
 
 
-def cpu_baseline(prob, ipm_iters):
-    """The FP64 dense-Cholesky oracle on a bounded sample of the same QP: the
-    dense Hessian formation plus one IPM iteration (condensed matrix,
-    Cholesky, recovery, update), extrapolated to a whole solve of `ipm_iters`
-    iterations."""
+def cpu_baseline(prob, mode="full", ipm_iters=None):
+    """The FP64 dense-Cholesky oracle on the host cores, on the same QP.
+    mode "full": the whole oracle solve (dense H formation, then every IPM
+    iteration to convergence), one progress line per iteration on stderr;
+    mode "sample": dense H formation plus one IPM iteration, extrapolated to
+    `ipm_iters` iterations."""
     import threadpoolctl
     import oracle
     from oracle import ipm_dense as O
@@ -69,28 +76,45 @@ def cpu_baseline(prob, ipm_iters):
         t0 = time.perf_counter()
         H = oracle.hessian_dense(prob)
         t1 = time.perf_counter()
-        zeta = O.objective_scale(prob, H)
-        H /= zeta
-        import copy
-        sp_ = copy.copy(prob)
-        sp_.p = prob.p / zeta
-        G = O.make_groups(sp_)
-        x, s, lam = O.initial_point(sp_, G)
-        mu = float(sum(s[g] @ lam[g] for g in O.GROUPS) / G.m_tot())
-        t2 = time.perf_counter()
-        Hx, rH, rg, rc = O.residuals(sp_, G, H, x, s, lam, mu)
-        dx, ds, dl = O.newton_direction(sp_, G, H, x, s, lam, mu, Hx, rg)
-        ax = O.max_step(s, ds, 0.995)
-        x = x + ax * dx
-        t3 = time.perf_counter()
-        used = threadpoolctl.threadpool_info()
+        print(f"[bench] oracle: dense H in {t1 - t0:.1f} s", file=sys.stderr, flush=True)
+        if mode == "full":
+            def report(it, mu, rn):
+                print(f"[bench] oracle IPM iteration {it}: mu {mu:.2e} rnorm {rn:.2e} "
+                      f"({time.perf_counter() - t1:.0f} s)", file=sys.stderr, flush=True)
+            res = oracle.solve(prob, H=H, progress=report)
+            t2 = time.perf_counter()
+            used = threadpoolctl.threadpool_info()
+            t_qp = t2 - t0
+            sample = (f"the whole FP64 dense-Cholesky oracle solve of the same n={prob.n} QP: dense H "
+                      f"formation ({t1 - t0:.1f} s) + {res.iters} IPM iterations ({t2 - t1:.1f} s)")
+            extra = {"oracle_ipm_iters": int(res.iters), "oracle_converged": bool(res.converged),
+                     "oracle_objective": res.objective}
+        else:
+            zeta = O.objective_scale(prob, H)
+            H /= zeta
+            import copy
+            sp_ = copy.copy(prob)
+            sp_.p = prob.p / zeta
+            G = O.make_groups(sp_)
+            x, s, lam = O.initial_point(sp_, G)
+            mu = float(sum(s[g] @ lam[g] for g in O.GROUPS) / G.m_tot())
+            t2 = time.perf_counter()
+            Hx, rH, rg, rc = O.residuals(sp_, G, H, x, s, lam, mu)
+            dx, ds, dl = O.newton_direction(sp_, G, H, x, s, lam, mu, Hx, rg)
+            ax = O.max_step(s, ds, 0.995)
+            x = x + ax * dx
+            t3 = time.perf_counter()
+            used = threadpoolctl.threadpool_info()
+            t_qp = (t1 - t0) + (t2 - t1) + ipm_iters * (t3 - t2)
+            sample = (f"dense H formation ({t1 - t0:.1f} s) + 1 IPM iteration ({t3 - t2:.1f} s) of the "
+                      f"FP64 dense-Cholesky oracle on the same n={prob.n} QP, extrapolated to "
+                      f"{ipm_iters} IPM iterations")
+            extra = {}
     nthreads = max([u.get("num_threads", 1) for u in used] + [1])
-    t_qp = (t1 - t0) + (t2 - t1) + ipm_iters * (t3 - t2)
-    return {"value": 1.0 / t_qp, "unit": "QP/s", "cores": int(nthreads), "kind": "oracle",
-            "sample": (f"dense H formation ({t1 - t0:.1f} s) + 1 IPM iteration ({t3 - t2:.1f} s) of the "
-                       f"FP64 dense-Cholesky oracle on the same n={prob.n} QP, extrapolated to "
-                       f"{ipm_iters} IPM iterations"),
-            "seconds_per_qp_extrapolated": t_qp}
+    out = {"value": 1.0 / t_qp, "unit": "QP/s", "cores": int(nthreads), "kind": "oracle", "sample": sample,
+           "seconds_per_qp": t_qp}
+    out.update(extra)
+    return out
 
 
 def kernel_source_hash():
@@ -299,8 +323,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--scale", type=float, default=1.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--log", type=int, default=1, help="per-IPM-iteration progress on stderr")
+    ap.add_argument("--cpu-baseline", default="full", choices=["full", "sample", "none"],
+                    help="full: the whole oracle solve on the host cores (about 2 minutes at n=20,000); "
+                         "sample: dense H + one IPM iteration, extrapolated; none")
+    ap.add_argument("--mixed", type=int, default=1, choices=[0, 1],
+                    help="1: also time the other two precisions on the same QP")
+    ap.add_argument("--csr", type=int, default=1, choices=[0, 1],
+                    help="1: also time the general CSR operator path on the same QP")
+    ap.add_argument("--log", type=int, default=0, help="per-IPM-iteration progress on stderr (untimed runs)")
     ap.add_argument("--mode", default="solve", choices=["solve", "operator", "copy", "stream"],
                     help="solve: whole QP solves (the benchmark); operator: repeated operator "
                          "products only (for counter runs); copy: a plain device copy of the "
@@ -343,76 +373,39 @@ def main():
     nnzJ, nnzA = int(prob.J.nnz), int(prob.A.nnz)
     print(f"[bench] generated n={n} nJ={nJ} nnzJ={nnzJ} m={m} nnzA={nnzA} in "
           f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    # the timed solves use the production settings (captured PCG graphs, no
-    # per-kernel events); one extra solve on a second handle with timing = 1
-    # gives the SpMV kernel durations for the roofline
-    settings = qpgpu.qp_default_settings(precision=args.precision, log_level=args.log, graphs=args.graphs)
-    t0 = time.perf_counter()
-    h = qpgpu.qp_create_from_problem(prob, settings=settings)
-    t_create = time.perf_counter() - t0
-    print(f"[bench] qp_create {t_create:.2f}s", file=sys.stderr, flush=True)
+    gold = None
+    gpath = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")
+    if args.workload == "config2" and args.scale == 1.0 and os.path.exists(gpath):
+        gold = json.load(open(gpath))
 
-    for i in range(args.warmup):
-        r = qpgpu.qp_solve(h)
-        print(f"[bench] warmup {i}: status={r.status} ipm={r.info['ipm_iters']} "
-              f"pcg={r.info['pcg_iters']} {r.info['t_solve_ms']:.1f} ms", file=sys.stderr, flush=True)
+    # The headline precision first, then the other two on the same QP (the
+    # metric compares mixed precision with FP64).  Timed solves use the
+    # production settings: captured PCG graphs, no per-kernel events, no log.
+    precs = [args.precision] + ([q for q in ("bf16", "fp32", "fp64") if q != args.precision]
+                                if args.mixed else [])
+    runs = {}
+    for prec in precs:
+        runs[prec] = time_solves(args, prob, prec, gold)
+    head = runs[args.precision]
 
-    infos = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        r = qpgpu.qp_solve(h)
-        infos.append(r.info)
-        print(f"[bench] step {i}: status={r.status} ipm={r.info['ipm_iters']} pcg={r.info['pcg_iters']} "
-              f"{r.info['t_solve_ms']:.1f} ms", file=sys.stderr, flush=True)
-    elapsed = time.perf_counter() - t0
-    x_last = r.x
-    status_ok = all(i["status"] == qpgpu.QP_OK for i in infos)
-
-    pcg_iters = sum(i["pcg_iters"] for i in infos)
-    pcg_ms = sum(i["t_pcg_ms"] for i in infos)
-    ht = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=args.precision,
-                                                                              timing=1))
-    rt = qpgpu.qp_solve(ht)
-    print(f"[bench] timing solve: status={rt.status} pcg={rt.info['pcg_iters']} {rt.info['t_solve_ms']:.1f} ms",
-          file=sys.stderr, flush=True)
-    tinfo = [rt.info]
-    fwd_ms = sum(i["t_spmv_fwd_ms"] for i in tinfo)
-    bwd_ms = sum(i["t_spmv_bwd_ms"] for i in tinfo)
-    nf = sum(i["n_spmv_fwd"] for i in tinfo)
-    nb = sum(i["n_spmv_bwd"] for i in tinfo)
-    vbytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
-    fmt = infos[-1]["spmv_format"]
-    bf, bb = spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes, fmt)
-    cf, cb = spmv_bytes(n, nJ, m, nnzJ, nnzA, vbytes, 0)
-    fwd_us = 1e3 * fwd_ms / max(nf, 1)
-    bwd_us = 1e3 * bwd_ms / max(nb, 1)
-    gbs_f = bf / (fwd_us * 1e-6) / 1e9
-    gbs_b = bb / (bwd_us * 1e-6) / 1e9
-    if fmt == 1:
-        names = ("k_line_pass (J p, W scaling and per-slot J^T contributions from one read of J; u from A z and A p)",
-                 "k_spot_pass (per-spot J^T sums, A^T u, epilogue and p.q partials)")
-    else:
-        names = ("k_op_fwd (J + A SpMV, fused W / Sigma_A scaling)",
-                 "k_op_bwd (J^T + A^T SpMV, fused epilogue and p.q partials)")
-    dom = (names[1], bb, bwd_us, gbs_b) if bwd_us >= fwd_us else (names[0], bf, fwd_us, gbs_f)
-
-    parity = None
-    gold = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")
-    if args.workload == "config2" and args.scale == 1.0 and os.path.exists(gold):
-        g = json.load(open(gold))
-        step = g["sample_index_step"]
-        xs = np.array(g["x_sample"])
-        parity = {"x_sample_max_abs_err_vs_oracle": float(np.abs(x_last[::step] - xs).max()),
-                  "objective_rel_err_vs_oracle": abs(infos[-1]["objective"] - g["objective"]) / abs(g["objective"])}
+    # Roofline: one more solve per precision on a handle with timing = 1 (HIP
+    # events around each operator kernel on the library's stream).
+    vbytes = {"fp64": 8, "fp32": 4, "bf16": 2}
+    kern = {}
+    for prec in precs:
+        kern[prec] = kernel_rates(prob, prec, vbytes[prec])
+    k0 = kern[args.precision]
+    dom = k0["dominant"]
+    csr = csr_operator_rates(prob, args.precision, vbytes[args.precision]) if args.csr else None
 
     out = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": head["value"],
         "unit": "QP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": head["ms_per_qp"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -423,25 +416,26 @@ def main():
                                f"bounds [0,50]; PCG tol 1e-8"
                                + (f"; rank-{prob.k} term; BF16-valued J" if prob.k else "") + ")",
                    "precision": args.precision, "scale": args.scale},
-        "time_to_solution_ms": 1e3 * elapsed / args.steps,
-        "ipm_iters": infos[-1]["ipm_iters"],
-        "pcg_iters_per_qp": pcg_iters / args.steps,
-        "pcg_iters_per_s": pcg_iters / (pcg_ms * 1e-3) if pcg_ms > 0 else None,
-        "status_ok": status_ok,
-        "spmv": {"format": ["csr", "line"][fmt], "fwd_us": fwd_us, "bwd_us": bwd_us, "fwd_GBs": gbs_f,
-                 "bwd_GBs": gbs_b, "fwd_bytes": bf, "bwd_bytes": bb, "timed_launches": nb,
-                 "csr_equivalent_fwd_GBs": cf / (fwd_us * 1e-6) / 1e9,
-                 "csr_equivalent_bwd_GBs": cb / (bwd_us * 1e-6) / 1e9},
-        "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": dom[3], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dom[3] / HBM_PEAK_GBS,
-                     "traffic": (counter_traffic(dom[0].split()[0], args.precision)
+        "time_to_solution_ms": head["ms_per_qp"],
+        "ipm_iters": head["ipm_iters"],
+        "pcg_iters_per_qp": head["pcg_iters_per_qp"],
+        "pcg_iters_per_s": head["pcg_iters_per_s"],
+        "status_ok": head["status_ok"],
+        "by_precision": {q: {**runs[q], "line_pass": kern[q]["line"], "spot_pass": kern[q]["spot"]}
+                         for q in precs},
+        "spmv": {"format": k0["format"], **k0["detail"]},
+        "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": dom["GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": dom["GBs"] / HBM_PEAK_GBS,
+                     "traffic": (counter_traffic(dom["name"].split()[0], args.precision)
                                  if args.scale == 1.0 and args.workload == "config2" else None),
-                     "bytes_per_launch": dom[1], "avg_launch_us": dom[2],
+                     "bytes_per_launch": dom["bytes"], "avg_launch_us": dom["us"],
                      "stream_read_ceiling_GBs": ceiling,
-                     "frac_of_stream_ceiling": dom[3] / ceiling if ceiling else None},
-        "create_s": t_create,
-        "parity": parity,
+                     "frac_of_stream_ceiling": dom["GBs"] / ceiling if ceiling else None},
+        "csr_operator": csr,
+        "create_s": head["create_s"],
     }
+    if args.mixed and "fp64" in runs:
+        out["mixed_vs_fp64"] = {q: runs["fp64"]["ms_per_qp"] / runs[q]["ms_per_qp"] for q in precs if q != "fp64"}
     # the paper's speedups are over a commercial CPU solver on its own clinical
     # QPs and machines: printed beside ours for context, not compared
     out["paper_context"] = {
@@ -450,14 +444,109 @@ def main():
         "paper_hardware": "paper's solver on an RTX 4080 GPU with a Ryzen 9 7900X host; RayStation 2024A "
                           "on an Intel i9-7940X",
         "precision": "FP64"}
-    if not args.no_cpu_baseline and args.workload == "config2":
-        print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
-        iters = infos[-1]["ipm_iters"]
-        if args.scale == 1.0 and os.path.exists(gold):
-            iters = json.load(open(gold))["ipm_iters"]
-        out["cpu_baseline"] = cpu_baseline(prob, iters)
+    if args.cpu_baseline != "none" and args.workload == "config2":
+        print(f"[bench] cpu baseline ({args.cpu_baseline} oracle)...", file=sys.stderr, flush=True)
+        iters = gold["ipm_iters"] if gold else head["ipm_iters"]
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_baseline, iters)
         out["speedup_over_cpu_oracle"] = out["value"] / out["cpu_baseline"]["value"]
     print(json.dumps(out), flush=True)
+
+
+def time_solves(args, prob, prec, gold):
+    """Whole solves of one QP at one precision: `warmup` untimed, `steps`
+    timed back to back (host clock around the calls, data resident in HBM)."""
+    from paper_2405_03584_amd import qpgpu
+    settings = qpgpu.qp_default_settings(precision=prec, log_level=args.log, graphs=args.graphs)
+    t0 = time.perf_counter()
+    h = qpgpu.qp_create_from_problem(prob, settings=settings)
+    t_create = time.perf_counter() - t0
+    print(f"[bench] {prec}: qp_create {t_create:.2f}s", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        r = qpgpu.qp_solve(h)
+        print(f"[bench] {prec} warmup {i}: status={r.status} ipm={r.info['ipm_iters']} "
+              f"pcg={r.info['pcg_iters']} {r.info['t_solve_ms']:.1f} ms", file=sys.stderr, flush=True)
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = qpgpu.qp_solve(h)
+        infos.append(r.info)
+    elapsed = time.perf_counter() - t0
+    h.close()
+    pcg = sum(i["pcg_iters"] for i in infos)
+    pcg_ms = sum(i["t_pcg_ms"] for i in infos)
+    out = {"value": args.steps / elapsed, "ms_per_qp": 1e3 * elapsed / args.steps,
+           "ipm_iters": infos[-1]["ipm_iters"], "pcg_iters_per_qp": pcg / args.steps,
+           "pcg_iters_per_s": pcg / (pcg_ms * 1e-3) if pcg_ms > 0 else None,
+           "status_ok": all(i["status"] == qpgpu.QP_OK for i in infos),
+           "prec_fallbacks": sum(i["prec_fallbacks"] for i in infos),
+           "certificate": max(infos[-1][k] for k in ("eps_d", "eps_p", "eps_c", "gap")),
+           "create_s": t_create}
+    if gold is not None:
+        out["parity"] = {"x_max_abs_err_vs_oracle": float(np.abs(r.x - np.array(gold["x"])).max()),
+                         "objective_rel_err_vs_oracle": abs(infos[-1]["objective"] - gold["objective"])
+                         / abs(gold["objective"])}
+    print(f"[bench] {prec}: {out['ms_per_qp']:.1f} ms per QP, ipm {out['ipm_iters']}, "
+          f"pcg {out['pcg_iters_per_qp']:.0f}", file=sys.stderr, flush=True)
+    return out
+
+
+def kernel_rates(prob, prec, vb):
+    """Per-launch duration of the operator kernels over a whole solve on a
+    handle with timing = 1 (direct launches, HIP events on the library's
+    stream; launches past a converged PCG solve excluded), and their
+    algorithmic GB/s."""
+    from paper_2405_03584_amd import qpgpu
+    n, m, nJ = prob.n, prob.m, prob.J.shape[0]
+    nnzJ, nnzA = int(prob.J.nnz), int(prob.A.nnz)
+    ht = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec, timing=1))
+    rt = qpgpu.qp_solve(ht)
+    ht.close()
+    i = rt.info
+    fmt = i["spmv_format"]
+    bf, bb = spmv_bytes(n, nJ, m, nnzJ, nnzA, vb, fmt)
+    cf, cb = spmv_bytes(n, nJ, m, nnzJ, nnzA, vb, 0)
+    fus = 1e3 * i["t_spmv_fwd_ms"] / max(i["n_spmv_fwd"], 1)
+    bus = 1e3 * i["t_spmv_bwd_ms"] / max(i["n_spmv_bwd"], 1)
+    if fmt == 1:
+        names = ("k_line_pass (J p, W scaling and per-slot J^T contributions from one read of J; u from A z and A p)",
+                 "k_spot_pass (per-spot J^T sums, A^T u, epilogue and p.q partials)")
+    else:
+        names = ("k_op_fwd (J + A SpMV, fused W / Sigma_A scaling)",
+                 "k_op_bwd (J^T + A^T SpMV, fused epilogue and p.q partials)")
+    fwd = {"name": names[0], "bytes": bf, "us": fus, "GBs": bf / (fus * 1e-6) / 1e9}
+    bwd = {"name": names[1], "bytes": bb, "us": bus, "GBs": bb / (bus * 1e-6) / 1e9}
+    print(f"[bench] {prec} kernels: {names[0].split()[0]} {fus:.1f} us ({fwd['GBs']:.0f} GB/s), "
+          f"{names[1].split()[0]} {bus:.1f} us", file=sys.stderr, flush=True)
+    return {"format": ["csr", "line"][fmt], "line": fwd, "spot": bwd,
+            "dominant": bwd if bus >= fus else fwd,
+            "detail": {"fwd_us": fus, "bwd_us": bus, "fwd_GBs": fwd["GBs"], "bwd_GBs": bwd["GBs"],
+                       "fwd_bytes": bf, "bwd_bytes": bb, "timed_launches": i["n_spmv_bwd"],
+                       "csr_equivalent_fwd_GBs": cf / (fus * 1e-6) / 1e9,
+                       "csr_equivalent_bwd_GBs": cb / (bus * 1e-6) / 1e9}}
+
+
+def csr_operator_rates(prob, prec, vb, reps=20):
+    """The same QP's operator on the general CSR path (spmv_format = 1: J and
+    the stored J^T, each pass reading values and column indices): per-launch
+    time of each pass over `reps` products and its algorithmic GB/s."""
+    from paper_2405_03584_amd import qpgpu
+    import qpsynth
+    it = qpsynth.random_iterate(prob, 1)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(timing=1, spmv_format=1))
+    _, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec, reps=reps)
+    h.close()
+    n, m, nJ = prob.n, prob.m, prob.J.shape[0]
+    bf, bb = spmv_bytes(n, nJ, m, int(prob.J.nnz), int(prob.A.nnz), vb, 0)
+    fus = 1e3 * info["t_spmv_fwd_ms"] / max(info["n_spmv_fwd"], 1)
+    bus = 1e3 * info["t_spmv_bwd_ms"] / max(info["n_spmv_bwd"], 1)
+    out = {"precision": prec, "reps": reps,
+           "J_pass": {"kernel": "k_op_fwd", "us": fus, "bytes": bf, "GBs": bf / (fus * 1e-6) / 1e9,
+                      "frac": bf / (fus * 1e-6) / 1e9 / HBM_PEAK_GBS},
+           "Jt_pass": {"kernel": "k_op_bwd", "us": bus, "bytes": bb, "GBs": bb / (bus * 1e-6) / 1e9,
+                       "frac": bb / (bus * 1e-6) / 1e9 / HBM_PEAK_GBS}}
+    print(f"[bench] CSR operator {prec}: J pass {fus:.1f} us ({out['J_pass']['GBs']:.0f} GB/s), "
+          f"J^T pass {bus:.1f} us ({out['Jt_pass']['GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":

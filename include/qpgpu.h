@@ -140,6 +140,16 @@ typedef struct {
     double  t_spmv_bwd_ms;    /* summed J^T (and A^T) SpMV launch time, when timing = 1 */
     int64_t n_spmv_fwd, n_spmv_bwd;
     int32_t spmv_format;      /* format the PCG operator used: 0 CSR, 1 line format */
+    int32_t prec_fallbacks;   /* constraint-block PCG solves repeated with the Jacobi diagonal */
+    /* KKT certificate of the returned (x, lam_x, lam_A) in the original units
+     * (qp_solve / qp_solve_from only, 0 elsewhere), with y_x = lam_x, y_A = lam_A
+     * and lambda_l = max(-y, 0), lambda_u = max(y, 0) per side:
+     *   eps_d = ||H x + p + y_x + A^T y_A||_inf / (1 + max(||H x||, ||p||, ||y_x||, ||A^T y_A||))
+     *   eps_p = largest bound or row violation / (1 + largest finite |bound|)
+     *   eps_c = largest lambda * slack / (1 + |x^T H x|/2 + |p^T x|)
+     *   gap   = |f - (-x^T H x/2 + sum lambda_l lo - sum lambda_u hi)| / (1 + |x^T H x|/2 + |p^T x|)
+     * (the optimality conditions of eq. (qp) with mu = 0 in eq. (perturbed_KKT)). */
+    double  eps_d, eps_p, eps_c, gap;
 } qp_info;
 
 /* Defaults listed above. */
@@ -160,6 +170,21 @@ void qp_default_settings(qp_settings* s);
 qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const double* W,
                     const qp_csr* A, const qp_range* b, const qp_range* bounds,
                     const qp_settings* s, void* hip_stream);
+
+/* qp_create_device: qp_create with every array in device memory of the
+ * current HIP device (the structs themselves on the host): H->p, H->U, H->w,
+ * J's and A's row_ptr/col_idx/val, W, b->lo/hi and bounds->lo/hi are device
+ * pointers, for callers whose data already sit in GPU memory (e.g. tensors
+ * allocated by a framework through the same HIP runtime).  The arrays are
+ * read on hip_stream (NULL: the null stream) and copied to host memory for
+ * the one-time preparation of qp_create (transposes, line format, value
+ * copies), which then runs unchanged; the caller keeps ownership and may free
+ * the arrays on return.  Validation runs on those host copies, before any
+ * device allocation.  Errors: as qp_create; QP_ERR_DEVICE when a pointer is
+ * not readable device memory. */
+qp_status qp_create_device(qp_handle** out, const qp_hessian* H, const qp_csr* J, const double* W,
+                           const qp_csr* A, const qp_range* b, const qp_range* bounds,
+                           const qp_settings* s, void* hip_stream);
 
 /* qp_solve: run Algorithm 1 from the default start point.
  *   x     (n) : minimiser.
@@ -220,7 +245,7 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
  * to 6 host workers (environment QPGPU_BATCH_WORKERS), largest nnz first.
  * Many QPs of uneven size are the intended use.  Returns QP_OK when every QP returned QP_OK, else the first failing
  * status (QP_ERR_DEVICE preferred); QP_ERR_INVALID for NULL or repeated
- * handles (text in qp_last_error(NULL)). */
+ * handles, or two handles on one stream (text in qp_last_error(NULL)). */
 qp_status qp_solve_batch(qp_handle* const* hs, int32_t count, double* const* xs, qp_info* infos);
 
 /* Text of the last error on this handle; h == NULL gives the calling

@@ -265,9 +265,10 @@ def objective_scale(prob, H: np.ndarray) -> float:
 
 
 def solve(prob, settings: Optional[OracleSettings] = None, H: Optional[np.ndarray] = None,
-          record: bool = False) -> OracleResult:
+          record: bool = False, progress=None) -> OracleResult:
     """Algorithm 1 with a dense Cholesky Newton solve, on the objective
-    divided by zeta (see the module docstring)."""
+    divided by zeta (see the module docstring).  ``progress(iter, mu, rnorm)``,
+    when given, is called after every iteration (it only reports)."""
     import copy
     st = settings or OracleSettings()
     if H is None:
@@ -276,14 +277,14 @@ def solve(prob, settings: Optional[OracleSettings] = None, H: Optional[np.ndarra
     sprob = copy.copy(prob)
     sprob.p = prob.p / zeta
     H = H / zeta
-    res = _solve_scaled(sprob, st, H, record)
+    res = _solve_scaled(sprob, st, H, record, progress)
     res.lam = {g: v * zeta for g, v in res.lam.items()}
     res.objective = res.objective * zeta
     res.zeta = zeta
     return res
 
 
-def _solve_scaled(prob, st: OracleSettings, H: np.ndarray, record: bool) -> OracleResult:
+def _solve_scaled(prob, st: OracleSettings, H: np.ndarray, record: bool, progress=None) -> OracleResult:
     G = make_groups(prob)
     x, s, lam = initial_point(prob, G)
     m_tot = G.m_tot()
@@ -308,6 +309,8 @@ def _solve_scaled(prob, st: OracleSettings, H: np.ndarray, record: bool) -> Orac
         s = {g: s[g] + a_x * ds[g] for g in GROUPS}
         Hx, rH, rg, rc = residuals(prob, G, H, x, s, lam, mu)
         rn = residual_norm(prob, G, Hx, rH, rg, rc)
+        if progress is not None:
+            progress(it, mu, rn)
         if record:
             hist.append({"iter": it, "mu": mu, "rnorm": rn, "alpha_x": a_x, "alpha_l": a_l,
                          "min_s": min((s[g].min() for g in GROUPS if len(s[g])), default=np.inf),

@@ -412,7 +412,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalars(const double* part_rz, i
         sc->iters = 0;
         sc->max_iter = max_iter;
         fl->pcg_iters = 0;
-        fl->pcg_converged = (rr == 0.0 || (mode == 2 && rr <= floor2)) ? 1 : 0;
+        const bool conv = rr == 0.0 || (mode == 2 && rr <= floor2);
+        fl->pcg_converged = conv ? 1 : 0;
+        // a preconditioner that is not positive definite on r (r^T z <= 0,
+        // or non-finite) cannot drive CG: stop at once
+        if (!conv && !(rz > 0.0 && finite_d(rz))) fl->pcg_breakdown = 1;
         return;
     }
     sc->rr = rr;
@@ -420,6 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalars(const double* part_rz, i
     sc->iters = it;
     fl->pcg_iters = it;
     if (rr <= sc->tol2) fl->pcg_converged = 1;
+    else if (!(rz > 0.0 && finite_d(rz))) fl->pcg_breakdown = 1;   // as at the start
     else if (it >= sc->max_iter) fl->pcg_capped = 1;
     sc->beta = rz / sc->rho;
     sc->rho = rz;
@@ -927,6 +932,125 @@ __global__ __launch_bounds__(kBlock) void k_ipm_output(IpmVec v, const IpmScal* 
     for (int k = blockIdx.x * kBlock + threadIdx.x; k < tot; k += gridDim.x * kBlock) {
         if (k < v.n) lam_x[k] = z * (v.l_ux[k] - v.l_lx[k]);
         else lam_A[k - v.n] = z * (v.l_uA[k - v.n] - v.l_lA[k - v.n]);
+    }
+}
+
+// ==========================================================================
+// KKT certificate of the returned point (original units)
+// ==========================================================================
+// The optimality conditions of eq. (qp) (eq. (perturbed_KKT) with mu = 0),
+// measured at the returned x and combined multipliers y_x = zeta(lambda_ux -
+// lambda_lx), y_A = zeta(lambda_uA - lambda_lA), with lambda_l = max(-y, 0),
+// lambda_u = max(y, 0) per side.  H x and A x come from the residual pass at
+// that x (hx is H x / zeta).  Per-block partials, reduced by k_cert_final in
+// a fixed order.
+constexpr int kCertBlocks = 512;
+constexpr int kCertX = 10;   // partials per block of k_cert_x
+constexpr int kCertA = 3;    // partials per block of k_cert_a
+
+// Per variable j (G lanes per row of A^T for (A^T y_A)_j): maxima of |r_H|,
+// |H x|, |p|, |y_x|, |A^T y_A|, bound violation, lambda*slack; sums of
+// x^T H x, p^T x and the bounds' dual term lambda_l lo - lambda_u hi.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_cert_x(IpmVec v, const int* Atp, const int* Atc, const double* Atv,
+                                                   int hasA, const IpmScal* sc, double* part) {
+    __shared__ double sh[kBlock / 64];
+    constexpr int RPB = kBlock / G;
+    const int lane = threadIdx.x % G;
+    const double z = sc->zeta;
+    double mx[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double xhx = 0.0, px = 0.0, dual = 0.0;
+    for (int base = blockIdx.x * RPB; base < v.n; base += gridDim.x * RPB) {
+        const int j = base + threadIdx.x / G;
+        if (j >= v.n) continue;   // whole groups
+        double aty = 0.0;
+        if (hasA) {
+            for (int e = Atp[j] + lane; e < Atp[j + 1]; e += G) aty += Atv[e] * (v.l_uA[Atc[e]] - v.l_lA[Atc[e]]);
+            aty = z * group_sum<double, G>(aty);
+        }
+        if (lane != 0) continue;
+        const double xj = v.x[j], hx = z * v.hx[j], pj = v.p[j];
+        const double lo = v.xlo[j], hi = v.xhi[j];
+        const bool hl = finite_d(lo), hu = finite_d(hi);
+        const double yx = z * (v.l_ux[j] - v.l_lx[j]);
+        const double ll = fmax(-yx, 0.0), lu = fmax(yx, 0.0);
+        const double rH = hx + pj + yx + aty;
+        mx[0] = fmax(mx[0], fabs(rH));
+        mx[1] = fmax(mx[1], fabs(hx));
+        mx[2] = fmax(mx[2], fabs(pj));
+        mx[3] = fmax(mx[3], fabs(yx));
+        mx[4] = fmax(mx[4], fabs(aty));
+        if (hl) mx[5] = fmax(mx[5], lo - xj);
+        if (hu) mx[5] = fmax(mx[5], xj - hi);
+        if (hl && ll > 0.0) { mx[6] = fmax(mx[6], fabs(ll * (xj - lo))); dual += ll * lo; }
+        if (hu && lu > 0.0) { mx[6] = fmax(mx[6], fabs(lu * (hi - xj))); dual -= lu * hi; }
+        xhx += xj * hx;
+        px += pj * xj;
+    }
+    double out[kCertX];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) out[k] = block_max(mx[k], sh);
+    out[7] = block_sum(xhx, sh);
+    out[8] = block_sum(px, sh);
+    out[9] = block_sum(dual, sh);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kCertX; ++k) part[size_t(blockIdx.x) * kCertX + k] = out[k];
+}
+
+// Per row i of A: row violation, lambda*slack maximum, dual term sum (A x
+// from the residual pass).
+__global__ __launch_bounds__(kBlock) void k_cert_a(IpmVec v, const IpmScal* sc, double* part) {
+    __shared__ double sh[kBlock / 64];
+    const double z = sc->zeta;
+    double viol = 0.0, comp = 0.0, dual = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < v.m; i += gridDim.x * kBlock) {
+        const double ax = v.ax[i], lo = v.alo[i], hi = v.ahi[i];
+        const bool hl = finite_d(lo), hu = finite_d(hi);
+        const double y = z * (v.l_uA[i] - v.l_lA[i]);
+        const double ll = fmax(-y, 0.0), lu = fmax(y, 0.0);
+        if (hl) viol = fmax(viol, lo - ax);
+        if (hu) viol = fmax(viol, ax - hi);
+        if (hl && ll > 0.0) { comp = fmax(comp, fabs(ll * (ax - lo))); dual += ll * lo; }
+        if (hu && lu > 0.0) { comp = fmax(comp, fabs(lu * (hi - ax))); dual -= lu * hi; }
+    }
+    viol = block_max(viol, sh);
+    comp = block_max(comp, sh);
+    dual = block_sum(dual, sh);
+    if (threadIdx.x == 0) {
+        part[size_t(blockIdx.x) * kCertA] = viol;
+        part[size_t(blockIdx.x) * kCertA + 1] = comp;
+        part[size_t(blockIdx.x) * kCertA + 2] = dual;
+    }
+}
+
+struct CertOut {
+    double eps_d, eps_p, eps_c, gap;
+};
+
+// One block: the certificate from the partials of k_cert_x (nx blocks) and
+// k_cert_a (na blocks, 0 when there are no rows of A).
+__global__ __launch_bounds__(kBlock) void k_cert_final(const double* px, int nx, const double* pa, int na,
+                                                       const IpmScal* sc, CertOut* out) {
+    __shared__ double sh[kBlock / 64];
+    double mx[7];
+    for (int k = 0; k < 7; ++k) mx[k] = reduce_partials_max(px + k, nx, kCertX, sh);
+    const double xhx = reduce_partials_sum(px + 7, nx, kCertX, sh);
+    const double ptx = reduce_partials_sum(px + 8, nx, kCertX, sh);
+    double dual = reduce_partials_sum(px + 9, nx, kCertX, sh);
+    double viol = mx[5], comp = mx[6];
+    if (na > 0) {
+        viol = fmax(viol, reduce_partials_max(pa, na, kCertA, sh));
+        comp = fmax(comp, reduce_partials_max(pa + 1, na, kCertA, sh));
+        dual += reduce_partials_sum(pa + 2, na, kCertA, sh);
+    }
+    if (threadIdx.x == 0) {
+        const double dscale = 1.0 + fmax(fmax(mx[1], mx[2]), fmax(mx[3], mx[4]));
+        const double oscale = 1.0 + 0.5 * fabs(xhx) + fabs(ptx);
+        const double f = 0.5 * xhx + ptx;
+        out->eps_d = mx[0] / dscale;
+        out->eps_p = viol / sc->cscale;
+        out->eps_c = comp / oscale;
+        out->gap = fabs(f - (-0.5 * xhx + dual)) / oscale;
     }
 }
 

@@ -115,6 +115,7 @@ struct qp_handle {
     double* log = nullptr;
     IpmScal* isc = nullptr;
     PcgScal* psc = nullptr;
+    CertOut* cert = nullptr;
     Flags* fl = nullptr;
     Flags* fl_host = nullptr;   // pinned, 2 slots
     int* k_host = nullptr;      // pinned: the strong-row count read back by build_precond
@@ -125,6 +126,7 @@ struct qp_handle {
         int prec = 0, wb = 0, n_rz = 0;
         const void* ops[4] = {nullptr, nullptr, nullptr, nullptr};   // sigx, sigA, d, dh
         double hs = 0.0;
+        hipGraph_t graph = nullptr;   // kept with its executable until both are dropped
         hipGraphExec_t exec = nullptr;
     };
     std::vector<PcgGraph> graphs;
@@ -166,8 +168,10 @@ struct qp_handle {
         if (fl_host) (void)hipHostFree(fl_host);
         if (k_host) (void)hipHostFree(k_host);
         if (ev_k) (void)hipEventDestroy(ev_k);
-        for (auto& g : graphs)
+        for (auto& g : graphs) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+        }
         for (auto e : tev) (void)hipEventDestroy(e);
         for (auto e : {ev_chunk[0], ev_chunk[1], ev_t0, ev_t1, ev_p0[0], ev_p0[1], ev_p1[0], ev_p1[1]})
             if (e) (void)hipEventDestroy(e);
@@ -688,16 +692,23 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
                 }
                 ok = hipStreamEndCapture(h->stream, &graph) == hipSuccess && graph != nullptr;
                 if (ok) ok = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) == hipSuccess;
-                if (graph) (void)hipGraphDestroy(graph);
+                if (!ok && graph) {
+                    (void)hipGraphDestroy(graph);
+                    graph = nullptr;
+                }
             }
             if (ok) {
                 if (h->graphs.size() >= 8) {   // keep a few operators per handle
+                    // the evicted graph may still be queued on the stream
+                    HIPCHK(hipStreamSynchronize(h->stream));
                     (void)hipGraphExecDestroy(h->graphs.front().exec);
+                    (void)hipGraphDestroy(h->graphs.front().graph);
                     h->graphs.erase(h->graphs.begin());
                 }
                 qp_handle::PcgGraph g;
                 g.prec = prec; g.wb = wb; g.n_rz = n_rz; g.hs = hs;
                 for (int i = 0; i < 4; ++i) g.ops[i] = ops[i];
+                g.graph = graph;
                 g.exec = gexec;
                 h->graphs.push_back(g);
             } else {
@@ -885,8 +896,11 @@ void compute_diag_h(qp_handle* h) {
 
 // Captured PCG graphs hold gamma, U and k by value: a new objective drops them.
 void drop_graphs(qp_handle* h) {
-    for (auto& g : h->graphs)
+    if (!h->graphs.empty()) HIPCHK(hipStreamSynchronize(h->stream));
+    for (auto& g : h->graphs) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
     h->graphs.clear();
 }
 
@@ -1133,6 +1147,7 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->isc = h->dalloc<IpmScal>(1);
         h->psc = h->dalloc<PcgScal>(1);
         HIPCHK(hipMemsetAsync(h->psc, 0, sizeof(PcgScal), h->stream));
+        h->cert = h->dalloc<CertOut>(1);
         h->fl = h->dalloc<Flags>(1);
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->fl_host), 2 * sizeof(Flags), hipHostMallocDefault));
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->k_host), sizeof(int), hipHostMallocDefault));
@@ -1163,6 +1178,94 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
     }
     *out = h;
     return QP_OK;
+}
+
+qp_status qp_create_device(qp_handle** out, const qp_hessian* H, const qp_csr* J, const double* W,
+                           const qp_csr* A, const qp_range* b, const qp_range* bounds, const qp_settings* s,
+                           void* hip_stream) {
+    g_create_error.clear();
+    if (!out || !H || !J) {
+        g_create_error = "out, H or J is NULL";
+        return QP_ERR_INVALID;
+    }
+    *out = nullptr;
+    if (J->rows < 0 || J->cols < 1 || J->nnz < 0 || (A && (A->rows < 0 || A->nnz < 0)) || H->k < 0) {
+        g_create_error = "negative size (or no columns)";
+        return QP_ERR_INVALID;
+    }
+    const size_t n = size_t(J->cols), nJ = size_t(J->rows);
+    const size_t m = A ? size_t(A->rows) : 0;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // Host copies of every device array (NULL stays NULL and is judged by
+    // qp_create's validation).
+    try {
+        (void)hipGetLastError();
+        hipError_t err = hipSuccess;
+        auto fetch = [&](const void* d, size_t count, auto& vec) {
+            vec.clear();
+            if (!d || count == 0 || err != hipSuccess) return;
+            vec.resize(count);
+            err = hipMemcpyAsync(vec.data(), d, count * sizeof(vec[0]), hipMemcpyDeviceToHost, st);
+        };
+        std::vector<double> p, U, w, Wv, Jv, Av, blo, bhi, xlo, xhi;
+        std::vector<int64_t> Jp, Ap;
+        std::vector<int32_t> Jc, Ac;
+        fetch(H->p, n, p);
+        fetch(H->U, n * size_t(H->k), U);
+        fetch(H->w, size_t(H->k), w);
+        fetch(W, nJ, Wv);
+        fetch(J->row_ptr, nJ + 1, Jp);
+        fetch(J->col_idx, size_t(J->nnz), Jc);
+        fetch(J->val, size_t(J->nnz), Jv);
+        if (A) {
+            fetch(A->row_ptr, m + 1, Ap);
+            fetch(A->col_idx, size_t(A->nnz), Ac);
+            fetch(A->val, size_t(A->nnz), Av);
+        }
+        if (b) {
+            fetch(b->lo, m, blo);
+            fetch(b->hi, m, bhi);
+        }
+        if (bounds) {
+            fetch(bounds->lo, n, xlo);
+            fetch(bounds->hi, n, xhi);
+        }
+        if (err == hipSuccess) err = hipStreamSynchronize(st);
+        if (err != hipSuccess) {
+            g_create_error = std::string("reading the device arrays: ") + hipGetErrorString(err);
+            return QP_ERR_DEVICE;
+        }
+        auto ptr = [](const auto& vec, const void* orig) { return orig ? vec.data() : nullptr; };
+        qp_hessian hH = *H;
+        hH.p = ptr(p, H->p);
+        hH.U = ptr(U, H->U);
+        hH.w = ptr(w, H->w);
+        qp_csr hJ = *J;
+        hJ.row_ptr = ptr(Jp, J->row_ptr);
+        hJ.col_idx = ptr(Jc, J->col_idx);
+        hJ.val = ptr(Jv, J->val);
+        qp_csr hA{};
+        if (A) {
+            hA = *A;
+            hA.row_ptr = ptr(Ap, A->row_ptr);
+            hA.col_idx = ptr(Ac, A->col_idx);
+            hA.val = ptr(Av, A->val);
+        }
+        qp_range hb{}, hx{};
+        if (b) {
+            hb.lo = ptr(blo, b->lo);
+            hb.hi = ptr(bhi, b->hi);
+        }
+        if (bounds) {
+            hx.lo = ptr(xlo, bounds->lo);
+            hx.hi = ptr(xhi, bounds->hi);
+        }
+        return qp_create(out, &hH, &hJ, ptr(Wv, W), A ? &hA : nullptr, b ? &hb : nullptr,
+                         bounds ? &hx : nullptr, s, hip_stream);
+    } catch (const std::bad_alloc&) {
+        g_create_error = "host allocation failed";
+        return QP_ERR_NOMEM;
+    }
 }
 
 qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* sigma_A, const double* v,
@@ -1246,7 +1349,9 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         PrecAttemptCap cap_guard(h);
         Flags f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d,
                                    wbp ? h->Dw : nullptr, 1.0, false, &ta, &nsolves);
+        int fallbacks = 0;
         if (wbp && cap_guard.stalled(f)) {
+            ++fallbacks;
             // stalled constraint-block solve: again with the Jacobi diagonal
             int more = 0;
             const int spent = f.pcg_iters;
@@ -1269,6 +1374,7 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
             info->pcg_solves = nsolves;
             info->pcg_capped = f.pcg_capped;
             info->pcg_relres = ps.bnorm2 > 0 ? std::sqrt(ps.rr / ps.bnorm2) : 0.0;
+            info->prec_fallbacks = fallbacks;
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
             info->t_solve_ms = info->t_pcg_ms = ms;
@@ -1416,6 +1522,7 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
         // diagonal, which then serves the rest of this QP
         PrecAttemptCap cap_guard(h);
         bool jacobi_only = false;
+        int fallbacks = 0;
         for (int it = 0; it < h->set.max_ipm_iter; ++it) {
             const int ps = it & 1;
             harvest_pcg_ms(ps);
@@ -1426,6 +1533,7 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
             if (!f.ipm_done && wbp && cap_guard.stalled(f)) {
                 pcg_total += f.pcg_iters;
                 pcg_solves += nsolves;
+                ++fallbacks;
                 jacobi_only = true;
                 wbp = false;
                 if (h->set.log_level > 0)
@@ -1442,7 +1550,8 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
             capped += f.pcg_capped;
             if (h->set.log_level > 0) {
                 IpmScal cur{};
-                HIPCHK(hipMemcpy(&cur, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpyAsync(&cur, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
+                HIPCHK(hipStreamSynchronize(h->stream));
                 std::fprintf(stderr, "[qpgpu] ipm %3d mu %.3e rnorm %.3e pcg %6d%s alpha %.3f/%.3f\n",
                              cur.iter, cur.mu, cur.rnorm, f.pcg_iters, f.pcg_capped ? " (cap)" : "",
                              cur.alpha_p, cur.alpha_d);
@@ -1465,8 +1574,22 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
             residuals(1);
             wbp = !jacobi_only && (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop);
         }
-        // outputs
+        // outputs: the KKT certificate of the returned point (H x and A x of
+        // the last residual pass are at that point), then the multipliers
         HIPCHK(hipEventRecord(h->ev_t1, h->stream));
+        {
+            const int gc = std::min(kCertBlocks, grid_rows(n, 16));
+            hipLaunchKernelGGL(k_cert_x<16>, dim3(gc), dim3(kBlock), 0, h->stream, v, (const int*)h->Atp,
+                               (const int*)h->Atc, (const double*)h->Atv, m > 0 ? 1 : 0, (const IpmScal*)h->isc,
+                               h->part2);
+            const int ga = m > 0 ? std::min(kCertBlocks, (m + kBlock - 1) / kBlock) : 0;
+            if (ga > 0)
+                hipLaunchKernelGGL(k_cert_a, dim3(ga), dim3(kBlock), 0, h->stream, v, (const IpmScal*)h->isc,
+                                   h->partA);
+            hipLaunchKernelGGL(k_cert_final, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part2, gc,
+                               (const double*)h->partA, ga, (const IpmScal*)h->isc, h->cert);
+            HIPCHK(hipGetLastError());
+        }
         double* lx = h->tmp_n;
         double* lA = h->tmp_m;
         hipLaunchKernelGGL(k_ipm_output, dim3(grid_elems(int64_t(n) + m)), dim3(kBlock), 0, h->stream, v,
@@ -1478,6 +1601,8 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
         HIPCHK(hipMemcpyAsync(&sc, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
         PcgScal ps{};
         HIPCHK(hipMemcpyAsync(&ps, h->psc, sizeof(PcgScal), hipMemcpyDeviceToHost, h->stream));
+        CertOut co{};
+        HIPCHK(hipMemcpyAsync(&co, h->cert, sizeof(CertOut), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         harvest_pcg_ms(0);
         harvest_pcg_ms(1);
@@ -1500,6 +1625,11 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
             info->t_solve_ms = ms;
             info->t_pcg_ms = pcg_ms;
             info->spmv_format = h->line ? 1 : 0;
+            info->prec_fallbacks = fallbacks;
+            info->eps_d = co.eps_d;
+            info->eps_p = co.eps_p;
+            info->eps_c = co.eps_c;
+            info->gap = co.gap;
             harvest_timing(h, ta, info);
         }
     } catch (const HipError& he) {
@@ -1565,11 +1695,17 @@ qp_status qp_solve_batch(qp_handle* const* hs, int32_t count, double* const* xs,
             g_create_error = "qp_solve_batch: NULL handle or output at index " + std::to_string(i);
             return QP_ERR_INVALID;
         }
-        for (int j = 0; j < i; ++j)
+        for (int j = 0; j < i; ++j) {
             if (hs[j] == hs[i]) {
                 g_create_error = "qp_solve_batch: a handle appears twice";
                 return QP_ERR_INVALID;
             }
+            // concurrent workers capture and launch on their handles' streams
+            if (hs[j]->stream == hs[i]->stream) {
+                g_create_error = "qp_solve_batch: two handles share a stream";
+                return QP_ERR_INVALID;
+            }
+        }
     }
     if (count == 0) return QP_OK;
     // largest problems first, so the tail of the batch is short

@@ -55,13 +55,15 @@ class qp_info(C.Structure):
                 ("rnorm", C.c_double), ("zeta", C.c_double), ("objective", C.c_double),
                 ("pcg_relres", C.c_double), ("t_solve_ms", C.c_double), ("t_pcg_ms", C.c_double),
                 ("t_spmv_fwd_ms", C.c_double), ("t_spmv_bwd_ms", C.c_double),
-                ("n_spmv_fwd", C.c_int64), ("n_spmv_bwd", C.c_int64), ("spmv_format", C.c_int32)]
+                ("n_spmv_fwd", C.c_int64), ("n_spmv_bwd", C.c_int64), ("spmv_format", C.c_int32),
+                ("prec_fallbacks", C.c_int32), ("eps_d", C.c_double), ("eps_p", C.c_double),
+                ("eps_c", C.c_double), ("gap", C.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-EXPORTS = ["qp_default_settings", "qp_create", "qp_solve", "qp_solve_from", "qp_update_hessian",
+EXPORTS = ["qp_default_settings", "qp_create", "qp_create_device", "qp_solve", "qp_solve_from", "qp_update_hessian",
            "qp_newton_step", "qp_operator_apply", "qp_solve_batch", "qp_last_error", "qp_destroy", "qp_sizes"]
 
 _lib = None
@@ -81,6 +83,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                               C.POINTER(qp_csr), C.POINTER(qp_range), C.POINTER(qp_range),
                               C.POINTER(qp_settings), C.c_void_p]
     lib.qp_create.restype = C.c_int
+    lib.qp_create_device.argtypes = lib.qp_create.argtypes
+    lib.qp_create_device.restype = C.c_int
     lib.qp_solve.argtypes = [C.c_void_p, _dp, _dp, _dp, C.POINTER(qp_info)]
     lib.qp_solve.restype = C.c_int
     lib.qp_solve_from.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.POINTER(qp_info)]
@@ -203,6 +207,84 @@ def qp_create(gamma: float, p, J, W, A=None, A_lo=None, A_hi=None, x_lo=None, x_
     if st != QP_OK:
         raise QPError(st, lib.qp_last_error(None).decode())
     return QPHandle(h, n, m)
+
+
+def hip_runtimes_mapped() -> list:
+    """Paths of the HIP runtime libraries (libamdhip64) mapped into this
+    process.  Device pointers are shared between the library and a caller
+    only when there is exactly one."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) >= 6 and "libamdhip64" in parts[-1]:
+                    paths.add(os.path.realpath(parts[-1]))
+    except OSError:
+        pass
+    return sorted(paths)
+
+
+_DEV_DTYPES = {"f64": ("torch.float64", "float64"), "i64": ("torch.int64", "int64"),
+               "i32": ("torch.int32", "int32")}
+
+
+def _dev_ptr(a, kind: str, count: int, name: str):
+    """Device address of a contiguous device array with `count` entries of
+    `kind`: any object with data_ptr(), numel(), dtype and is_contiguous()
+    (a torch tensor on the GPU, or a buffer of the same runtime)."""
+    if a is None:
+        return None
+    if str(a.dtype) not in _DEV_DTYPES[kind]:
+        raise TypeError(f"{name}: dtype {a.dtype}, expected {_DEV_DTYPES[kind][1]}")
+    if int(a.numel()) != count:
+        raise ValueError(f"{name}: {int(a.numel())} entries, expected {count}")
+    if not a.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    if hasattr(a, "is_cuda") and not a.is_cuda:
+        raise ValueError(f"{name}: not in device memory")
+    return C.cast(C.c_void_p(int(a.data_ptr())), _dp if kind == "f64" else (_lp if kind == "i64" else _ip))
+
+
+def qp_create_device(gamma: float, p, J, W, A=None, A_lo=None, A_hi=None, x_lo=None, x_hi=None,
+                     U=None, w=None, settings: Optional[qp_settings] = None, stream=None) -> QPHandle:
+    """qp_create_device: the problem's arrays already in device memory.
+    J and A are (indptr int64, indices int32, data float64, (rows, cols))
+    tuples of device arrays; p, W, bounds, U (n*k, column-major, flat) and w
+    are float64 device arrays.  The library and the arrays' allocator must
+    share one HIP runtime: with torch, import torch before this module loads
+    the library (checked here)."""
+    lib = load_library()
+    rt = hip_runtimes_mapped()
+    if len(rt) > 1:
+        raise RuntimeError("two HIP runtimes in this process (" + ", ".join(rt) + "): device pointers of one "
+                           "are not valid in the other; load the library after the allocating framework")
+    Jp, Ji, Jd, (nJ, n) = J
+    nnzJ = int(Jd.numel())
+    k = 0 if U is None else int(U.numel()) // n
+    H = qp_hessian(float(gamma), _dev_ptr(p, "f64", n, "p"), k, _dev_ptr(U, "f64", n * k, "U") if k else None,
+                   _dev_ptr(w, "f64", k, "w") if k else None)
+    Js = qp_csr(int(nJ), int(n), nnzJ, _dev_ptr(Jp, "i64", nJ + 1, "J.indptr"),
+                _dev_ptr(Ji, "i32", nnzJ, "J.indices"), _dev_ptr(Jd, "f64", nnzJ, "J.data"))
+    As = b = None
+    m = 0
+    if A is not None:
+        Ap, Ai, Ad, (m, nA) = A
+        if nA != n:
+            raise ValueError("A must have n columns")
+        nnzA = int(Ad.numel())
+        As = qp_csr(int(m), int(n), nnzA, _dev_ptr(Ap, "i64", m + 1, "A.indptr"),
+                    _dev_ptr(Ai, "i32", nnzA, "A.indices"), _dev_ptr(Ad, "f64", nnzA, "A.data"))
+        b = qp_range(_dev_ptr(A_lo, "f64", m, "A_lo"), _dev_ptr(A_hi, "f64", m, "A_hi"))
+    bnd = qp_range(_dev_ptr(x_lo, "f64", n, "x_lo"), _dev_ptr(x_hi, "f64", n, "x_hi"))
+    h = C.c_void_p()
+    st = lib.qp_create_device(C.byref(h), C.byref(H), C.byref(Js), _dev_ptr(W, "f64", nJ, "W"),
+                              C.byref(As) if As is not None else None,
+                              C.byref(b) if b is not None else None, C.byref(bnd),
+                              C.byref(settings) if settings is not None else None, _stream_handle(stream))
+    if st != QP_OK:
+        raise QPError(st, lib.qp_last_error(None).decode())
+    return QPHandle(h, int(n), int(m))
 
 
 def qp_create_from_problem(prob, settings: Optional[qp_settings] = None, stream=None) -> QPHandle:

@@ -1,0 +1,60 @@
+"""Parity bars of the GPU tests against the FP64 oracle, per precision.
+
+* x: ||x - x_oracle||_inf <= 1e-7 when the PCG operator holds J in FP64,
+  1e-5 with FP32 or BF16 values (the mixed-precision target);
+* objective: |f - f_oracle| <= 1e-10 |f_oracle| (FP64) or 1e-6 |f_oracle|
+  (FP32, BF16), plus the gap the stopping rule itself allows both solvers:
+  at exit every scaled lambda_i s_i is below 2 mu_tol, so the objective of
+  either is within 2 m_tot mu_tol zeta of the optimum (original units);
+* KKT certificate of the returned point <= 1e-9, computed by the oracle from
+  (x, lam_x, lam_A) and by the library on the device (qp_info), the two
+  agreeing to 1e-11.
+"""
+import numpy as np
+
+import oracle
+
+X_BAR = {"fp64": 1e-7, "fp32": 1e-5, "bf16": 1e-5}
+OBJ_REL_BAR = {"fp64": 1e-10, "fp32": 1e-6, "bf16": 1e-6}
+CERT_BAR = 1e-9
+CERT_AGREE = 1e-11
+
+
+def m_tot(prob) -> int:
+    t = int(np.isfinite(prob.x_lo).sum() + np.isfinite(prob.x_hi).sum())
+    if prob.A is not None and prob.m > 0:
+        t += int(np.isfinite(prob.A_lo).sum() + np.isfinite(prob.A_hi).sum())
+    return t
+
+
+def gap_bound(prob, zeta, mu_tol=1e-10) -> float:
+    return 2.0 * m_tot(prob) * mu_tol * zeta
+
+
+def check_certificate(prob, res):
+    """Oracle certificate of the returned point <= CERT_BAR, and the device's
+    own certificate (qp_info) equal to it within CERT_AGREE."""
+    cert = oracle.kkt_certificate(prob, res.x, res.lam_x, res.lam_A if prob.m else None)
+    assert cert.worst() <= CERT_BAR, cert
+    info = res.info
+    for k in ("eps_d", "eps_p", "eps_c", "gap"):
+        assert info[k] <= CERT_BAR, (k, info[k])
+        assert abs(info[k] - getattr(cert, k)) <= CERT_AGREE, (k, info[k], getattr(cert, k))
+    return cert
+
+
+def check_solve(prob, res, x_ref, f_ref, zeta, prec="fp64", status_ok=True):
+    """The bars above for one solve.  Returns (max |x - x_ref|, certificate)."""
+    if status_ok:
+        assert res.status == 0, res.info
+    dx = float(np.abs(res.x - x_ref).max()) if prob.n else 0.0
+    assert dx <= X_BAR[prec], (prec, dx)
+    dobj = abs(res.info["objective"] - f_ref)
+    assert dobj <= OBJ_REL_BAR[prec] * abs(f_ref) + gap_bound(prob, zeta), (prec, dobj, f_ref)
+    cert = check_certificate(prob, res)
+    return dx, cert
+
+
+def check_solve_vs_oracle(prob, res, ref, prec="fp64"):
+    """check_solve against an oracle.solve result."""
+    return check_solve(prob, res, ref.x, ref.objective, ref.zeta, prec)

@@ -1,5 +1,5 @@
 """Writes tests/golden/config2_oracle.json: the FP64 oracle's solution of the
-n=20,000 banded-dose QP (seed 2000), sampled at every 50th variable.
+n=20,000 banded-dose QP (seed 2000), every entry of x.
 
 Calls only ``oracle/`` and the input generator.  Run from the repository root:
     python tests/golden/make_config2_golden.py
@@ -32,7 +32,6 @@ def main(out=os.path.join(ROOT, "tests", "golden", "config2_oracle.json")):
     yx = oracle.lambda_x_combined(res, prob)
     yA = oracle.lambda_A_combined(res, prob)
     cert = oracle.kkt_certificate(prob, res.x, yx, yA)
-    idx = np.arange(0, prob.n, 50)
     rec = {
         "about": "FP64 dense-Cholesky oracle on the banded-dose QP n=20000 (qpsynth.config2, seed 2000)",
         "written_by": "tests/golden/make_config2_golden.py",
@@ -42,8 +41,7 @@ def main(out=os.path.join(ROOT, "tests", "golden", "config2_oracle.json")):
         "x_inf_norm": float(np.abs(res.x).max()),
         "n_at_lower": int(np.sum(res.x < 1e-6)), "n_at_upper": int(np.sum(res.x > 50 - 1e-6)),
         "n_rows_active": int(np.sum(yA > 1e-9 * np.abs(yA).max())),
-        "sample_index_step": 50,
-        "x_sample": [float(v) for v in res.x[idx]],
+        "x": [float(v) for v in res.x],
         "seconds": {"generate": t1 - t0, "hessian": t2 - t1, "ipm": t3 - t2},
         "history": res.history,
     }

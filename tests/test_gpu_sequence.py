@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 import qpsynth
+from bars import X_BAR, check_certificate, check_solve_vs_oracle
 from paper_2405_03584_amd import qpgpu
 
 pytestmark = pytest.mark.gpu
@@ -23,17 +24,9 @@ def _bases():
             "band": lambda: qpsynth.config2(scale=0.02)}
 
 
-def _check(prob, res, ref):
+def _check(prob, res, ref, prec="fp64"):
     assert res.status == qpgpu.QP_OK, (qpgpu.STATUS_NAMES[res.status], res.info)
-    xs = 1 + np.abs(ref.x).max()
-    dx = np.abs(res.x - ref.x).max()
-    assert dx <= 1e-6 * xs, dx
-    m_tot = sum(len(v) for v in ref.lam.values())
-    gap = 2.0 * m_tot * 1e-10 * ref.zeta
-    dobj = abs(res.info["objective"] - ref.objective)
-    assert dobj <= 1e-8 * (1 + abs(ref.objective)) + gap, dobj
-    cert = oracle.kkt_certificate(prob, res.x, res.lam_x, res.lam_A if prob.m else None)
-    assert cert.worst() <= 1e-9, cert
+    check_solve_vs_oracle(prob, res, ref, prec)
 
 
 def _update(h, q):
@@ -58,7 +51,7 @@ def test_updated_handle_equals_fresh_handle(which, prec):
         print(f"  step {t} k={q.k} ipm={res.info['ipm_iters']} pcg={res.info['pcg_iters']}", flush=True)
         assert np.array_equal(res.x, ref_res.x), t
         assert res.info["ipm_iters"] == ref_res.info["ipm_iters"], t
-        _check(q, res, oracle.solve(q))
+        _check(q, res, oracle.solve(q), prec)
 
 
 @pytest.mark.parametrize("which,prec", [("cfg1", "fp64"), ("band", "fp64"), ("band", "bf16")])
@@ -77,8 +70,8 @@ def test_warm_start_sequence(which, prec):
         print(f"  step {t} ipm cold {cold.info['ipm_iters']} warm {warm.info['ipm_iters']} "
               f"pcg cold {cold.info['pcg_iters']} warm {warm.info['pcg_iters']}", flush=True)
         ref = oracle.solve(q)
-        _check(q, cold, ref)
-        _check(q, warm, ref)
+        _check(q, cold, ref, prec)
+        _check(q, warm, ref, prec)
         x_prev = warm.x
 
 
@@ -128,9 +121,11 @@ def test_stalled_constraint_block_solve_falls_back_to_jacobi():
     assert res.status == qpgpu.QP_OK
     assert res.info["pcg_iters"] < 20000
     ref = oracle.solve(q)
+    # 55 dose-free variables (curvature gamma only) sit in a flat region where
+    # x is fixed only to about tolerance * |p| / gamma: x is compared at that
+    # scale, the certificate at the usual bar
     assert np.abs(res.x - ref.x).max() <= 1e-5 * (1 + np.abs(ref.x).max())
-    cert = oracle.kkt_certificate(q, res.x, res.lam_x, res.lam_A)
-    assert cert.worst() <= 1e-9, cert
+    check_certificate(q, res)
 
 
 def test_batch_of_updated_handles():
@@ -146,4 +141,4 @@ def test_batch_of_updated_handles():
         single = qpgpu.qp_solve(h)
         assert np.array_equal(x, single.x)
         ref = oracle.solve(s[2])
-        assert np.abs(x - ref.x).max() <= 1e-6 * (1 + np.abs(ref.x).max())
+        assert np.abs(x - ref.x).max() <= X_BAR["fp64"]

@@ -2,7 +2,9 @@
 
 P1  the paper's literal Newton system (eq. (newton_system)), its 2x2 reduced
     form (eq. (2x2_reduced)) and its doubly augmented form (eq. (2x2_augmented))
-    give the same direction as the oracle's condensed solve;
+    give the same direction as the oracle's condensed solve, and the condensed
+    operator the GPU tests compare with is the Schur complement of the literal
+    Newton matrix;
 P2  brute-force active-set enumeration (n <= 8);
 P3  closed form x = clip(-p/gamma, l, u) when H = gamma*I;
 P4  scipy's bounded least squares (BVLS) and NNLS for box-constrained
@@ -228,14 +230,12 @@ def _random_state(prob, seed):
     return G, x, s, lam, mu
 
 
-@pytest.mark.parametrize("inst", [0, 1, 2, 12, 42, 54])
-def test_p1_full_newton_system(inst):
+def _literal_newton_matrix(prob, s, lam, x, mu):
     """eq. (newton_system) written with the paper's single constraint matrix
     R = [I; A] and l <= R x <= u (bounds are rows of R), assembled as the
-    5x5 block matrix and solved densely."""
-    prob = qpsynth.tiny(inst)
+    5x5 block matrix over (dx, dlambda_l, dlambda_u, ds_l, ds_u), with its
+    right-hand side.  Returns (M, rhs, block offsets)."""
     n = prob.n
-    G, x, s, lam, mu = _random_state(prob, 100 + inst)
     H = ipm_dense.hessian_dense(prob)
     R = np.eye(n) if prob.m == 0 else np.vstack([np.eye(n), prob.A.toarray()])
     lo = prob.x_lo if prob.m == 0 else np.concatenate([prob.x_lo, prob.A_lo])
@@ -268,7 +268,19 @@ def test_p1_full_newton_system(inst):
     M[o[3]:o[4], o[3]:o[4]] = np.diag(l_l)
     M[o[4]:o[5], o[2]:o[3]] = np.diag(s_u)
     M[o[4]:o[5], o[4]:o[5]] = np.diag(l_u)
-    sol = np.linalg.solve(M, -np.concatenate([r_H, r_l, r_u, r_c1, r_c2]))
+    return M, -np.concatenate([r_H, r_l, r_u, r_c1, r_c2]), o
+
+
+@pytest.mark.parametrize("inst", [0, 1, 2, 12, 42, 54])
+def test_p1_full_newton_system(inst):
+    """The literal eq. (newton_system), solved densely, against the oracle's
+    condensed solve and recovery."""
+    prob = qpsynth.tiny(inst)
+    n = prob.n
+    G, x, s, lam, mu = _random_state(prob, 100 + inst)
+    H = ipm_dense.hessian_dense(prob)
+    M, rhs, o = _literal_newton_matrix(prob, s, lam, x, mu)
+    sol = np.linalg.solve(M, rhs)
     dx_full = sol[:n]
     dl_l, dl_u = sol[o[1]:o[2]], sol[o[2]:o[3]]
     ds_l, ds_u = sol[o[3]:o[4]], sol[o[4]:o[5]]
@@ -321,6 +333,63 @@ def test_p1_reduced_and_doubly_augmented(inst):
     for sol in (red, aug):
         assert np.abs(sol[:n] - dx).max() <= 1e-9 * sc
         assert np.abs(sol[n:n + k] - dlA).max() <= 1e-9 * sc
+
+
+@pytest.mark.parametrize("inst", [0, 1, 2, 5, 12, 17, 42, 54])
+def test_p1_condensed_operator_is_schur_complement(inst):
+    """condensed_operator_dense(prob, sigma_x, sigma_A) -- the operator every
+    GPU operator and Newton-step test compares with -- equals the Schur
+    complement onto dx of the literal eq. (newton_system) matrix, eliminated
+    here numerically (M11 - M12 M22^-1 M21), with sigma_x = Sigma_lx + Sigma_ux
+    per variable and sigma_A = Sigma_lA + Sigma_uA per row of A, Sigma_g =
+    lambda_g / s_g.  Variables and rows without a finite side get weight 0."""
+    prob = qpsynth.tiny(inst)
+    n = prob.n
+    G, x, s, lam, mu = _random_state(prob, 300 + inst)
+    M, _, o = _literal_newton_matrix(prob, s, lam, x, mu)
+    K_schur = M[:n, :n] - M[:n, n:] @ np.linalg.solve(M[n:, n:], M[n:, :n])
+    sig_x = np.zeros(n)
+    sig_x[G.idx["lx"]] += lam["lx"] / s["lx"]
+    sig_x[G.idx["ux"]] += lam["ux"] / s["ux"]
+    sig_A = None
+    if prob.m:
+        sig_A = np.zeros(prob.m)
+        sig_A[G.idx["lA"]] += lam["lA"] / s["lA"]
+        sig_A[G.idx["uA"]] += lam["uA"] / s["uA"]
+    K = oracle.condensed_operator_dense(prob, sig_x, sig_A)
+    assert np.abs(K - K_schur).max() <= 1e-12 * (1 + np.abs(K_schur).max())
+    # and against the condensed matrix of the oracle's own iteration (pinned by
+    # the solves above), with the groups' weights kept apart
+    Kc = ipm_dense.condensed_matrix(prob, G, ipm_dense.hessian_dense(prob),
+                                    {g: lam[g] / s[g] for g in ipm_dense.GROUPS})
+    assert np.abs(K - Kc).max() <= 1e-13 * (1 + np.abs(Kc).max())
+
+
+def test_p1_condensed_operator_catches_planted_mistakes(monkeypatch):
+    """The Schur-complement pin above fails for each plausible slip in the
+    operator: a dropped A^T Sigma_A A term, sqrt(Sigma_A) in place of Sigma_A,
+    a dropped Sigma_x, and the row weights counted twice (lower and upper
+    sides merged twice)."""
+    prob = qpsynth.tiny(12)
+    assert prob.m > 0 and prob.n != prob.m
+    n = prob.n
+    G, x, s, lam, mu = _random_state(prob, 312)
+    M, _, o = _literal_newton_matrix(prob, s, lam, x, mu)
+    K_schur = M[:n, :n] - M[:n, n:] @ np.linalg.solve(M[n:, n:], M[n:, :n])
+    sig_x = np.zeros(n)
+    sig_x[G.idx["lx"]] += lam["lx"] / s["lx"]
+    sig_x[G.idx["ux"]] += lam["ux"] / s["ux"]
+    sig_A = np.zeros(prob.m)
+    sig_A[G.idx["lA"]] += lam["lA"] / s["lA"]
+    sig_A[G.idx["uA"]] += lam["uA"] / s["uA"]
+    H = ipm_dense.hessian_dense(prob)
+    Ad = prob.A.toarray()
+    mutants = [H + np.diag(sig_x),
+               H + np.diag(sig_x) + (Ad * np.sqrt(sig_A)[:, None]).T @ Ad,
+               H + (Ad * sig_A[:, None]).T @ Ad,
+               H + np.diag(sig_x) + 2.0 * (Ad * sig_A[:, None]).T @ Ad]
+    for Km in mutants:
+        assert np.abs(Km - K_schur).max() > 1e-6 * (1 + np.abs(K_schur).max())
 
 
 # ----------------------------------------------------------------------------
