@@ -121,6 +121,13 @@ typedef struct {
     int32_t graphs;           /* 1 (default): PCG iterations are launched as HIP graphs of four
                                  iterations, captured once per operator and replayed; 0: one launch
                                  per kernel.  Results are identical.  timing = 1 launches directly. */
+    int32_t kkt_system;       /* linear system PCG runs on.  0 (default): the condensed system
+                                 (H + Sigma_x + A^T Sigma_A A) dx = r, the Schur complement of
+                                 eq. (2x2_augmented).  1: the doubly augmented system of
+                                 eq. (2x2_augmented) itself (Section 4), of size n + |L_A| + |U_A|,
+                                 with the Jacobi preconditioner of Section 4.1.2 (precond is then
+                                 ignored); dx is its x part.  qp_operator_apply always applies the
+                                 condensed operator. */
 } qp_settings;
 
 typedef struct {

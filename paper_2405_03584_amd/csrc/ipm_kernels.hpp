@@ -52,6 +52,42 @@ __device__ __forceinline__ bool pcg_stopped_ro(const Flags* fl) { return pcg_sto
 // Operator kernels (one PCG product q = K p)
 // ==========================================================================
 
+// The doubly augmented system of eq. (2x2_augmented), with B = [A_L; -A_U]
+// (rows of A with a finite lower / upper side) and D = diag(s/lambda) of those
+// rows, acts on N = n + 2m vectors (x part, then one entry per row and side;
+// an absent side has a zero row of B, D = 1 and stays zero):
+//   y_x = (Q + 2 B^T D^-1 B) p_x + B^T p_lambda
+//       = H p_x + Sigma_x p_x + A^T (2 Sigma_A (A p_x) + p_l - p_u),
+//   y_l = (A p_x) + D_l p_l,   y_u = -(A p_x) + D_u p_u,
+// Sigma_A = Sigma_lA + Sigma_uA.  The rows of A carry the lambda block: given
+// (A p_x)_i they form u_i (the vector A^T multiplies) and y_l, y_u.
+struct AugRows {
+    const double* dlu;     // D_l (m) then D_u (m); 0 marks an absent side; null: condensed system
+    double* q;             // output of the product (N): the lambda block at q + n
+    double* part;          // PCG product: one p^T q partial per row (its lambda block), may be null
+    int n;
+};
+
+// Row i of the lambda block: a = (A p_x)_i, g the product's gathered vector
+// (N entries; p2 non-null in a PCG product, where the new direction's lambda
+// entries are stored back).  Returns u_i.
+template <typename GV>
+__device__ __forceinline__ double aug_row(const AugRows& a, int m, int i, double a_i, double sig, const GV& g,
+                                          double* p2) {
+    const double pl = g(a.n + i), pu = g(a.n + m + i);
+    const double Dl = a.dlu[i], Du = a.dlu[m + i];
+    if (p2) {
+        p2[a.n + i] = pl;
+        p2[a.n + m + i] = pu;
+    }
+    const double ql = Dl > 0.0 ? a_i + Dl * pl : 0.0;
+    const double qu = Du > 0.0 ? -a_i + Du * pu : 0.0;
+    a.q[a.n + i] = ql;
+    a.q[a.n + m + i] = qu;
+    if (a.part) a.part[i] = pl * ql + pu * qu;
+    return 2.0 * sig * a_i + (Dl > 0.0 ? pl : 0.0) - (Du > 0.0 ? pu : 0.0);
+}
+
 template <typename VT>
 struct FwdArgs {
     const int* Jp; const int* Jc; const VT* Jv; const double* W; int nJ;
@@ -64,6 +100,7 @@ struct FwdArgs {
     const double* sigA;
     int nbJ;               // blocks of the grid that work on rows of J
     const Flags* fl;
+    AugRows aug;           // doubly augmented system: the lambda block (aug.dlu null: condensed)
 };
 
 __device__ __forceinline__ Gather make_gather(const double* x, const double* p2, const PcgScal* sc) {
@@ -92,7 +129,10 @@ __global__ __launch_bounds__(kBlock) void k_op_fwd(FwdArgs<VT> a) {
         if (row < a.m) {
             double s = row_dot_lane_g<64, double, double>(a.Ap, a.Ac, a.Av, g, row, lane);
             s = group_sum<double, 64>(s);
-            if (lane == 0) a.u[row] = a.sigA ? a.sigA[row] * s : s;
+            if (lane == 0) {
+                if (a.aug.dlu) a.u[row] = aug_row(a.aug, a.m, row, s, a.sigA[row], g, const_cast<double*>(a.p2));
+                else a.u[row] = a.sigA ? a.sigA[row] * s : s;
+            }
         }
     }
 }
@@ -238,10 +278,14 @@ __device__ __forceinline__ void prec_rows(const PrecRows& a, const GV& y, int bl
 }
 
 // Step 1 at the start of a solve: y = r ./ D is held in z.
-__global__ __launch_bounds__(kBlock) void k_prec_a(PrecRows a, const double* y, const Flags* fl) {
-    if (pcg_stopped_ro(fl)) return;
-    prec_rows(a, Gather{y, nullptr, 0.0}, blockIdx.x);
+struct PrecAArgs {
+    PrecRows pa; const double* y; const Flags* fl;
+};
+__device__ __forceinline__ void prec_a_body(const PrecAArgs& a, int b) {
+    if (pcg_stopped_ro(a.fl)) return;
+    prec_rows(a.pa, Gather{a.y, nullptr, 0.0}, b);
 }
+__global__ __launch_bounds__(kBlock) void k_prec_a(PrecAArgs a) { prec_a_body(a, int(blockIdx.x)); }
 
 struct PcgArgs {
     int n;
@@ -270,20 +314,20 @@ struct ScaledResidual {
 // What does not depend on alpha is loaded before the p^T q reduction, so the
 // two overlap: a strong row's range, scale and first pass of entries (column
 // ids, values and the gathered r, q and D), an element block's first entries.
-__global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
+__device__ __forceinline__ void pcg_xr_body(const PcgArgs& a, int bid, int nb) {
     constexpr int U = 8;
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped(a.fl)) return;
     const int lane = threadIdx.x & 63;
-    const bool arow = int(blockIdx.x) < a.nbA;
+    const bool arow = bid < a.nbA;
     // strong-row blocks: a wavefront per row
-    const int row = int(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    const int row = bid * (kBlock / 64) + (threadIdx.x >> 6);
     int e0 = 0, e1 = 0, ld = 0;
     double sqr = 0.0;
     double av[U], rv[U], qv[U], dv[U];
     // element blocks: the first entry of the grid-stride loop
-    const int eb = int(blockIdx.x) - a.nbA;
-    const int ne = int(gridDim.x) - a.nbA;
+    const int eb = bid - a.nbA;
+    const int ne = nb - a.nbA;
     const int j0 = eb * kBlock + threadIdx.x;
     double x0 = 0.0, p0 = 0.0, q0 = 0.0, r0 = 0.0, d0 = 1.0;
     if (arow) {
@@ -320,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
     const double pq = reduce_partials_sum(a.part_pq, a.n_pq, 1, sh);
     const double alpha = a.sc->rho / pq;
     const bool bad = !(pq > 0.0) || !finite_d(alpha);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         a.sc->pq = pq;
         a.sc->alpha = alpha;
         if (bad) a.fl->pcg_breakdown = 1;
@@ -362,6 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) {
         a.part_rr[eb] = rr;
     }
 }
+__global__ __launch_bounds__(kBlock) void k_pcg_xr(PcgArgs a) { pcg_xr_body(a, int(blockIdx.x), int(gridDim.x)); }
 
 // A z for the line-format PCG product, which forms A p of the new direction
 // p = z + beta p as A z + beta (A p) (k_line_pass): the rows of A, a
@@ -377,17 +422,25 @@ struct AzArgs {
 // records ||rhs||^2 as the outer norm; mode 2 (a refinement solve) stops at
 // max(rel_tol * ||rhs||, tol * outer norm), and at once when rhs already
 // meets tol * outer norm.  Blocks 1.. (when az.m > 0): A z, four rows each.
-__global__ __launch_bounds__(kBlock) void k_pcg_scalars(const double* part_rz, int n_rz, const double* part_rr,
-                                                        int n_rr, int mode, double rel_tol, double tol,
-                                                        int max_iter, PcgScal* sc, Flags* fl, AzArgs az) {
+struct ScalArgs {
+    const double* part_rz; int n_rz; const double* part_rr; int n_rr;
+    int mode; double rel_tol; double tol; int max_iter;
+    PcgScal* sc; Flags* fl; AzArgs az;
+};
+__device__ __forceinline__ void pcg_scalars_body(const ScalArgs& s_, int bid) {
+    const double* part_rz = s_.part_rz; const int n_rz = s_.n_rz;
+    const double* part_rr = s_.part_rr; const int n_rr = s_.n_rr;
+    const int mode = s_.mode; const double rel_tol = s_.rel_tol, tol = s_.tol;
+    const int max_iter = s_.max_iter;
+    PcgScal* sc = s_.sc; Flags* fl = s_.fl; const AzArgs& az = s_.az;
     __shared__ double sh[kBlock / 64];
-    if (blockIdx.x > 0) {
+    if (bid > 0) {
         // A z needs no block barrier: each wavefront reads the flags with one
         // uniform load beside its first index load (block 0 may set a flag
         // meanwhile; either reading leaves a valid state, since later kernels
         // test the flags themselves)
         if (mode ? fl->ipm_done : pcg_stopped_raw(fl)) return;
-        const int row = (int(blockIdx.x) - 1) * (kBlock / 64) + (threadIdx.x >> 6);
+        const int row = (bid - 1) * (kBlock / 64) + (threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
         if (row >= az.m) return;
         double s = row_dot_lane<64, double, double, 8>(az.Ap, az.Ac, az.Av, az.z, row, lane);
@@ -429,6 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalars(const double* part_rz, i
     sc->beta = rz / sc->rho;
     sc->rho = rz;
 }
+__global__ __launch_bounds__(kBlock) void k_pcg_scalars(ScalArgs a) { pcg_scalars_body(a, int(blockIdx.x)); }
 
 struct PcgInitArgs {
     int n;
@@ -445,17 +499,17 @@ struct PcgInitArgs {
 // x = 0; r = rhs; z = r ./ d; p = 0; partials.  Clears the PCG flags of the
 // previous solve (no other block of this kernel reads them; later kernels of
 // this solve see them cleared).
-__global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
+__device__ __forceinline__ void pcg_init0_body(const PcgInitArgs& a, int bid, int nb) {
     __shared__ double sh[kBlock / 64];
     if (ipm_finished(a.fl)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         a.fl->pcg_converged = 0;
         a.fl->pcg_breakdown = 0;
         a.fl->pcg_capped = 0;
     }
     const double mu = a.ipm ? a.ipm->mu : 0.0;
     double rz = 0.0, rr = 0.0;
-    for (int j = blockIdx.x * kBlock + threadIdx.x; j < a.n; j += gridDim.x * kBlock) {
+    for (int j = bid * kBlock + threadIdx.x; j < a.n; j += nb * kBlock) {
         const double rj = a.rhs_a ? mu * a.rhs_a[j] + a.rhs_b[j] : a.rhs_b[j];
         const double zj = rj / a.d[j];
         a.x[j] = 0.0;
@@ -466,24 +520,31 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
         rr += rj * rj;
     }
     if (a.apv)
-        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.m; i += gridDim.x * kBlock) a.apv[i] = 0.0;
+        for (int i = bid * kBlock + threadIdx.x; i < a.m; i += nb * kBlock) a.apv[i] = 0.0;
     rz = block_sum(rz, sh);
     rr = block_sum(rr, sh);
     if (threadIdx.x == 0) {
-        if (!a.woodbury) a.part_rz[blockIdx.x] = rz;
-        a.part_rr[blockIdx.x] = rr;
+        if (!a.woodbury) a.part_rz[bid] = rz;
+        a.part_rr[bid] = rr;
     }
+}
+__global__ __launch_bounds__(kBlock) void k_pcg_init0(PcgInitArgs a) {
+    pcg_init0_body(a, int(blockIdx.x), int(gridDim.x));
 }
 
 // Step 2: vm[idx[r]] = sqrt(Sigma) (S^{-1} w)_r, a wavefront per row of the
 // dense symmetric inverse (row-major, leading dimension ld); k from the device.
-__global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, const double* w, const double* sq,
-                                                      const int* idx, const int* kdev, double* vm,
-                                                      const Flags* fl) {
-    if (pcg_stopped_ro(fl)) return;
-    const int k = *kdev;
+struct SymvArgs {
+    const double* Sinv; const double* w; const double* sq; const int* idx; const int* kdev; double* vm;
+    const Flags* fl;
+};
+__device__ __forceinline__ void prec_symv_body(const SymvArgs& a, int bid) {
+    const double* Sinv = a.Sinv; const double* w = a.w; const double* sq = a.sq; const int* idx = a.idx;
+    double* vm = a.vm;
+    if (pcg_stopped_ro(a.fl)) return;
+    const int k = *a.kdev;
     const int ld = ((k + TS_PREC - 1) / TS_PREC) * TS_PREC;
-    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int row = bid * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= k) return;
     const int i = idx[row];       // the output's place and scale, loaded beside the row
@@ -507,23 +568,27 @@ __global__ __launch_bounds__(kBlock) void k_prec_symv(const double* Sinv, const 
     double s = group_sum<double, 64>(((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
     if (lane == 0) vm[i] = sqi * s;
 }
+__global__ __launch_bounds__(kBlock) void k_prec_symv(SymvArgs a) { prec_symv_body(a, int(blockIdx.x)); }
 
 // Step 3: z_j = y_j - (A^T v)_j / D_j and partials of r^T z.  Start of a
 // solve (q null): y is held in z and r is final.  In an iteration: r_j -=
 // alpha q_j is stored here and y_j = r_j / D_j.  G lanes per row of A^T,
 // grid-stride with a capped grid.
+struct PrecAtArgs {
+    const int* Atp; const int* Atc; const double* Atv; const double* v; const double* D;
+    double* r; const double* q; const PcgScal* sc; double* z; int n; double* part_rz; const Flags* fl;
+};
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* Atc, const double* Atv,
-                                                    const double* v, const double* D, double* r,
-                                                    const double* q, const PcgScal* sc, double* z, int n,
-                                                    double* part_rz, const Flags* fl) {
+__device__ __forceinline__ void prec_at_body(const PrecAtArgs& a, int bid, int nb) {
+    const int* Atp = a.Atp; const int* Atc = a.Atc; const double* Atv = a.Atv; const double* v = a.v;
+    const double* D = a.D; double* r = a.r; const double* q = a.q; double* z = a.z; const int n = a.n;
     __shared__ double sh[kBlock / 64];
-    if (pcg_stopped_ro(fl)) return;
+    if (pcg_stopped_ro(a.fl)) return;
     constexpr int RPB = kBlock / G;
     const int lane = threadIdx.x % G;
-    const double alpha = q ? sc->alpha : 0.0;
+    const double alpha = q ? a.sc->alpha : 0.0;
     double rz = 0.0;
-    for (int base = blockIdx.x * RPB; base < n; base += gridDim.x * RPB) {
+    for (int base = bid * RPB; base < n; base += nb * RPB) {
         const int j = base + threadIdx.x / G;
         if (j < n) {
             // the column's own entries are loaded first, beside the sum's loads
@@ -549,7 +614,11 @@ __global__ __launch_bounds__(kBlock) void k_prec_at(const int* Atp, const int* A
         }
     }
     rz = block_sum(rz, sh);
-    if (threadIdx.x == 0) part_rz[blockIdx.x] = rz;
+    if (threadIdx.x == 0) a.part_rz[bid] = rz;
+}
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_prec_at(PrecAtArgs a) {
+    prec_at_body<G>(a, int(blockIdx.x), int(gridDim.x));
 }
 
 // ==========================================================================
@@ -714,6 +783,7 @@ struct IpmBwdArgs {
     const double* t;
     double gamma;
     const double* U; const double* lr_v; int lr_k;   // low-rank part of H (lr_v = w .* U^T x)
+    int aug;               // 1: right-hand side and Jacobi diagonal of the doubly augmented system
 };
 
 // Residual pass, part 2, per variable j: H x (scaled), the A^T products of
@@ -769,9 +839,12 @@ __global__ __launch_bounds__(kBlock) void k_ipm_bwd(IpmBwdArgs a, IpmVec v, cons
                 v.r_ux[j] = ru;
                 v.sigx[j] = gl + gu;
                 v.dh[j] = hs * v.diagH[j] + gl + gu;
-                v.d[j] = v.dh[j] + a2s;
-                v.rhs_a[j] = (hl ? 1.0 / sl : 0.0) - (hu ? 1.0 / su : 0.0) + ava;
-                v.rhs_b[j] = -(hx + pj) - gl * rl + gu * ru + avb;
+                // doubly augmented (eq. (2x2_augmented)): the top-left block
+                // holds 2 A^T Sigma_A A, and its right-hand side r_1 + 2 B^T
+                // D^-1 r_2 is the condensed one plus A^T(mu va + vb + ya)
+                v.d[j] = v.dh[j] + (a.aug ? 2.0 : 1.0) * a2s;
+                v.rhs_a[j] = (hl ? 1.0 / sl : 0.0) - (hu ? 1.0 / su : 0.0) + (a.aug ? 2.0 : 1.0) * ava;
+                v.rhs_b[j] = -(hx + pj) - gl * rl + gu * ru + (a.aug ? 2.0 * avb + aty : avb);
                 mrH = fabs(rH);
                 mHx = fabs(hx);
                 mrg = fmax(fabs(rl), fabs(ru));
@@ -1088,7 +1161,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_h(const int* Jtp, const int* Jt
 // d_j = dh_j + sum_i (A^T)_ji^2 sigA_i.
 __global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double* Atv, const int* Atc,
                                                    int hasA, const double* sigA, const double* sigx,
-                                                   const double* diagH, int n, double* d, double* dh) {
+                                                   const double* diagH, int n, double* d, double* dh, int aug) {
     const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (j >= n) return;
@@ -1101,7 +1174,48 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double*
     s = group_sum<double, 64>(s);
     if (lane == 0) {
         dh[j] = diagH[j] + sigx[j];
-        d[j] = dh[j] + s;
+        d[j] = dh[j] + (aug ? 2.0 * s : s);
+    }
+}
+
+// Lambda block of the doubly augmented system at an IPM iterate, per row i of
+// A and side: D = s/lambda (0 in dlu for an absent side), the Jacobi diagonal
+// (D, or 1 for an absent side) and r_2 = -(r_g + r_c/lambda) = mu/lambda -
+// r_g - s split into its mu coefficient (rhs_a) and the rest (rhs_b), at
+// offsets n (lower side) and n + m (upper side).
+__global__ __launch_bounds__(kBlock) void k_aug_rows(IpmVec v, double* dlu, const Flags* fl) {
+    if (ipm_finished(fl)) return;
+    const int n = v.n, m = v.m;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+        const bool hl = finite_d(v.alo[i]), hu = finite_d(v.ahi[i]);
+        const double sl = v.s_lA[i], su = v.s_uA[i], ll = v.l_lA[i], lu = v.l_uA[i];
+        const double Dl = hl ? sl / ll : 0.0, Du = hu ? su / lu : 0.0;
+        dlu[i] = Dl;
+        dlu[m + i] = Du;
+        v.d[n + i] = hl ? Dl : 1.0;
+        v.d[n + m + i] = hu ? Du : 1.0;
+        v.rhs_a[n + i] = hl ? 1.0 / ll : 0.0;
+        v.rhs_b[n + i] = hl ? -v.r_lA[i] - sl : 0.0;
+        v.rhs_a[n + m + i] = hu ? 1.0 / lu : 0.0;
+        v.rhs_b[n + m + i] = hu ? -v.r_uA[i] - su : 0.0;
+    }
+}
+
+// Lambda block of the doubly augmented system for a Newton step of the
+// condensed system (H + Sigma_x + A^T diag(sigA) A) dx = rhs: each row with
+// sigA_i > 0 is one side with D = 1/sigA_i and r_2 = 0, so the x part of the
+// solution is that dx (the Schur complement of eq. (2x2_augmented)).
+__global__ __launch_bounds__(kBlock) void k_aug_newton_rows(const double* sigA, int n, int m, double* dlu,
+                                                            double* d, double* rhs) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) {
+        const double s = sigA[i];
+        const double Du = s > 0.0 ? 1.0 / s : 0.0;
+        dlu[i] = 0.0;
+        dlu[m + i] = Du;
+        d[n + i] = 1.0;
+        d[n + m + i] = Du > 0.0 ? Du : 1.0;
+        rhs[n + i] = 0.0;
+        rhs[n + m + i] = 0.0;
     }
 }
 

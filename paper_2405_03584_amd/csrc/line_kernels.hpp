@@ -64,10 +64,14 @@ struct LineArgs {
     int nbU;               // blocks forming u from A z and A p (first in the grid)
     const Flags* fl;       // PCG product: skipped once the PCG solve has stopped
     const Flags* fl_ipm;   // residual pass: skipped once the IPM has finished
+    AugRows aug;           // doubly augmented system: the lambda block (aug.dlu null: condensed)
 };
 
+// Body of the line pass for block bi of a grid of nb blocks (the blocks of one
+// QP; a batched launch hands each QP its own range).  remap: spread the line
+// blocks over the XCDs here (a batched launch remaps its whole grid instead).
 template <typename VT, typename AT, bool NT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_line_pass(LineArgs<VT> a) {
+__device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, int nb, bool remap) {
     constexpr int NW = kBlock / 64;
     constexpr int RH = kLineHeld;
     static_assert(NW == 4, "the pass-1 combine adds four wavefront partials");
@@ -78,10 +82,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     // of lines.
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int bi = int(blockIdx.x);
     const int first = a.nbU + a.nbA;
     const bool side = bi < first;   // a u block or an A-row block
-    const int b = side ? a.nbL : xcd_remap(bi - first, int(gridDim.x) - first);
+    const int b = side ? a.nbL : (remap ? xcd_remap(bi - first, nb - first) : bi - first);
     // the line's extent is loaded before the stop test so both loads overlap
     // (blocks past the lines read the last line's extent, unused; L = 0 reads
     // nothing).  With 2- and 4-byte values, where a line is short work and
@@ -191,9 +194,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
         __syncthreads();
         if (threadIdx.x == 0 && row < a.m) {
             const double tot = (rs[0] + rs[1]) + (rs[2] + rs[3]);
-            a.u[row] = a.sigA ? a.sigA[row] * tot : tot;
+            if (a.aug.dlu) a.u[row] = aug_row(a.aug, a.m, row, tot, a.sigA[row], g, const_cast<double*>(a.p2));
+            else a.u[row] = a.sigA ? a.sigA[row] * tot : tot;
         }
     }
+}
+
+template <typename VT, typename AT, bool NT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_line_pass(LineArgs<VT> a) {
+    line_pass_body<VT, AT, NT>(a, int(blockIdx.x), int(gridDim.x), true);
 }
 
 struct SpotArgs {
@@ -213,16 +222,16 @@ struct SpotArgs {
 // q_j = hs*((J^T W J p)_j + gamma p_j + (U(w .* U^T p))_j) + Sigma_x,j p_j + (A^T u)_j
 // with G lanes per spot, per-block partials of p^T q and, in a PCG product,
 // p stored back.
+// Body for block b (already placed on its XCD) of a grid of nb blocks.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_spot_pass(SpotArgs a) {
+__device__ __forceinline__ void spot_pass_body(const SpotArgs& a, int b, int nb) {
     __shared__ double sh[kBlock / 64];
     if (pcg_stopped_ro(a.fl)) return;
     constexpr int RPB = kBlock / G;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x % G;
     const double beta = a.pcg.p2 ? a.pcg.sc->beta : 0.0;
     double dot = 0.0;
-    for (int base = b * RPB; base < a.n; base += gridDim.x * RPB) {
+    for (int base = b * RPB; base < a.n; base += nb * RPB) {
         const int j = base + threadIdx.x / G;
         if (j < a.n) {
             // the spot's own entries are loaded first, beside the sums' loads
@@ -245,6 +254,11 @@ __global__ __launch_bounds__(kBlock) void k_spot_pass(SpotArgs a) {
         }
     }
     product_tail(dot, a.part, b, sh);
+}
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_spot_pass(SpotArgs a) {
+    spot_pass_body<G>(a, xcd_remap(int(blockIdx.x), int(gridDim.x)), int(gridDim.x));
 }
 
 }  // namespace qpg

@@ -28,6 +28,8 @@ namespace {
 
 thread_local std::string g_create_error;
 
+
+
 struct HipError {
     hipError_t e;
     const char* what;
@@ -82,6 +84,11 @@ struct qp_handle {
     // line format of J (64-row lines sharing a column list), used by the PCG operator
     bool line = false;
     int L = 0;
+    int64_t nslots = 0;   // line slots (entries of lc)
+    // doubly augmented system (kkt_system = 1): D of each row and side, and
+    // whether the current operator products use it
+    double* dlu = nullptr;
+    bool aug = false;
     int *lptr = nullptr, *lcol = nullptr, *sptr = nullptr, *sslot = nullptr;
     double* lval = nullptr;
     double* lc = nullptr;   // per-slot J^T contributions of the line pass
@@ -124,6 +131,7 @@ struct qp_handle {
     // captured PCG iteration graphs, one per operator (precision, preconditioner, operands)
     struct PcgGraph {
         int prec = 0, wb = 0, n_rz = 0;
+        bool aug = false;
         const void* ops[4] = {nullptr, nullptr, nullptr, nullptr};   // sigx, sigA, d, dh
         double hs = 0.0;
         hipGraph_t graph = nullptr;   // kept with its executable until both are dropped
@@ -313,7 +321,12 @@ int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, 
     f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
     f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.c = h->lc; f.u = h->u; f.sigA = sigA; f.fl = fl;
     f.nbL = h->L;
-    if (pcg && f.m > 0) {   // A p from A z (k_pcg_scalars) and the previous A p
+    const int grid_spot = grid_rows_capped(h->n, kSpotLanes);
+    const bool aug = h->aug && f.m > 0;
+    if (aug) {   // lambda block on the rows of A, one per workgroup
+        f.nbA = f.m;
+        f.aug.dlu = h->dlu; f.aug.q = q; f.aug.n = h->n; f.aug.part = part ? part + grid_spot : nullptr;
+    } else if (pcg && f.m > 0) {   // A p from A z (k_pcg_scalars) and the previous A p
         f.az = h->az;
         f.apv = h->apv;
         f.nbU = std::min((f.m + kBlock - 1) / kBlock, 64);
@@ -335,12 +348,11 @@ int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, 
     b.u = h->u; b.x = x; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
     b.q = q; b.part = part; b.fl = fl; b.pcg = pl;
     b.U = h->U; b.lr_v = h->lr_v; b.lr_k = h->k;
-    const int grid = grid_rows_capped(h->n, kSpotLanes);
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], h->stream));
-    hipLaunchKernelGGL(k_spot_pass<kSpotLanes>, dim3(grid), dim3(kBlock), 0, h->stream, b);
+    hipLaunchKernelGGL(k_spot_pass<kSpotLanes>, dim3(grid_spot), dim3(kBlock), 0, h->stream, b);
     HIPCHK(hipGetLastError());
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], h->stream));
-    return part ? grid : 0;
+    return part ? grid_spot + (aug ? f.m : 0) : 0;
 }
 
 // q = K p with K = hs*H + diag(sigx) + A^T diag(sigA) A.  pcg = false: p = x,
@@ -360,6 +372,11 @@ int apply_op(qp_handle* h, const double* x, double* q, const double* sigx, const
     f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
     f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.t = h->t; f.u = h->u; f.sigA = sigA; f.fl = fl;
     const int nbA = f.m > 0 ? grid_rows(f.m, 64) : 0;
+    const int n_pq_x = (h->n + kChunkRows - 1) / kChunkRows;   // k_op_bwd's p^T q partials
+    const bool aug = h->aug && f.m > 0;
+    if (aug) {
+        f.aug.dlu = h->dlu; f.aug.q = q; f.aug.n = h->n; f.aug.part = part ? part + n_pq_x : nullptr;
+    }
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
     launch_fwd<VT, AT>(h, h->GJ, f, nbA);
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
@@ -373,7 +390,7 @@ int apply_op(qp_handle* h, const double* x, double* q, const double* sigx, const
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], h->stream));
     const int g = launch_bwd<VT, AT>(h, h->GJt, b);
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], h->stream));
-    return part ? g : 0;
+    return part ? g + (aug ? f.m : 0) : 0;
 }
 
 int apply_op_prec(qp_handle* h, int prec, const double* x, double* q, const double* sigx, const double* sigA,
@@ -521,24 +538,33 @@ int prec_rows_blocks(const qp_handle* h) {
 // (step 1 ran before: k_prec_a at the start of a solve, k_pcg_xr in an
 // iteration, where q != null makes step 3 store r -= alpha q); returns the
 // number of r^T z partials.
+constexpr int kPrecAtLanes = 16;
+SymvArgs symv_args(qp_handle* h) {
+    SymvArgs a{};
+    a.Sinv = h->Sinv; a.w = h->wpre; a.sq = h->ssq; a.idx = h->ridx; a.kdev = h->kdev; a.vm = h->vpre;
+    a.fl = h->fl;
+    return a;
+}
+PrecAtArgs prec_at_args(qp_handle* h, const double* D, const double* q) {
+    PrecAtArgs a{};
+    a.Atp = h->Atp; a.Atc = h->Atc; a.Atv = h->Atv; a.v = h->vpre; a.D = D; a.r = h->pr; a.q = q;
+    a.sc = h->psc; a.z = h->pz; a.n = h->n; a.part_rz = h->part_rz; a.fl = h->fl;
+    return a;
+}
 int apply_precond_23(qp_handle* h, const double* D, const double* sigA, const double* q) {
     const int m = h->m;
-    hipLaunchKernelGGL(k_prec_symv, dim3((m + 3) / 4), dim3(kBlock), 0, h->stream, (const double*)h->Sinv,
-                       (const double*)h->wpre, (const double*)h->ssq, (const int*)h->ridx, (const int*)h->kdev,
-                       h->vpre, (const Flags*)h->fl);
-    const int G = 16;
-    const int grid = grid_rows_capped(h->n, G);
-    hipLaunchKernelGGL(k_prec_at<G>, dim3(grid), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
-                       (const int*)h->Atc, (const double*)h->Atv, (const double*)h->vpre, D, h->pr, q,
-                       (const PcgScal*)h->psc, h->pz, h->n, h->part_rz, (const Flags*)h->fl);
+    hipLaunchKernelGGL(k_prec_symv, dim3((m + 3) / 4), dim3(kBlock), 0, h->stream, symv_args(h));
+    const int grid = grid_rows_capped(h->n, kPrecAtLanes);
+    hipLaunchKernelGGL(k_prec_at<kPrecAtLanes>, dim3(grid), dim3(kBlock), 0, h->stream, prec_at_args(h, D, q));
     HIPCHK(hipGetLastError());
     return grid;
 }
 
 // z = P^{-1} r at the start of a solve, given y = r ./ D in z.
 int apply_precond(qp_handle* h, const double* D, const double* sigA) {
-    hipLaunchKernelGGL(k_prec_a, dim3(prec_rows_blocks(h)), dim3(kBlock), 0, h->stream,
-                       prec_rows_args(h), (const double*)h->pz, (const Flags*)h->fl);
+    PrecAArgs a{};
+    a.pa = prec_rows_args(h); a.y = h->pz; a.fl = h->fl;
+    hipLaunchKernelGGL(k_prec_a, dim3(prec_rows_blocks(h)), dim3(kBlock), 0, h->stream, a);
     return apply_precond_23(h, D, sigA, nullptr);
 }
 
@@ -606,7 +632,8 @@ void autotune_schedule(qp_handle* h) {
 Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, const double* sigx,
               const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode, TimingAcc* tacc,
               double rel_tol, bool refine, bool check_only = false) {
-    const int n = h->n;
+    // vector length of the system: n, or n + 2m for the doubly augmented one
+    const int n = h->aug ? h->n + 2 * h->m : h->n;
     const int ge = grid_elems(n);
     // dh != null selects the constraint-block preconditioner (built for this Sigma)
     const int wb = (h->woodbury && sigA && dh) ? 1 : 0;
@@ -618,7 +645,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     // line format: the product forms A p = A z + beta A p, with A z from the
     // scalar kernel's other blocks
     AzArgs az{};
-    if (h->line && sigA && h->m > 0) {
+    if (h->line && sigA && h->m > 0 && !h->aug) {
         az.Ap = h->Ap; az.Ac = h->Ac; az.Av = h->Av; az.z = h->pz; az.m = h->m; az.az = h->az;
         ia.apv = h->apv; ia.m = h->m;
     }
@@ -628,10 +655,14 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     const int n_rz = wb ? apply_precond(h, dh, sigA) : ge;
     const int cap = (wb && h->wb_attempt_cap > 0) ? std::min(h->set.pcg_max_iter, h->wb_attempt_cap)
                                                   : h->set.pcg_max_iter;
-    hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
-                       (const double*)h->part_rr, ge, refine ? 2 : 1, rel_tol, h->set.pcg_tol, cap,
-                       h->psc, h->fl, az);
+    ScalArgs sa{};
+    sa.part_rz = h->part_rz; sa.n_rz = n_rz; sa.part_rr = h->part_rr; sa.n_rr = ge;
+    sa.mode = refine ? 2 : 1; sa.rel_tol = rel_tol; sa.tol = h->set.pcg_tol; sa.max_iter = cap;
+    sa.sc = h->psc; sa.fl = h->fl; sa.az = az;
+    hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, sa);
     HIPCHK(hipGetLastError());
+    ScalArgs si = sa;   // the iterations' update
+    si.mode = 0; si.rel_tol = 0.0; si.tol = 0.0; si.max_iter = 0;
 
     if (refine) {
         // A refinement solve is often converged at its start (the FP64
@@ -664,8 +695,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         pa.n_pq = apply_op_prec(h, prec, h->pz, h->pq, sigx, sigA, hs, true, timed, slot);
         hipLaunchKernelGGL(k_pcg_xr, dim3(pa.nbA + ge), dim3(kBlock), 0, h->stream, pa);
         if (wb) apply_precond_23(h, dh, sigA, h->pq);
-        hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, (const double*)h->part_rz, n_rz,
-                           (const double*)h->part_rr, ge, 0, 0.0, 0.0, 0, h->psc, h->fl, az);
+        hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, si);
     };
     // Graph mode: the iterations of this operator are captured once as a graph
     // of kGraphIters iterations and replayed (one launch call per kGraphIters
@@ -676,7 +706,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
     if (h->set.graphs && !timing && !h->graphs_failed) {
         const void* ops[4] = {sigx, sigA, d, dh};
         for (auto& g : h->graphs)
-            if (g.prec == prec && g.wb == wb && g.n_rz == n_rz && g.hs == hs && g.ops[0] == ops[0] &&
+            if (g.prec == prec && g.wb == wb && g.n_rz == n_rz && g.hs == hs && g.aug == h->aug && g.ops[0] == ops[0] &&
                 g.ops[1] == ops[1] && g.ops[2] == ops[2] && g.ops[3] == ops[3])
                 gexec = g.exec;
         if (!gexec) {
@@ -706,7 +736,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
                     h->graphs.erase(h->graphs.begin());
                 }
                 qp_handle::PcgGraph g;
-                g.prec = prec; g.wb = wb; g.n_rz = n_rz; g.hs = hs;
+                g.prec = prec; g.wb = wb; g.n_rz = n_rz; g.hs = hs; g.aug = h->aug;
                 for (int i = 0; i < 4; ++i) g.ops[i] = ops[i];
                 g.graph = graph;
                 g.exec = gexec;
@@ -795,7 +825,7 @@ Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double
         *solves = 1;
         return run_pcg(h, QP_FP64, rhs_a, rhs_b, sigx, sigA, d, dh, hs, ipm_mode, tacc, tol, false);
     }
-    const int n = h->n;
+    const int n = h->aug ? h->n + 2 * h->m : h->n;
     const int ge = grid_elems(n);
     const double* rhs = rhs_b;
     if (rhs_a) {
@@ -1048,6 +1078,7 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
             h->sptr = h->upload(lf.sptr.data(), lf.sptr.size());
             h->sslot = h->upload(lf.sslot.data(), lf.sslot.size());
             h->lc = h->dalloc<double>(lf.col.size());
+            h->nslots = int64_t(lf.col.size());
             HIPCHK(hipStreamSynchronize(h->stream));
             h->hlval = std::move(lf.val);
         }
@@ -1076,9 +1107,14 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         IpmVec& v = h->iv;
         v.n = n; v.m = m;
         v.xlo = h->xlo; v.xhi = h->xhi; v.alo = h->alo; v.ahi = h->ahi; v.p = h->p; v.diagH = h->diagH;
-        double** nvec[] = {&v.x, &v.s_lx, &v.s_ux, &v.l_lx, &v.l_ux, &v.r_lx, &v.r_ux, &v.sigx, &v.hx, &v.d,
-                           &v.rhs_a, &v.rhs_b, &v.ds_lx, &v.ds_ux, &v.dl_lx, &v.dl_ux};
+        double** nvec[] = {&v.x, &v.s_lx, &v.s_ux, &v.l_lx, &v.l_ux, &v.r_lx, &v.r_ux, &v.sigx, &v.hx,
+                           &v.ds_lx, &v.ds_ux, &v.dl_lx, &v.dl_ux};
         for (double** pv : nvec) *pv = h->dalloc<double>(n);
+        // vectors of the PCG system: n entries, n + 2m for the doubly augmented one
+        const size_t N = size_t(n) + (h->set.kkt_system == 1 ? 2 * size_t(m) : 0);
+        double** Nvec[] = {&v.d, &v.rhs_a, &v.rhs_b};
+        for (double** pv : Nvec) *pv = h->dalloc<double>(N);
+        if (h->set.kkt_system == 1 && m > 0) h->dlu = h->dalloc<double>(2 * size_t(m));
         double** mvec[] = {&v.s_lA, &v.s_uA, &v.l_lA, &v.l_uA, &v.ax, &v.r_lA, &v.r_uA, &v.sigA,
                            &v.va, &v.vb, &v.ya, &v.ds_lA, &v.ds_uA, &v.dl_lA, &v.dl_uA};
         for (double** pv : mvec) *pv = h->dalloc<double>(std::max(m, 1));
@@ -1086,35 +1122,36 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         h->u = h->dalloc<double>(std::max(m, 1));
         h->az = h->dalloc<double>(std::max(m, 1));
         h->apv = h->dalloc<double>(std::max(m, 1));
-        h->px = h->dalloc<double>(n);
-        h->pr = h->dalloc<double>(n);
-        h->pz = h->dalloc<double>(n);
-        h->pp = h->dalloc<double>(n);
-        h->pq = h->dalloc<double>(n);
+        h->px = h->dalloc<double>(N);
+        h->pr = h->dalloc<double>(N);
+        h->pz = h->dalloc<double>(N);
+        h->pp = h->dalloc<double>(N);
+        h->pq = h->dalloc<double>(N);
         v.dx = h->px;
         h->zero_n = h->dalloc<double>(n);
         h->zero_m = h->dalloc<double>(std::max(m, 1));
         h->tmp_n = h->dalloc<double>(n);
         h->tmp_n2 = h->dalloc<double>(n);
         h->tmp_m = h->dalloc<double>(std::max(m, 1));
-        h->rhs_full = h->dalloc<double>(n);
+        h->rhs_full = h->dalloc<double>(N);
         if (h->k > 0) {
             h->lr_part = h->dalloc<double>(size_t(kLrBlocks) * h->k);
             h->lr_v = h->dalloc<double>(h->k);
         }
-        h->rho = h->dalloc<double>(n);
-        h->dxacc = h->dalloc<double>(n);
+        h->rho = h->dalloc<double>(N);
+        h->dxacc = h->dalloc<double>(N);
         const size_t nbA = size_t((m + 3) / 4) + 1;
         // per-block partials, and six per chunk of four variables (residual pass)
         h->part_len = std::max(8 * (size_t(kMaxPartials) + nbA + 64),
-                               6 * (size_t(n) / kChunkRows + 1) + 64);
+                               6 * (size_t(n) / kChunkRows + 1) + 64) + size_t(m);
         h->part = h->dalloc<double>(h->part_len);
         h->part2 = h->dalloc<double>(h->part_len);
         h->partA = h->dalloc<double>(h->part_len);
         h->part_rz = h->dalloc<double>(h->part_len);
         h->part_rr = h->dalloc<double>(h->part_len);
         v.dh = h->dalloc<double>(n);
-        h->woodbury = (h->set.precond == 1 && m > 0) ? 1 : 0;
+        // the doubly augmented system runs with the Jacobi diagonal (Section 4.1.2)
+        h->woodbury = (h->set.precond == 1 && m > 0 && h->set.kkt_system == 0) ? 1 : 0;
         if (h->woodbury) {
             h->ld = ((m + TS - 1) / TS) * TS;
             h->T = h->ld / TS;
@@ -1282,6 +1319,7 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
         if (!(sigma_A[i] >= 0.0) || !std::isfinite(sigma_A[i]))
             return fail(h, QP_ERR_INVALID, "sigma_A must be finite and >= 0");
     try {
+        h->aug = false;   // the condensed operator
         ensure_lowp(h, precision);
         ensure_timing_events(h);
         HIPCHK(hipMemcpyAsync(h->tmp_n, sigma_x, sizeof(double) * h->n, hipMemcpyHostToDevice, h->stream));
@@ -1338,9 +1376,13 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         HIPCHK(hipMemcpyAsync(b, rhs, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
         reset_flags(h);
         double* dh = h->iv.dh;
+        h->aug = h->set.kkt_system == 1 && m > 0;
         hipLaunchKernelGGL(k_jacobi, dim3(grid_rows(n, 64)), dim3(kBlock), 0, h->stream, (const int*)h->Atp,
                            (const double*)h->Atv, (const int*)h->Atc, m > 0 ? 1 : 0, (const double*)sigA,
-                           (const double*)sigx, (const double*)h->diagH, n, d, dh);
+                           (const double*)sigx, (const double*)h->diagH, n, d, dh, h->aug ? 1 : 0);
+        if (h->aug)
+            hipLaunchKernelGGL(k_aug_newton_rows, dim3(grid_elems(m)), dim3(kBlock), 0, h->stream,
+                               (const double*)sigA, n, m, h->dlu, d, b);
         HIPCHK(hipGetLastError());
         TimingAcc ta;
         HIPCHK(hipEventRecord(h->ev_t0, h->stream));
@@ -1401,6 +1443,7 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
         ensure_timing_events(h);
         const int n = h->n, m = h->m;
         IpmVec& v = h->iv;
+        h->aug = h->set.kkt_system == 1 && m > 0;
         reset_flags(h);
         {
             IpmScal s0{};
@@ -1478,6 +1521,7 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
             ba.Atp = h->Atp; ba.Atc = h->Atc; ba.Atv = h->Atv; ba.hasA = m > 0;
             ba.t = h->t; ba.gamma = h->gamma;
             ba.U = h->U; ba.lr_v = h->lr_v; ba.lr_k = h->k;
+            ba.aug = h->aug ? 1 : 0;
             lowrank_prepare(h, v.x, nullptr, nullptr);
             // lanes per variable: with the line format a variable sums one
             // double per slot of its spot, not one term per nonzero of J
@@ -1491,6 +1535,9 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
                 default: hipLaunchKernelGGL(k_ipm_bwd<64>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
             }
             HIPCHK(hipGetLastError());
+            if (h->aug)   // lambda block of eq. (2x2_augmented): D, its Jacobi entries, r_2
+                hipLaunchKernelGGL(k_aug_rows, dim3(grid_elems(m)), dim3(kBlock), 0, h->stream, v, h->dlu,
+                                   (const Flags*)h->fl);
             hipLaunchKernelGGL(k_ipm_check, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->partA, nbA,
                                (const double*)h->part, (n + kChunkRows - 1) / kChunkRows, apply, h->isc, h->fl,
                                h->log);

@@ -1,7 +1,12 @@
 """Parity bars of the GPU tests against the FP64 oracle, per precision.
 
-* x: ||x - x_oracle||_inf <= 1e-7 when the PCG operator holds J in FP64,
-  1e-5 with FP32 or BF16 values (the mixed-precision target);
+* x: ||x - x_oracle||_inf <= 1e-7 (1 + ||x_oracle||_inf) when the PCG
+  operator holds J in FP64, and <= 1e-5 (absolute, the mixed-precision
+  target) with FP32 or BF16 values.  The FP64 bar is relative to the
+  solution's size because the oracle itself pins x only that far at its
+  stopping rule (mu_tol = 1e-10): its own minimiser moves by 4.4e-7 on the
+  n = 1000 band QP when mu_tol is tightened to 1e-13, and by 4.6e-7 on the
+  ragged-lines QP with the BLAS thread count (||x||_inf = 50 on both);
 * objective: |f - f_oracle| <= 1e-10 |f_oracle| (FP64) or 1e-6 |f_oracle|
   (FP32, BF16), plus the gap the stopping rule itself allows both solvers:
   at exit every scaled lambda_i s_i is below 2 mu_tol, so the objective of
@@ -18,6 +23,13 @@ X_BAR = {"fp64": 1e-7, "fp32": 1e-5, "bf16": 1e-5}
 OBJ_REL_BAR = {"fp64": 1e-10, "fp32": 1e-6, "bf16": 1e-6}
 CERT_BAR = 1e-9
 CERT_AGREE = 1e-11
+
+
+def x_bar(prec, x_ref) -> float:
+    """The x bar of the precision for a reference solution x_ref."""
+    if prec == "fp64":
+        return X_BAR["fp64"] * (1.0 + float(np.abs(x_ref).max(initial=0.0)))
+    return X_BAR[prec]
 
 
 def m_tot(prob) -> int:
@@ -48,7 +60,7 @@ def check_solve(prob, res, x_ref, f_ref, zeta, prec="fp64", status_ok=True):
     if status_ok:
         assert res.status == 0, res.info
     dx = float(np.abs(res.x - x_ref).max()) if prob.n else 0.0
-    assert dx <= X_BAR[prec], (prec, dx)
+    assert dx <= x_bar(prec, x_ref), (prec, dx, x_bar(prec, x_ref))
     dobj = abs(res.info["objective"] - f_ref)
     assert dobj <= OBJ_REL_BAR[prec] * abs(f_ref) + gap_bound(prob, zeta), (prec, dobj, f_ref)
     cert = check_certificate(prob, res)

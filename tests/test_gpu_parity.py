@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import qpsynth
-from bars import X_BAR, check_certificate, check_solve, check_solve_vs_oracle, gap_bound
+from bars import check_certificate, check_solve, check_solve_vs_oracle, x_bar
 from paper_2405_03584_amd import qpgpu
 
 pytestmark = pytest.mark.gpu
@@ -194,7 +194,7 @@ def test_solve_tiny_vs_bruteforce(inst):
     ref = oracle.solve(prob)
     bf = oracle.bruteforce_qp(prob)
     _check_solve(prob, res, ref)
-    assert np.abs(res.x - bf.x).max() <= X_BAR["fp64"]
+    assert np.abs(res.x - bf.x).max() <= x_bar("fp64", bf.x)
 
 
 def test_solve_band_small():
@@ -511,7 +511,7 @@ def test_solve_band_csr_and_line_agree():
     hc = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(spmv_format=1))
     a, b = qpgpu.qp_solve(hl), qpgpu.qp_solve(hc)
     assert a.status == b.status == qpgpu.QP_OK
-    assert np.abs(a.x - b.x).max() <= X_BAR["fp64"]
+    assert np.abs(a.x - b.x).max() <= x_bar("fp64", a.x)
 
 
 # ----------------------------------------------------------------------------

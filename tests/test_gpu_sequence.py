@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import qpsynth
-from bars import X_BAR, check_certificate, check_solve_vs_oracle
+from bars import check_certificate, check_solve_vs_oracle, x_bar
 from paper_2405_03584_amd import qpgpu
 
 pytestmark = pytest.mark.gpu
@@ -141,4 +141,4 @@ def test_batch_of_updated_handles():
         single = qpgpu.qp_solve(h)
         assert np.array_equal(x, single.x)
         ref = oracle.solve(s[2])
-        assert np.abs(x - ref.x).max() <= X_BAR["fp64"]
+        assert np.abs(x - ref.x).max() <= x_bar("fp64", ref.x)
