@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <tuple>
@@ -20,6 +21,7 @@
 #include "schur_kernels.hpp"
 #include "line_kernels.hpp"
 #include "sequence_kernels.hpp"
+#include "batch_kernels.hpp"
 #include "qpgpu.h"
 
 using namespace qpg;
@@ -209,24 +211,39 @@ struct PrecAttemptCap {
     qp_handle* h;
     explicit PrecAttemptCap(qp_handle* hh) : h(hh) { h->wb_attempt_cap = kPrecAttemptIters; }
     ~PrecAttemptCap() { h->wb_attempt_cap = 0; }
-    // a constraint-block solve ended in a way that calls for the Jacobi repeat
-    // (a cap of pcg_max_iter itself, when not above the attempt cap, is final)
-    bool stalled(const Flags& f) const {
-        return f.pcg_breakdown || (f.pcg_capped && h->set.pcg_max_iter > kPrecAttemptIters);
-    }
 };
+// A constraint-block solve ended in a way that calls for the Jacobi repeat
+// (a cap of pcg_max_iter itself, when not above the attempt cap, is final).
+bool prec_stalled(const qp_handle* h, const Flags& f) {
+    return f.pcg_breakdown || (f.pcg_capped && h->set.pcg_max_iter > kPrecAttemptIters);
+}
 constexpr int kGraphIters = 4;   // PCG iterations per captured graph (and per trailing chunk)
+
+// Where an operator product keeps its intermediates, and the stream it is
+// enqueued on (by default the handle's own buffers and stream).
+struct OpWork {
+    hipStream_t st;
+    double* t;         // W .* (J p), CSR format (nJ)
+    double* c;         // per-slot J^T contributions, line format (nslots)
+    double* u;         // Sigma_A .* (A p) (m)
+    double* lr_part;   // U^T p partials (kLrBlocks * k)
+    double* lr_v;      // w .* (U^T p) (k)
+};
+OpWork handle_work(qp_handle* h) { return OpWork{h->stream, h->t, h->lc, h->u, h->lr_part, h->lr_v}; }
 
 // v = w .* (U^T p) for the low-rank part of H (no-op when k = 0); p is x, or
 // x + beta*p2 in a PCG product.
-void lowrank_prepare(qp_handle* h, const double* x, const double* p2, const Flags* fl) {
+void lowrank_prepare(qp_handle* h, const OpWork& wk, const double* x, const double* p2, const Flags* fl) {
     if (h->k == 0) return;
     const int gy = (h->k + 31) / 32;
-    hipLaunchKernelGGL(k_lr_partial, dim3(kLrBlocks, gy), dim3(kBlock), 0, h->stream, (const double*)h->U, h->n,
-                       h->k, x, p2, (const PcgScal*)h->psc, h->lr_part, fl);
-    hipLaunchKernelGGL(k_lr_reduce, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->lr_part, kLrBlocks,
-                       h->k, (const double*)h->w, h->lr_v, fl);
+    hipLaunchKernelGGL(k_lr_partial, dim3(kLrBlocks, gy), dim3(kBlock), 0, wk.st, (const double*)h->U, h->n,
+                       h->k, x, p2, (const PcgScal*)h->psc, wk.lr_part, fl);
+    hipLaunchKernelGGL(k_lr_reduce, dim3(1), dim3(kBlock), 0, wk.st, (const double*)wk.lr_part, kLrBlocks,
+                       h->k, (const double*)h->w, wk.lr_v, fl);
     HIPCHK(hipGetLastError());
+}
+void lowrank_prepare(qp_handle* h, const double* x, const double* p2, const Flags* fl) {
+    lowrank_prepare(h, handle_work(h), x, p2, fl);
 }
 
 int grid_elems(int64_t n) {
@@ -240,30 +257,30 @@ int grid_rows(int64_t rows, int G) {
 int grid_rows_capped(int64_t rows, int G) { return std::min(grid_rows(rows, G), kMaxPartials); }
 
 template <typename VT, typename AT>
-void launch_fwd(qp_handle* h, int G, const FwdArgs<VT>& a0, int nbA) {
+void launch_fwd(hipStream_t st, int G, const FwdArgs<VT>& a0, int nbA) {
     FwdArgs<VT> a = a0;
     a.nbJ = (a.nJ > 0) ? grid_rows(a.nJ, G) : 0;
     const int grid = a.nbJ + nbA;
     if (grid == 0) return;
     switch (G) {
-        case 4: hipLaunchKernelGGL((k_op_fwd<4, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
-        case 8: hipLaunchKernelGGL((k_op_fwd<8, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
-        case 16: hipLaunchKernelGGL((k_op_fwd<16, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
-        case 32: hipLaunchKernelGGL((k_op_fwd<32, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
-        default: hipLaunchKernelGGL((k_op_fwd<64, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        case 4: hipLaunchKernelGGL((k_op_fwd<4, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_op_fwd<8, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((k_op_fwd<16, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 32: hipLaunchKernelGGL((k_op_fwd<32, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_op_fwd<64, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
     }
     HIPCHK(hipGetLastError());
 }
 
 template <typename VT, typename AT>
-int launch_bwd(qp_handle* h, int G, const BwdArgs<VT>& a) {
+int launch_bwd(hipStream_t st, int G, const BwdArgs<VT>& a) {
     const int grid = grid_rows_capped(a.n, G);
     switch (G) {
-        case 4: hipLaunchKernelGGL((k_op_bwd<4, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
-        case 8: hipLaunchKernelGGL((k_op_bwd<8, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
-        case 16: hipLaunchKernelGGL((k_op_bwd<16, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
-        case 32: hipLaunchKernelGGL((k_op_bwd<32, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
-        default: hipLaunchKernelGGL((k_op_bwd<64, VT, AT>), dim3(grid), dim3(kBlock), 0, h->stream, a); break;
+        case 4: hipLaunchKernelGGL((k_op_bwd<4, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_op_bwd<8, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((k_op_bwd<16, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 32: hipLaunchKernelGGL((k_op_bwd<32, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_op_bwd<64, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
     }
     HIPCHK(hipGetLastError());
     return (a.n + kChunkRows - 1) / kChunkRows;   // p^T q partials: one per chunk of rows
@@ -310,16 +327,16 @@ PcgLink pcg_link(qp_handle* h, bool pcg) {
 // (J and the per-slot J^T contributions, A) and the spot pass.
 constexpr int kSpotLanes = 16;
 
-template <typename VT, typename AT>
-int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, const double* sigA, double hs,
-                  bool pcg, bool timed, int tslot) {
+// Arguments of the two kernels of a line-format product (shared by single
+// solves and batched ones).
+template <typename VT>
+LineArgs<VT> line_args(qp_handle* h, const OpWork& wk, const double* x, double* q, const double* sigA, bool pcg) {
     const PcgLink pl = pcg_link(h, pcg);
-    const Flags* fl = pcg ? h->fl : nullptr;
     double* part = pcg ? h->part : nullptr;
     LineArgs<VT> f{};
     f.lptr = h->lptr; f.lcol = h->lcol; f.lval = line_vals<VT>(h); f.L = h->L; f.W = h->W;
     f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
-    f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.c = h->lc; f.u = h->u; f.sigA = sigA; f.fl = fl;
+    f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.c = wk.c; f.u = wk.u; f.sigA = sigA; f.fl = pcg ? h->fl : nullptr;
     f.nbL = h->L;
     const int grid_spot = grid_rows_capped(h->n, kSpotLanes);
     const bool aug = h->aug && f.m > 0;
@@ -333,26 +350,46 @@ int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, 
     } else {
         f.nbA = f.m;
     }
-    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
-    const dim3 lgrid(std::max(1, f.nbL + f.nbA + f.nbU));
-    if (line_vals_streamed<VT>(h))
-        hipLaunchKernelGGL((k_line_pass<VT, AT, true>), lgrid, dim3(kBlock), 0, h->stream, f);
-    else
-        hipLaunchKernelGGL((k_line_pass<VT, AT, false>), lgrid, dim3(kBlock), 0, h->stream, f);
-    HIPCHK(hipGetLastError());
-    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
-    lowrank_prepare(h, x, pl.p2, fl);
+    return f;
+}
+template <typename VT>
+int line_blocks(const LineArgs<VT>& f) { return std::max(1, f.nbL + f.nbA + f.nbU); }
+
+SpotArgs spot_args(qp_handle* h, const OpWork& wk, const double* x, double* q, const double* sigx,
+                   const double* sigA, double hs, bool pcg) {
     SpotArgs b{};
-    b.sptr = h->sptr; b.sslot = h->sslot; b.c = h->lc; b.n = h->n;
-    b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = f.m > 0;
-    b.u = h->u; b.x = x; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
-    b.q = q; b.part = part; b.fl = fl; b.pcg = pl;
-    b.U = h->U; b.lr_v = h->lr_v; b.lr_k = h->k;
-    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], h->stream));
-    hipLaunchKernelGGL(k_spot_pass<kSpotLanes>, dim3(grid_spot), dim3(kBlock), 0, h->stream, b);
+    b.sptr = h->sptr; b.sslot = h->sslot; b.c = wk.c; b.n = h->n;
+    b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = (sigA && h->m > 0) ? 1 : 0;
+    b.u = wk.u; b.x = x; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
+    b.q = q; b.part = pcg ? h->part : nullptr; b.fl = pcg ? h->fl : nullptr; b.pcg = pcg_link(h, pcg);
+    b.U = h->U; b.lr_v = wk.lr_v; b.lr_k = h->k;
+    return b;
+}
+int spot_blocks(const qp_handle* h) { return grid_rows_capped(h->n, kSpotLanes); }
+// p^T q partials of a PCG product on the line format
+int line_pq_partials(const qp_handle* h, const double* sigA) {
+    return spot_blocks(h) + ((h->aug && sigA && h->m > 0) ? h->m : 0);
+}
+
+template <typename VT, typename AT>
+int apply_op_line(qp_handle* h, const OpWork& wk, const double* x, double* q, const double* sigx,
+                  const double* sigA, double hs, bool pcg, bool timed, int tslot) {
+    const LineArgs<VT> f = line_args<VT>(h, wk, x, q, sigA, pcg);
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], wk.st));
+    const dim3 lgrid(line_blocks(f));
+    if (line_vals_streamed<VT>(h))
+        hipLaunchKernelGGL((k_line_pass<VT, AT, true>), lgrid, dim3(kBlock), 0, wk.st, f);
+    else
+        hipLaunchKernelGGL((k_line_pass<VT, AT, false>), lgrid, dim3(kBlock), 0, wk.st, f);
     HIPCHK(hipGetLastError());
-    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], h->stream));
-    return part ? grid_spot + (aug ? f.m : 0) : 0;
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], wk.st));
+    lowrank_prepare(h, wk, x, f.p2, f.fl);
+    const SpotArgs b = spot_args(h, wk, x, q, sigx, sigA, hs, pcg);
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], wk.st));
+    hipLaunchKernelGGL(k_spot_pass<kSpotLanes>, dim3(spot_blocks(h)), dim3(kBlock), 0, wk.st, b);
+    HIPCHK(hipGetLastError());
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], wk.st));
+    return pcg ? line_pq_partials(h, sigA) : 0;
 }
 
 // q = K p with K = hs*H + diag(sigx) + A^T diag(sigA) A.  pcg = false: p = x,
@@ -360,8 +397,8 @@ int apply_op_line(qp_handle* h, const double* x, double* q, const double* sigx, 
 // (x = z), skipped once the solve has stopped.  Returns the number of p^T q
 // partials (0 when pcg is false).
 template <typename VT, typename AT>
-int apply_op(qp_handle* h, const double* x, double* q, const double* sigx, const double* sigA, double hs,
-             bool pcg, bool timed, int tslot) {
+int apply_op(qp_handle* h, const OpWork& wk, const double* x, double* q, const double* sigx, const double* sigA,
+             double hs, bool pcg, bool timed, int tslot) {
     const PcgLink pl = pcg_link(h, pcg);
     const Flags* fl = pcg ? h->fl : nullptr;
     double* part = pcg ? h->part : nullptr;
@@ -370,43 +407,47 @@ int apply_op(qp_handle* h, const double* x, double* q, const double* sigx, const
     mat_ptrs<VT>(h, jv, jtv);
     f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = jv; f.W = h->W; f.nJ = h->nJ;
     f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = sigA ? h->m : 0;
-    f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.t = h->t; f.u = h->u; f.sigA = sigA; f.fl = fl;
+    f.x = x; f.p2 = pl.p2; f.sc = h->psc; f.t = wk.t; f.u = wk.u; f.sigA = sigA; f.fl = fl;
     const int nbA = f.m > 0 ? grid_rows(f.m, 64) : 0;
     const int n_pq_x = (h->n + kChunkRows - 1) / kChunkRows;   // k_op_bwd's p^T q partials
     const bool aug = h->aug && f.m > 0;
     if (aug) {
         f.aug.dlu = h->dlu; f.aug.q = q; f.aug.n = h->n; f.aug.part = part ? part + n_pq_x : nullptr;
     }
-    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], h->stream));
-    launch_fwd<VT, AT>(h, h->GJ, f, nbA);
-    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], h->stream));
-    lowrank_prepare(h, x, pl.p2, fl);
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], wk.st));
+    launch_fwd<VT, AT>(wk.st, h->GJ, f, nbA);
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], wk.st));
+    lowrank_prepare(h, wk, x, pl.p2, fl);
     BwdArgs<VT> b{};
     b.Jtp = h->Jtp; b.Jtc = h->Jtc; b.Jtv = jtv; b.n = h->n;
     b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = f.m > 0;
-    b.t = h->t; b.u = h->u; b.x = x; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
+    b.t = wk.t; b.u = wk.u; b.x = x; b.sigx = sigx; b.hs = hs; b.gamma = h->gamma;
     b.q = q; b.part = part; b.fl = fl; b.pcg = pl;
-    b.U = h->U; b.lr_v = h->lr_v; b.lr_k = h->k;
-    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], h->stream));
-    const int g = launch_bwd<VT, AT>(h, h->GJt, b);
-    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], h->stream));
+    b.U = h->U; b.lr_v = wk.lr_v; b.lr_k = h->k;
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], wk.st));
+    const int g = launch_bwd<VT, AT>(wk.st, h->GJt, b);
+    if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], wk.st));
     return part ? g + (aug ? f.m : 0) : 0;
 }
 
-int apply_op_prec(qp_handle* h, int prec, const double* x, double* q, const double* sigx, const double* sigA,
-                  double hs, bool pcg, bool timed, int tslot) {
+int apply_op_prec(qp_handle* h, const OpWork& wk, int prec, const double* x, double* q, const double* sigx,
+                  const double* sigA, double hs, bool pcg, bool timed, int tslot) {
     if (h->line) {
         switch (prec) {
-            case QP_FP32: return apply_op_line<float, float>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
-            case QP_BF16: return apply_op_line<bf16_t, float>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
-            default: return apply_op_line<double, double>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
+            case QP_FP32: return apply_op_line<float, float>(h, wk, x, q, sigx, sigA, hs, pcg, timed, tslot);
+            case QP_BF16: return apply_op_line<bf16_t, float>(h, wk, x, q, sigx, sigA, hs, pcg, timed, tslot);
+            default: return apply_op_line<double, double>(h, wk, x, q, sigx, sigA, hs, pcg, timed, tslot);
         }
     }
     switch (prec) {
-        case QP_FP32: return apply_op<float, float>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
-        case QP_BF16: return apply_op<bf16_t, float>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
-        default: return apply_op<double, double>(h, x, q, sigx, sigA, hs, pcg, timed, tslot);
+        case QP_FP32: return apply_op<float, float>(h, wk, x, q, sigx, sigA, hs, pcg, timed, tslot);
+        case QP_BF16: return apply_op<bf16_t, float>(h, wk, x, q, sigx, sigA, hs, pcg, timed, tslot);
+        default: return apply_op<double, double>(h, wk, x, q, sigx, sigA, hs, pcg, timed, tslot);
     }
+}
+int apply_op_prec(qp_handle* h, int prec, const double* x, double* q, const double* sigx, const double* sigA,
+                  double hs, bool pcg, bool timed, int tslot) {
+    return apply_op_prec(h, handle_work(h), prec, x, q, sigx, sigA, hs, pcg, timed, tslot);
 }
 
 // SpMV schedule autotuner for CSR matrices: time each lane-group size for the
@@ -535,9 +576,9 @@ int prec_rows_blocks(const qp_handle* h) {
 }
 
 // Steps 2 and 3 of z = P^{-1} r for the constraint-block preconditioner
-// (step 1 ran before: k_prec_a at the start of a solve, k_pcg_xr in an
-// iteration, where q != null makes step 3 store r -= alpha q); returns the
-// number of r^T z partials.
+// (step 1 runs before: k_prec_a at the start of a solve, k_pcg_xr in an
+// iteration, where q != null makes step 3 store r -= alpha q).  Step 3's
+// blocks each leave one r^T z partial.
 constexpr int kPrecAtLanes = 16;
 SymvArgs symv_args(qp_handle* h) {
     SymvArgs a{};
@@ -550,22 +591,6 @@ PrecAtArgs prec_at_args(qp_handle* h, const double* D, const double* q) {
     a.Atp = h->Atp; a.Atc = h->Atc; a.Atv = h->Atv; a.v = h->vpre; a.D = D; a.r = h->pr; a.q = q;
     a.sc = h->psc; a.z = h->pz; a.n = h->n; a.part_rz = h->part_rz; a.fl = h->fl;
     return a;
-}
-int apply_precond_23(qp_handle* h, const double* D, const double* sigA, const double* q) {
-    const int m = h->m;
-    hipLaunchKernelGGL(k_prec_symv, dim3((m + 3) / 4), dim3(kBlock), 0, h->stream, symv_args(h));
-    const int grid = grid_rows_capped(h->n, kPrecAtLanes);
-    hipLaunchKernelGGL(k_prec_at<kPrecAtLanes>, dim3(grid), dim3(kBlock), 0, h->stream, prec_at_args(h, D, q));
-    HIPCHK(hipGetLastError());
-    return grid;
-}
-
-// z = P^{-1} r at the start of a solve, given y = r ./ D in z.
-int apply_precond(qp_handle* h, const double* D, const double* sigA) {
-    PrecAArgs a{};
-    a.pa = prec_rows_args(h); a.y = h->pz; a.fl = h->fl;
-    hipLaunchKernelGGL(k_prec_a, dim3(prec_rows_blocks(h)), dim3(kBlock), 0, h->stream, a);
-    return apply_precond_23(h, D, sigA, nullptr);
 }
 
 void autotune_schedule(qp_handle* h) {
@@ -596,7 +621,7 @@ void autotune_schedule(qp_handle* h) {
             f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = h->Jv; f.W = h->W; f.nJ = h->nJ;
             f.x = h->zero_n; f.t = h->t; f.u = h->u;
             HIPCHK(hipEventRecord(e0, h->stream));
-            launch_fwd<double, double>(h, g, f, 0);
+            launch_fwd<double, double>(h->stream, g, f, 0);
             HIPCHK(hipEventRecord(e1, h->stream));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -607,7 +632,7 @@ void autotune_schedule(qp_handle* h) {
             b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = h->m > 0;
             b.t = h->t; b.u = h->zero_m; b.x = h->zero_n; b.hs = 1.0; b.q = h->tmp_n;
             HIPCHK(hipEventRecord(e0, h->stream));
-            launch_bwd<double, double>(h, g, b);
+            launch_bwd<double, double>(h->stream, g, b);
             HIPCHK(hipEventRecord(e1, h->stream));
             HIPCHK(hipEventSynchronize(e1));
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
@@ -629,19 +654,36 @@ void autotune_schedule(qp_handle* h) {
 // read on the device).  Preconditioner: Jacobi with d, or (h->woodbury and
 // sigA given) the constraint block with D = dh.  dx is written to h->px.
 // Returns the flags after the solve.
-Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, const double* sigx,
-              const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode, TimingAcc* tacc,
-              double rel_tol, bool refine, bool check_only = false) {
+// Launch arguments of one PCG solve of a QP (shared by run_pcg and the
+// batched solves): the start (k_pcg_init0, the preconditioner's first
+// application, k_pcg_scalars in mode 1 or 2) and the iterations (k_pcg_xr,
+// steps 2 and 3 of the preconditioner, k_pcg_scalars in mode 0), with the
+// grid of each.
+struct PcgSetup {
+    int n = 0, ge = 0, wb = 0, n_rz = 0, gs = 0;
+    PcgInitArgs ia{};
+    PrecAArgs prea{};      // wb: step 1 at the start
+    SymvArgs sy{};         // wb: step 2
+    PrecAtArgs at0{}, at{};   // wb: step 3 at the start / in an iteration
+    ScalArgs sa{}, si{};   // start / iteration
+    PcgArgs pa{};          // pa.n_pq is the product's to fill
+    int nb_preca = 0, nb_symv = 0, nb_at = 0, nb_xr = 0;
+};
+
+PcgSetup pcg_setup(qp_handle* h, const double* rhs_a, const double* rhs_b, const double* sigA, const double* d,
+                   const double* dh, bool ipm_mode, double rel_tol, bool refine) {
+    PcgSetup S;
     // vector length of the system: n, or n + 2m for the doubly augmented one
     const int n = h->aug ? h->n + 2 * h->m : h->n;
-    const int ge = grid_elems(n);
+    S.n = n;
+    S.ge = grid_elems(n);
     // dh != null selects the constraint-block preconditioner (built for this Sigma)
-    const int wb = (h->woodbury && sigA && dh) ? 1 : 0;
-    const double* dd = wb ? dh : d;
-    PcgInitArgs ia{};
+    S.wb = (h->woodbury && sigA && dh) ? 1 : 0;
+    const double* dd = S.wb ? dh : d;
+    PcgInitArgs& ia = S.ia;
     ia.n = n; ia.rhs_a = rhs_a; ia.rhs_b = rhs_b; ia.ipm = ipm_mode ? h->isc : nullptr;
     ia.x = h->px; ia.r = h->pr; ia.z = h->pz; ia.p = h->pp; ia.d = dd;
-    ia.part_rz = h->part_rz; ia.part_rr = h->part_rr; ia.woodbury = wb; ia.fl = h->fl;
+    ia.part_rz = h->part_rz; ia.part_rr = h->part_rr; ia.woodbury = S.wb; ia.fl = h->fl;
     // line format: the product forms A p = A z + beta A p, with A z from the
     // scalar kernel's other blocks
     AzArgs az{};
@@ -649,20 +691,57 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         az.Ap = h->Ap; az.Ac = h->Ac; az.Av = h->Av; az.z = h->pz; az.m = h->m; az.az = h->az;
         ia.apv = h->apv; ia.m = h->m;
     }
-    const int gs = 1 + (az.m + kBlock / 64 - 1) / (kBlock / 64);
-    hipLaunchKernelGGL(k_pcg_init0, dim3(ge), dim3(kBlock), 0, h->stream, ia);
-    HIPCHK(hipGetLastError());
-    const int n_rz = wb ? apply_precond(h, dh, sigA) : ge;
-    const int cap = (wb && h->wb_attempt_cap > 0) ? std::min(h->set.pcg_max_iter, h->wb_attempt_cap)
-                                                  : h->set.pcg_max_iter;
-    ScalArgs sa{};
-    sa.part_rz = h->part_rz; sa.n_rz = n_rz; sa.part_rr = h->part_rr; sa.n_rr = ge;
+    S.gs = 1 + (az.m + kBlock / 64 - 1) / (kBlock / 64);
+    if (S.wb) {
+        S.prea.pa = prec_rows_args(h); S.prea.y = h->pz; S.prea.fl = h->fl;
+        S.nb_preca = prec_rows_blocks(h);
+        S.sy = symv_args(h);
+        S.nb_symv = (h->m + 3) / 4;
+        S.at0 = prec_at_args(h, dh, nullptr);
+        S.at = prec_at_args(h, dh, h->pq);
+        S.nb_at = grid_rows_capped(h->n, kPrecAtLanes);
+    }
+    S.n_rz = S.wb ? S.nb_at : S.ge;
+    const int cap = (S.wb && h->wb_attempt_cap > 0) ? std::min(h->set.pcg_max_iter, h->wb_attempt_cap)
+                                                    : h->set.pcg_max_iter;
+    ScalArgs& sa = S.sa;
+    sa.part_rz = h->part_rz; sa.n_rz = S.n_rz; sa.part_rr = h->part_rr; sa.n_rr = S.ge;
     sa.mode = refine ? 2 : 1; sa.rel_tol = rel_tol; sa.tol = h->set.pcg_tol; sa.max_iter = cap;
     sa.sc = h->psc; sa.fl = h->fl; sa.az = az;
-    hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, sa);
+    S.si = sa;   // the iterations' update
+    S.si.mode = 0; S.si.rel_tol = 0.0; S.si.tol = 0.0; S.si.max_iter = 0;
+    PcgArgs& pa = S.pa;
+    pa.n = n; pa.x = h->px; pa.r = h->pr; pa.z = h->pz; pa.p = h->pp; pa.q = h->pq; pa.d = dd;
+    pa.part_pq = h->part; pa.part_rz = h->part_rz; pa.part_rr = h->part_rr;
+    pa.woodbury = S.wb; pa.sc = h->psc; pa.fl = h->fl;
+    if (S.wb) {
+        pa.pa = prec_rows_args(h);
+        pa.nbA = prec_rows_blocks(h);
+    }
+    S.nb_xr = pa.nbA + S.ge;
+    return S;
+}
+
+// One PCG solve of K dx = rhs (rhs = mu*rhs_a + rhs_b when rhs_a is given, mu
+// read on the device).  Preconditioner: Jacobi with d, or (h->woodbury and
+// sigA given) the constraint block with D = dh.  dx is written to h->px.
+// Returns the flags after the solve.
+Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, const double* sigx,
+              const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode, TimingAcc* tacc,
+              double rel_tol, bool refine, bool check_only = false) {
+    PcgSetup S = pcg_setup(h, rhs_a, rhs_b, sigA, d, dh, ipm_mode, rel_tol, refine);
+    const int wb = S.wb, n_rz = S.n_rz, ge = S.ge, gs = S.gs;
+    hipLaunchKernelGGL(k_pcg_init0, dim3(ge), dim3(kBlock), 0, h->stream, S.ia);
     HIPCHK(hipGetLastError());
-    ScalArgs si = sa;   // the iterations' update
-    si.mode = 0; si.rel_tol = 0.0; si.tol = 0.0; si.max_iter = 0;
+    if (wb) {
+        hipLaunchKernelGGL(k_prec_a, dim3(S.nb_preca), dim3(kBlock), 0, h->stream, S.prea);
+        hipLaunchKernelGGL(k_prec_symv, dim3(S.nb_symv), dim3(kBlock), 0, h->stream, S.sy);
+        hipLaunchKernelGGL(k_prec_at<kPrecAtLanes>, dim3(S.nb_at), dim3(kBlock), 0, h->stream, S.at0);
+        HIPCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, S.sa);
+    HIPCHK(hipGetLastError());
+    const ScalArgs si = S.si;
 
     if (refine) {
         // A refinement solve is often converged at its start (the FP64
@@ -673,14 +752,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         if (f0.pcg_converged || f0.pcg_breakdown || f0.pcg_capped || f0.ipm_done || check_only) return f0;
     }
 
-    PcgArgs pa{};
-    pa.n = n; pa.x = h->px; pa.r = h->pr; pa.z = h->pz; pa.p = h->pp; pa.q = h->pq; pa.d = dd;
-    pa.part_pq = h->part; pa.part_rz = h->part_rz; pa.part_rr = h->part_rr;
-    pa.woodbury = wb; pa.sc = h->psc; pa.fl = h->fl;
-    if (wb) {
-        pa.pa = prec_rows_args(h);
-        pa.nbA = prec_rows_blocks(h);
-    }
+    PcgArgs pa = S.pa;
 
     const bool timing = h->set.timing != 0 && tacc != nullptr;
     const int slot_begin = tacc ? tacc->pairs : 0;
@@ -693,8 +765,11 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
             tacc->valid.push_back(1);
         }
         pa.n_pq = apply_op_prec(h, prec, h->pz, h->pq, sigx, sigA, hs, true, timed, slot);
-        hipLaunchKernelGGL(k_pcg_xr, dim3(pa.nbA + ge), dim3(kBlock), 0, h->stream, pa);
-        if (wb) apply_precond_23(h, dh, sigA, h->pq);
+        hipLaunchKernelGGL(k_pcg_xr, dim3(S.nb_xr), dim3(kBlock), 0, h->stream, pa);
+        if (wb) {
+            hipLaunchKernelGGL(k_prec_symv, dim3(S.nb_symv), dim3(kBlock), 0, h->stream, S.sy);
+            hipLaunchKernelGGL(k_prec_at<kPrecAtLanes>, dim3(S.nb_at), dim3(kBlock), 0, h->stream, S.at);
+        }
         hipLaunchKernelGGL(k_pcg_scalars, dim3(gs), dim3(kBlock), 0, h->stream, si);
     };
     // Graph mode: the iterations of this operator are captured once as a graph
@@ -939,6 +1014,1044 @@ qp_status fail(qp_handle* h, qp_status st, const std::string& msg) {
     return st;
 }
 
+
+
+// ==========================================================================
+// Algorithm 1 in phases: start, direction, step, finish.  qp_solve runs the
+// phases of one QP in turn; qp_solve_batch interleaves the phases of many
+// QPs around batched PCG solves.
+// ==========================================================================
+
+// State of one QP's run, kept between its phases.
+struct IpmRun {
+    qp_handle* h = nullptr;
+    double hs = 1.0;              // objective scale 1/zeta
+    bool wbp = false;             // constraint-block preconditioner built for the current iterate
+    bool jacobi_only = false;     // a stalled constraint-block solve switched this QP to Jacobi
+    int fallbacks = 0;
+    int64_t pcg_total = 0;
+    int pcg_solves = 0, capped = 0;
+    float pcg_ms = 0.f;
+    bool pcg_timed[2] = {false, false};
+    int it = 0;                   // IPM iterations whose direction was computed
+    bool done = false;            // the IPM has finished or stopped on an error
+    qp_status st = QP_OK;
+    TimingAcc ta;
+};
+
+// Residual pass at the current iterate (Algorithm 1, the residuals before
+// the barrier rule): H x, A x, r_H, r_g, Sigma, the Jacobi diagonals, the
+// right-hand side, and the barrier rule on the device (k_ipm_check; apply = 0
+// at the start point).
+void ipm_residuals(qp_handle* h, int apply) {
+    const int n = h->n, m = h->m;
+    IpmVec& v = h->iv;
+    const int G = h->GJ, Gt = h->GJt;
+    FwdArgs<double> f{};
+    f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = h->Jv; f.W = h->W; f.nJ = h->nJ;
+    f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = m;
+    f.x = v.x; f.t = h->t; f.u = h->u; f.sigA = nullptr; f.fl = nullptr;
+    // line format: J x and the per-slot shares of J^T W J x come from
+    // one read of J in the line pass; k_ipm_fwd keeps the rows of A
+    f.nbJ = (h->nJ > 0 && !h->line) ? grid_rows(h->nJ, G) : 0;
+    const int nbA = m > 0 ? grid_rows(m, 64) : 0;
+    if (h->line) {
+        LineArgs<double> la{};
+        la.lptr = h->lptr; la.lcol = h->lcol; la.lval = h->lval; la.L = h->L; la.W = h->W;
+        la.x = v.x; la.c = h->lc; la.u = h->u; la.nbL = h->L; la.nbA = 0; la.fl_ipm = h->fl;
+        if (line_vals_streamed<double>(h))
+            hipLaunchKernelGGL((k_line_pass<double, double, true>), dim3(std::max(1, h->L)), dim3(kBlock), 0,
+                               h->stream, la);
+        else
+            hipLaunchKernelGGL((k_line_pass<double, double, false>), dim3(std::max(1, h->L)), dim3(kBlock), 0,
+                               h->stream, la);
+        HIPCHK(hipGetLastError());
+    }
+    const int grid = std::max(1, f.nbJ + nbA);
+    const IpmScal* isc = h->isc;
+    const Flags* fl = h->fl;
+    switch (G) {
+        case 4: hipLaunchKernelGGL(k_ipm_fwd<4>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, isc, h->partA, fl); break;
+        case 8: hipLaunchKernelGGL(k_ipm_fwd<8>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, isc, h->partA, fl); break;
+        case 16: hipLaunchKernelGGL(k_ipm_fwd<16>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, isc, h->partA, fl); break;
+        case 32: hipLaunchKernelGGL(k_ipm_fwd<32>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, isc, h->partA, fl); break;
+        default: hipLaunchKernelGGL(k_ipm_fwd<64>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, isc, h->partA, fl); break;
+    }
+    HIPCHK(hipGetLastError());
+    IpmBwdArgs ba{};
+    ba.Jtp = h->Jtp; ba.Jtc = h->Jtc; ba.Jtv = h->Jtv;
+    if (h->line) { ba.sptr = h->sptr; ba.sslot = h->sslot; ba.lc = h->lc; }
+    ba.Atp = h->Atp; ba.Atc = h->Atc; ba.Atv = h->Atv; ba.hasA = m > 0;
+    ba.t = h->t; ba.gamma = h->gamma;
+    ba.U = h->U; ba.lr_v = h->lr_v; ba.lr_k = h->k;
+    ba.aug = h->aug ? 1 : 0;
+    lowrank_prepare(h, v.x, nullptr, nullptr);
+    // lanes per variable: with the line format a variable sums one
+    // double per slot of its spot, not one term per nonzero of J
+    const int Gb = h->line ? pick_lanes(h->nnzJ / 64 + h->nnzA, n) : Gt;
+    const int gb = grid_rows_capped(n, Gb);
+    switch (Gb) {
+        case 4: hipLaunchKernelGGL(k_ipm_bwd<4>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, isc, h->part, fl); break;
+        case 8: hipLaunchKernelGGL(k_ipm_bwd<8>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, isc, h->part, fl); break;
+        case 16: hipLaunchKernelGGL(k_ipm_bwd<16>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, isc, h->part, fl); break;
+        case 32: hipLaunchKernelGGL(k_ipm_bwd<32>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, isc, h->part, fl); break;
+        default: hipLaunchKernelGGL(k_ipm_bwd<64>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, isc, h->part, fl); break;
+    }
+    HIPCHK(hipGetLastError());
+    if (h->aug)   // lambda block of eq. (2x2_augmented): D, its Jacobi entries, r_2
+        hipLaunchKernelGGL(k_aug_rows, dim3(grid_elems(m)), dim3(kBlock), 0, h->stream, v, h->dlu, fl);
+    hipLaunchKernelGGL(k_ipm_check, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->partA, nbA,
+                       (const double*)h->part, (n + kChunkRows - 1) / kChunkRows, apply, h->isc, h->fl, h->log);
+    HIPCHK(hipGetLastError());
+}
+
+const int* ipm_stop_flag(qp_handle* h) { return reinterpret_cast<const int*>(&h->fl->ipm_done); }
+
+// Start point (R6 reading of Section 3.1), objective scale, mu0, the first
+// residual pass and the first preconditioner.
+void ipm_start(IpmRun& r, const double* x0) {
+    qp_handle* h = r.h;
+    ensure_timing_events(h);
+    const int n = h->n, m = h->m;
+    IpmVec& v = h->iv;
+    h->aug = h->set.kkt_system == 1 && m > 0;
+    reset_flags(h);
+    {
+        IpmScal s0{};
+        s0.mu_tol = h->set.mu_tol;
+        s0.tau = h->set.tau;
+        s0.cscale = h->cscale;
+        s0.step_mode = h->set.step_mode;
+        HIPCHK(hipMemcpyAsync(h->isc, &s0, sizeof(IpmScal), hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHK(hipEventRecord(h->ev_t0, h->stream));
+    const int gx = grid_elems(n);
+    if (x0) {
+        if (!h->x0d) h->x0d = h->dalloc<double>(n);
+        HIPCHK(hipMemcpyAsync(h->x0d, x0, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+        hipLaunchKernelGGL(k_ipm_init_x_from, dim3(gx), dim3(kBlock), 0, h->stream, v, (const double*)h->x0d,
+                           h->partA);
+    } else {
+        hipLaunchKernelGGL(k_ipm_init_x, dim3(gx), dim3(kBlock), 0, h->stream, v, h->partA);
+    }
+    HIPCHK(hipGetLastError());
+    int nps = gx;
+    if (m > 0) {
+        const int ga = grid_rows(m, 64);
+        hipLaunchKernelGGL(k_ipm_init_A, dim3(ga), dim3(kBlock), 0, h->stream, v, (const int*)h->Ap,
+                           (const int*)h->Ac, (const double*)h->Av, h->partA + gx);
+        HIPCHK(hipGetLastError());
+        nps += ga;
+    }
+    apply_op<double, double>(h, handle_work(h), v.x, h->tmp_n, nullptr, nullptr, 1.0, false, false, 0);
+    hipLaunchKernelGGL(k_ipm_scale, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->tmp_n,
+                       (const double*)h->p, n, (const double*)h->partA, nps, h->mtot, h->set.scale_objective,
+                       h->set.mu0, h->isc);
+    HIPCHK(hipGetLastError());
+    IpmScal sc{};
+    HIPCHK(hipMemcpyAsync(&sc, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    r.hs = sc.hs;
+    ipm_residuals(h, 0);
+    r.wbp = (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop_flag(h));
+}
+
+// The PCG time of an IPM iteration is read two iterations later (its events
+// are long complete by then), so the host never waits for the device just
+// to time it.
+void harvest_pcg_ms(IpmRun& r, int slot) {
+    if (!r.pcg_timed[slot]) return;
+    qp_handle* h = r.h;
+    HIPCHK(hipEventSynchronize(h->ev_p1[slot]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev_p0[slot], h->ev_p1[slot]));
+    r.pcg_ms += ms;
+    r.pcg_timed[slot] = false;
+}
+
+// The Newton direction of the current iterate (Algorithm 1, first line) into
+// h->px, repeated with the Jacobi diagonal when a constraint-block solve
+// stalls.
+Flags ipm_direction(IpmRun& r, int* nsolves) {
+    qp_handle* h = r.h;
+    IpmVec& v = h->iv;
+    const int m = h->m;
+    const int ps = r.it & 1;
+    harvest_pcg_ms(r, ps);
+    HIPCHK(hipEventRecord(h->ev_p0[ps], h->stream));
+    *nsolves = 0;
+    Flags f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
+                               r.wbp ? h->Dw : nullptr, r.hs, true, &r.ta, nsolves);
+    if (!f.ipm_done && r.wbp && prec_stalled(h, f)) {
+        r.pcg_total += f.pcg_iters;
+        r.pcg_solves += *nsolves;
+        ++r.fallbacks;
+        r.jacobi_only = true;
+        r.wbp = false;
+        if (h->set.log_level > 0)
+            std::fprintf(stderr, "[qpgpu] constraint-block PCG stopped after %d iterations: Jacobi from here\n",
+                         f.pcg_iters);
+        f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
+                             nullptr, r.hs, true, &r.ta, nsolves);
+    }
+    HIPCHK(hipEventRecord(h->ev_p1[ps], h->stream));
+    if (!f.ipm_done) r.pcg_timed[ps] = true;
+    return f;
+}
+
+// Accounting after a direction; false when the run ends here (the IPM had
+// finished, or PCG broke down).
+bool ipm_after_direction(IpmRun& r, const Flags& f, int nsolves) {
+    qp_handle* h = r.h;
+    if (f.ipm_done) {
+        r.done = true;
+        return false;
+    }
+    ++r.it;
+    r.pcg_total += f.pcg_iters;
+    r.pcg_solves += nsolves;
+    r.capped += f.pcg_capped;
+    if (h->set.log_level > 0) {
+        IpmScal cur{};
+        HIPCHK(hipMemcpyAsync(&cur, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        std::fprintf(stderr, "[qpgpu] ipm %3d mu %.3e rnorm %.3e pcg %6d%s alpha %.3f/%.3f\n", cur.iter, cur.mu,
+                     cur.rnorm, f.pcg_iters, f.pcg_capped ? " (cap)" : "", cur.alpha_p, cur.alpha_d);
+        std::fflush(stderr);
+    }
+    if (f.pcg_breakdown) {
+        r.st = QP_ERR_NUMERIC;
+        r.done = true;
+        return false;
+    }
+    if (r.it >= h->set.max_ipm_iter) r.done = true;   // the step below is the last
+    return true;
+}
+
+// Recovery of ds and dlambda, the ratio test, the update (Algorithm 1,
+// lines 2-6), then the residual pass, the barrier rule and the next
+// preconditioner.
+void ipm_step(IpmRun& r) {
+    qp_handle* h = r.h;
+    IpmVec& v = h->iv;
+    const int n = h->n, m = h->m;
+    const int nbA = m > 0 ? grid_rows(m, 64) : 0;
+    const int nbx = grid_elems(n);
+    hipLaunchKernelGGL(k_ipm_recover, dim3(nbA + nbx), dim3(kBlock), 0, h->stream, v, (const int*)h->Ap,
+                       (const int*)h->Ac, (const double*)h->Av, nbA, (const IpmScal*)h->isc, h->part2,
+                       (const Flags*)h->fl);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_ipm_update, dim3(grid_elems(int64_t(n) + m)), dim3(kBlock), 0, h->stream, v,
+                       (const double*)h->part2, nbA + nbx, h->isc, (const Flags*)h->fl);
+    HIPCHK(hipGetLastError());
+    ipm_residuals(h, 1);
+    r.wbp = !r.jacobi_only && (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop_flag(h));
+}
+
+// Outputs: the KKT certificate of the returned point (H x and A x of the
+// last residual pass are at that point), the multipliers, x, and the info.
+void ipm_finish(IpmRun& r, double* x, double* lam_A, double* lam_x, qp_info* info) {
+    qp_handle* h = r.h;
+    IpmVec& v = h->iv;
+    const int n = h->n, m = h->m;
+    HIPCHK(hipEventRecord(h->ev_t1, h->stream));
+    {
+        const int gc = std::min(kCertBlocks, grid_rows(n, 16));
+        hipLaunchKernelGGL(k_cert_x<16>, dim3(gc), dim3(kBlock), 0, h->stream, v, (const int*)h->Atp,
+                           (const int*)h->Atc, (const double*)h->Atv, m > 0 ? 1 : 0, (const IpmScal*)h->isc,
+                           h->part2);
+        const int ga = m > 0 ? std::min(kCertBlocks, (m + kBlock - 1) / kBlock) : 0;
+        if (ga > 0)
+            hipLaunchKernelGGL(k_cert_a, dim3(ga), dim3(kBlock), 0, h->stream, v, (const IpmScal*)h->isc,
+                               h->partA);
+        hipLaunchKernelGGL(k_cert_final, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part2, gc,
+                           (const double*)h->partA, ga, (const IpmScal*)h->isc, h->cert);
+        HIPCHK(hipGetLastError());
+    }
+    double* lx = h->tmp_n;
+    double* lA = h->tmp_m;
+    hipLaunchKernelGGL(k_ipm_output, dim3(grid_elems(int64_t(n) + m)), dim3(kBlock), 0, h->stream, v,
+                       (const IpmScal*)h->isc, lx, lA);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(x, v.x, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+    if (lam_x) HIPCHK(hipMemcpyAsync(lam_x, lx, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+    if (lam_A && m > 0) HIPCHK(hipMemcpyAsync(lam_A, lA, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
+    IpmScal sc{};
+    HIPCHK(hipMemcpyAsync(&sc, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
+    PcgScal ps{};
+    HIPCHK(hipMemcpyAsync(&ps, h->psc, sizeof(PcgScal), hipMemcpyDeviceToHost, h->stream));
+    CertOut co{};
+    HIPCHK(hipMemcpyAsync(&co, h->cert, sizeof(CertOut), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    harvest_pcg_ms(r, 0);
+    harvest_pcg_ms(r, 1);
+    if (r.st == QP_OK && !sc.done) r.st = QP_ERR_NOT_CONVERGED;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->status = r.st;
+        info->ipm_iters = sc.iter;
+        info->pcg_iters = r.pcg_total;
+        info->pcg_solves = r.pcg_solves;
+        info->pcg_capped = r.capped;
+        info->mu = sc.mu;
+        info->rnorm = sc.rnorm;
+        info->zeta = sc.zeta;
+        info->objective = sc.zeta * (0.5 * sc.xHx + sc.px);
+        info->pcg_relres = ps.bnorm2 > 0 ? std::sqrt(ps.rr / ps.bnorm2) : 0.0;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
+        info->t_solve_ms = ms;
+        info->t_pcg_ms = r.pcg_ms;
+        info->spmv_format = h->line ? 1 : 0;
+        info->prec_fallbacks = r.fallbacks;
+        info->eps_d = co.eps_d;
+        info->eps_p = co.eps_p;
+        info->eps_c = co.eps_c;
+        info->gap = co.gap;
+        harvest_timing(h, r.ta, info);
+    }
+    if (r.st == QP_ERR_NUMERIC) h->err = "PCG breakdown";
+    else if (r.st == QP_ERR_NOT_CONVERGED) h->err = "IPM reached max_ipm_iter";
+}
+
+
+// ==========================================================================
+// Batched solves: many QPs, one persistent launch per kind of PCG work
+// (batch_kernels.hpp).  Every QP keeps its own handle state and runs the
+// phases of Algorithm 1 (start, step, finish) on its own stream, driven by
+// host workers; the search directions of all QPs still iterating are
+// computed together on the batch stream by batched PCG solves whose
+// iterations are captured once as a HIP graph.  A QP whose PCG solve has
+// stopped leaves the work lists on the device; a QP whose IPM has finished
+// leaves the batch.
+// ==========================================================================
+
+// Work-list schedule of the persistent launches: workgroups of the line
+// pass and of the other kinds.  Picked per batch by batch_autotune.
+struct BatchSched {
+    int line_grid = 1536;   // 6 per CU: the line pass's occupancy
+    int grid = 2048;
+};
+
+struct BatchRun {
+    std::vector<qp_handle*> hs;
+    std::vector<IpmRun> runs;
+    int nq = 0;
+    int prec = QP_FP64;
+    bool nt_lo = false, nt_64 = false;   // value arrays above the cache: non-temporal loads
+    BatchSched sch;
+    hipStream_t st = nullptr;
+    hipEvent_t ev_dir = nullptr;         // end of the last direction phase
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+    hipEvent_t ev_snap[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> ev_q;        // per QP: end of its last step
+    // device memory (one allocation)
+    void* dmem = nullptr;
+    BatchQp* d_qs = nullptr;
+    int* d_phase = nullptr;
+    BatchList* d_lists = nullptr;
+    BatchStatus* d_status = nullptr;
+    Flags* d_flags = nullptr;
+    void* d_line_lo = nullptr;           // LineArgs<VT> of the batch precision, PCG products
+    LineArgs<double>* d_line_64 = nullptr;     // FP64 PCG products
+    LineArgs<double>* d_line_plain = nullptr;  // FP64 plain products
+    SpotArgs* d_spot = nullptr;
+    SpotArgs* d_spot_plain = nullptr;
+    PcgInitArgs* d_init[3] = {nullptr, nullptr, nullptr};   // IPM right-hand side, rhs_full, rho
+    ScalArgs* d_scal0[3] = {nullptr, nullptr, nullptr};     // mode 1 at pcg_tol, mode 1 at refine_tol, mode 2
+    ScalArgs* d_scal = nullptr;
+    PrecAArgs* d_preca = nullptr;
+    SymvArgs* d_symv = nullptr;
+    PrecAtArgs* d_at0 = nullptr;
+    PrecAtArgs* d_at = nullptr;
+    PcgArgs* d_xr = nullptr;
+    VecArgs* d_vec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // pinned host memory: the table image, the phase mask, two snapshots
+    char* h_tab = nullptr;
+    size_t tab_bytes = 0;
+    int* h_phase = nullptr;
+    char* h_snap = nullptr;
+    size_t snap_bytes = 0;
+    hipEvent_t ev_stage = nullptr;       // last copy out of the pinned table image / mask
+    bool staged = false;
+    // graphs of kGraphIters batched iterations: low-precision and FP64 products
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int hist[2][2] = {{0, 0}, {0, 0}};   // longest solves of the previous two phases of each kind
+    float pcg_ms = 0.f;
+
+    ~BatchRun() {
+        if (st) (void)hipStreamSynchronize(st);
+        for (int i = 0; i < 2; ++i) {
+            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+        }
+        if (dmem) (void)hipFree(dmem);
+        if (h_tab) (void)hipHostFree(h_tab);
+        if (h_phase) (void)hipHostFree(h_phase);
+        if (h_snap) (void)hipHostFree(h_snap);
+        for (hipEvent_t e : {ev_dir, ev_t0, ev_t1, ev_snap[0], ev_snap[1], ev_stage})
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev_q)
+            if (e) (void)hipEventDestroy(e);
+        if (st) (void)hipStreamDestroy(st);
+    }
+    const BatchList* list(int k) const { return d_lists + k; }
+    const BatchStatus& snap_status(int slot) const {
+        return *reinterpret_cast<const BatchStatus*>(h_snap + slot * snap_bytes);
+    }
+    const Flags* snap_flags(int slot) const {
+        return reinterpret_cast<const Flags*>(h_snap + slot * snap_bytes + sizeof(BatchStatus));
+    }
+};
+
+// The persistent path serves handles on the line format with the condensed
+// system, no low-rank term, one precision, no event timing, on one device;
+// other batches run each QP's own solve on host workers.
+bool batch_persistent_ok(qp_handle* const* hs, int count) {
+    if (count < 2 || count > kMaxBatch) return false;
+    for (int i = 0; i < count; ++i) {
+        const qp_handle* h = hs[i];
+        if (!h->line || h->k > 0 || h->set.kkt_system != 0 || h->set.timing || h->set.graphs == 0) return false;
+        if (h->set.precision != hs[0]->set.precision || h->set.refine_steps != hs[0]->set.refine_steps ||
+            h->device != hs[0]->device)
+            return false;
+    }
+    return true;
+}
+
+// Offsets of the tables in the table image (each 256-byte aligned).
+struct TabLayout {
+    size_t qs, line_lo, line_64, line_plain, spot, spot_plain, init[3], scal0[3], scal, preca, symv, at0, at, xr,
+        vec[5], total;
+};
+TabLayout tab_layout(int nq, size_t line_lo_size) {
+    TabLayout t{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    t.qs = take(sizeof(BatchQp) * nq);
+    t.line_lo = take(line_lo_size * nq);
+    t.line_64 = take(sizeof(LineArgs<double>) * nq);
+    t.line_plain = take(sizeof(LineArgs<double>) * nq);
+    t.spot = take(sizeof(SpotArgs) * nq);
+    t.spot_plain = take(sizeof(SpotArgs) * nq);
+    for (auto& v : t.init) v = take(sizeof(PcgInitArgs) * nq);
+    for (auto& v : t.scal0) v = take(sizeof(ScalArgs) * nq);
+    t.scal = take(sizeof(ScalArgs) * nq);
+    t.preca = take(sizeof(PrecAArgs) * nq);
+    t.symv = take(sizeof(SymvArgs) * nq);
+    t.at0 = take(sizeof(PrecAtArgs) * nq);
+    t.at = take(sizeof(PrecAtArgs) * nq);
+    t.xr = take(sizeof(PcgArgs) * nq);
+    for (auto& v : t.vec) v = take(sizeof(VecArgs) * nq);
+    t.total = o;
+    return t;
+}
+
+size_t line_args_size(int prec) {
+    return prec == QP_FP32 ? sizeof(LineArgs<float>) : prec == QP_BF16 ? sizeof(LineArgs<bf16_t>)
+                                                                       : sizeof(LineArgs<double>);
+}
+
+void batch_alloc(BatchRun& B) {
+    const int nq = B.nq;
+    const TabLayout t = tab_layout(nq, line_args_size(B.prec));
+    B.tab_bytes = t.total;
+    size_t o = t.total;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    const size_t o_phase = take(sizeof(int) * kMaxBatch);
+    const size_t o_lists = take(sizeof(BatchList) * BK_COUNT);
+    const size_t o_status = take(sizeof(BatchStatus));
+    const size_t o_flags = take(sizeof(Flags) * kMaxBatch);
+    HIPCHK(hipMalloc(&B.dmem, o));
+    char* d = static_cast<char*>(B.dmem);
+    B.d_qs = reinterpret_cast<BatchQp*>(d + t.qs);
+    B.d_line_lo = d + t.line_lo;
+    B.d_line_64 = reinterpret_cast<LineArgs<double>*>(d + t.line_64);
+    B.d_line_plain = reinterpret_cast<LineArgs<double>*>(d + t.line_plain);
+    B.d_spot = reinterpret_cast<SpotArgs*>(d + t.spot);
+    B.d_spot_plain = reinterpret_cast<SpotArgs*>(d + t.spot_plain);
+    for (int i = 0; i < 3; ++i) {
+        B.d_init[i] = reinterpret_cast<PcgInitArgs*>(d + t.init[i]);
+        B.d_scal0[i] = reinterpret_cast<ScalArgs*>(d + t.scal0[i]);
+    }
+    B.d_scal = reinterpret_cast<ScalArgs*>(d + t.scal);
+    B.d_preca = reinterpret_cast<PrecAArgs*>(d + t.preca);
+    B.d_symv = reinterpret_cast<SymvArgs*>(d + t.symv);
+    B.d_at0 = reinterpret_cast<PrecAtArgs*>(d + t.at0);
+    B.d_at = reinterpret_cast<PrecAtArgs*>(d + t.at);
+    B.d_xr = reinterpret_cast<PcgArgs*>(d + t.xr);
+    for (int i = 0; i < 5; ++i) B.d_vec[i] = reinterpret_cast<VecArgs*>(d + t.vec[i]);
+    B.d_phase = reinterpret_cast<int*>(d + o_phase);
+    B.d_lists = reinterpret_cast<BatchList*>(d + o_lists);
+    B.d_status = reinterpret_cast<BatchStatus*>(d + o_status);
+    B.d_flags = reinterpret_cast<Flags*>(d + o_flags);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&B.h_tab), B.tab_bytes, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&B.h_phase), sizeof(int) * kMaxBatch, hipHostMallocDefault));
+    B.snap_bytes = (sizeof(BatchStatus) + sizeof(Flags) * kMaxBatch + 255) / 256 * 256;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&B.h_snap), 2 * B.snap_bytes, hipHostMallocDefault));
+    std::memset(B.h_phase, 0, sizeof(int) * kMaxBatch);
+}
+
+// The host rewrites the pinned table image or mask only after the copy that
+// last read it has finished.
+void batch_stage_wait(BatchRun& B) {
+    if (B.staged) HIPCHK(hipEventSynchronize(B.ev_stage));
+    B.staged = false;
+}
+void batch_stage_done(BatchRun& B) {
+    HIPCHK(hipEventRecord(B.ev_stage, B.st));
+    B.staged = true;
+}
+
+// Fill and upload every QP's tables for the current iterate: the arguments
+// its own solve would launch with (pcg_setup, line_args, spot_args), with the
+// constraint-block preconditioner where the QP's run has one built.
+template <typename VT>
+void batch_tables_t(BatchRun& B, const std::vector<char>& jacobi) {
+    const int nq = B.nq;
+    const TabLayout t = tab_layout(nq, sizeof(LineArgs<VT>));
+    batch_stage_wait(B);
+    char* img = B.h_tab;
+    std::memset(img, 0, B.tab_bytes);
+    for (int q = 0; q < nq; ++q) {
+        qp_handle* h = B.hs[q];
+        const IpmRun& r = B.runs[q];
+        IpmVec& v = h->iv;
+        const int m = h->m;
+        const double* sigA = m > 0 ? v.sigA : nullptr;
+        const double* dh = (r.wbp && !jacobi[q]) ? h->Dw : nullptr;
+        const double tol = h->set.pcg_tol;
+        const double inner = h->set.refine_steps > 0 ? std::max(h->set.refine_tol, tol) : tol;
+        const PcgSetup S_ipm = pcg_setup(h, v.rhs_a, v.rhs_b, sigA, v.d, dh, true, tol, false);
+        const PcgSetup S_lo = pcg_setup(h, nullptr, h->rhs_full, sigA, v.d, dh, false, inner, false);
+        const PcgSetup S_rho = pcg_setup(h, nullptr, h->rho, sigA, v.d, dh, false, inner, true);
+        const OpWork wk = handle_work(h);
+        const LineArgs<VT> lo = line_args<VT>(h, wk, h->pz, h->pq, sigA, true);
+        const LineArgs<double> l64 = line_args<double>(h, wk, h->pz, h->pq, sigA, true);
+        const LineArgs<double> lpl = line_args<double>(h, wk, h->dxacc, h->pq, sigA, false);
+        BatchQp bq{};
+        bq.fl = h->fl;
+        bq.nblk[BK_INIT] = S_ipm.ge;
+        bq.nblk[BK_PRECA] = S_ipm.wb ? S_ipm.nb_preca : 0;
+        bq.nblk[BK_SYMV] = S_ipm.wb ? S_ipm.nb_symv : 0;
+        bq.nblk[BK_AT] = S_ipm.wb ? S_ipm.nb_at : 0;
+        bq.nblk[BK_SCAL] = S_ipm.gs;
+        bq.nblk[BK_LINE] = line_blocks(lo);
+        bq.nblk[BK_LINE_PLAIN] = line_blocks(lpl);
+        bq.nblk[BK_SPOT] = spot_blocks(h);
+        bq.nblk[BK_XR] = S_ipm.nb_xr;
+        bq.nblk[BK_VEC] = grid_elems(h->n);
+        auto put = [&](size_t off, const auto& val) {
+            std::memcpy(img + off + sizeof(val) * size_t(q), &val, sizeof(val));
+        };
+        put(t.qs, bq);
+        put(t.line_lo, lo);
+        put(t.line_64, l64);
+        put(t.line_plain, lpl);
+        put(t.spot, spot_args(h, wk, h->pz, h->pq, v.sigx, sigA, r.hs, true));
+        put(t.spot_plain, spot_args(h, wk, h->dxacc, h->pq, v.sigx, sigA, r.hs, false));
+        put(t.init[0], S_ipm.ia);
+        put(t.init[1], S_lo.ia);
+        put(t.init[2], S_rho.ia);
+        put(t.scal0[0], S_ipm.sa);   // mode 1 at pcg_tol (FP64 solves and the FP64 fallback)
+        put(t.scal0[1], S_lo.sa);    // mode 1 at refine_tol
+        put(t.scal0[2], S_rho.sa);   // mode 2
+        put(t.scal, S_ipm.si);
+        put(t.preca, S_ipm.prea);
+        put(t.symv, S_ipm.sy);
+        put(t.at0, S_ipm.at0);
+        put(t.at, S_ipm.at);
+        PcgArgs pa = S_ipm.pa;
+        pa.n_pq = line_pq_partials(h, sigA);
+        put(t.xr, pa);
+        const int n = h->n;
+        put(t.vec[0], VecArgs{VEC_RHS, n, v.rhs_a, v.rhs_b, h->isc, h->rhs_full});
+        put(t.vec[1], VecArgs{VEC_SET, n, h->px, nullptr, nullptr, h->dxacc});
+        put(t.vec[2], VecArgs{VEC_ADD, n, h->px, nullptr, nullptr, h->dxacc});
+        put(t.vec[3], VecArgs{VEC_SUB, n, h->rhs_full, h->pq, nullptr, h->rho});
+        put(t.vec[4], VecArgs{VEC_SET, n, h->dxacc, nullptr, nullptr, h->px});
+    }
+    HIPCHK(hipMemcpyAsync(B.d_qs, img, B.tab_bytes, hipMemcpyHostToDevice, B.st));
+    batch_stage_done(B);
+}
+void batch_tables(BatchRun& B, const std::vector<char>& jacobi) {
+    switch (B.prec) {
+        case QP_FP32: batch_tables_t<float>(B, jacobi); break;
+        case QP_BF16: batch_tables_t<bf16_t>(B, jacobi); break;
+        default: batch_tables_t<double>(B, jacobi); break;
+    }
+}
+
+// Plan the work lists for the QPs in `mask` (mode BP_START or BP_ITER).
+void batch_plan(BatchRun& B, int mode) {
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kMaxBatch), 0, B.st, (const BatchQp*)B.d_qs,
+                       (const int*)B.d_phase, B.nq, mode, B.d_lists, B.d_status, B.d_flags);
+}
+void batch_set_phase(BatchRun& B, const std::vector<char>& mask) {
+    batch_stage_wait(B);
+    for (int q = 0; q < B.nq; ++q) B.h_phase[q] = mask[q] ? 1 : 0;
+    HIPCHK(hipMemcpyAsync(B.d_phase, B.h_phase, sizeof(int) * B.nq, hipMemcpyHostToDevice, B.st));
+    batch_stage_done(B);
+}
+void batch_snapshot(BatchRun& B, int slot) {
+    HIPCHK(hipMemcpyAsync(B.h_snap + slot * B.snap_bytes, B.d_status, sizeof(BatchStatus), hipMemcpyDeviceToHost,
+                          B.st));
+    HIPCHK(hipMemcpyAsync(B.h_snap + slot * B.snap_bytes + sizeof(BatchStatus), B.d_flags, sizeof(Flags) * B.nq,
+                          hipMemcpyDeviceToHost, B.st));
+    HIPCHK(hipEventRecord(B.ev_snap[slot], B.st));
+}
+
+template <typename VT, typename AT>
+void batch_line_launch(BatchRun& B, const void* tab, const BatchList* L, bool nt) {
+    const LineArgs<VT>* tb = static_cast<const LineArgs<VT>*>(tab);
+    if (nt) hipLaunchKernelGGL((kb_line<VT, AT, true>), dim3(B.sch.line_grid), dim3(kBlock), 0, B.st, tb, L);
+    else hipLaunchKernelGGL((kb_line<VT, AT, false>), dim3(B.sch.line_grid), dim3(kBlock), 0, B.st, tb, L);
+}
+// Line pass of a PCG product, in the batch precision (lo) or FP64.
+void batch_line(BatchRun& B, bool lo) {
+    if (lo && B.prec == QP_FP32) batch_line_launch<float, float>(B, B.d_line_lo, B.list(BK_LINE), B.nt_lo);
+    else if (lo && B.prec == QP_BF16) batch_line_launch<bf16_t, float>(B, B.d_line_lo, B.list(BK_LINE), B.nt_lo);
+    else batch_line_launch<double, double>(B, lo ? B.d_line_lo : B.d_line_64, B.list(BK_LINE), B.nt_64);
+}
+
+// One batched PCG iteration (kernels in the order of run_pcg's).
+void batch_iter(BatchRun& B, bool lo) {
+    batch_line(B, lo);
+    hipLaunchKernelGGL(kb_spot<kSpotLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const SpotArgs*)B.d_spot,
+                       B.list(BK_SPOT));
+    hipLaunchKernelGGL(kb_xr, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PcgArgs*)B.d_xr, B.list(BK_XR));
+    hipLaunchKernelGGL(kb_symv, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const SymvArgs*)B.d_symv, B.list(BK_SYMV));
+    hipLaunchKernelGGL(kb_at<kPrecAtLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PrecAtArgs*)B.d_at,
+                       B.list(BK_AT));
+    hipLaunchKernelGGL(kb_scal, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const ScalArgs*)B.d_scal, B.list(BK_SCAL));
+    batch_plan(B, BP_ITER);
+    HIPCHK(hipGetLastError());
+}
+
+// Graph of kGraphIters batched iterations (its launches read the tables and
+// lists through fixed pointers, so one capture serves every later solve).
+hipGraphExec_t batch_graph(BatchRun& B, bool lo) {
+    const int g = lo ? 0 : 1;
+    if (B.gexec[g]) return B.gexec[g];
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(B.st, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int i = 0; i < kGraphIters; ++i) batch_iter(B, lo);
+    } catch (...) {
+        (void)hipStreamEndCapture(B.st, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(B.st, &graph));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        throw HipError{e, "hipGraphInstantiate (batch)"};
+    }
+    B.graph[g] = graph;
+    B.gexec[g] = ex;
+    return ex;
+}
+
+// Start variants of a batched solve.
+enum { BS_IPM = 0, BS_LO = 1, BS_RHO = 2, BS_FULL64 = 3 };
+
+// One batched PCG solve for the QPs in `mask` (start variant sv; products in
+// the batch precision when lo, else FP64).  check_only: stop after the start
+// (a refinement pass that only measures its residual).  Returns every QP's
+// flags after the solve.
+std::vector<Flags> batch_pcg(BatchRun& B, const std::vector<char>& mask, int sv, bool lo, bool check_only) {
+    const int init_tab = sv == BS_IPM ? 0 : sv == BS_RHO ? 2 : 1;
+    const int scal_tab = (sv == BS_IPM || sv == BS_FULL64) ? 0 : sv == BS_LO ? 1 : 2;
+    const bool refine = sv == BS_RHO;
+    batch_set_phase(B, mask);
+    batch_plan(B, BP_START);
+    hipLaunchKernelGGL(kb_init0, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PcgInitArgs*)B.d_init[init_tab],
+                       B.list(BK_INIT));
+    hipLaunchKernelGGL(kb_preca, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PrecAArgs*)B.d_preca,
+                       B.list(BK_PRECA));
+    hipLaunchKernelGGL(kb_symv, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const SymvArgs*)B.d_symv, B.list(BK_SYMV));
+    hipLaunchKernelGGL(kb_at<kPrecAtLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PrecAtArgs*)B.d_at0,
+                       B.list(BK_AT));
+    hipLaunchKernelGGL(kb_scal, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const ScalArgs*)B.d_scal0[scal_tab],
+                       B.list(BK_SCAL));
+    batch_plan(B, BP_ITER);
+    HIPCHK(hipGetLastError());
+    std::vector<Flags> out(B.nq);
+    auto harvest = [&](int slot) {
+        const Flags* f = B.snap_flags(slot);
+        std::copy(f, f + B.nq, out.begin());
+    };
+    if (refine || check_only) {
+        // often every QP's refinement residual already meets pcg_tol
+        batch_snapshot(B, 0);
+        HIPCHK(hipEventSynchronize(B.ev_snap[0]));
+        harvest(0);
+        if (check_only || B.snap_status(0).active == 0) return out;
+    }
+    const hipGraphExec_t gx = batch_graph(B, lo);
+    int* hist = B.hist[refine ? 1 : 0];
+    const int pred = std::min(hist[0], hist[1]);
+    int chunk = std::max(kGraphIters, std::min(512, (pred * 3) / 4));
+    chunk = ((chunk + kGraphIters - 1) / kGraphIters) * kGraphIters;
+    auto queue = [&](int iters) {
+        for (int i = 0; i < iters; i += kGraphIters) HIPCHK(hipGraphLaunch(gx, B.st));
+    };
+    int64_t launched = 0;
+    int64_t guard = 4096;
+    for (int q = 0; q < B.nq; ++q)
+        if (mask[q]) guard = std::max<int64_t>(guard, int64_t(B.hs[q]->set.pcg_max_iter) + 4096);
+    int cur = 0;
+    queue(chunk);
+    launched += chunk;
+    batch_snapshot(B, cur);
+    while (true) {
+        queue(kGraphIters);
+        launched += kGraphIters;
+        batch_snapshot(B, cur ^ 1);
+        HIPCHK(hipEventSynchronize(B.ev_snap[cur]));
+        if (B.snap_status(cur).active == 0) {
+            harvest(cur);
+            break;
+        }
+        if (launched > guard) {
+            HIPCHK(hipEventSynchronize(B.ev_snap[cur ^ 1]));
+            harvest(cur ^ 1);
+            break;
+        }
+        cur ^= 1;
+    }
+    int longest = 0;
+    for (int q = 0; q < B.nq; ++q)
+        if (mask[q] && !out[q].ipm_done) longest = std::max(longest, out[q].pcg_iters);
+    hist[1] = hist[0];
+    hist[0] = longest;
+    return out;
+}
+
+// A batched elementwise step (table i of d_vec) or the plain FP64 product
+// (dxacc -> pq) for the QPs in mask.
+void batch_vec(BatchRun& B, const std::vector<char>& mask, int i) {
+    batch_set_phase(B, mask);
+    batch_plan(B, BP_START);
+    hipLaunchKernelGGL(kb_vec, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const VecArgs*)B.d_vec[i], B.list(BK_VEC));
+    HIPCHK(hipGetLastError());
+}
+void batch_plain_product(BatchRun& B, const std::vector<char>& mask) {
+    batch_set_phase(B, mask);
+    batch_plan(B, BP_START);
+    batch_line_launch<double, double>(B, B.d_line_plain, B.list(BK_LINE_PLAIN), B.nt_64);
+    hipLaunchKernelGGL(kb_spot<kSpotLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st,
+                       (const SpotArgs*)B.d_spot_plain, B.list(BK_SPOT));
+    HIPCHK(hipGetLastError());
+}
+
+bool any_of(const std::vector<char>& v) {
+    for (char c : v)
+        if (c) return true;
+    return false;
+}
+
+// The Newton directions of the QPs in mask, as newton_direction computes
+// each (FP64: one solve; FP32/BF16: the low-precision solve, refinement
+// passes against the FP64 product, the FP64 fallback), batched step by
+// step.  Fills f (flags with the PCG iterations summed) and solves per QP.
+void batch_direction(BatchRun& B, const std::vector<char>& mask, std::vector<Flags>& f, std::vector<int>& solves) {
+    const int nq = B.nq;
+    f.assign(nq, Flags{});
+    solves.assign(nq, 0);
+    if (B.prec == QP_FP64) {
+        const std::vector<Flags> r = batch_pcg(B, mask, BS_IPM, true, false);
+        for (int q = 0; q < nq; ++q)
+            if (mask[q]) {
+                f[q] = r[q];
+                solves[q] = 1;
+            }
+        return;
+    }
+    batch_vec(B, mask, 0);   // rhs_full = mu rhs_a + rhs_b
+    const std::vector<Flags> r0 = batch_pcg(B, mask, BS_LO, true, false);
+    std::vector<int> total(nq, 0);
+    std::vector<char> refining(nq, 0), met(nq, 0), fixed(nq, 0);   // fixed: direction final
+    for (int q = 0; q < nq; ++q) {
+        if (!mask[q]) continue;
+        f[q] = r0[q];
+        solves[q] = 1;
+        total[q] = r0[q].pcg_iters;
+        const qp_handle* h = B.hs[q];
+        if (r0[q].ipm_done || r0[q].pcg_breakdown || h->set.refine_steps == 0) fixed[q] = 1;
+        else refining[q] = 1;
+    }
+    batch_vec(B, refining, 1);   // dxacc = px
+    std::vector<char> live = refining;   // passes still to run
+    const int steps = B.hs[0]->set.refine_steps;
+    for (int k = 0; k <= steps && any_of(live); ++k) {
+        batch_plain_product(B, live);
+        batch_vec(B, live, 3);   // rho = rhs_full - K dxacc
+        const bool check = k == steps;
+        const std::vector<Flags> r2 = batch_pcg(B, live, BS_RHO, true, check);
+        std::vector<char> add(nq, 0);
+        for (int q = 0; q < nq; ++q) {
+            if (!live[q]) continue;
+            const Flags& g = r2[q];
+            if (g.ipm_done) {
+                f[q] = g;
+                fixed[q] = 1;
+                refining[q] = 0;
+                live[q] = 0;
+                continue;
+            }
+            met[q] = (g.pcg_iters == 0 && g.pcg_converged) ? 1 : 0;
+            if (check) {
+                live[q] = 0;
+                continue;
+            }
+            solves[q] += 1;
+            total[q] += g.pcg_iters;
+            f[q].pcg_capped |= g.pcg_capped;
+            f[q].pcg_converged = g.pcg_converged;
+            if (g.pcg_breakdown) {
+                f[q].pcg_breakdown = 1;
+                live[q] = 0;
+                continue;
+            }
+            if (met[q]) {
+                live[q] = 0;
+                continue;
+            }
+            add[q] = 1;
+        }
+        batch_vec(B, add, 2);   // dxacc += px
+    }
+    std::vector<char> fb(nq, 0), keep(nq, 0);
+    for (int q = 0; q < nq; ++q) {
+        if (!refining[q]) continue;
+        if (!met[q] && !f[q].pcg_breakdown) fb[q] = 1;
+        else keep[q] = 1;
+    }
+    if (any_of(fb)) {
+        const std::vector<Flags> r3 = batch_pcg(B, fb, BS_FULL64, false, false);
+        for (int q = 0; q < nq; ++q)
+            if (fb[q]) {
+                Flags g = r3[q];
+                solves[q] += 1;
+                g.pcg_iters += total[q];
+                g.pcg_capped |= f[q].pcg_capped;
+                f[q] = g;
+            }
+    }
+    batch_vec(B, keep, 4);   // px = dxacc
+    for (int q = 0; q < nq; ++q)
+        if (keep[q]) f[q].pcg_iters = total[q];
+}
+
+// Per-QP phases on host workers, each QP on its own stream.
+template <typename F>
+void batch_each(BatchRun& B, const std::vector<char>& mask, int workers, F&& fn, std::vector<qp_status>& st) {
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        (void)hipSetDevice(B.hs[0]->device);
+        while (true) {
+            const int q = next.fetch_add(1);
+            if (q >= B.nq) break;
+            if (!mask[q] || st[q] != QP_OK) continue;
+            try {
+                fn(q);
+            } catch (const HipError& he) {
+                B.hs[q]->err = std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e);
+                st[q] = QP_ERR_DEVICE;
+                B.runs[q].done = true;
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int w = 1; w < workers; ++w) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+}
+
+// Persistent-path schedule autotuner: times one batched PCG product of the
+// batch (line pass + spot pass, all QPs) for each candidate schedule and
+// keeps the fastest; cached per batch shape for the process.
+std::mutex g_btune_mu;
+std::map<std::tuple<int, int, int64_t, int64_t>, BatchSched> g_btune;
+
+void batch_autotune(BatchRun& B) {
+    int64_t nnz = 0, nsum = 0;
+    for (auto* h : B.hs) {
+        nnz += h->nnzJ;
+        nsum += h->n;
+    }
+    const auto key = std::make_tuple(B.nq, B.prec, nnz, nsum);
+    {
+        std::lock_guard<std::mutex> lk(g_btune_mu);
+        auto it = g_btune.find(key);
+        if (it != g_btune.end()) {
+            B.sch = it->second;
+            return;
+        }
+    }
+    // every QP's plain FP64 product of dxacc (zeroed here) as the probe; the
+    // low-precision products have the same lists
+    std::vector<char> all(B.nq, 1);
+    for (auto* h : B.hs) HIPCHK(hipMemsetAsync(h->dxacc, 0, sizeof(double) * h->n, B.st));
+    const int cand_line[] = {1024, 1536, 2048, 3072};
+    const int cand_grid[] = {1024, 2048, 4096};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    BatchSched best = B.sch;
+    float best_ms = 1e30f;
+    for (int lg : cand_line)
+        for (int gg : cand_grid) {
+            B.sch.line_grid = lg;
+            B.sch.grid = gg;
+            batch_set_phase(B, all);
+            batch_plan(B, BP_START);
+            float tot = 0.f;
+            for (int rep = 0; rep < 3; ++rep) {   // first repetition warms up
+                HIPCHK(hipEventRecord(e0, B.st));
+                batch_line_launch<double, double>(B, B.d_line_plain, B.list(BK_LINE_PLAIN), B.nt_64);
+                hipLaunchKernelGGL(kb_spot<kSpotLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st,
+                                   (const SpotArgs*)B.d_spot_plain, B.list(BK_SPOT));
+                HIPCHK(hipEventRecord(e1, B.st));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (rep) tot += ms;
+            }
+            if (tot < best_ms) {
+                best_ms = tot;
+                best = B.sch;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B.sch = best;
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    g_btune[key] = best;
+}
+
+// The whole batch on the persistent path.  Returns per-QP statuses.
+std::vector<qp_status> batch_solve(qp_handle* const* hs, int count, double* const* xs, qp_info* infos) {
+    BatchRun B;
+    B.nq = count;
+    B.hs.assign(hs, hs + count);
+    B.runs.resize(count);
+    B.prec = hs[0]->set.precision;
+    std::vector<qp_status> st(count, QP_OK);
+    HIPCHK(hipSetDevice(hs[0]->device));
+    HIPCHK(hipStreamCreateWithFlags(&B.st, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&B.ev_dir, &B.ev_snap[0], &B.ev_snap[1], &B.ev_stage})
+        HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    HIPCHK(hipEventCreate(&B.ev_t0));
+    HIPCHK(hipEventCreate(&B.ev_t1));
+    B.ev_q.assign(count, nullptr);
+    for (auto& e : B.ev_q) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    size_t bytes_lo = 0, bytes_64 = 0;
+    for (int q = 0; q < count; ++q) {
+        B.runs[q].h = hs[q];
+        ensure_lowp(hs[q], B.prec);
+        bytes_lo += size_t(hs[q]->nnzJ) * (B.prec == QP_FP32 ? 4 : B.prec == QP_BF16 ? 2 : 8);
+        bytes_64 += size_t(hs[q]->nnzJ) * 8;
+    }
+    B.nt_lo = bytes_lo > kStreamedValueBytes;
+    B.nt_64 = bytes_64 > kStreamedValueBytes;
+    batch_alloc(B);
+    int workers = 6;
+    if (const char* e = std::getenv("QPGPU_BATCH_WORKERS")) workers = std::max(1, std::atoi(e));
+    workers = std::min(workers, count);
+    std::vector<char> all(count, 1), jacobi(count, 0);
+
+    // start every QP on its own stream; then the tables and the schedule
+    std::vector<std::unique_ptr<PrecAttemptCap>> caps;
+    for (auto* h : B.hs) caps.emplace_back(new PrecAttemptCap(h));
+    batch_each(B, all, workers, [&](int q) {
+        ipm_start(B.runs[q], nullptr);
+        HIPCHK(hipEventRecord(B.ev_q[q], B.hs[q]->stream));
+    }, st);
+    for (int q = 0; q < count; ++q) HIPCHK(hipStreamWaitEvent(B.st, B.ev_q[q], 0));
+    batch_tables(B, jacobi);
+    batch_autotune(B);
+    while (true) {
+        std::vector<char> live(count, 0);
+        for (int q = 0; q < count; ++q) live[q] = (st[q] == QP_OK && !B.runs[q].done) ? 1 : 0;
+        if (!any_of(live)) break;
+        // the directions of every live QP (their steps ended before: events)
+        for (int q = 0; q < count; ++q)
+            if (live[q]) HIPCHK(hipStreamWaitEvent(B.st, B.ev_q[q], 0));
+        batch_tables(B, jacobi);
+        HIPCHK(hipEventRecord(B.ev_t0, B.st));
+        std::vector<Flags> f;
+        std::vector<int> ns;
+        batch_direction(B, live, f, ns);
+        // a stalled constraint-block solve: that QP's direction again with
+        // the Jacobi diagonal, which then serves the rest of its run
+        std::vector<char> redo(count, 0);
+        for (int q = 0; q < count; ++q) {
+            IpmRun& r = B.runs[q];
+            if (live[q] && !f[q].ipm_done && r.wbp && prec_stalled(B.hs[q], f[q])) {
+                r.pcg_total += f[q].pcg_iters;
+                r.pcg_solves += ns[q];
+                ++r.fallbacks;
+                r.jacobi_only = true;
+                r.wbp = false;
+                jacobi[q] = 1;
+                redo[q] = 1;
+            }
+        }
+        if (any_of(redo)) {
+            batch_tables(B, jacobi);
+            std::vector<Flags> f2;
+            std::vector<int> ns2;
+            batch_direction(B, redo, f2, ns2);
+            for (int q = 0; q < count; ++q)
+                if (redo[q]) {
+                    f[q] = f2[q];
+                    ns[q] = ns2[q];
+                }
+        }
+        HIPCHK(hipEventRecord(B.ev_t1, B.st));
+        HIPCHK(hipEventRecord(B.ev_dir, B.st));
+        HIPCHK(hipEventSynchronize(B.ev_t1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, B.ev_t0, B.ev_t1));
+        B.pcg_ms += ms;
+        // accounting, then each QP's step on its own stream after the directions
+        std::vector<char> step(count, 0);
+        for (int q = 0; q < count; ++q) {
+            if (!live[q]) continue;
+            IpmRun& r = B.runs[q];
+            r.pcg_ms += ms;
+            if (ipm_after_direction(r, f[q], ns[q])) step[q] = 1;
+        }
+        batch_each(B, step, workers, [&](int q) {
+            qp_handle* h = B.hs[q];
+            HIPCHK(hipStreamWaitEvent(h->stream, B.ev_dir, 0));
+            ipm_step(B.runs[q]);
+            HIPCHK(hipEventRecord(B.ev_q[q], h->stream));
+        }, st);
+    }
+    caps.clear();
+    batch_each(B, all, workers, [&](int q) {
+        qp_info inf{};
+        HIPCHK(hipStreamWaitEvent(B.hs[q]->stream, B.ev_dir, 0));
+        ipm_finish(B.runs[q], xs[q], nullptr, nullptr, &inf);
+        st[q] = B.runs[q].st;
+        if (infos) infos[q] = inf;
+    }, st);
+    return st;
+}
 }  // namespace
 
 // ==========================================================================
@@ -1392,7 +2505,7 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         Flags f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d,
                                    wbp ? h->Dw : nullptr, 1.0, false, &ta, &nsolves);
         int fallbacks = 0;
-        if (wbp && cap_guard.stalled(f)) {
+        if (wbp && prec_stalled(h, f)) {
             ++fallbacks;
             // stalled constraint-block solve: again with the Jacobi diagonal
             int more = 0;
@@ -1438,253 +2551,24 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
     if (x0)
         for (int j = 0; j < h->n; ++j)
             if (!std::isfinite(x0[j])) return fail(h, QP_ERR_INVALID, "x0 has a non-finite entry");
-    qp_status st = QP_OK;
+    IpmRun r;
+    r.h = h;
     try {
-        ensure_timing_events(h);
-        const int n = h->n, m = h->m;
-        IpmVec& v = h->iv;
-        h->aug = h->set.kkt_system == 1 && m > 0;
-        reset_flags(h);
-        {
-            IpmScal s0{};
-            s0.mu_tol = h->set.mu_tol;
-            s0.tau = h->set.tau;
-            s0.cscale = h->cscale;
-            s0.step_mode = h->set.step_mode;
-            HIPCHK(hipMemcpyAsync(h->isc, &s0, sizeof(IpmScal), hipMemcpyHostToDevice, h->stream));
-        }
-        HIPCHK(hipEventRecord(h->ev_t0, h->stream));
-        // start point, objective scale, mu0
-        const int gx = grid_elems(n);
-        if (x0) {
-            if (!h->x0d) h->x0d = h->dalloc<double>(n);
-            HIPCHK(hipMemcpyAsync(h->x0d, x0, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
-            hipLaunchKernelGGL(k_ipm_init_x_from, dim3(gx), dim3(kBlock), 0, h->stream, v,
-                               (const double*)h->x0d, h->partA);
-        } else {
-            hipLaunchKernelGGL(k_ipm_init_x, dim3(gx), dim3(kBlock), 0, h->stream, v, h->partA);
-        }
-        HIPCHK(hipGetLastError());
-        int nps = gx;
-        if (m > 0) {
-            const int ga = grid_rows(m, 64);
-            hipLaunchKernelGGL(k_ipm_init_A, dim3(ga), dim3(kBlock), 0, h->stream, v, (const int*)h->Ap,
-                               (const int*)h->Ac, (const double*)h->Av, h->partA + gx);
-            HIPCHK(hipGetLastError());
-            nps += ga;
-        }
-        apply_op<double, double>(h, v.x, h->tmp_n, nullptr, nullptr, 1.0, false, false, 0);
-        hipLaunchKernelGGL(k_ipm_scale, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->tmp_n,
-                           (const double*)h->p, n, (const double*)h->partA, nps, h->mtot,
-                           h->set.scale_objective, h->set.mu0, h->isc);
-        HIPCHK(hipGetLastError());
-        IpmScal sc{};
-        HIPCHK(hipMemcpyAsync(&sc, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        const double hs = sc.hs;
-
-        // residual pass + barrier rule
-        const int G = h->GJ, Gt = h->GJt;
-        auto residuals = [&](int apply) {
-            FwdArgs<double> f{};
-            f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = h->Jv; f.W = h->W; f.nJ = h->nJ;
-            f.Ap = h->Ap; f.Ac = h->Ac; f.Av = h->Av; f.m = m;
-            f.x = v.x; f.t = h->t; f.u = h->u; f.sigA = nullptr; f.fl = nullptr;
-            // line format: J x and the per-slot shares of J^T W J x come from
-            // one read of J in the line pass; k_ipm_fwd keeps the rows of A
-            f.nbJ = (h->nJ > 0 && !h->line) ? grid_rows(h->nJ, G) : 0;
-            const int nbA = m > 0 ? grid_rows(m, 64) : 0;
-            if (h->line) {
-                LineArgs<double> la{};
-                la.lptr = h->lptr; la.lcol = h->lcol; la.lval = h->lval; la.L = h->L; la.W = h->W;
-                la.x = v.x; la.c = h->lc; la.u = h->u; la.nbL = h->L; la.nbA = 0; la.fl_ipm = h->fl;
-                if (line_vals_streamed<double>(h))
-                    hipLaunchKernelGGL((k_line_pass<double, double, true>), dim3(std::max(1, h->L)), dim3(kBlock),
-                                       0, h->stream, la);
-                else
-                    hipLaunchKernelGGL((k_line_pass<double, double, false>), dim3(std::max(1, h->L)),
-                                       dim3(kBlock), 0, h->stream, la);
-                HIPCHK(hipGetLastError());
-            }
-            const int grid = std::max(1, f.nbJ + nbA);
-            switch (G) {
-                case 4: hipLaunchKernelGGL(k_ipm_fwd<4>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
-                case 8: hipLaunchKernelGGL(k_ipm_fwd<8>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
-                case 16: hipLaunchKernelGGL(k_ipm_fwd<16>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
-                case 32: hipLaunchKernelGGL(k_ipm_fwd<32>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
-                default: hipLaunchKernelGGL(k_ipm_fwd<64>, dim3(grid), dim3(kBlock), 0, h->stream, f, v, (const IpmScal*)h->isc, h->partA, (const Flags*)h->fl); break;
-            }
-            HIPCHK(hipGetLastError());
-            IpmBwdArgs ba{};
-            ba.Jtp = h->Jtp; ba.Jtc = h->Jtc; ba.Jtv = h->Jtv;
-            if (h->line) { ba.sptr = h->sptr; ba.sslot = h->sslot; ba.lc = h->lc; }
-            ba.Atp = h->Atp; ba.Atc = h->Atc; ba.Atv = h->Atv; ba.hasA = m > 0;
-            ba.t = h->t; ba.gamma = h->gamma;
-            ba.U = h->U; ba.lr_v = h->lr_v; ba.lr_k = h->k;
-            ba.aug = h->aug ? 1 : 0;
-            lowrank_prepare(h, v.x, nullptr, nullptr);
-            // lanes per variable: with the line format a variable sums one
-            // double per slot of its spot, not one term per nonzero of J
-            const int Gb = h->line ? pick_lanes(h->nnzJ / 64 + h->nnzA, n) : Gt;
-            const int gb = grid_rows_capped(n, Gb);
-            switch (Gb) {
-                case 4: hipLaunchKernelGGL(k_ipm_bwd<4>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
-                case 8: hipLaunchKernelGGL(k_ipm_bwd<8>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
-                case 16: hipLaunchKernelGGL(k_ipm_bwd<16>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
-                case 32: hipLaunchKernelGGL(k_ipm_bwd<32>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
-                default: hipLaunchKernelGGL(k_ipm_bwd<64>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, (const IpmScal*)h->isc, h->part, (const Flags*)h->fl); break;
-            }
-            HIPCHK(hipGetLastError());
-            if (h->aug)   // lambda block of eq. (2x2_augmented): D, its Jacobi entries, r_2
-                hipLaunchKernelGGL(k_aug_rows, dim3(grid_elems(m)), dim3(kBlock), 0, h->stream, v, h->dlu,
-                                   (const Flags*)h->fl);
-            hipLaunchKernelGGL(k_ipm_check, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->partA, nbA,
-                               (const double*)h->part, (n + kChunkRows - 1) / kChunkRows, apply, h->isc, h->fl,
-                               h->log);
-            HIPCHK(hipGetLastError());
-        };
-        const int* ipm_stop = reinterpret_cast<const int*>(&h->fl->ipm_done);
-        residuals(0);
-        bool wbp = (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop);
-
-        TimingAcc ta;
-        int64_t pcg_total = 0;
-        int pcg_solves = 0, capped = 0;
-        double last_relres = 0.0;
-        float pcg_ms = 0.f;
-        // The PCG time of an IPM iteration is read two iterations later (its
-        // events are long complete by then), so the host never waits for the
-        // device just to time it.
-        bool pcg_timed[2] = {false, false};
-        auto harvest_pcg_ms = [&](int slot) {
-            if (!pcg_timed[slot]) return;
-            HIPCHK(hipEventSynchronize(h->ev_p1[slot]));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, h->ev_p0[slot], h->ev_p1[slot]));
-            pcg_ms += ms;
-            pcg_timed[slot] = false;
-        };
-        Flags f{};
         // a stalled constraint-block solve is repeated with the Jacobi
         // diagonal, which then serves the rest of this QP
         PrecAttemptCap cap_guard(h);
-        bool jacobi_only = false;
-        int fallbacks = 0;
-        for (int it = 0; it < h->set.max_ipm_iter; ++it) {
-            const int ps = it & 1;
-            harvest_pcg_ms(ps);
-            HIPCHK(hipEventRecord(h->ev_p0[ps], h->stream));
+        ipm_start(r, x0);
+        while (!r.done) {
             int nsolves = 0;
-            f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
-                                 wbp ? h->Dw : nullptr, hs, true, &ta, &nsolves);
-            if (!f.ipm_done && wbp && cap_guard.stalled(f)) {
-                pcg_total += f.pcg_iters;
-                pcg_solves += nsolves;
-                ++fallbacks;
-                jacobi_only = true;
-                wbp = false;
-                if (h->set.log_level > 0)
-                    std::fprintf(stderr, "[qpgpu] constraint-block PCG stopped after %d iterations: Jacobi from here\n",
-                                 f.pcg_iters);
-                f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr,
-                                     v.d, nullptr, hs, true, &ta, &nsolves);
-            }
-            HIPCHK(hipEventRecord(h->ev_p1[ps], h->stream));
-            if (f.ipm_done) break;
-            pcg_timed[ps] = true;
-            pcg_total += f.pcg_iters;
-            pcg_solves += nsolves;
-            capped += f.pcg_capped;
-            if (h->set.log_level > 0) {
-                IpmScal cur{};
-                HIPCHK(hipMemcpyAsync(&cur, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
-                HIPCHK(hipStreamSynchronize(h->stream));
-                std::fprintf(stderr, "[qpgpu] ipm %3d mu %.3e rnorm %.3e pcg %6d%s alpha %.3f/%.3f\n",
-                             cur.iter, cur.mu, cur.rnorm, f.pcg_iters, f.pcg_capped ? " (cap)" : "",
-                             cur.alpha_p, cur.alpha_d);
-                std::fflush(stderr);
-            }
-            if (f.pcg_breakdown) {
-                st = QP_ERR_NUMERIC;
-                break;
-            }
-            // recovery, ratio test, update
-            const int nbA = m > 0 ? grid_rows(m, 64) : 0;
-            const int nbx = grid_elems(n);
-            hipLaunchKernelGGL(k_ipm_recover, dim3(nbA + nbx), dim3(kBlock), 0, h->stream, v, (const int*)h->Ap,
-                               (const int*)h->Ac, (const double*)h->Av, nbA, (const IpmScal*)h->isc, h->part2,
-                               (const Flags*)h->fl);
-            HIPCHK(hipGetLastError());
-            hipLaunchKernelGGL(k_ipm_update, dim3(grid_elems(int64_t(n) + m)), dim3(kBlock), 0, h->stream, v,
-                               (const double*)h->part2, nbA + nbx, h->isc, (const Flags*)h->fl);
-            HIPCHK(hipGetLastError());
-            residuals(1);
-            wbp = !jacobi_only && (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop);
+            const Flags f = ipm_direction(r, &nsolves);
+            if (!ipm_after_direction(r, f, nsolves)) break;
+            ipm_step(r);
         }
-        // outputs: the KKT certificate of the returned point (H x and A x of
-        // the last residual pass are at that point), then the multipliers
-        HIPCHK(hipEventRecord(h->ev_t1, h->stream));
-        {
-            const int gc = std::min(kCertBlocks, grid_rows(n, 16));
-            hipLaunchKernelGGL(k_cert_x<16>, dim3(gc), dim3(kBlock), 0, h->stream, v, (const int*)h->Atp,
-                               (const int*)h->Atc, (const double*)h->Atv, m > 0 ? 1 : 0, (const IpmScal*)h->isc,
-                               h->part2);
-            const int ga = m > 0 ? std::min(kCertBlocks, (m + kBlock - 1) / kBlock) : 0;
-            if (ga > 0)
-                hipLaunchKernelGGL(k_cert_a, dim3(ga), dim3(kBlock), 0, h->stream, v, (const IpmScal*)h->isc,
-                                   h->partA);
-            hipLaunchKernelGGL(k_cert_final, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->part2, gc,
-                               (const double*)h->partA, ga, (const IpmScal*)h->isc, h->cert);
-            HIPCHK(hipGetLastError());
-        }
-        double* lx = h->tmp_n;
-        double* lA = h->tmp_m;
-        hipLaunchKernelGGL(k_ipm_output, dim3(grid_elems(int64_t(n) + m)), dim3(kBlock), 0, h->stream, v,
-                           (const IpmScal*)h->isc, lx, lA);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(x, v.x, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
-        if (lam_x) HIPCHK(hipMemcpyAsync(lam_x, lx, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
-        if (lam_A && m > 0) HIPCHK(hipMemcpyAsync(lam_A, lA, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(&sc, h->isc, sizeof(IpmScal), hipMemcpyDeviceToHost, h->stream));
-        PcgScal ps{};
-        HIPCHK(hipMemcpyAsync(&ps, h->psc, sizeof(PcgScal), hipMemcpyDeviceToHost, h->stream));
-        CertOut co{};
-        HIPCHK(hipMemcpyAsync(&co, h->cert, sizeof(CertOut), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        harvest_pcg_ms(0);
-        harvest_pcg_ms(1);
-        if (st == QP_OK && !sc.done) st = QP_ERR_NOT_CONVERGED;
-        last_relres = ps.bnorm2 > 0 ? std::sqrt(ps.rr / ps.bnorm2) : 0.0;
-        if (info) {
-            std::memset(info, 0, sizeof(*info));
-            info->status = st;
-            info->ipm_iters = sc.iter;
-            info->pcg_iters = pcg_total;
-            info->pcg_solves = pcg_solves;
-            info->pcg_capped = capped;
-            info->mu = sc.mu;
-            info->rnorm = sc.rnorm;
-            info->zeta = sc.zeta;
-            info->objective = sc.zeta * (0.5 * sc.xHx + sc.px);
-            info->pcg_relres = last_relres;
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
-            info->t_solve_ms = ms;
-            info->t_pcg_ms = pcg_ms;
-            info->spmv_format = h->line ? 1 : 0;
-            info->prec_fallbacks = fallbacks;
-            info->eps_d = co.eps_d;
-            info->eps_p = co.eps_p;
-            info->eps_c = co.eps_c;
-            info->gap = co.gap;
-            harvest_timing(h, ta, info);
-        }
+        ipm_finish(r, x, lam_A, lam_x, info);
     } catch (const HipError& he) {
         return fail(h, QP_ERR_DEVICE, std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e));
     }
-    if (st == QP_ERR_NUMERIC) h->err = "PCG breakdown";
-    else if (st == QP_ERR_NOT_CONVERGED) h->err = "IPM reached max_ipm_iter";
-    return st;
+    return r.st;
 }
 
 qp_status qp_solve(qp_handle* h, double* x, double* lam_A, double* lam_x, qp_info* info) {
@@ -1755,6 +2639,21 @@ qp_status qp_solve_batch(qp_handle* const* hs, int32_t count, double* const* xs,
         }
     }
     if (count == 0) return QP_OK;
+    if (batch_persistent_ok(hs, count) && !std::getenv("QPGPU_BATCH_THREADS")) {
+        std::vector<qp_status> st;
+        try {
+            st = batch_solve(hs, count, xs, infos);
+        } catch (const HipError& he) {
+            g_create_error = std::string("qp_solve_batch: HIP error in ") + he.what + ": " + hipGetErrorString(he.e);
+            return he.e == hipErrorOutOfMemory ? QP_ERR_NOMEM : QP_ERR_DEVICE;
+        }
+        qp_status worst = QP_OK;
+        for (int i = 0; i < count; ++i) {
+            if (infos && st[i] != QP_OK) infos[i].status = st[i];
+            if (st[i] != QP_OK && (worst == QP_OK || st[i] == QP_ERR_DEVICE)) worst = st[i];
+        }
+        return worst;
+    }
     // largest problems first, so the tail of the batch is short
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
