@@ -245,6 +245,31 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
                             const double* v, double* y, int32_t precision, int32_t reps,
                             qp_info* info);
 
+/* qp_operator_apply_noalloc: the product of qp_operator_apply,
+ *   y = (H + diag(sigma_x) + A^T diag(sigma_A) A) v,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): it calls no
+ * hipMalloc, hipFree, copy or synchronisation, only enqueues the product's
+ * kernels on hip_stream (NULL: the handle's stream) and returns; y is ready
+ * when the stream reaches that point.
+ *   sigma_x (n), sigma_A (m; may be NULL when m = 0), v (n), y (n): DEVICE
+ *   pointers of the handle's device, caller-owned; sigma entries must be
+ *   finite and >= 0 (not checked: the arrays are in device memory).
+ *   precision: as qp_operator_apply; the J copy of that precision must
+ *   already be resident (a handle created with it, or one earlier
+ *   qp_operator_apply call with it), else QP_ERR_INVALID.
+ * The intermediates (per-slot or per-row products of J, the rows of A, the
+ * low-rank partials) go to one static 32 MiB device array of the library per
+ * GPU, held until the process ends: problems needing more (line slots or J
+ * rows, plus m, plus 256*k + k doubles, each part rounded up to 32, above
+ * 4,194,304) get QP_ERR_INVALID.  Every call on one GPU uses that same array:
+ * calls whose products overlap in time on one GPU (different streams, or
+ * several host threads) race; calls on one stream are ordered.
+ * Errors: QP_ERR_INVALID (NULL argument, precision, size, copy not resident;
+ * nothing enqueued), QP_ERR_DEVICE (launch failure). */
+qp_status qp_operator_apply_noalloc(qp_handle* h, const double* sigma_x, const double* sigma_A,
+                                    const double* v, double* y, int32_t precision, void* hip_stream);
+
 /* qp_solve_batch: solve `count` independent QPs (each a handle from
  * qp_create) together; xs[i] (n_i doubles) receives QP i's minimiser and
  * infos[i] (may be NULL) its info.  Handles run concurrently, each on its own

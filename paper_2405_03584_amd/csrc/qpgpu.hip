@@ -220,7 +220,8 @@ bool prec_stalled(const qp_handle* h, const Flags& f) {
 constexpr int kGraphIters = 4;   // PCG iterations per captured graph (and per trailing chunk)
 
 // Where an operator product keeps its intermediates, and the stream it is
-// enqueued on (by default the handle's own buffers and stream).
+// enqueued on: the handle's own buffers, or (qp_operator_apply_noalloc) the
+// library's static scratch array and the caller's stream.
 struct OpWork {
     hipStream_t st;
     double* t;         // W .* (J p), CSR format (nJ)
@@ -1014,6 +1015,54 @@ qp_status fail(qp_handle* h, qp_status st, const std::string& msg) {
     return st;
 }
 
+// --------------------------------------------------------------------------
+// Scratch of qp_operator_apply_noalloc: one array per GPU, part of the
+// library's code object (loaded with it, held until the process ends).  In
+// host code its name is only a stand-in for the symbol; the device address
+// comes from hipGetSymbolAddress, resolved once per device by
+// resolve_scratch (qp_create, with the handle's device current) and kept
+// per device.
+// --------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = size_t(4) << 20;   // 32 MiB
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+// Device address of `scratch` on device dev (current), resolved on the first
+// call for that device.
+hipError_t resolve_scratch(int dev, double** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// Layout of the scratch for one operator product of h: the per-slot sums
+// (line format) or W .* (J p) (CSR), then Sigma_A .* (A p), then the low-rank
+// partials and w .* (U^T p); each part starts on a 256-byte boundary.  Returns
+// the doubles needed.
+size_t scratch_layout(const qp_handle* h, size_t off[4]) {
+    auto up = [](size_t v) { return (v + 31) / 32 * 32; };
+    const size_t first = h->line ? size_t(h->nslots) : size_t(std::max(h->nJ, 1));
+    off[0] = 0;
+    off[1] = up(first);
+    off[2] = off[1] + up(size_t(std::max(h->m, 1)));
+    off[3] = off[2] + up(size_t(kLrBlocks) * size_t(h->k));
+    return off[3] + up(size_t(h->k));
+}
 
 
 // ==========================================================================
@@ -2168,6 +2217,11 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
 
         // device
         HIPCHK(hipGetDevice(&h->device));
+        {   // once per device: the scratch of qp_operator_apply_noalloc (a failure
+            // here is reported by that entry point, which retries)
+            double* sp = nullptr;
+            if (resolve_scratch(h->device, &sp) != hipSuccess) (void)hipGetLastError();
+        }
         if (hip_stream) {
             h->stream = static_cast<hipStream_t>(hip_stream);
         } else {
@@ -2462,6 +2516,53 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
     } catch (const HipError& he) {
         return fail(h, QP_ERR_DEVICE, std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e));
     }
+    return QP_OK;
+}
+
+qp_status qp_operator_apply_noalloc(qp_handle* h, const double* sigma_x, const double* sigma_A, const double* v,
+                                    double* y, int32_t precision, void* hip_stream) {
+    if (!h) return QP_ERR_INVALID;
+    if (!sigma_x || !v || !y || (h->m > 0 && !sigma_A)) return fail(h, QP_ERR_INVALID, "NULL argument");
+    if (precision < QP_FP64 || precision > QP_BF16) return fail(h, QP_ERR_INVALID, "precision out of range");
+    const bool resident = precision == QP_FP64 ||
+                          (h->line ? (precision == QP_FP32 ? h->lval32 != nullptr : h->lval16 != nullptr)
+                                   : (precision == QP_FP32 ? h->Jv32 != nullptr : h->Jv16 != nullptr));
+    if (!resident)
+        return fail(h, QP_ERR_INVALID,
+                    "the J values of this precision are not resident (create the handle with that precision, or "
+                    "call qp_operator_apply with it once)");
+    size_t off[4];
+    const size_t need = scratch_layout(h, off);
+    if (need > kScratchDoubles)
+        return fail(h, QP_ERR_INVALID,
+                    "problem too large for the static scratch: needs " + std::to_string(need) +
+                        " doubles, the maximum is " + std::to_string(kScratchDoubles) +
+                        " (32 MiB); use qp_operator_apply");
+    double* sp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        sp = (h->device >= 0 && h->device < kMaxDevices) ? g_scratch_ptr[h->device] : nullptr;
+    }
+    if (!sp) {   // not resolved by qp_create on this device: resolve now
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != h->device)
+            return fail(h, QP_ERR_DEVICE, "scratch address unresolved and the handle's device is not current");
+        const hipError_t e = resolve_scratch(h->device, &sp);
+        if (e != hipSuccess)
+            return fail(h, QP_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    const OpWork wk{hip_stream ? static_cast<hipStream_t>(hip_stream) : h->stream, sp + off[0], sp + off[0],
+                    sp + off[1], sp + off[2], sp + off[3]};
+    const bool aug = h->aug;
+    h->aug = false;   // the condensed operator
+    try {
+        (void)hipGetLastError();   // drop an error left by an earlier, unrelated call
+        apply_op_prec(h, wk, precision, v, y, sigma_x, h->m > 0 ? sigma_A : nullptr, 1.0, false, false, 0);
+    } catch (const HipError& he) {
+        h->aug = aug;
+        return fail(h, QP_ERR_DEVICE, std::string("HIP error in ") + he.what + ": " + hipGetErrorString(he.e));
+    }
+    h->aug = aug;
     return QP_OK;
 }
 

@@ -64,7 +64,8 @@ class qp_info(C.Structure):
 
 
 EXPORTS = ["qp_default_settings", "qp_create", "qp_create_device", "qp_solve", "qp_solve_from", "qp_update_hessian",
-           "qp_newton_step", "qp_operator_apply", "qp_solve_batch", "qp_last_error", "qp_destroy", "qp_sizes"]
+           "qp_newton_step", "qp_operator_apply", "qp_operator_apply_noalloc", "qp_solve_batch", "qp_last_error",
+           "qp_destroy", "qp_sizes"]
 
 _lib = None
 
@@ -96,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.qp_operator_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int32, C.c_int32,
                                       C.POINTER(qp_info)]
     lib.qp_operator_apply.restype = C.c_int
+    lib.qp_operator_apply_noalloc.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int32, C.c_void_p]
+    lib.qp_operator_apply_noalloc.restype = C.c_int
     lib.qp_solve_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(_dp), C.POINTER(qp_info)]
     lib.qp_solve_batch.restype = C.c_int
     lib.qp_last_error.argtypes = [C.c_void_p]
@@ -385,6 +388,22 @@ def qp_operator_apply(h: QPHandle, sigma_x, sigma_A, v, precision=QP_FP64, reps:
     if st != QP_OK:
         raise QPError(st, h.last_error())
     return y, info.as_dict()
+
+
+def qp_operator_apply_noalloc(h: QPHandle, sigma_x, sigma_A, v, y, precision=QP_FP64, stream=None) -> int:
+    """qp_operator_apply_noalloc: y = K v with every vector in device memory
+    (float64 device arrays: torch tensors or buffers of the same HIP
+    runtime), enqueued on `stream` (None: the handle's stream) without any
+    allocation.  Returns the status; the product is complete once the stream
+    has reached it."""
+    lib = load_library()
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    sx = _dev_ptr(sigma_x, "f64", h.n, "sigma_x")
+    sa = _dev_ptr(sigma_A, "f64", h.m, "sigma_A") if h.m > 0 else None
+    vv = _dev_ptr(v, "f64", h.n, "v")
+    yy = _dev_ptr(y, "f64", h.n, "y")
+    return lib.qp_operator_apply_noalloc(h._h, sx, sa, vv, yy, int(precision), _stream_handle(stream))
 
 
 def qp_sizes(h: QPHandle):

@@ -112,3 +112,28 @@ def test_sqp_sequence_shares_constraints_and_grows_rank():
             assert np.all(q.w > 0) and q.U.flags.f_contiguous
     again = qpsynth.sqp_sequence(base, 4)
     np.testing.assert_array_equal(again[3].p, seq[3].p)
+
+
+def test_noalloc_scratch_symbol_is_registrable():
+    """The static scratch array of qp_operator_apply_noalloc must reach the
+    device code object as a global symbol: the HIP runtime registers every
+    __device__ variable at load time and cannot find a local one (the whole
+    library would then fail to load on a GPU)."""
+    import subprocess
+    import tempfile
+    llvm = "/opt/rocm/llvm/bin"
+    tools = [os.path.join(llvm, t) for t in ("llvm-objcopy", "clang-offload-bundler", "llvm-readelf")]
+    if not all(os.path.exists(t) for t in tools):
+        pytest.skip("ROCm LLVM tools not present")
+    lib = qpgpu.LIB_PATH
+    with tempfile.TemporaryDirectory() as d:
+        fat, co = os.path.join(d, "lib.fat"), os.path.join(d, "lib.co")
+        subprocess.run([tools[0], f"--dump-section=.hip_fatbin={fat}", lib], check=True)
+        subprocess.run([tools[1], "--unbundle", "--type=o", f"--input={fat}",
+                        "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--output={co}"], check=True)
+        syms = subprocess.run([tools[2], "-s", co], check=True, capture_output=True, text=True).stdout
+    rows = [ln.split() for ln in syms.splitlines() if ln.strip().endswith("scratch") and "uses_flat" not in ln]
+    assert rows, "scratch array missing from the device code object"
+    for r in rows:
+        assert r[3] == "OBJECT" and r[4] == "GLOBAL", r
+        assert int(r[2]) == 32 * 1024 * 1024, r
