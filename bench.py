@@ -12,11 +12,12 @@ rate; the same QP is then timed with BF16 and FP32 values of J
 with per-kernel HIP events gives the operator kernels' durations for the
 roofline, the general CSR path's operator is timed on the same QP
 (`csr_operator`), a child process measures the streaming-read ceiling with
-torch, and the FP64 dense-Cholesky oracle solves the same QP on the host
-cores (`cpu_baseline`).
+torch, the 64 uneven QPs of the batch workload are solved together by
+qp_solve_batch in each precision (`batch64`), and the FP64 dense-Cholesky
+oracle solves the same QP on the host cores (`cpu_baseline`).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
-                    [--scale 1.0] [--cpu-baseline full|sample|none] [--mixed 1] [--csr 1]
+                    [--scale 1.0] [--cpu-baseline full|sample|none] [--mixed 1] [--csr 1] [--batch 1]
 
 Prints one JSON line.
 """
@@ -171,9 +172,42 @@ def operator_only(args, prob):
                       "checksum": float(np.abs(y).sum())}), flush=True)
 
 
+def batch_run(probs, prec, steps, warmup):
+    """`probs` created once at precision `prec`, then solved together by
+    qp_solve_batch `warmup` times untimed and `steps` times timed (host clock
+    around the calls, data resident in HBM).  The handles are freed before
+    returning."""
+    from paper_2405_03584_amd import qpgpu
+    t0 = time.perf_counter()
+    st = qpgpu.qp_default_settings(precision=prec)
+    hs = [qpgpu.qp_create_from_problem(p, settings=st) for p in probs]
+    t_create = time.perf_counter() - t0
+    print(f"[bench] batch {prec}: created {len(hs)} handles in {t_create:.1f}s", file=sys.stderr, flush=True)
+    for i in range(warmup):
+        s, _, infos = qpgpu.qp_solve_batch(hs)
+        print(f"[bench] batch {prec} warmup {i}: status={s}", file=sys.stderr, flush=True)
+    infos_all = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        s, _, infos = qpgpu.qp_solve_batch(hs)
+        infos_all += infos
+    el = time.perf_counter() - t0
+    for h in hs:
+        h.close()
+    ms = 1e3 * el / steps
+    pcg = sum(f["pcg_iters"] for f in infos_all) / steps
+    print(f"[bench] batch {prec}: {ms:.1f} ms per batch, pcg {pcg:.0f}", file=sys.stderr, flush=True)
+    return {"ms_per_batch": ms, "qp_per_s": len(probs) / (ms * 1e-3),
+            "status_ok": all(f["status"] == qpgpu.QP_OK for f in infos_all),
+            "ipm_iters_total": sum(f["ipm_iters"] for f in infos_all) // steps,
+            "pcg_iters_total": int(pcg), "create_s": t_create,
+            "max_certificate": max(max(f[k] for k in ("eps_d", "eps_p", "eps_c", "gap")) for f in infos_all)}
+
+
 def batch_bench(args):
     """The uneven batch: `count` members of the 64-QP set, created once, then
-    solved together (qp_solve_batch) per step."""
+    solved together (qp_solve_batch) per step; for comparison the same handles
+    solved one after another, and (QPGPU_BATCH_THREADS=1) on host workers."""
     import qpsynth
     from paper_2405_03584_amd import qpgpu
     t0 = time.perf_counter()
@@ -201,16 +235,27 @@ def batch_bench(args):
         qpgpu.qp_solve(h)
     seq = time.perf_counter() - t1
     print(f"[bench] sequential: {1e3 * seq:.1f} ms", file=sys.stderr, flush=True)
+    # the same batch on host workers, each QP's own solve on its own stream
+    os.environ["QPGPU_BATCH_THREADS"] = "1"
+    qpgpu.qp_solve_batch(hs)
+    t2 = time.perf_counter()
+    qpgpu.qp_solve_batch(hs)
+    thr = time.perf_counter() - t2
+    del os.environ["QPGPU_BATCH_THREADS"]
+    print(f"[bench] host workers: {1e3 * thr:.1f} ms", file=sys.stderr, flush=True)
     print(json.dumps({"metric": METRIC, "value": args.count * args.steps / el, "unit": "QP/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                       "dtype": args.precision, "data": "synthetic",
                       "config": {"workload": f"batch of {args.count} uneven banded-dose QPs "
-                                             f"(n in [2000, 20000], {nnz} nnz of J in all)",
+                                             f"(n in [2000, 20000], {nnz} nnz of J in all), persistent "
+                                             f"batched launches",
                                  "precision": args.precision},
                       "status_ok": ok,
                       "sequential_ms": 1e3 * seq,
+                      "host_workers_ms": 1e3 * thr,
                       "batch_speedup_vs_sequential": seq / (el / args.steps),
+                      "batch_speedup_vs_host_workers": thr / (el / args.steps),
                       "ipm_iters_total": sum(f["ipm_iters"] for f in all_infos),
                       "pcg_iters_total": sum(f["pcg_iters"] for f in all_infos)}), flush=True)
 
@@ -328,6 +373,8 @@ def main():
                          "sample: dense H + one IPM iteration, extrapolated; none")
     ap.add_argument("--mixed", type=int, default=1, choices=[0, 1],
                     help="1: also time the other two precisions on the same QP")
+    ap.add_argument("--batch", type=int, default=1, choices=[0, 1],
+                    help="1: also time the 64-QP batch (qp_solve_batch) in each precision")
     ap.add_argument("--csr", type=int, default=1, choices=[0, 1],
                     help="1: also time the general CSR operator path on the same QP")
     ap.add_argument("--log", type=int, default=0, help="per-IPM-iteration progress on stderr (untimed runs)")
@@ -436,6 +483,20 @@ def main():
     }
     if args.mixed and "fp64" in runs:
         out["mixed_vs_fp64"] = {q: runs["fp64"]["ms_per_qp"] / runs[q]["ms_per_qp"] for q in precs if q != "fp64"}
+    if args.batch and args.workload == "config2":
+        # the 64 uneven QPs (n in [2000, 20000]) solved together, per precision
+        t0 = time.perf_counter()
+        probs = [qpsynth.config4_instance(i) for i in range(64)]
+        bnnz = sum(int(p.J.nnz) for p in probs)
+        print(f"[bench] batch: generated 64 QPs ({bnnz} nnz of J) in {time.perf_counter() - t0:.1f}s",
+              file=sys.stderr, flush=True)
+        bruns = {q: batch_run(probs, q, 1, 1) for q in ("fp64", "bf16", "fp32")}
+        del probs
+        out["batch64"] = {"workload": f"64 uneven banded-dose QPs, n in [2000, 20000], {bnnz} nnz of J in all, "
+                                      "one qp_solve_batch (persistent batched launches) per step",
+                          "by_precision": bruns,
+                          "mixed_vs_fp64": {q: bruns["fp64"]["ms_per_batch"] / bruns[q]["ms_per_batch"]
+                                            for q in ("bf16", "fp32")}}
     # the paper's speedups are over a commercial CPU solver on its own clinical
     # QPs and machines: printed beside ours for context, not compared
     out["paper_context"] = {

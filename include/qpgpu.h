@@ -112,8 +112,12 @@ typedef struct {
                                  Sigma_i sum_j A_ij^2 / D_j >= 1 through the dense inverse of their
                                  Schur complement, the other rows folded into the diagonal;
                                  falls back to 0 when m = 0 or m > 8192.  A solve with it that
-                                 reaches 2000 PCG iterations or breaks down is repeated with 0
-                                 (qp_solve then keeps 0 for the rest of the QP) */
+                                 reaches 2000 PCG iterations or breaks down (r^T z <= 0: late in
+                                 the IPM the block's rounding can cost it definiteness) is
+                                 repeated with the block's Sigma capped so that no diagonal entry
+                                 of its Schur complement exceeds 1 + 1e4, and a solve that stalls
+                                 with that too, with 0; qp_solve keeps the tier reached for the
+                                 rest of the QP */
     int32_t spmv_format;      /* 0 (default): line format for J when its rows come in lines of 64
                                  sharing one column list (the 64-voxel bands), else CSR; 1: CSR */
     double  refine_tol;       /* relative residual target of each low-precision PCG solve when
@@ -147,7 +151,8 @@ typedef struct {
     double  t_spmv_bwd_ms;    /* summed J^T (and A^T) SpMV launch time, when timing = 1 */
     int64_t n_spmv_fwd, n_spmv_bwd;
     int32_t spmv_format;      /* format the PCG operator used: 0 CSR, 1 line format */
-    int32_t prec_fallbacks;   /* constraint-block PCG solves repeated with the Jacobi diagonal */
+    int32_t prec_fallbacks;   /* PCG solves repeated with the next preconditioner tier (capped block,
+                                 then the Jacobi diagonal) */
     /* KKT certificate of the returned (x, lam_x, lam_A) in the original units
      * (qp_solve / qp_solve_from only, 0 elsewhere), with y_x = lam_x, y_A = lam_A
      * and lambda_l = max(-y, 0), lambda_u = max(y, 0) per side:
@@ -157,6 +162,8 @@ typedef struct {
      *   gap   = |f - (-x^T H x/2 + sum lambda_l lo - sum lambda_u hi)| / (1 + |x^T H x|/2 + |p^T x|)
      * (the optimality conditions of eq. (qp) with mu = 0 in eq. (perturbed_KKT)). */
     double  eps_d, eps_p, eps_c, gap;
+    int32_t prec_tier;        /* preconditioner tier the call ended on: 0 constraint block, 1 capped
+                                 block, 2 Jacobi diagonal (see precond) */
 } qp_info;
 
 /* Defaults listed above. */

@@ -1157,6 +1157,74 @@ __global__ __launch_bounds__(kBlock) void k_diag_h(const int* Jtp, const int* Jt
     }
 }
 
+// diag(H) on the line format of J, in two steps: k_line_diag gives every
+// slot s of a line the weighted squares sum_r W_r J_(r,s)^2 over the line's
+// 64 rows (a wavefront per slot, lane = row, fixed butterfly), and
+// k_spot_diag sums them over each spot's slots: diag(H)_j = gamma +
+// sum_slots + sum_c w_c U_jc^2.  A block per line; slot values contiguous per
+// slot (64 rows).
+__global__ __launch_bounds__(kBlock) void k_line_diag(const int* lptr, const double* lval, const double* W, int L,
+                                                      double* d) {
+    const int l = blockIdx.x;
+    if (l >= L) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int off = lptr[l], end = lptr[l + 1];
+    const double wr = W[size_t(l) * 64 + lane];
+    for (int k = off + w; k < end; k += kBlock / 64) {
+        const double v = lval[size_t(k) * 64 + lane];
+        const double s = group_sum<double, 64>(wr * v * v);
+        if (lane == 0) d[k] = s;
+    }
+}
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_spot_diag(const int* sptr, const int* sslot, const double* d, int n,
+                                                      double gamma, const double* U, const double* w, int k,
+                                                      double* diagH) {
+    constexpr int RPB = kBlock / G;
+    const int j = blockIdx.x * RPB + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
+    if (j >= n) return;   // whole groups leave together
+    double s = canon_sum<G, double>(sptr[j], sptr[j + 1], lane, [&](int e) { return d[sslot[e]]; });
+    if (lane == 0) {
+        double dj = gamma + s;
+        for (int c = 0; c < k; ++c) {
+            const double u = U[j + size_t(n) * c];
+            dj += w[c] * u * u;
+        }
+        diagH[j] = dj;
+    }
+}
+
+// Low-precision copies of FP64 values, rounded on the device exactly as the
+// host does it (host_prep.cpp): FP32 by the conversion's round to nearest
+// even; BF16 by rounding to odd onto binary32 first, then to nearest even
+// (the two-step rounding that is exact, Boldo and Melquiond), values outside
+// the binary32 normal range through the plain conversion.
+__device__ __forceinline__ uint32_t d2f_bits(double v) { return __float_as_uint(float(v)); }
+__device__ __forceinline__ uint16_t d2bf16_bits(double v) {
+    const uint64_t d = uint64_t(__double_as_longlong(v));
+    const uint64_t sign = d >> 63;
+    const int64_t e = int64_t((d >> 52) & 0x7FF) - 1023 + 127;
+    const uint64_t m = d & ((uint64_t(1) << 52) - 1);
+    uint32_t b;
+    if (e >= 1 && e <= 254) {
+        b = uint32_t(sign << 31) | uint32_t(uint64_t(e) << 23) | uint32_t(m >> 29);
+        if (m & ((uint64_t(1) << 29) - 1)) b |= 1u;
+    } else {
+        b = d2f_bits(v);
+    }
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return uint16_t(b >> 16);
+}
+__global__ __launch_bounds__(kBlock) void k_round_f32(const double* src, size_t count, uint32_t* dst) {
+    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < count; i += size_t(gridDim.x) * kBlock)
+        dst[i] = d2f_bits(src[i]);
+}
+__global__ __launch_bounds__(kBlock) void k_round_bf16(const double* src, size_t count, uint16_t* dst) {
+    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < count; i += size_t(gridDim.x) * kBlock)
+        dst[i] = d2bf16_bits(src[i]);
+}
+
 // Jacobi diagonals for a given Sigma: dh_j = diagH_j + sigx_j and
 // d_j = dh_j + sum_i (A^T)_ji^2 sigA_i.
 __global__ __launch_bounds__(kBlock) void k_jacobi(const int* Atp, const double* Atv, const int* Atc,

@@ -76,7 +76,6 @@ struct qp_handle {
     double *Jv = nullptr, *Jtv = nullptr;
     float *Jv32 = nullptr, *Jtv32 = nullptr;
     bf16_t *Jv16 = nullptr, *Jtv16 = nullptr;
-    std::vector<double> hJv, hJtv;     // kept to build low-precision copies on demand
     double* W = nullptr;
     int *Ap = nullptr, *Ac = nullptr, *Atp = nullptr, *Atc = nullptr;
     double *Av = nullptr, *Atv = nullptr;
@@ -96,7 +95,6 @@ struct qp_handle {
     double* lc = nullptr;   // per-slot J^T contributions of the line pass
     float* lval32 = nullptr;
     bf16_t* lval16 = nullptr;
-    std::vector<double> hlval;
     double *xlo = nullptr, *xhi = nullptr, *alo = nullptr, *ahi = nullptr;
     double *p = nullptr, *diagH = nullptr, *U = nullptr, *w = nullptr;
 
@@ -115,6 +113,7 @@ struct qp_handle {
     double* Dw = nullptr;                        // D plus the weak rows' diagonal
     double *lr_part = nullptr, *lr_v = nullptr;  // low-rank term: U^T p partials and w .* U^T p
     int *rflag = nullptr, *rpos = nullptr, *ridx = nullptr, *kdev = nullptr;
+    double* rmii = nullptr;     // M_ii of every row of A (k_row_strength)
     int* sext = nullptr;        // per strong row: range in A (k_strong_rows)
     int *scr = nullptr, *scnt = nullptr;   // per column of A: strong entries' ranks, count (k_fold_weak)
     double* scv = nullptr;                 // and their values
@@ -217,6 +216,14 @@ struct PrecAttemptCap {
 bool prec_stalled(const qp_handle* h, const Flags& f) {
     return f.pcg_breakdown || (f.pcg_capped && h->set.pcg_max_iter > kPrecAttemptIters);
 }
+// Preconditioner tiers of a QP: the constraint block; the capped block
+// (Sigma of the dense block limited so that S_ii <= 1 + kPrecCapTau), used
+// once the exact block has stalled or broken down; the Jacobi diagonal, once
+// the capped block has too.  A QP moves down the tiers only, and keeps its
+// tier for the rest of its run.
+constexpr double kPrecCapTau = 1e4;
+enum { TIER_BLOCK = 0, TIER_CAPPED = 1, TIER_JACOBI = 2 };
+double tier_tau(int tier) { return tier == TIER_CAPPED ? kPrecCapTau : 0.0; }
 constexpr int kGraphIters = 4;   // PCG iterations per captured graph (and per trailing chunk)
 
 // Where an operator product keeps its intermediates, and the stream it is
@@ -459,35 +466,47 @@ std::map<std::tuple<int, int, int64_t, int, int>, std::pair<int, int>> g_tune_ca
 
 void autotune_schedule(qp_handle* h);
 
+// Low-precision copies of J's values for the PCG operator, made on first use
+// by rounding the resident FP64 values on the device: the line format's
+// values when J has it (the CSR copies are then never read), else J's and
+// J^T's CSR values.
 void ensure_lowp(qp_handle* h, int prec) {
-    if (h->line && prec == QP_FP32 && !h->lval32) {
-        std::vector<uint32_t> a(h->hlval.size());
-        for (size_t i = 0; i < a.size(); ++i) a[i] = f64_to_f32_bits(h->hlval[i]);
-        h->lval32 = reinterpret_cast<float*>(h->upload(a.data(), a.size()));
-        HIPCHK(hipStreamSynchronize(h->stream));
+    if (prec != QP_FP32 && prec != QP_BF16) return;
+    auto round = [&](const double* src, size_t count, void* dst) {
+        const int g = int(std::max<size_t>(1, std::min<size_t>((count + kBlock - 1) / kBlock, 8192)));
+        if (prec == QP_FP32)
+            hipLaunchKernelGGL(k_round_f32, dim3(g), dim3(kBlock), 0, h->stream, src, count,
+                               static_cast<uint32_t*>(dst));
+        else
+            hipLaunchKernelGGL(k_round_bf16, dim3(g), dim3(kBlock), 0, h->stream, src, count,
+                               static_cast<uint16_t*>(dst));
+        HIPCHK(hipGetLastError());
+    };
+    const size_t nz = size_t(h->nnzJ);
+    if (h->line) {
+        if (prec == QP_FP32 && !h->lval32) {
+            h->lval32 = h->dalloc<float>(nz);
+            round(h->lval, nz, h->lval32);
+        }
+        if (prec == QP_BF16 && !h->lval16) {
+            h->lval16 = h->dalloc<bf16_t>(nz);
+            round(h->lval, nz, h->lval16);
+        }
+    } else {
+        if (prec == QP_FP32 && !h->Jv32) {
+            h->Jv32 = h->dalloc<float>(nz);
+            h->Jtv32 = h->dalloc<float>(nz);
+            round(h->Jv, nz, h->Jv32);
+            round(h->Jtv, nz, h->Jtv32);
+        }
+        if (prec == QP_BF16 && !h->Jv16) {
+            h->Jv16 = h->dalloc<bf16_t>(nz);
+            h->Jtv16 = h->dalloc<bf16_t>(nz);
+            round(h->Jv, nz, h->Jv16);
+            round(h->Jtv, nz, h->Jtv16);
+        }
     }
-    if (h->line && prec == QP_BF16 && !h->lval16) {
-        std::vector<uint16_t> a(h->hlval.size());
-        for (size_t i = 0; i < a.size(); ++i) a[i] = f64_to_bf16_bits(h->hlval[i]);
-        h->lval16 = reinterpret_cast<bf16_t*>(h->upload(a.data(), a.size()));
-        HIPCHK(hipStreamSynchronize(h->stream));
-    }
-    if (prec == QP_FP32 && !h->Jv32) {
-        std::vector<uint32_t> a(h->hJv.size()), b(h->hJtv.size());
-        for (size_t i = 0; i < a.size(); ++i) a[i] = f64_to_f32_bits(h->hJv[i]);
-        for (size_t i = 0; i < b.size(); ++i) b[i] = f64_to_f32_bits(h->hJtv[i]);
-        h->Jv32 = reinterpret_cast<float*>(h->upload(a.data(), a.size()));
-        h->Jtv32 = reinterpret_cast<float*>(h->upload(b.data(), b.size()));
-        HIPCHK(hipStreamSynchronize(h->stream));
-    }
-    if (prec == QP_BF16 && !h->Jv16) {
-        std::vector<uint16_t> a(h->hJv.size()), b(h->hJtv.size());
-        for (size_t i = 0; i < a.size(); ++i) a[i] = f64_to_bf16_bits(h->hJv[i]);
-        for (size_t i = 0; i < b.size(); ++i) b[i] = f64_to_bf16_bits(h->hJtv[i]);
-        h->Jv16 = reinterpret_cast<bf16_t*>(h->upload(a.data(), a.size()));
-        h->Jtv16 = reinterpret_cast<bf16_t*>(h->upload(b.data(), b.size()));
-        HIPCHK(hipStreamSynchronize(h->stream));
-    }
+    HIPCHK(hipStreamSynchronize(h->stream));
 }
 
 struct TimingAcc {
@@ -500,11 +519,12 @@ struct TimingAcc {
 // strong rows, factor it and build S^{-1} (schur_kernels.hpp).  `stop`
 // (device int, may be null) turns every launch into a no-op once set.
 // Returns true when the dense block is non-empty (else Jacobi with d applies).
-bool build_precond(qp_handle* h, const double* D, const double* sigA, const int* stop) {
+// tau > 0: the capped block (k_strong_rows).
+bool build_precond(qp_handle* h, const double* D, const double* sigA, const int* stop, double tau = 0.0) {
     if (!h->woodbury) return false;
     const int m = h->m, n = h->n;
     hipLaunchKernelGGL(k_row_strength, dim3((m + 3) / 4), dim3(256), 0, h->stream, (const int*)h->Ap,
-                       (const int*)h->Ac, (const double*)h->Av, D, sigA, m, h->rflag, stop);
+                       (const int*)h->Ac, (const double*)h->Av, D, sigA, m, h->rflag, h->rmii, stop);
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, h->stream, (const int*)h->rflag, m, h->rpos, h->ridx,
                        h->kdev, stop);
     // k goes to the host as soon as it is known; the two kernels below keep
@@ -512,7 +532,8 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
     HIPCHK(hipMemcpyAsync(h->k_host, h->kdev, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipEventRecord(h->ev_k, h->stream));
     hipLaunchKernelGGL(k_strong_rows, dim3((h->srows + 255) / 256), dim3(256), 0, h->stream, (const int*)h->Ap,
-                       (const int*)h->ridx, sigA, (const int*)h->kdev, h->srows, h->sext, h->ssq, stop);
+                       (const int*)h->ridx, sigA, (const double*)h->rmii, tau, (const int*)h->kdev, h->srows,
+                       h->sext, h->ssq, stop);
     hipLaunchKernelGGL(k_fold_weak, dim3((n + 15) / 16), dim3(256), 0, h->stream, (const int*)h->Atp,
                        (const int*)h->Atc, (const double*)h->Atv, sigA, (const int*)h->rpos, D, n, h->Dw, h->scr,
                        h->scv, h->scnt, stop);
@@ -991,8 +1012,20 @@ void ensure_timing_events(qp_handle* h) {
     }
 }
 
-// diag(H) = gamma + sum_i W_i J_ij^2 + sum_c w_c U_jc^2 into h->diagH.
+// diag(H) = gamma + sum_i W_i J_ij^2 + sum_c w_c U_jc^2 into h->diagH: from
+// the line format (per-slot weighted squares in h->lc, then per spot), or
+// from the CSR rows of J^T.
 void compute_diag_h(qp_handle* h) {
+    if (h->line) {
+        if (h->L > 0)
+            hipLaunchKernelGGL(k_line_diag, dim3(h->L), dim3(kBlock), 0, h->stream, (const int*)h->lptr,
+                               (const double*)h->lval, (const double*)h->W, h->L, h->lc);
+        hipLaunchKernelGGL(k_spot_diag<kSpotLanes>, dim3(grid_rows(h->n, kSpotLanes)), dim3(kBlock), 0, h->stream,
+                           (const int*)h->sptr, (const int*)h->sslot, (const double*)h->lc, h->n, h->gamma,
+                           (const double*)h->U, (const double*)h->w, h->k, h->diagH);
+        HIPCHK(hipGetLastError());
+        return;
+    }
     const int G = 64;
     hipLaunchKernelGGL(k_diag_h<G>, dim3(grid_rows(h->n, G)), dim3(kBlock), 0, h->stream, (const int*)h->Jtp,
                        (const int*)h->Jtc, (const double*)h->Jtv, (const double*)h->W, h->n, h->gamma,
@@ -1076,7 +1109,7 @@ struct IpmRun {
     qp_handle* h = nullptr;
     double hs = 1.0;              // objective scale 1/zeta
     bool wbp = false;             // constraint-block preconditioner built for the current iterate
-    bool jacobi_only = false;     // a stalled constraint-block solve switched this QP to Jacobi
+    int tier = TIER_BLOCK;        // preconditioner tier (a stalled solve moves the QP down)
     int fallbacks = 0;
     int64_t pcg_total = 0;
     int pcg_solves = 0, capped = 0;
@@ -1192,7 +1225,7 @@ void ipm_start(IpmRun& r, const double* x0) {
         HIPCHK(hipGetLastError());
         nps += ga;
     }
-    apply_op<double, double>(h, handle_work(h), v.x, h->tmp_n, nullptr, nullptr, 1.0, false, false, 0);
+    apply_op_prec(h, QP_FP64, v.x, h->tmp_n, nullptr, nullptr, 1.0, false, false, 0);
     hipLaunchKernelGGL(k_ipm_scale, dim3(1), dim3(kBlock), 0, h->stream, (const double*)h->tmp_n,
                        (const double*)h->p, n, (const double*)h->partA, nps, h->mtot, h->set.scale_objective,
                        h->set.mu0, h->isc);
@@ -1231,17 +1264,17 @@ Flags ipm_direction(IpmRun& r, int* nsolves) {
     *nsolves = 0;
     Flags f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
                                r.wbp ? h->Dw : nullptr, r.hs, true, &r.ta, nsolves);
-    if (!f.ipm_done && r.wbp && prec_stalled(h, f)) {
+    while (!f.ipm_done && r.wbp && prec_stalled(h, f)) {
         r.pcg_total += f.pcg_iters;
         r.pcg_solves += *nsolves;
         ++r.fallbacks;
-        r.jacobi_only = true;
-        r.wbp = false;
+        ++r.tier;
         if (h->set.log_level > 0)
-            std::fprintf(stderr, "[qpgpu] constraint-block PCG stopped after %d iterations: Jacobi from here\n",
-                         f.pcg_iters);
+            std::fprintf(stderr, "[qpgpu] constraint-block PCG stopped after %d iterations: %s from here\n",
+                         f.pcg_iters, r.tier == TIER_CAPPED ? "capped block" : "Jacobi");
+        r.wbp = r.tier == TIER_CAPPED && build_precond(h, v.dh, v.sigA, ipm_stop_flag(h), kPrecCapTau);
         f = newton_direction(h, h->set.precision, v.rhs_a, v.rhs_b, v.sigx, m > 0 ? v.sigA : nullptr, v.d,
-                             nullptr, r.hs, true, &r.ta, nsolves);
+                             r.wbp ? h->Dw : nullptr, r.hs, true, &r.ta, nsolves);
     }
     HIPCHK(hipEventRecord(h->ev_p1[ps], h->stream));
     if (!f.ipm_done) r.pcg_timed[ps] = true;
@@ -1294,7 +1327,7 @@ void ipm_step(IpmRun& r) {
                        (const double*)h->part2, nbA + nbx, h->isc, (const Flags*)h->fl);
     HIPCHK(hipGetLastError());
     ipm_residuals(h, 1);
-    r.wbp = !r.jacobi_only && (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop_flag(h));
+    r.wbp = r.tier < TIER_JACOBI && (m > 0) && build_precond(h, v.dh, v.sigA, ipm_stop_flag(h), tier_tau(r.tier));
 }
 
 // Outputs: the KKT certificate of the returned point (H x and A x of the
@@ -1353,6 +1386,7 @@ void ipm_finish(IpmRun& r, double* x, double* lam_A, double* lam_x, qp_info* inf
         info->t_pcg_ms = r.pcg_ms;
         info->spmv_format = h->line ? 1 : 0;
         info->prec_fallbacks = r.fallbacks;
+        info->prec_tier = (h->woodbury && h->m > 0) ? r.tier : TIER_JACOBI;
         info->eps_d = co.eps_d;
         info->eps_p = co.eps_p;
         info->eps_c = co.eps_c;
@@ -1563,9 +1597,10 @@ void batch_stage_done(BatchRun& B) {
 
 // Fill and upload every QP's tables for the current iterate: the arguments
 // its own solve would launch with (pcg_setup, line_args, spot_args), with the
-// constraint-block preconditioner where the QP's run has one built.
+// constraint-block preconditioner (exact or capped) where the QP's run has
+// one built.
 template <typename VT>
-void batch_tables_t(BatchRun& B, const std::vector<char>& jacobi) {
+void batch_tables_t(BatchRun& B) {
     const int nq = B.nq;
     const TabLayout t = tab_layout(nq, sizeof(LineArgs<VT>));
     batch_stage_wait(B);
@@ -1577,7 +1612,7 @@ void batch_tables_t(BatchRun& B, const std::vector<char>& jacobi) {
         IpmVec& v = h->iv;
         const int m = h->m;
         const double* sigA = m > 0 ? v.sigA : nullptr;
-        const double* dh = (r.wbp && !jacobi[q]) ? h->Dw : nullptr;
+        const double* dh = r.wbp ? h->Dw : nullptr;
         const double tol = h->set.pcg_tol;
         const double inner = h->set.refine_steps > 0 ? std::max(h->set.refine_tol, tol) : tol;
         const PcgSetup S_ipm = pcg_setup(h, v.rhs_a, v.rhs_b, sigA, v.d, dh, true, tol, false);
@@ -1632,11 +1667,11 @@ void batch_tables_t(BatchRun& B, const std::vector<char>& jacobi) {
     HIPCHK(hipMemcpyAsync(B.d_qs, img, B.tab_bytes, hipMemcpyHostToDevice, B.st));
     batch_stage_done(B);
 }
-void batch_tables(BatchRun& B, const std::vector<char>& jacobi) {
+void batch_tables(BatchRun& B) {
     switch (B.prec) {
-        case QP_FP32: batch_tables_t<float>(B, jacobi); break;
-        case QP_BF16: batch_tables_t<bf16_t>(B, jacobi); break;
-        default: batch_tables_t<double>(B, jacobi); break;
+        case QP_FP32: batch_tables_t<float>(B); break;
+        case QP_BF16: batch_tables_t<bf16_t>(B); break;
+        default: batch_tables_t<double>(B); break;
     }
 }
 
@@ -2020,7 +2055,7 @@ std::vector<qp_status> batch_solve(qp_handle* const* hs, int count, double* cons
     int workers = 6;
     if (const char* e = std::getenv("QPGPU_BATCH_WORKERS")) workers = std::max(1, std::atoi(e));
     workers = std::min(workers, count);
-    std::vector<char> all(count, 1), jacobi(count, 0);
+    std::vector<char> all(count, 1);
 
     // start every QP on its own stream; then the tables and the schedule
     std::vector<std::unique_ptr<PrecAttemptCap>> caps;
@@ -2030,7 +2065,7 @@ std::vector<qp_status> batch_solve(qp_handle* const* hs, int count, double* cons
         HIPCHK(hipEventRecord(B.ev_q[q], B.hs[q]->stream));
     }, st);
     for (int q = 0; q < count; ++q) HIPCHK(hipStreamWaitEvent(B.st, B.ev_q[q], 0));
-    batch_tables(B, jacobi);
+    batch_tables(B);
     batch_autotune(B);
     while (true) {
         std::vector<char> live(count, 0);
@@ -2039,28 +2074,42 @@ std::vector<qp_status> batch_solve(qp_handle* const* hs, int count, double* cons
         // the directions of every live QP (their steps ended before: events)
         for (int q = 0; q < count; ++q)
             if (live[q]) HIPCHK(hipStreamWaitEvent(B.st, B.ev_q[q], 0));
-        batch_tables(B, jacobi);
+        batch_tables(B);
         HIPCHK(hipEventRecord(B.ev_t0, B.st));
         std::vector<Flags> f;
         std::vector<int> ns;
         batch_direction(B, live, f, ns);
         // a stalled constraint-block solve: that QP's direction again with
-        // the Jacobi diagonal, which then serves the rest of its run
-        std::vector<char> redo(count, 0);
-        for (int q = 0; q < count; ++q) {
-            IpmRun& r = B.runs[q];
-            if (live[q] && !f[q].ipm_done && r.wbp && prec_stalled(B.hs[q], f[q])) {
-                r.pcg_total += f[q].pcg_iters;
-                r.pcg_solves += ns[q];
-                ++r.fallbacks;
-                r.jacobi_only = true;
-                r.wbp = false;
-                jacobi[q] = 1;
-                redo[q] = 1;
+        // the next preconditioner tier, which then serves the rest of its run
+        for (int round = 0; round < 2; ++round) {
+            std::vector<char> redo(count, 0);
+            for (int q = 0; q < count; ++q) {
+                IpmRun& r = B.runs[q];
+                if (live[q] && !f[q].ipm_done && r.wbp && prec_stalled(B.hs[q], f[q])) {
+                    r.pcg_total += f[q].pcg_iters;
+                    r.pcg_solves += ns[q];
+                    ++r.fallbacks;
+                    ++r.tier;
+                    r.wbp = false;
+                    redo[q] = 1;
+                }
             }
-        }
-        if (any_of(redo)) {
-            batch_tables(B, jacobi);
+            if (!any_of(redo)) break;
+            // the capped block is built on the QP's own stream, after the
+            // batched solve that read the exact one
+            HIPCHK(hipEventRecord(B.ev_dir, B.st));
+            batch_each(B, redo, workers, [&](int q) {
+                IpmRun& r = B.runs[q];
+                qp_handle* h = B.hs[q];
+                if (r.tier == TIER_CAPPED) {
+                    HIPCHK(hipStreamWaitEvent(h->stream, B.ev_dir, 0));
+                    r.wbp = build_precond(h, h->iv.dh, h->iv.sigA, ipm_stop_flag(h), kPrecCapTau);
+                }
+                HIPCHK(hipEventRecord(B.ev_q[q], h->stream));
+            }, st);
+            for (int q = 0; q < count; ++q)
+                if (redo[q]) HIPCHK(hipStreamWaitEvent(B.st, B.ev_q[q], 0));
+            batch_tables(B);
             std::vector<Flags> f2;
             std::vector<int> ns2;
             batch_direction(B, redo, f2, ns2);
@@ -2175,9 +2224,11 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
 
         // host preparation (no device calls yet)
         HostCsr hJ = to_host_csr(J);
-        HostCsr hJt = transpose(hJ);
         LineFormat lf;
         const bool use_line = (h->set.spmv_format != 1) && build_line_format(hJ, 64, lf);
+        // the CSR J and its stored transpose serve matrices without the line structure
+        HostCsr hJt;
+        if (!use_line) hJt = transpose(hJ);
         HostCsr hA, hAt;
         if (m > 0) {
             hA = to_host_csr(A);
@@ -2228,14 +2279,14 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
             HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
             h->own_stream = true;
         }
-        h->Jp = h->upload(hJ.ptr.data(), hJ.ptr.size());
-        h->Jc = h->upload(hJ.col.data(), hJ.col.size());
-        h->Jv = h->upload(hJ.val.data(), hJ.val.size());
-        h->Jtp = h->upload(hJt.ptr.data(), hJt.ptr.size());
-        h->Jtc = h->upload(hJt.col.data(), hJt.col.size());
-        h->Jtv = h->upload(hJt.val.data(), hJt.val.size());
-        h->hJv = std::move(hJ.val);
-        h->hJtv = std::move(hJt.val);
+        if (!use_line) {
+            h->Jp = h->upload(hJ.ptr.data(), hJ.ptr.size());
+            h->Jc = h->upload(hJ.col.data(), hJ.col.size());
+            h->Jv = h->upload(hJ.val.data(), hJ.val.size());
+            h->Jtp = h->upload(hJt.ptr.data(), hJt.ptr.size());
+            h->Jtc = h->upload(hJt.col.data(), hJt.col.size());
+            h->Jtv = h->upload(hJt.val.data(), hJt.val.size());
+        }
         if (use_line) {
             h->line = true;
             h->L = lf.lines;
@@ -2246,8 +2297,6 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
             h->sslot = h->upload(lf.sslot.data(), lf.sslot.size());
             h->lc = h->dalloc<double>(lf.col.size());
             h->nslots = int64_t(lf.col.size());
-            HIPCHK(hipStreamSynchronize(h->stream));
-            h->hlval = std::move(lf.val);
         }
         h->W = nJ > 0 ? h->upload(W, size_t(nJ)) : h->dalloc<double>(1);
         if (m > 0) {
@@ -2338,6 +2387,7 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
                 h->scv = h->dalloc<double>(std::max<int64_t>(h->nnzA, 1));
                 h->scnt = h->dalloc<int>(n);
                 h->rflag = h->dalloc<int>(m);
+                h->rmii = h->dalloc<double>(m);
                 h->rpos = h->dalloc<int>(m);
                 h->ridx = h->dalloc<int>(m);
                 h->kdev = h->dalloc<int>(1);
@@ -2600,19 +2650,22 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
         HIPCHK(hipGetLastError());
         TimingAcc ta;
         HIPCHK(hipEventRecord(h->ev_t0, h->stream));
-        const bool wbp = (m > 0) && build_precond(h, dh, sigA, nullptr);
+        bool wbp = (m > 0) && build_precond(h, dh, sigA, nullptr);
         int nsolves = 0;
         PrecAttemptCap cap_guard(h);
         Flags f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d,
                                    wbp ? h->Dw : nullptr, 1.0, false, &ta, &nsolves);
-        int fallbacks = 0;
-        if (wbp && prec_stalled(h, f)) {
+        int fallbacks = 0, tier = TIER_BLOCK;
+        while (wbp && prec_stalled(h, f)) {
+            // a stalled constraint-block solve: again with the next tier
+            // (the capped block, then the Jacobi diagonal)
             ++fallbacks;
-            // stalled constraint-block solve: again with the Jacobi diagonal
+            ++tier;
+            wbp = tier == TIER_CAPPED && build_precond(h, dh, sigA, nullptr, kPrecCapTau);
             int more = 0;
             const int spent = f.pcg_iters;
-            f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d, nullptr, 1.0,
-                                 false, &ta, &more);
+            f = newton_direction(h, h->set.precision, nullptr, b, sigx, m > 0 ? sigA : nullptr, d,
+                                 wbp ? h->Dw : nullptr, 1.0, false, &ta, &more);
             f.pcg_iters += spent;
             nsolves += more;
         }
@@ -2631,6 +2684,7 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
             info->pcg_capped = f.pcg_capped;
             info->pcg_relres = ps.bnorm2 > 0 ? std::sqrt(ps.rr / ps.bnorm2) : 0.0;
             info->prec_fallbacks = fallbacks;
+            info->prec_tier = (h->woodbury && m > 0) ? tier : TIER_JACOBI;
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
             info->t_solve_ms = info->t_pcg_ms = ms;

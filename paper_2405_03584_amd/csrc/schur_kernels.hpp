@@ -29,10 +29,11 @@ constexpr int TS = TS_PREC;   // tile edge of the dense kernels (the preconditio
 
 constexpr double kStrongRow = 1.0;   // M_ii threshold for the dense block
 
-// M_ii = Sigma_i sum_j A_ij^2 / D_j (a wavefront per row) and the strong flag.
+// M_ii = Sigma_i sum_j A_ij^2 / D_j (a wavefront per row), kept in mii, and
+// the strong flag.
 __global__ __launch_bounds__(256) void k_row_strength(const int* Ap, const int* Ac, const double* Av,
                                                       const double* D, const double* sigA, int m, int* flag,
-                                                      const int* stop) {
+                                                      double* mii, const int* stop) {
     if (stop && *stop) return;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -43,7 +44,11 @@ __global__ __launch_bounds__(256) void k_row_strength(const int* Ap, const int* 
         s += a * a / D[Ac[e]];
     }
     s = group_sum<double, 64>(s);
-    if (lane == 0) flag[i] = (sigA[i] * s >= kStrongRow) ? 1 : 0;
+    if (lane == 0) {
+        const double mi = sigA[i] * s;
+        mii[i] = mi;
+        flag[i] = (mi >= kStrongRow) ? 1 : 0;
+    }
 }
 
 // Deterministic compaction by one block: pos[i] = rank of strong row i (or
@@ -78,10 +83,14 @@ __global__ __launch_bounds__(1024) void k_compact(const int* flag, int m, int* p
 
 // Per strong row r, what the per-iteration kernels read in one load: the
 // range of row idx[r] in A (ext[2r], ext[2r+1]) and sqrt(Sigma) of it (sq[r]);
-// rows r in [k, rows) get an empty range and 0.
+// rows r in [k, rows) get an empty range and 0.  With tau > 0 the block
+// takes Sigma_i min(1, tau / M_ii) in place of Sigma_i, so that no diagonal
+// entry of S exceeds 1 + tau: the capped block, the preconditioner used once
+// the exact one has lost definiteness to rounding (its correction cancels
+// D^-1 in the row space of the active rows when Sigma / D passes about 1e8).
 __global__ __launch_bounds__(256) void k_strong_rows(const int* Ap, const int* idx, const double* sigA,
-                                                     const int* kdev, int rows, int* ext, double* sq,
-                                                     const int* stop) {
+                                                     const double* mii, double tau, const int* kdev, int rows,
+                                                     int* ext, double* sq, const int* stop) {
     if (stop && *stop) return;
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= rows) return;
@@ -92,7 +101,8 @@ __global__ __launch_bounds__(256) void k_strong_rows(const int* Ap, const int* i
         const int i = idx[r];
         e0 = Ap[i];
         e1 = Ap[i + 1];
-        q = sqrt(sigA[i]);
+        const double sig = sigA[i];
+        q = sqrt((tau > 0.0 && mii[i] > tau) ? sig * (tau / mii[i]) : sig);
     }
     ext[2 * r] = e0;
     ext[2 * r + 1] = e1;

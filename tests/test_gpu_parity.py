@@ -13,6 +13,7 @@ Bars (derived in DESIGN.md):
 """
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle
 import qpsynth
@@ -774,3 +775,45 @@ def test_newton_step_on_sqp_iterate_matches_cholesky():
     x_chol = oracle.newton_solve_dense(K, rhs)
     r_chol = np.linalg.norm(K @ x_chol - rhs) / np.linalg.norm(rhs)
     assert r_gpu <= 1e-9, (r_gpu, r_chol)
+
+
+def _round_sig(v, bits):
+    """v rounded to `bits` significant bits, nearest with ties to even (from
+    the definition: scale to an integer range exactly, Python's round, scale
+    back)."""
+    import math
+    if v == 0.0:
+        return 0.0
+    _, e = math.frexp(v)                      # v = m 2^e, 0.5 <= |m| < 1
+    scaled = math.ldexp(v, bits - e)          # exact: a power-of-two scaling
+    return math.ldexp(float(round(scaled)), e - bits)
+
+
+@pytest.mark.parametrize("prec,bits", [("bf16", 8), ("fp32", 24)])
+def test_low_precision_copies_round_to_nearest_even(prec, bits):
+    """The FP32/BF16 copies of J are rounded on the device.  One 64-row line
+    whose row 0 holds the test values, only row 0 weighted, gamma = 0 and
+    v = e_0 (column 0 holds 1): the product is y_j = J~_0j J~_00 = J~_0j, the
+    rounded values themselves (their products with 1 and the FP32 sum of one
+    term are exact).  Ties, values a hair off a tie (where rounding twice to
+    nearest, through binary32, would go wrong), and ordinary values."""
+    u = 2.0 ** -bits
+    base = [1.0, 1.0 + u, 1.0 + u + 2.0 ** -40, 1.0 + u - 2.0 ** -40, 1.0 + 3 * u, 1.5 + 3 * u,
+            3.0 * (1.0 + u), 0.7, 0.1, 123.456, 1e-3, 2.0 ** -100 * (1 + u), 1e30, 7.0]
+    vals = [1.0] + [b for b in base[1:]] + [-b for b in base[1:]]
+    K = len(vals)
+    rows = np.repeat(np.arange(64), K)
+    cols = np.tile(np.arange(K), 64)
+    data = np.ones(64 * K)
+    data[:K] = vals
+    J = sp.csr_matrix((data, (rows, cols)), shape=(64, K))
+    W = np.zeros(64)
+    W[0] = 1.0
+    h = qpgpu.qp_create(0.0, np.zeros(K), J, W, settings=qpgpu.qp_default_settings(precision=prec))
+    assert h is not None
+    v = np.zeros(K)
+    v[0] = 1.0
+    y, info = qpgpu.qp_operator_apply(h, np.zeros(K), None, v, precision=prec)
+    assert info["spmv_format"] == 1   # the line format's copy
+    ref = np.array([_round_sig(x, bits) for x in vals])
+    assert np.array_equal(y, ref), [(x, a, b) for x, a, b in zip(vals, y, ref) if a != b]

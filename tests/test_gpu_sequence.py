@@ -108,17 +108,22 @@ def test_update_hessian_shrinks_and_rejects():
         qpgpu.qp_solve_from(h, x0, raise_on_error=True)
 
 
-def test_stalled_constraint_block_solve_falls_back_to_jacobi():
+def test_stalled_constraint_block_solve_falls_back_to_the_capped_block():
     """Second sub-problem of the ragged-lines sequence: late in the IPM the
-    constraint-block preconditioner stops converging (its Woodbury
-    correction cancels D^-1 to rounding); the capped solve is repeated with
-    the Jacobi diagonal.  Without the fallback this QP took 38 IPM and
-    244,174 PCG iterations."""
+    exact constraint-block preconditioner loses definiteness to rounding
+    (its Woodbury correction cancels D^-1 in the row space of the active
+    rows once Sigma/D passes about 1e8: r^T z <= 0, a breakdown); the solve
+    is repeated with the capped block, which stays definite there (shown on
+    the CPU at the oracle's iterates: 35-38 PCG iterations per direction
+    where Jacobi takes about 100), so the Jacobi tier is never reached.
+    Without any fallback this QP took 38 IPM and 244,174 PCG iterations."""
     q = qpsynth.sqp_sequence(qpsynth.ragged_lines(), 2)[1]
     h = qpgpu.qp_create_from_problem(q)
     res = qpgpu.qp_solve(h)
-    print(f"ipm {res.info['ipm_iters']} pcg {res.info['pcg_iters']}", flush=True)
+    print(f"ipm {res.info['ipm_iters']} pcg {res.info['pcg_iters']} fallbacks {res.info['prec_fallbacks']} "
+          f"tier {res.info['prec_tier']}", flush=True)
     assert res.status == qpgpu.QP_OK
+    assert res.info["prec_fallbacks"] >= 1 and res.info["prec_tier"] == 1
     assert res.info["pcg_iters"] < 20000
     ref = oracle.solve(q)
     # 55 dose-free variables (curvature gamma only) sit in a flat region where
