@@ -229,20 +229,22 @@ def batch_bench(args):
         print(f"[bench] step {i}: status={s} pcg={sum(f['pcg_iters'] for f in infos)}", file=sys.stderr, flush=True)
     el = time.perf_counter() - t0
     ok = all(f["status"] == qpgpu.QP_OK for f in all_infos)
-    # the same handles solved one after another (one stream busy at a time)
-    t1 = time.perf_counter()
-    for h in hs:
-        qpgpu.qp_solve(h)
-    seq = time.perf_counter() - t1
-    print(f"[bench] sequential: {1e3 * seq:.1f} ms", file=sys.stderr, flush=True)
-    # the same batch on host workers, each QP's own solve on its own stream
-    os.environ["QPGPU_BATCH_THREADS"] = "1"
-    qpgpu.qp_solve_batch(hs)
-    t2 = time.perf_counter()
-    qpgpu.qp_solve_batch(hs)
-    thr = time.perf_counter() - t2
-    del os.environ["QPGPU_BATCH_THREADS"]
-    print(f"[bench] host workers: {1e3 * thr:.1f} ms", file=sys.stderr, flush=True)
+    seq = thr = None
+    if args.compare:
+        # the same handles solved one after another (one stream busy at a time)
+        t1 = time.perf_counter()
+        for h in hs:
+            qpgpu.qp_solve(h)
+        seq = time.perf_counter() - t1
+        print(f"[bench] sequential: {1e3 * seq:.1f} ms", file=sys.stderr, flush=True)
+        # the same batch on host workers, each QP's own solve on its own stream
+        os.environ["QPGPU_BATCH_THREADS"] = "1"
+        qpgpu.qp_solve_batch(hs)
+        t2 = time.perf_counter()
+        qpgpu.qp_solve_batch(hs)
+        thr = time.perf_counter() - t2
+        del os.environ["QPGPU_BATCH_THREADS"]
+        print(f"[bench] host workers: {1e3 * thr:.1f} ms", file=sys.stderr, flush=True)
     print(json.dumps({"metric": METRIC, "value": args.count * args.steps / el, "unit": "QP/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -252,10 +254,10 @@ def batch_bench(args):
                                              f"batched launches",
                                  "precision": args.precision},
                       "status_ok": ok,
-                      "sequential_ms": 1e3 * seq,
-                      "host_workers_ms": 1e3 * thr,
-                      "batch_speedup_vs_sequential": seq / (el / args.steps),
-                      "batch_speedup_vs_host_workers": thr / (el / args.steps),
+                      "sequential_ms": 1e3 * seq if seq else None,
+                      "host_workers_ms": 1e3 * thr if thr else None,
+                      "batch_speedup_vs_sequential": seq / (el / args.steps) if seq else None,
+                      "batch_speedup_vs_host_workers": thr / (el / args.steps) if thr else None,
                       "ipm_iters_total": sum(f["ipm_iters"] for f in all_infos),
                       "pcg_iters_total": sum(f["pcg_iters"] for f in all_infos)}), flush=True)
 
@@ -391,6 +393,8 @@ def main():
                          "n=60,000, BF16-valued J with 200M nnz and a rank-20 term; batch: the 64 "
                          "uneven QPs (n in [2000, 20000]) solved together by qp_solve_batch")
     ap.add_argument("--count", type=int, default=64, help="batch size for --workload batch")
+    ap.add_argument("--compare", type=int, default=1, choices=[0, 1],
+                    help="--workload batch: also time the QPs one at a time and on host workers")
     ap.add_argument("--seq-len", type=int, default=6, help="sub-problems timed for --workload sqp")
     ap.add_argument("--warm", type=int, default=0, choices=[0, 1],
                     help="--workload sqp: start each solve at the previous minimiser")

@@ -112,14 +112,19 @@ typedef struct {
                                  Sigma_i sum_j A_ij^2 / D_j >= 1 through the dense inverse of their
                                  Schur complement, the other rows folded into the diagonal;
                                  falls back to 0 when m = 0 or m > 8192.  A solve with it that
-                                 reaches 2000 PCG iterations or breaks down (r^T z <= 0: late in
+                                 reaches its attempt cap (the larger of 2000 and 4 times the
+                                 longest converged constraint-block solve of the call so far) or
+                                 breaks down (r^T z <= 0: late in
                                  the IPM the block's rounding can cost it definiteness) is
                                  repeated with the block's Sigma capped so that no diagonal entry
                                  of its Schur complement exceeds 1 + 1e4, and a solve that stalls
                                  with that too, with 0; qp_solve keeps the tier reached for the
                                  rest of the QP */
     int32_t spmv_format;      /* 0 (default): line format for J when its rows come in lines of 64
-                                 sharing one column list (the 64-voxel bands), else CSR; 1: CSR */
+                                 that share most of their columns (the 64-voxel bands): each line
+                                 stores the union of its rows' column lists, zeros where a row
+                                 lacks one, taken when that stores at most 2 nnz(J) values; else
+                                 CSR.  1: CSR */
     double  refine_tol;       /* relative residual target of each low-precision PCG solve when
                                  refine_steps > 0, in [pcg_tol, 1); default 1e-3 */
     int32_t graphs;           /* 1 (default): PCG iterations are launched as HIP graphs of four

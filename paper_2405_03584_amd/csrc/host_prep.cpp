@@ -2,6 +2,7 @@
 #include "host_prep.h"
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <limits>
 
@@ -68,44 +69,57 @@ HostCsr transpose(const HostCsr& M) {
     return T;
 }
 
-bool build_line_format(const HostCsr& M, int32_t R, LineFormat& lf) {
-    if (R <= 0 || M.rows == 0 || M.rows % R != 0) return false;
-    const int32_t L = M.rows / R;
+bool build_line_format(const HostCsr& M, int32_t R, LineFormat& lf, double max_fill) {
+    if (R <= 0 || M.rows == 0) return false;
+    const int32_t L = (M.rows + R - 1) / R;   // the last line may have fewer rows (padded with empty ones)
+    const double budget = max_fill * double(M.nnz());
+    // each line's column list: the union of its rows' sorted lists, padded to
+    // a multiple of kLineSlotAlign slots (repeats of its last column, zero
+    // values: the packed low-precision loads read whole slot groups)
+    std::vector<int32_t> lptr(size_t(L) + 1, 0), lcol, lreal(size_t(L), 0);
+    std::vector<int32_t> scratch;
+    int64_t real = 0;
     for (int32_t l = 0; l < L; ++l) {
-        const int32_t r0 = l * R;
-        const int32_t len = M.ptr[r0 + 1] - M.ptr[r0];
-        const int32_t* c0 = M.col.data() + M.ptr[r0];
-        for (int32_t r = 1; r < R; ++r) {
-            if (M.ptr[r0 + r + 1] - M.ptr[r0 + r] != len) return false;
-            if (len && std::memcmp(c0, M.col.data() + M.ptr[r0 + r], sizeof(int32_t) * size_t(len)) != 0)
-                return false;
-        }
+        const int32_t r0 = l * R, r1 = std::min(M.rows, r0 + R);
+        scratch.assign(M.col.begin() + M.ptr[r0], M.col.begin() + M.ptr[r1]);
+        std::sort(scratch.begin(), scratch.end());
+        scratch.erase(std::unique(scratch.begin(), scratch.end()), scratch.end());
+        lreal[l] = int32_t(scratch.size());
+        real += int64_t(scratch.size());
+        while (scratch.size() % kLineSlotAlign) scratch.push_back(scratch.back());
+        lcol.insert(lcol.end(), scratch.begin(), scratch.end());
+        lptr[l + 1] = int32_t(lcol.size());
+        if (double(real) * R > budget) return false;   // too many stored zeros
     }
     LineFormat f;
     f.R = R;
     f.lines = L;
     f.cols = M.cols;
-    f.ptr.assign(size_t(L) + 1, 0);
-    for (int32_t l = 0; l < L; ++l) f.ptr[l + 1] = f.ptr[l] + (M.ptr[l * R + 1] - M.ptr[l * R]);
-    f.col.resize(size_t(f.ptr[L]));
-    f.val.resize(M.val.size());
+    f.ptr = std::move(lptr);
+    f.col = std::move(lcol);
+    f.val.assign(f.col.size() * size_t(R), 0.0);
     for (int32_t l = 0; l < L; ++l) {
-        const int32_t len = f.ptr[l + 1] - f.ptr[l];
-        std::memcpy(f.col.data() + f.ptr[l], M.col.data() + M.ptr[l * R], sizeof(int32_t) * size_t(len));
-        for (int32_t r = 0; r < R; ++r) {
-            const double* src = M.val.data() + M.ptr[l * R + r];
-            for (int32_t k = 0; k < len; ++k) f.val[(size_t(f.ptr[l]) + k) * R + r] = src[k];
+        const int32_t* lc = f.col.data() + f.ptr[l];
+        const int32_t len = lreal[l];
+        for (int32_t r = 0; r < R && l * R + r < M.rows; ++r) {
+            const int32_t row = l * R + r;
+            int32_t k = 0;   // both lists sorted: one merge walk
+            for (int32_t e = M.ptr[row]; e < M.ptr[row + 1]; ++e) {
+                while (k < len && lc[k] < M.col[e]) ++k;
+                f.val[(size_t(f.ptr[l]) + k) * R + r] = M.val[e];
+            }
         }
     }
     // transpose of the (line x spot) incidence, counting sort over spots
     f.sptr.assign(size_t(M.cols) + 1, 0);
-    for (int32_t s : f.col) f.sptr[size_t(s) + 1]++;
+    for (int32_t l = 0; l < L; ++l)
+        for (int32_t k = f.ptr[l]; k < f.ptr[l] + lreal[l]; ++k) f.sptr[size_t(f.col[k]) + 1]++;
     for (int32_t j = 0; j < M.cols; ++j) f.sptr[j + 1] += f.sptr[j];
-    f.sline.resize(f.col.size());
-    f.sslot.resize(f.col.size());
+    f.sline.resize(size_t(real));
+    f.sslot.resize(size_t(real));
     std::vector<int32_t> next(f.sptr.begin(), f.sptr.end() - 1);
     for (int32_t l = 0; l < L; ++l)
-        for (int32_t k = f.ptr[l]; k < f.ptr[l + 1]; ++k) {
+        for (int32_t k = f.ptr[l]; k < f.ptr[l] + lreal[l]; ++k) {
             const int32_t j = f.col[k];
             const int32_t d = next[j]++;
             f.sline[d] = l;

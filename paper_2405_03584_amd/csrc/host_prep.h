@@ -36,19 +36,30 @@ HostCsr transpose(const HostCsr& M);
 //   row R*l + r, slot k of line l  ->  val[(ptr[l] + k) * R + r], column col[ptr[l] + k].
 // The transpose is a per-spot list of (line, slot) pairs in increasing line
 // order, so J^T reads the same value array.
+// Slots of a line come in groups of this many (the line's list padded with
+// repeats of its last column and zero values), so that a lane can load a
+// group of its row's low-precision values at once (4 BF16 or 2 FP32 values
+// in 8 bytes).
+constexpr int32_t kLineSlotAlign = 4;
+
 struct LineFormat {
     int32_t R = 64, lines = 0, cols = 0;
     std::vector<int32_t> ptr;      // lines + 1
-    std::vector<int32_t> col;      // sum of line lengths
+    std::vector<int32_t> col;      // sum of line lengths (padded to kLineSlotAlign)
     std::vector<double> val;       // nnz, slot-major
     std::vector<int32_t> sptr;     // cols + 1
     std::vector<int32_t> sline;    // per spot: lines covered
     std::vector<int32_t> sslot;    // per spot: slot index ptr[l] + k
 };
 
-// True (and fills lf) when every group of R consecutive rows of M shares one
-// column list; false leaves lf untouched.
-bool build_line_format(const HostCsr& M, int32_t R, LineFormat& lf);
+// Line format of M: lines of R consecutive rows (the last one padded with
+// empty rows), each storing the union of its rows' column lists (padded to a
+// multiple of kLineSlotAlign slots), slot-major, with zeros where a row lacks
+// a column.  The per-spot lists name only real slots.  True (and fills lf)
+// when the union slots times R number at most max_fill * nnz(M) (1 when every
+// line's rows share one list, as in the 64-voxel bands); false leaves lf
+// untouched.
+bool build_line_format(const HostCsr& M, int32_t R, LineFormat& lf, double max_fill = 2.0);
 
 // Round-to-nearest-even conversions (IEEE 754 binary32 / bfloat16 formats).
 uint32_t f64_to_f32_bits(double v);

@@ -50,6 +50,55 @@ __device__ __forceinline__ bf16_t load_val(const bf16_t* p) {
     else return *p;
 }
 
+// Slot groups of the low-precision copies: the P values of one row in P
+// consecutive slots of a line sit together (8 bytes), so a lane loads its
+// row's group in one load and a wavefront moves 512 bytes per load, as with
+// FP64 values.  Group g of a line (slots gP .. gP+P-1) occupies 64 lanes x 8
+// bytes at the line's values + g*64*P; lines hold whole groups (their slot
+// counts are multiples of kLineGroup).  FP64 values keep one slot per load.
+constexpr int kLineGroup = 4;
+template <typename VT> struct SlotPack { static constexpr int P = 8 / int(sizeof(VT)); };
+template <> struct SlotPack<double> { static constexpr int P = 1; };
+
+// The P values of slot group gi of a line (values at base) for row `lane`.
+template <typename VT, typename AT, bool NT>
+__device__ __forceinline__ void load_group(const VT* base, int gi, int lane, AT* out) {
+    constexpr int P = SlotPack<VT>::P;
+    if constexpr (P == 1) {
+        out[0] = cvt<AT>(load_val<NT>(base + size_t(gi) * 64 + lane));
+    } else {
+        const uint64_t* pb = reinterpret_cast<const uint64_t*>(base) + size_t(gi) * 64 + lane;
+        const uint64_t wv = NT ? __builtin_nontemporal_load(pb) : *pb;
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+            if constexpr (P == 4)
+                out[s] = cvt<AT>(bf16_t{uint16_t(wv >> (16 * s))});
+            else
+                out[s] = AT(__uint_as_float(uint32_t(wv >> (32 * s))));
+        }
+    }
+}
+
+// The packed low-precision copy of a line format's values (FP64, slot-major,
+// nslots * 64): thread (g, r) writes the 8-byte group of row r in slot group g,
+// each value rounded as d2f_bits / d2bf16_bits round.
+template <typename VT>
+__global__ __launch_bounds__(kBlock) void k_pack_line(const double* src, size_t groups, uint64_t* dst) {
+    constexpr int P = SlotPack<VT>::P;
+    static_assert(P == 2 || P == 4, "packed copies hold 2- or 4-byte values");
+    for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < groups * 64; i += size_t(gridDim.x) * kBlock) {
+        const size_t g = i >> 6, r = i & 63;
+        uint64_t wv = 0;
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+            const double x = src[(g * P + s) * 64 + r];
+            const uint64_t bits = P == 4 ? uint64_t(d2bf16_bits(x)) : uint64_t(d2f_bits(x));
+            wv |= bits << ((64 / P) * s);
+        }
+        dst[i] = wv;
+    }
+}
+
 template <typename VT>
 struct LineArgs {
     const int* lptr; const int* lcol; const VT* lval; int L; const double* W;
@@ -108,25 +157,33 @@ __device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, in
         return;
     }
     if (b < a.nbL) {
+        constexpr int P = SlotPack<VT>::P;
+        static_assert(kLineGroup % P == 0 && RH % P == 0 && 8 % P == 0, "whole slot groups");
         const int l = b;
-        const int len = end - off;
-        const int q = (len + NW - 1) / NW;
+        const int len = end - off;   // a multiple of kLineGroup
+        // each wavefront's range holds whole slot groups
+        const int q = (((len + NW - 1) / NW) + P - 1) / P * P;
         const int k0 = __builtin_amdgcn_readfirstlane(min(len, w * q));
         const int k1 = __builtin_amdgcn_readfirstlane(min(len, k0 + q));
         // held slots [kh, k1): the last RH of the wavefront's range; the
         // slots before them (only in lines longer than NW*RH slots) are
         // streamed first, so their registers are free before the held loads
         const int kh = max(k0, k1 - RH);
-        const VT* v = a.lval + size_t(off) * 64 + lane;
+        const VT* v = a.lval + size_t(off) * 64;
         const int* col = a.lcol + off;
         AT acc = AT(0);
         for (int k = k0; k < kh; k += 4) {
             AT s4 = AT(0);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int kk = min(k + i, kh - 1);
-                const AT prod = cvt<AT>(load_val<NT>(&v[size_t(kk) * 64])) * AT(g(col[kk]));
-                s4 += (k + i < kh) ? prod : AT(0);
+            for (int j = 0; j < 4 / P; ++j) {
+                AT gv[P];
+                load_group<VT, AT, NT>(v, min((k + j * P) / P, kh / P - 1), lane, gv);
+#pragma unroll
+                for (int t = 0; t < P; ++t) {
+                    const int kk = min(k + j * P + t, kh - 1);
+                    const AT prod = gv[t] * AT(g(col[kk]));
+                    s4 += (k + j * P + t < kh) ? prod : AT(0);
+                }
             }
             acc += s4;
         }
@@ -141,9 +198,11 @@ __device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, in
             const double pl = g(col[min(kh + (lane & (RH - 1)), k1 - 1)]);
             const int plo = __double2loint(pl), phi = __double2hiint(pl);
 #pragma unroll
-            for (int i = 0; i < RH; ++i) {
-                const AT val = cvt<AT>(load_val<NT>(&v[size_t(min(kh + i, k1 - 1)) * 64]));
-                hv[i] = (kh + i < k1) ? val : AT(0);
+            for (int j = 0; j < RH / P; ++j) {
+                AT gv[P];
+                load_group<VT, AT, NT>(v, min(kh / P + j, k1 / P - 1), lane, gv);
+#pragma unroll
+                for (int t = 0; t < P; ++t) hv[j * P + t] = (kh + j * P < k1) ? gv[t] : AT(0);
             }
             AT a2[2] = {AT(0), AT(0)};   // two chains, no product array
 #pragma unroll
@@ -174,9 +233,11 @@ __device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, in
         for (int kg = k0; kg < kh; kg += 8) {   // streamed slots of long lines, 8 at a time
             AT pv[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const AT val = cvt<AT>(load_val<NT>(&v[size_t(min(kg + i, kh - 1)) * 64]));
-                pv[i] = (kg + i < kh) ? val * t : AT(0);
+            for (int j = 0; j < 8 / P; ++j) {
+                AT gv[P];
+                load_group<VT, AT, NT>(v, min(kg / P + j, kh / P - 1), lane, gv);
+#pragma unroll
+                for (int u = 0; u < P; ++u) pv[j * P + u] = (kg + j * P < kh) ? gv[u] * t : AT(0);
             }
             const AT cs = wave_reduce_scatter<8>(pv, lane);
             if ((lane & 7) == 0 && kg + (lane >> 3) < kh) a.c[off + kg + (lane >> 3)] = double(cs);

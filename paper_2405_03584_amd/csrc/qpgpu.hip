@@ -26,6 +26,8 @@
 
 using namespace qpg;
 
+static_assert(kLineSlotAlign == kLineGroup, "line slot counts hold whole packed groups");
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -63,9 +65,12 @@ struct qp_handle {
 
     int32_t n = 0, m = 0, nJ = 0, k = 0;
     int64_t nnzJ = 0, nnzA = 0;
+    int64_t nvals = 0;          // J values the PCG operator stores: line slots * 64 (zeros included), or nnzJ
     double gamma = 0.0, cscale = 1.0, mtot = 0.0;
     int k_cap = 0;              // columns U, w, lr_part, lr_v have room for
-    int wb_attempt_cap = 0;     // > 0: iteration cap of constraint-block-preconditioned solves
+    int wb_attempt_cap = 0;     // > 0: the attempt cap of constraint-block-preconditioned solves is on
+    int wb_seen = 0;            // longest converged constraint-block solve of the current run
+    int wb_cap_used = 0;        // iteration cap the last constraint-block solve set up with
     double* x0d = nullptr;      // caller's start point (qp_solve_from), allocated on first use
     int GJ = 16, GJt = 64;   // lanes per row of J and of J^T (and A^T)
 
@@ -194,27 +199,43 @@ struct qp_handle {
 namespace {
 
 constexpr int kLrBlocks = 256;   // blocks of the U^T p partial pass
-// iteration cap of a constraint-block-preconditioned solve inside qp_solve
-// (its solves take tens of iterations when the preconditioner is sound)
+// Attempt cap of a constraint-block-preconditioned solve: the larger of
+// kPrecAttemptIters and kPrecAttemptGrowth times the longest converged
+// constraint-block solve of the run so far.  Its solves take tens of
+// iterations when the preconditioner is sound and the H part well
+// conditioned; with an ill-conditioned H part their counts grow steadily
+// over the IPM (hundreds, then thousands), which is no reason to leave the
+// block, while a block that has lost definiteness (below) usually shows it
+// at once through r^T z <= 0 (a breakdown) and otherwise stops converging.
 constexpr int kPrecAttemptIters = 2000;
+constexpr int kPrecAttemptGrowth = 4;
 
 // The constraint-block preconditioner subtracts from D^-1 a Woodbury
 // correction that nearly cancels it in the row space of the active rows of
 // A; late in the IPM (Sigma_A -> infinity, cond(S) beyond about 1e8) its
 // rounding can make the computed preconditioner indefinite, and PCG then
-// cannot converge.  While an entry point
-// holds this guard its constraint-block solves stop at kPrecAttemptIters;
-// the caller repeats a solve that hits the cap (or breaks down) with the
-// Jacobi diagonal.
+// cannot converge.  While an entry point holds this guard its
+// constraint-block solves stop at the attempt cap; the caller repeats a
+// solve that hits the cap (or breaks down) with the next preconditioner tier.
 struct PrecAttemptCap {
     qp_handle* h;
-    explicit PrecAttemptCap(qp_handle* hh) : h(hh) { h->wb_attempt_cap = kPrecAttemptIters; }
+    explicit PrecAttemptCap(qp_handle* hh) : h(hh) {
+        h->wb_attempt_cap = kPrecAttemptIters;
+        h->wb_seen = 0;
+    }
     ~PrecAttemptCap() { h->wb_attempt_cap = 0; }
 };
-// A constraint-block solve ended in a way that calls for the Jacobi repeat
-// (a cap of pcg_max_iter itself, when not above the attempt cap, is final).
+int wb_attempt_cap(const qp_handle* h) {
+    return std::max(h->wb_attempt_cap, kPrecAttemptGrowth * h->wb_seen);
+}
+// A constraint-block solve ended in a way that calls for the next tier (a
+// cap of pcg_max_iter itself, when not above the attempt cap, is final).
 bool prec_stalled(const qp_handle* h, const Flags& f) {
-    return f.pcg_breakdown || (f.pcg_capped && h->set.pcg_max_iter > kPrecAttemptIters);
+    return f.pcg_breakdown || (f.pcg_capped && h->wb_cap_used < h->set.pcg_max_iter);
+}
+// Record a finished constraint-block solve for the attempt cap.
+void note_wb_solve(qp_handle* h, const Flags& f) {
+    if (f.pcg_converged && !f.ipm_done) h->wb_seen = std::max(h->wb_seen, int(f.pcg_iters));
 }
 // Preconditioner tiers of a QP: the constraint block; the capped block
 // (Sigma of the dense block limited so that S_ii <= 1 + kPrecCapTau), used
@@ -317,7 +338,7 @@ const bf16_t* line_vals<bf16_t>(qp_handle* h) { return h->lval16; }
 constexpr size_t kStreamedValueBytes = size_t(192) << 20;
 template <typename VT>
 bool line_vals_streamed(const qp_handle* h) {
-    return size_t(h->nnzJ) * sizeof(VT) > kStreamedValueBytes;
+    return size_t(h->nvals) * sizeof(VT) > kStreamedValueBytes;
 }
 
 // PCG link of a product: in a PCG product (pcg = true) the gathered vector is
@@ -482,15 +503,24 @@ void ensure_lowp(qp_handle* h, int prec) {
                                static_cast<uint16_t*>(dst));
         HIPCHK(hipGetLastError());
     };
-    const size_t nz = size_t(h->nnzJ);
+    const size_t nz = size_t(h->nvals);
     if (h->line) {
+        // packed slot groups (line_kernels.hpp: k_pack_line)
+        auto pack = [&](auto* dst, auto tag) {
+            using VT = decltype(tag);
+            const size_t groups = size_t(h->nslots) / SlotPack<VT>::P;
+            const int g = int(std::max<size_t>(1, std::min<size_t>((groups * 64 + kBlock - 1) / kBlock, 8192)));
+            hipLaunchKernelGGL(k_pack_line<VT>, dim3(g), dim3(kBlock), 0, h->stream, (const double*)h->lval, groups,
+                               reinterpret_cast<uint64_t*>(dst));
+            HIPCHK(hipGetLastError());
+        };
         if (prec == QP_FP32 && !h->lval32) {
             h->lval32 = h->dalloc<float>(nz);
-            round(h->lval, nz, h->lval32);
+            pack(h->lval32, float{});
         }
         if (prec == QP_BF16 && !h->lval16) {
             h->lval16 = h->dalloc<bf16_t>(nz);
-            round(h->lval, nz, h->lval16);
+            pack(h->lval16, bf16_t{});
         }
     } else {
         if (prec == QP_FP32 && !h->Jv32) {
@@ -724,8 +754,9 @@ PcgSetup pcg_setup(qp_handle* h, const double* rhs_a, const double* rhs_b, const
         S.nb_at = grid_rows_capped(h->n, kPrecAtLanes);
     }
     S.n_rz = S.wb ? S.nb_at : S.ge;
-    const int cap = (S.wb && h->wb_attempt_cap > 0) ? std::min(h->set.pcg_max_iter, h->wb_attempt_cap)
+    const int cap = (S.wb && h->wb_attempt_cap > 0) ? std::min(h->set.pcg_max_iter, wb_attempt_cap(h))
                                                     : h->set.pcg_max_iter;
+    if (S.wb) h->wb_cap_used = cap;
     ScalArgs& sa = S.sa;
     sa.part_rz = h->part_rz; sa.n_rz = S.n_rz; sa.part_rr = h->part_rr; sa.n_rr = S.ge;
     sa.mode = refine ? 2 : 1; sa.rel_tol = rel_tol; sa.tol = h->set.pcg_tol; sa.max_iter = cap;
@@ -897,6 +928,7 @@ Flags run_pcg(qp_handle* h, int prec, const double* rhs_a, const double* rhs_b, 
         hist[1] = hist[0];
         hist[0] = f.pcg_iters;
     }
+    if (wb) note_wb_solve(h, f);
     if (timing) {
         // launches past the last executed iteration returned at once: drop them
         for (int sl = slot_begin + std::max(f.pcg_iters, 0); sl < tacc->pairs; ++sl) tacc->valid[sl] = 0;
@@ -1170,7 +1202,7 @@ void ipm_residuals(qp_handle* h, int apply) {
     lowrank_prepare(h, v.x, nullptr, nullptr);
     // lanes per variable: with the line format a variable sums one
     // double per slot of its spot, not one term per nonzero of J
-    const int Gb = h->line ? pick_lanes(h->nnzJ / 64 + h->nnzA, n) : Gt;
+    const int Gb = h->line ? pick_lanes(h->nslots + h->nnzA, n) : Gt;
     const int gb = grid_rows_capped(n, Gb);
     switch (Gb) {
         case 4: hipLaunchKernelGGL(k_ipm_bwd<4>, dim3(gb), dim3(kBlock), 0, h->stream, ba, v, isc, h->part, fl); break;
@@ -1816,8 +1848,11 @@ std::vector<Flags> batch_pcg(BatchRun& B, const std::vector<char>& mask, int sv,
         cur ^= 1;
     }
     int longest = 0;
-    for (int q = 0; q < B.nq; ++q)
-        if (mask[q] && !out[q].ipm_done) longest = std::max(longest, out[q].pcg_iters);
+    for (int q = 0; q < B.nq; ++q) {
+        if (!mask[q]) continue;
+        if (!out[q].ipm_done) longest = std::max(longest, out[q].pcg_iters);
+        if (B.runs[q].wbp) note_wb_solve(B.hs[q], out[q]);
+    }
     hist[1] = hist[0];
     hist[0] = longest;
     return out;
@@ -2046,8 +2081,8 @@ std::vector<qp_status> batch_solve(qp_handle* const* hs, int count, double* cons
     for (int q = 0; q < count; ++q) {
         B.runs[q].h = hs[q];
         ensure_lowp(hs[q], B.prec);
-        bytes_lo += size_t(hs[q]->nnzJ) * (B.prec == QP_FP32 ? 4 : B.prec == QP_BF16 ? 2 : 8);
-        bytes_64 += size_t(hs[q]->nnzJ) * 8;
+        bytes_lo += size_t(hs[q]->nvals) * (B.prec == QP_FP32 ? 4 : B.prec == QP_BF16 ? 2 : 8);
+        bytes_64 += size_t(hs[q]->nvals) * 8;
     }
     B.nt_lo = bytes_lo > kStreamedValueBytes;
     B.nt_64 = bytes_64 > kStreamedValueBytes;
@@ -2298,7 +2333,15 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
             h->lc = h->dalloc<double>(lf.col.size());
             h->nslots = int64_t(lf.col.size());
         }
-        h->W = nJ > 0 ? h->upload(W, size_t(nJ)) : h->dalloc<double>(1);
+        h->nvals = use_line ? h->nslots * 64 : h->nnzJ;
+        if (use_line && size_t(h->L) * 64 > size_t(nJ)) {
+            // the last line's padding rows weigh nothing
+            h->W = h->dalloc<double>(size_t(h->L) * 64);
+            HIPCHK(hipMemsetAsync(h->W, 0, sizeof(double) * size_t(h->L) * 64, h->stream));
+            if (nJ > 0) HIPCHK(hipMemcpyAsync(h->W, W, sizeof(double) * size_t(nJ), hipMemcpyHostToDevice, h->stream));
+        } else {
+            h->W = nJ > 0 ? h->upload(W, size_t(nJ)) : h->dalloc<double>(1);
+        }
         if (m > 0) {
             h->Ap = h->upload(hA.ptr.data(), hA.ptr.size());
             h->Ac = h->upload(hA.col.data(), hA.col.size());

@@ -297,6 +297,37 @@ def config2(seed: int = 2000, scale: float = 1.0) -> QPProblem:
                      name=f"config2(scale={scale})", meta={"seed": seed, "scale": scale})
 
 
+def irregular_bands(seed: int = 2100, scale: float = 0.05, drop: float = 0.15, trim: int = 23) -> QPProblem:
+    """A banded-dose QP whose bands are irregular, as measured dose matrices
+    are: the config2 pattern at `scale`, each nonzero of J dropped with
+    probability `drop` (so the 64 rows of a line no longer share one column
+    list), and the last `trim` rows removed (the row count is then not a
+    multiple of 64).  The rest as config2.
+
+    Draw order: J (pattern, values), the drop mask, W, A (pattern, values),
+    x0, s0, x_t.
+    """
+    rng = np.random.default_rng(seed)
+    n = int(round(20000 * scale))
+    Z = max(2, int(round(50 * scale)))
+    m = max(1, int(round(2000 * scale)))
+    J = band_dose_matrix(rng, n, Z, 125, int(round(n * 31.25)) * 64).tocoo()
+    keep = rng.uniform(size=J.nnz) >= drop
+    J = sp.csr_matrix((J.data[keep], (J.row[keep], J.col[keep])), shape=J.shape)[:J.shape[0] - trim]
+    J.sort_indices()
+    W = rng.uniform(0.5, 2.0, size=J.shape[0])
+    A = random_sparse(rng, m, n, max(1, n // 50))
+    hi = 50.0
+    x0 = rng.uniform(0.0, 1.0, size=n)
+    s0 = rng.uniform(0.1, 1.0, size=m)
+    x_t = rng.uniform(-0.2 * hi, 1.2 * hi, size=n)
+    return QPProblem(gamma=GAMMA, p=_linear_term(J, W, x_t), J=J, W=W,
+                     x_lo=np.zeros(n), x_hi=np.full(n, hi),
+                     A=A, A_lo=np.full(m, -np.inf), A_hi=_feasible_rhs(A, x0, s0),
+                     name=f"irregular_bands(scale={scale}, drop={drop})",
+                     meta={"seed": seed, "scale": scale, "drop": drop, "trim": trim})
+
+
 def config5(seed: int = 5000, scale: float = 1.0) -> QPProblem:
     """n=60,000; J 2,000,000x60,000 with 200M nnz (grid 125x250x64, ~52.1 lines
     per spot), values lognormal(0,1) *rounded to bfloat16* (the problem is

@@ -29,19 +29,21 @@ void hp_bf16(const double* in, unsigned short* out, long n) {
     for (long i = 0; i < n; ++i) out[i] = f64_to_bf16_bits(in[i]);
 }
 
-// returns 1 and fills the outputs (sized by the caller from the CSR) when the
-// line format applies
-int hp_line_format(int rows, int cols, const int* ptr, const int* col, const double* val, int R, int* lptr,
-                   int* lcol, double* lval, int* sptr, int* sline, int* sslot, int* nslots) {
+// returns 1 and fills the outputs when the line format applies (0 when it
+// does not, -1 when its slots exceed cap_slots); lval holds nslots * R values
+int hp_line_format(int rows, int cols, const int* ptr, const int* col, const double* val, int R, double max_fill,
+                   int cap_slots, int* lptr, int* lcol, double* lval, int* sptr, int* sline, int* sslot,
+                   int* nslots) {
     LineFormat lf;
-    if (!build_line_format(make(rows, cols, ptr, col, val), R, lf)) return 0;
+    if (!build_line_format(make(rows, cols, ptr, col, val), R, lf, max_fill)) return 0;
+    *nslots = int(lf.col.size());
+    if (*nslots > cap_slots) return -1;
     std::memcpy(lptr, lf.ptr.data(), sizeof(int) * lf.ptr.size());
     std::memcpy(lcol, lf.col.data(), sizeof(int) * lf.col.size());
     std::memcpy(lval, lf.val.data(), sizeof(double) * lf.val.size());
     std::memcpy(sptr, lf.sptr.data(), sizeof(int) * lf.sptr.size());
     std::memcpy(sline, lf.sline.data(), sizeof(int) * lf.sline.size());
     std::memcpy(sslot, lf.sslot.data(), sizeof(int) * lf.sslot.size());
-    *nslots = int(lf.col.size());
     return 1;
 }
 }

@@ -817,3 +817,45 @@ def test_low_precision_copies_round_to_nearest_even(prec, bits):
     assert info["spmv_format"] == 1   # the line format's copy
     ref = np.array([_round_sig(x, bits) for x in vals])
     assert np.array_equal(y, ref), [(x, a, b) for x, a, b in zip(vals, y, ref) if a != b]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_irregular_bands_operator_on_padded_line_format(prec):
+    """Bands whose rows miss 15% of their line's columns, row count not a
+    multiple of 64: the line format with stored zeros serves them (no CSR
+    fallback), and the product meets the operator bars against the oracle.
+    The low-precision bound counts every stored slot of a line as a term."""
+    prob = qpsynth.irregular_bands()
+    it = qpsynth.random_iterate(prob, 13)
+    print(f"irregular bands operator {prec}: nJ={prob.J.shape[0]} nnz={prob.J.nnz}", flush=True)
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
+    y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
+    assert info["spmv_format"] == 1
+    ref = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"]) @ it["v"]
+    bound = _abs_op(prob, it["sigma_x"], it["sigma_A"]) @ np.abs(it["v"])
+    if prec == "fp64":
+        c = 1e-12
+    else:
+        u = 2.0 ** -24 if prec == "fp32" else 2.0 ** -8
+        lines = -(-prob.J.shape[0] // 64)
+        slots = max(len(np.unique(prob.J[64 * l:64 * (l + 1)].indices)) for l in range(lines))
+        Lt = np.diff(prob.J.tocsc().indptr).max()
+        c = 2 * u + (slots + Lt + 2) * 2.0 ** -24
+    err = np.abs(y - ref)
+    assert np.all(err <= c * bound + 1e-300), float((err / bound).max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_irregular_bands_solve_matches_oracle_and_csr(prec):
+    prob = qpsynth.irregular_bands()
+    ref = oracle.solve(prob)
+    hl = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
+    a = qpgpu.qp_solve(hl)
+    print(f"irregular bands {prec}: format {a.info['spmv_format']} ipm {a.info['ipm_iters']} "
+          f"pcg {a.info['pcg_iters']}", flush=True)
+    assert a.info["spmv_format"] == 1
+    check_solve_vs_oracle(prob, a, ref, prec)
+    hc = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec, spmv_format=1))
+    b = qpgpu.qp_solve(hc)
+    assert b.info["spmv_format"] == 0
+    check_solve_vs_oracle(prob, b, ref, prec)

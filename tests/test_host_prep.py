@@ -73,41 +73,89 @@ def test_bf16_round_to_nearest_even(hp):
     assert np.array_equal(gen, lib)
 
 
-def _line_format(hp, M, R=64):
+def _line_format(hp, M, R=64, max_fill=2.0):
     ptr = M.indptr.astype(np.int32); col = M.indices.astype(np.int32); val = M.data.copy()
-    L = M.shape[0] // R if M.shape[0] % R == 0 else 0
-    lptr = np.zeros(max(L, 1) + 1, np.int32); lcol = np.zeros(M.nnz, np.int32); lval = np.zeros(M.nnz)
-    sptr = np.zeros(M.shape[1] + 1, np.int32); sline = np.zeros(M.nnz, np.int32)
-    sslot = np.zeros(M.nnz, np.int32); ns = C.c_int(0)
+    L = -(-M.shape[0] // R)
+    cap = int(max_fill * M.nnz / R) + 4 * L + 1   # real slots within the budget, plus group padding
+    lptr = np.zeros(L + 1, np.int32); lcol = np.zeros(cap, np.int32); lval = np.zeros(cap * R)
+    sptr = np.zeros(M.shape[1] + 1, np.int32); sline = np.zeros(cap, np.int32)
+    sslot = np.zeros(cap, np.int32); ns = C.c_int(0)
     ok = hp.hp_line_format(M.shape[0], M.shape[1], _p(ptr, C.c_int), _p(col, C.c_int), _p(val, C.c_double), R,
-                           _p(lptr, C.c_int), _p(lcol, C.c_int), _p(lval, C.c_double), _p(sptr, C.c_int),
-                           _p(sline, C.c_int), _p(sslot, C.c_int), C.byref(ns))
-    return ok, L, lptr, lcol[:ns.value], lval, sptr, sline[:ns.value], sslot[:ns.value]
+                           C.c_double(max_fill), cap, _p(lptr, C.c_int), _p(lcol, C.c_int), _p(lval, C.c_double),
+                           _p(sptr, C.c_int), _p(sline, C.c_int), _p(sslot, C.c_int), C.byref(ns))
+    assert ok != -1
+    n = ns.value
+    nreal = int(sptr[-1]) if ok == 1 else 0   # the per-spot lists name real slots only
+    return ok, L, lptr, lcol[:n], lval[:n * R], sptr, sline[:nreal], sslot[:nreal]
 
 
-def test_line_format_reconstructs_banded_matrix(hp):
-    M = qpsynth.config2(scale=0.02).J
-    ok, L, lptr, lcol, lval, sptr, sline, sslot = _line_format(hp, M)
-    assert ok == 1
+def _reconstruct(M, L, lptr, lcol, lval, R=64):
     rows, cols, vals = [], [], []
     for l in range(L):
         for k in range(lptr[l], lptr[l + 1]):
-            for r in range(64):
-                rows.append(64 * l + r); cols.append(lcol[k]); vals.append(lval[k * 64 + r])
-    R = sp.csr_matrix((vals, (rows, cols)), shape=M.shape)
-    assert (R != M).nnz == 0
+            for r in range(R):
+                if R * l + r < M.shape[0]:
+                    rows.append(R * l + r); cols.append(lcol[k]); vals.append(lval[k * R + r])
+                else:
+                    assert lval[k * R + r] == 0.0   # padding rows of the last line hold nothing
+    return sp.csr_matrix((vals, (rows, cols)), shape=M.shape)
+
+
+def _check_spot_lists(M, lcol, sptr, sline, sslot, R=64):
     # per-spot (line, slot) lists are the transpose of the line incidence, lines increasing
     for j in range(0, M.shape[1], 37):
         ls = sline[sptr[j]:sptr[j + 1]]
         assert np.all(np.diff(ls) > 0)
         assert np.all(lcol[sslot[sptr[j]:sptr[j + 1]]] == j)
         col_rows = M.tocsc()[:, j].indices
-        assert np.array_equal(np.unique(col_rows // 64), ls)
+        assert np.array_equal(np.unique(col_rows // R), ls)
+
+
+def _check_slot_groups(lptr, lcol, lval, real, R=64):
+    """Lines hold whole groups of 4 slots; the padding slots repeat the
+    line's last real column and hold zeros."""
+    for l in range(len(lptr) - 1):
+        a, b = lptr[l], lptr[l + 1]
+        assert (b - a) % 4 == 0 and (b - a) - real[l] in range(4)
+        for k in range(a + real[l], b):
+            assert lcol[k] == lcol[a + real[l] - 1]
+            assert not np.any(lval[k * R:(k + 1) * R])
+
+
+def test_line_format_reconstructs_banded_matrix(hp):
+    M = qpsynth.config2(scale=0.02).J
+    ok, L, lptr, lcol, lval, sptr, sline, sslot = _line_format(hp, M, max_fill=1.0)
+    assert ok == 1
+    real = [len(np.unique(M[64 * l:64 * (l + 1)].indices)) for l in range(L)]
+    assert sum(real) * 64 == M.nnz             # the bands share their column lists: only group padding
+    _check_slot_groups(lptr, lcol, lval, real)
+    assert (_reconstruct(M, L, lptr, lcol, lval) != M).nnz == 0
+    _check_spot_lists(M, lcol, sptr, sline, sslot)
+
+
+def test_line_format_pads_rows_that_miss_columns(hp):
+    """A banded matrix with 15% of its entries dropped at random and a row
+    count that is not a multiple of 64: each line stores the union of its
+    rows' columns, zeros where a row lacks one, and empty padding rows."""
+    M = qpsynth.config2(scale=0.02).J.tocoo()
+    keep = np.random.default_rng(4).uniform(size=M.nnz) >= 0.15
+    M = sp.csr_matrix((M.data[keep], (M.row[keep], M.col[keep])), shape=M.shape)[:M.shape[0] - 23]
+    M.sort_indices()
+    ok, L, lptr, lcol, lval, sptr, sline, sslot = _line_format(hp, M)
+    assert ok == 1 and L == -(-M.shape[0] // 64)
+    real = [len(np.unique(M[64 * l:64 * (l + 1)].indices)) for l in range(L)]
+    assert M.nnz < 64 * sum(real) <= 2 * M.nnz
+    _check_slot_groups(lptr, lcol, lval, real)
+    assert (_reconstruct(M, L, lptr, lcol, lval) != M).nnz == 0
+    # each line's list starts with exactly the union of its rows' columns, sorted
+    for l in range(L):
+        union = np.unique(M[64 * l:64 * (l + 1)].indices)
+        assert np.array_equal(lcol[lptr[l]:lptr[l] + len(union)], union)
+    _check_spot_lists(M, lcol, sptr, sline, sslot)
+    # a fill budget below what the lines need refuses the format
+    assert _line_format(hp, M, max_fill=1.0)[0] == 0
 
 
 def test_line_format_rejects_unstructured(hp):
-    M = qpsynth.config1(0).J   # 2000 rows (not a multiple of 64 -> 2000 = 31*64+16)
+    M = qpsynth.config1(0).J   # 2000 x 200 at 5%, uniform positions: a line's rows share almost nothing
     assert _line_format(hp, M)[0] == 0
-    M2 = qpsynth.config2(scale=0.02).J.tolil()
-    M2[5, 7] = 1.0 if M2[5, 7] == 0 else 0.0
-    assert _line_format(hp, M2.tocsr())[0] == 0
