@@ -200,6 +200,7 @@ def batch_run(probs, prec, steps, warmup):
     return {"ms_per_batch": ms, "qp_per_s": len(probs) / (ms * 1e-3),
             "status_ok": all(f["status"] == qpgpu.QP_OK for f in infos_all),
             "ipm_iters_total": sum(f["ipm_iters"] for f in infos_all) // steps,
+            "pcg_phase_ms": max(f["t_pcg_ms"] for f in infos_all) / steps,
             "pcg_iters_total": int(pcg), "create_s": t_create,
             "max_certificate": max(max(f[k] for k in ("eps_d", "eps_p", "eps_c", "gap")) for f in infos_all)}
 
@@ -215,7 +216,7 @@ def batch_bench(args):
     nnz = sum(int(p.J.nnz) for p in probs)
     print(f"[bench] generated {len(probs)} QPs, n in [{min(p.n for p in probs)}, {max(p.n for p in probs)}], "
           f"{nnz} nnz of J in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    st = qpgpu.qp_default_settings(precision=args.precision)
+    st = qpgpu.qp_default_settings(precision=args.precision, graphs=args.graphs)
     hs = [qpgpu.qp_create_from_problem(p, settings=st) for p in probs]
     print(f"[bench] created handles", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -259,7 +260,8 @@ def batch_bench(args):
                       "batch_speedup_vs_sequential": seq / (el / args.steps) if seq else None,
                       "batch_speedup_vs_host_workers": thr / (el / args.steps) if thr else None,
                       "ipm_iters_total": sum(f["ipm_iters"] for f in all_infos),
-                      "pcg_iters_total": sum(f["pcg_iters"] for f in all_infos)}), flush=True)
+                      "pcg_iters_total": sum(f["pcg_iters"] for f in all_infos),
+                      "pcg_phase_ms": max(f["t_pcg_ms"] for f in all_infos) / args.steps}), flush=True)
 
 
 def sqp_bench(args):

@@ -23,15 +23,17 @@ namespace qpg {
 
 constexpr int kMaxBatch = 256;   // QPs of one batched launch (one planning thread each)
 
-// Kinds of work.  PCG products use the BK_LINE / BK_SPOT lists; plain FP64
-// products (the refinement residual) BK_LINE_PLAIN / BK_SPOT.
+// Kinds of work.  PCG products use the BK_LINE (or, with FP64 values in a
+// low-precision batch, BK_LINE64) and BK_SPOT lists; plain FP64 products
+// (the refinement residual) BK_LINE_PLAIN and BK_SPOT.
 enum BatchKind : int {
     BK_INIT = 0,     // k_pcg_init0
     BK_PRECA,        // constraint-block step 1 at a solve's start (k_prec_a)
     BK_SYMV,         // step 2 (k_prec_symv)
     BK_AT,           // step 3 (k_prec_at)
     BK_SCAL,         // k_pcg_scalars (block 0 the scalars, then the rows of A z)
-    BK_LINE,         // line pass of a PCG product
+    BK_LINE,         // line pass of a PCG product in the batch's precision
+    BK_LINE64,       // line pass of an FP64 PCG product (sized from the FP64 line arguments)
     BK_LINE_PLAIN,   // line pass of a plain product (rows of A in the grid)
     BK_SPOT,         // spot pass
     BK_XR,           // k_pcg_xr
@@ -151,9 +153,14 @@ __device__ __forceinline__ void batch_walk(const BatchList* L, F&& body) {
     }
 }
 
+// The walk around the line pass takes a few registers more than the single
+// QP's kernel: with FP64 values the budget of six (or five) wavefronts per
+// SIMD would spill, so that one runs four.
+template <typename VT>
+constexpr int kb_line_waves() { return sizeof(VT) == 8 ? 4 : 6; }
 template <typename VT, typename AT, bool NT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void kb_line(const LineArgs<VT>* tab,
-                                                                                          const BatchList* L) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kb_line_waves<VT>()))) void kb_line(
+    const LineArgs<VT>* tab, const BatchList* L) {
     batch_walk(L, [&](int q, int b, int nb) { line_pass_body<VT, AT, NT>(tab[q], b, nb, false); });
 }
 

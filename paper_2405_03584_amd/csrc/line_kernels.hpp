@@ -25,6 +25,8 @@
 // the HBM traffic of J; c is one double per slot (1/64 per nonzero).
 #pragma once
 
+#include <type_traits>
+
 #include "ipm_kernels.hpp"
 
 namespace qpg {
@@ -60,14 +62,24 @@ constexpr int kLineGroup = 4;
 template <typename VT> struct SlotPack { static constexpr int P = 8 / int(sizeof(VT)); };
 template <> struct SlotPack<double> { static constexpr int P = 1; };
 
-// The P values of slot group gi of a line (values at base) for row `lane`.
+// A lane's base pointer into a line's values: its row's first value (P = 1)
+// or its row's 8-byte word of the first slot group (P > 1); group gi is 64
+// words further per group.
+template <typename VT>
+using LaneWord = typename std::conditional<SlotPack<VT>::P == 1, VT, uint64_t>::type;
+template <typename VT>
+__device__ __forceinline__ const LaneWord<VT>* lane_base(const VT* lval, int off, int lane) {
+    return reinterpret_cast<const LaneWord<VT>*>(lval + size_t(off) * 64) + lane;
+}
+
+// The P values of slot group gi (slots gi*P ...) of the lane's row.
 template <typename VT, typename AT, bool NT>
-__device__ __forceinline__ void load_group(const VT* base, int gi, int lane, AT* out) {
+__device__ __forceinline__ void load_group(const LaneWord<VT>* v, int gi, AT* out) {
     constexpr int P = SlotPack<VT>::P;
     if constexpr (P == 1) {
-        out[0] = cvt<AT>(load_val<NT>(base + size_t(gi) * 64 + lane));
+        out[0] = cvt<AT>(load_val<NT>(&v[size_t(gi) * 64]));
     } else {
-        const uint64_t* pb = reinterpret_cast<const uint64_t*>(base) + size_t(gi) * 64 + lane;
+        const uint64_t* pb = &v[size_t(gi) * 64];
         const uint64_t wv = NT ? __builtin_nontemporal_load(pb) : *pb;
 #pragma unroll
         for (int s = 0; s < P; ++s) {
@@ -169,7 +181,7 @@ __device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, in
         // slots before them (only in lines longer than NW*RH slots) are
         // streamed first, so their registers are free before the held loads
         const int kh = max(k0, k1 - RH);
-        const VT* v = a.lval + size_t(off) * 64;
+        const LaneWord<VT>* v = lane_base(a.lval, off, lane);
         const int* col = a.lcol + off;
         AT acc = AT(0);
         for (int k = k0; k < kh; k += 4) {
@@ -177,7 +189,7 @@ __device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, in
 #pragma unroll
             for (int j = 0; j < 4 / P; ++j) {
                 AT gv[P];
-                load_group<VT, AT, NT>(v, min((k + j * P) / P, kh / P - 1), lane, gv);
+                load_group<VT, AT, NT>(v, min((k + j * P) / P, kh / P - 1), gv);
 #pragma unroll
                 for (int t = 0; t < P; ++t) {
                     const int kk = min(k + j * P + t, kh - 1);
@@ -200,7 +212,7 @@ __device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, in
 #pragma unroll
             for (int j = 0; j < RH / P; ++j) {
                 AT gv[P];
-                load_group<VT, AT, NT>(v, min(kh / P + j, k1 / P - 1), lane, gv);
+                load_group<VT, AT, NT>(v, min(kh / P + j, k1 / P - 1), gv);
 #pragma unroll
                 for (int t = 0; t < P; ++t) hv[j * P + t] = (kh + j * P < k1) ? gv[t] : AT(0);
             }
@@ -235,7 +247,7 @@ __device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, in
 #pragma unroll
             for (int j = 0; j < 8 / P; ++j) {
                 AT gv[P];
-                load_group<VT, AT, NT>(v, min(kg / P + j, kh / P - 1), lane, gv);
+                load_group<VT, AT, NT>(v, min(kg / P + j, kh / P - 1), gv);
 #pragma unroll
                 for (int u = 0; u < P; ++u) pv[j * P + u] = (kg + j * P < kh) ? gv[u] * t : AT(0);
             }

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <thread>
 #include <tuple>
+#include <type_traits>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -71,6 +72,7 @@ struct qp_handle {
     int wb_attempt_cap = 0;     // > 0: the attempt cap of constraint-block-preconditioned solves is on
     int wb_seen = 0;            // longest converged constraint-block solve of the current run
     int wb_cap_used = 0;        // iteration cap the last constraint-block solve set up with
+    int wb_cap_dir = 0;         // attempt cap of the current direction's constraint-block solves
     double* x0d = nullptr;      // caller's start point (qp_solve_from), allocated on first use
     int GJ = 16, GJt = 64;   // lanes per row of J and of J^T (and A^T)
 
@@ -754,7 +756,7 @@ PcgSetup pcg_setup(qp_handle* h, const double* rhs_a, const double* rhs_b, const
         S.nb_at = grid_rows_capped(h->n, kPrecAtLanes);
     }
     S.n_rz = S.wb ? S.nb_at : S.ge;
-    const int cap = (S.wb && h->wb_attempt_cap > 0) ? std::min(h->set.pcg_max_iter, wb_attempt_cap(h))
+    const int cap = (S.wb && h->wb_attempt_cap > 0) ? std::min(h->set.pcg_max_iter, h->wb_cap_dir)
                                                     : h->set.pcg_max_iter;
     if (S.wb) h->wb_cap_used = cap;
     ScalArgs& sa = S.sa;
@@ -950,6 +952,7 @@ Flags newton_direction(qp_handle* h, int prec, const double* rhs_a, const double
                        const double* sigA, const double* d, const double* dh, double hs, bool ipm_mode,
                        TimingAcc* tacc, int* solves) {
     const double tol = h->set.pcg_tol;
+    h->wb_cap_dir = wb_attempt_cap(h);   // one attempt cap for all solves of this direction
     if (prec == QP_FP64) {
         *solves = 1;
         return run_pcg(h, QP_FP64, rhs_a, rhs_b, sigx, sigA, d, dh, hs, ipm_mode, tacc, tol, false);
@@ -1521,15 +1524,16 @@ struct BatchRun {
 };
 
 // The persistent path serves handles on the line format with the condensed
-// system, no low-rank term, one precision, no event timing, on one device;
-// other batches run each QP's own solve on host workers.
+// system, no low-rank term, one precision and graph setting, no event
+// timing, on one device; other batches run each QP's own solve on host
+// workers.
 bool batch_persistent_ok(qp_handle* const* hs, int count) {
     if (count < 2 || count > kMaxBatch) return false;
     for (int i = 0; i < count; ++i) {
         const qp_handle* h = hs[i];
-        if (!h->line || h->k > 0 || h->set.kkt_system != 0 || h->set.timing || h->set.graphs == 0) return false;
+        if (!h->line || h->k > 0 || h->set.kkt_system != 0 || h->set.timing) return false;
         if (h->set.precision != hs[0]->set.precision || h->set.refine_steps != hs[0]->set.refine_steps ||
-            h->device != hs[0]->device)
+            h->set.graphs != hs[0]->set.graphs || h->device != hs[0]->device)
             return false;
     }
     return true;
@@ -1647,6 +1651,7 @@ void batch_tables_t(BatchRun& B) {
         const double* dh = r.wbp ? h->Dw : nullptr;
         const double tol = h->set.pcg_tol;
         const double inner = h->set.refine_steps > 0 ? std::max(h->set.refine_tol, tol) : tol;
+        h->wb_cap_dir = wb_attempt_cap(h);   // as newton_direction: one cap per direction
         const PcgSetup S_ipm = pcg_setup(h, v.rhs_a, v.rhs_b, sigA, v.d, dh, true, tol, false);
         const PcgSetup S_lo = pcg_setup(h, nullptr, h->rhs_full, sigA, v.d, dh, false, inner, false);
         const PcgSetup S_rho = pcg_setup(h, nullptr, h->rho, sigA, v.d, dh, false, inner, true);
@@ -1662,6 +1667,7 @@ void batch_tables_t(BatchRun& B) {
         bq.nblk[BK_AT] = S_ipm.wb ? S_ipm.nb_at : 0;
         bq.nblk[BK_SCAL] = S_ipm.gs;
         bq.nblk[BK_LINE] = line_blocks(lo);
+        bq.nblk[BK_LINE64] = line_blocks(l64);
         bq.nblk[BK_LINE_PLAIN] = line_blocks(lpl);
         bq.nblk[BK_SPOT] = spot_blocks(h);
         bq.nblk[BK_XR] = S_ipm.nb_xr;
@@ -1736,7 +1742,8 @@ void batch_line_launch(BatchRun& B, const void* tab, const BatchList* L, bool nt
 void batch_line(BatchRun& B, bool lo) {
     if (lo && B.prec == QP_FP32) batch_line_launch<float, float>(B, B.d_line_lo, B.list(BK_LINE), B.nt_lo);
     else if (lo && B.prec == QP_BF16) batch_line_launch<bf16_t, float>(B, B.d_line_lo, B.list(BK_LINE), B.nt_lo);
-    else batch_line_launch<double, double>(B, lo ? B.d_line_lo : B.d_line_64, B.list(BK_LINE), B.nt_64);
+    else batch_line_launch<double, double>(B, lo ? B.d_line_lo : B.d_line_64, B.list(lo ? BK_LINE : BK_LINE64),
+                                           B.nt_64);
 }
 
 // One batched PCG iteration (kernels in the order of run_pcg's).
@@ -1815,13 +1822,18 @@ std::vector<Flags> batch_pcg(BatchRun& B, const std::vector<char>& mask, int sv,
         harvest(0);
         if (check_only || B.snap_status(0).active == 0) return out;
     }
-    const hipGraphExec_t gx = batch_graph(B, lo);
+    // graphs = 0 (the handles' setting): the same iterations launched directly
+    const hipGraphExec_t gx = B.hs[0]->set.graphs ? batch_graph(B, lo) : nullptr;
     int* hist = B.hist[refine ? 1 : 0];
     const int pred = std::min(hist[0], hist[1]);
     int chunk = std::max(kGraphIters, std::min(512, (pred * 3) / 4));
     chunk = ((chunk + kGraphIters - 1) / kGraphIters) * kGraphIters;
     auto queue = [&](int iters) {
-        for (int i = 0; i < iters; i += kGraphIters) HIPCHK(hipGraphLaunch(gx, B.st));
+        for (int i = 0; i < iters; i += kGraphIters) {
+            if (gx) HIPCHK(hipGraphLaunch(gx, B.st));
+            else
+                for (int j = 0; j < kGraphIters; ++j) batch_iter(B, lo);
+        }
     };
     int64_t launched = 0;
     int64_t guard = 4096;
