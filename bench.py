@@ -606,12 +606,14 @@ def csr_operator_rates(prob, prec, vb, reps=20):
     bf, bb = spmv_bytes(n, nJ, m, int(prob.J.nnz), int(prob.A.nnz), vb, 0)
     fus = 1e3 * info["t_spmv_fwd_ms"] / max(info["n_spmv_fwd"], 1)
     bus = 1e3 * info["t_spmv_bwd_ms"] / max(info["n_spmv_bwd"], 1)
-    out = {"precision": prec, "reps": reps,
-           "J_pass": {"kernel": "k_op_fwd", "us": fus, "bytes": bf, "GBs": bf / (fus * 1e-6) / 1e9,
+    sched = info["spmv_schedule"]
+    out = {"precision": prec, "reps": reps, "schedule": sched,
+           "J_pass": {"kernel": "k_op_fwd_stream" if sched == 1 else f"k_op_fwd<{sched}>", "us": fus, "bytes": bf,
+                      "GBs": bf / (fus * 1e-6) / 1e9,
                       "frac": bf / (fus * 1e-6) / 1e9 / HBM_PEAK_GBS},
            "Jt_pass": {"kernel": "k_op_bwd", "us": bus, "bytes": bb, "GBs": bb / (bus * 1e-6) / 1e9,
                        "frac": bb / (bus * 1e-6) / 1e9 / HBM_PEAK_GBS}}
-    print(f"[bench] CSR operator {prec}: J pass {fus:.1f} us ({out['J_pass']['GBs']:.0f} GB/s), "
+    print(f"[bench] CSR operator {prec} (schedule {sched}): J pass {fus:.1f} us ({out['J_pass']['GBs']:.0f} GB/s), "
           f"J^T pass {bus:.1f} us ({out['Jt_pass']['GBs']:.0f} GB/s)", file=sys.stderr, flush=True)
     return out
 

@@ -103,7 +103,9 @@ typedef struct {
     int32_t max_ipm_iter;     /* default 200 */
     int32_t step_mode;        /* 0: separate primal/dual steps (Algorithm 1), 1: equal */
     int32_t scale_objective;  /* 1 (default): divide H, p by max(1, ||H x0 + p||_inf) */
-    int32_t schedule;         /* 0: automatic SpMV row grouping, else lanes per row (4..64) */
+    int32_t schedule;         /* CSR SpMV schedule (results are the same bits for every one):
+                                 0: autotuned; 4..64: lanes per row; 1: the J pass over
+                                 nonzero-balanced blocks of rows, default lane counts elsewhere */
     int32_t timing;           /* 1: time the J and J^T SpMV launches with HIP events */
     int32_t log_level;        /* 0: quiet; 1: one line per IPM iteration on stderr */
     int32_t precond;          /* 0: Jacobi, diag(K) (Section 4.1.2); 1 (default): Jacobi on the H
@@ -169,6 +171,8 @@ typedef struct {
     double  eps_d, eps_p, eps_c, gap;
     int32_t prec_tier;        /* preconditioner tier the call ended on: 0 constraint block, 1 capped
                                  block, 2 Jacobi diagonal (see precond) */
+    int32_t spmv_schedule;    /* CSR format: the J pass's schedule (1: nonzero-balanced row
+                                 blocks, else lanes per row; see settings.schedule); 0: line format */
 } qp_info;
 
 /* Defaults listed above. */

@@ -146,6 +146,15 @@ __device__ __forceinline__ double block_min(double v, double* sh) {
 
 // Gathered vector of a product: x, or (PCG) the search direction z + beta p
 // formed on the fly from the last z and the previous p.
+// A product that is never fused into a later addition: sums whose terms are
+// formed in different kernels (a term kept in registers, or staged in LDS)
+// then round every term the same way.
+template <typename T>
+__device__ __forceinline__ T mul_nc(T a, T b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
 struct Gather {
     const double* x;
     const double* p2;   // null: plain x

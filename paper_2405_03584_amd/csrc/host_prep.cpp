@@ -129,6 +129,22 @@ bool build_line_format(const HostCsr& M, int32_t R, LineFormat& lf, double max_f
     return true;
 }
 
+void build_row_blocks(const std::vector<int32_t>& ptr, int32_t rows, int32_t max_nnz, int32_t max_rows,
+                      std::vector<int32_t>& out) {
+    out.clear();
+    int32_t r = 0;
+    while (r < rows) {
+        out.push_back(r);
+        out.push_back(ptr[r]);
+        const int32_t start = r;
+        const int32_t e0 = ptr[r];
+        ++r;   // the first row always fits (alone when longer than max_nnz)
+        while (r < rows && r - start < max_rows && int64_t(ptr[r + 1]) - e0 <= max_nnz) ++r;
+    }
+    out.push_back(rows);
+    out.push_back(rows > 0 ? ptr[rows] : 0);
+}
+
 // binary64 -> binary32 with round to nearest, ties to even.  The C++ cast
 // rounds with the current rounding mode, which is round-to-nearest-even by
 // default; values beyond the float range become +-inf.
@@ -185,9 +201,9 @@ std::string validate_settings(const qp_settings* s) {
     if (!(s->tau > 0.0) || !(s->tau < 1.0)) return "settings.tau must be in (0, 1)";
     if (s->max_ipm_iter < 1) return "settings.max_ipm_iter must be >= 1";
     if (s->step_mode != 0 && s->step_mode != 1) return "settings.step_mode must be 0 or 1";
-    if (s->schedule != 0 && s->schedule != 4 && s->schedule != 8 && s->schedule != 16 &&
+    if (s->schedule != 0 && s->schedule != 1 && s->schedule != 4 && s->schedule != 8 && s->schedule != 16 &&
         s->schedule != 32 && s->schedule != 64)
-        return "settings.schedule must be 0, 4, 8, 16, 32 or 64";
+        return "settings.schedule must be 0, 1, 4, 8, 16, 32 or 64";
     if (s->precond != 0 && s->precond != 1) return "settings.precond must be 0 or 1";
     if (s->graphs != 0 && s->graphs != 1) return "settings.graphs must be 0 or 1";
     if (s->spmv_format != 0 && s->spmv_format != 1) return "settings.spmv_format must be 0 or 1";

@@ -61,6 +61,15 @@ struct LineFormat {
 // untouched.
 bool build_line_format(const HostCsr& M, int32_t R, LineFormat& lf, double max_fill = 2.0);
 
+// Nonzero-balanced blocks of consecutive rows of a CSR matrix (row pointers
+// ptr, rows + 1 entries): block b holds rows out[2b] .. out[2b+2] - 1 and
+// nonzeros out[2b+1] .. out[2b+3] - 1 (out holds 2(blocks + 1) entries, pairs of
+// first row and first nonzero).  Rows join a block while it keeps at most
+// max_nnz nonzeros and max_rows rows; a row longer than max_nnz forms a block
+// of its own.  Every row falls in exactly one block; rows == 0 gives no block.
+void build_row_blocks(const std::vector<int32_t>& ptr, int32_t rows, int32_t max_nnz, int32_t max_rows,
+                      std::vector<int32_t>& out);
+
 // Round-to-nearest-even conversions (IEEE 754 binary32 / bfloat16 formats).
 uint32_t f64_to_f32_bits(double v);
 uint16_t f64_to_bf16_bits(double v);

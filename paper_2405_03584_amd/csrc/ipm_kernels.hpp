@@ -107,6 +107,22 @@ __device__ __forceinline__ Gather make_gather(const double* x, const double* p2,
     return Gather{x, p2, p2 ? sc->beta : 0.0};
 }
 
+// Rows of A in the forward pass: a full wavefront per row, four rows per
+// block ab.
+template <typename VT>
+__device__ __forceinline__ void fwd_a_rows(const FwdArgs<VT>& a, const Gather& g, int ab) {
+    const int row = ab * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row < a.m) {
+        double s = row_dot_lane_g<64, double, double>(a.Ap, a.Ac, a.Av, g, row, lane);
+        s = group_sum<double, 64>(s);
+        if (lane == 0) {
+            if (a.aug.dlu) a.u[row] = aug_row(a.aug, a.m, row, s, a.sigA[row], g, const_cast<double*>(a.p2));
+            else a.u[row] = a.sigA ? a.sigA[row] * s : s;
+        }
+    }
+}
+
 // t = W .* (J x) and u = Sigma_A .* (A x).  Rows of J: G lanes per row; rows
 // of A: a full wavefront per row.
 template <int G, typename VT, typename AT>
@@ -120,20 +136,94 @@ __global__ __launch_bounds__(kBlock) void k_op_fwd(FwdArgs<VT> a) {
         const int lane = threadIdx.x % G;
         if (row < a.nJ) {   // whole groups are uniform: inactive groups skip together
             const AT s = canon_sum<G, AT>(a.Jp[row], a.Jp[row + 1], lane,
-                                          [&](int e) { return cvt<AT>(a.Jv[e]) * AT(g(a.Jc[e])); });
+                                          [&](int e) { return mul_nc(cvt<AT>(a.Jv[e]), AT(g(a.Jc[e]))); });
             if (lane == 0) a.t[row] = a.W[row] * double(s);
         }
     } else {
-        const int row = (b - a.nbJ) * (kBlock / 64) + (threadIdx.x >> 6);
-        const int lane = threadIdx.x & 63;
-        if (row < a.m) {
-            double s = row_dot_lane_g<64, double, double>(a.Ap, a.Ac, a.Av, g, row, lane);
-            s = group_sum<double, 64>(s);
-            if (lane == 0) {
-                if (a.aug.dlu) a.u[row] = aug_row(a.aug, a.m, row, s, a.sigA[row], g, const_cast<double*>(a.p2));
-                else a.u[row] = a.sigA ? a.sigA[row] * s : s;
-            }
+        fwd_a_rows(a, g, b - a.nbJ);
+    }
+}
+
+// The forward pass over nonzero-balanced blocks of rows of J, for rows short
+// against the 64 x 8 terms a wavefront pass of canon_sum spans (where most of
+// a G-lane group's clamped loads would repeat an address).  Block b takes the
+// rows rb[b].x .. rb[b+1].x - 1, whose nonzeros rb[b].y .. rb[b+1].y - 1 are
+// at most kStreamNnz (and the rows at most kStreamRows), or a single longer
+// row.  Its threads load the nonzeros contiguously (every load useful and
+// coalesced) and store the products in LDS; then a wavefront per row adds
+// them in the order canon_sum defines (virtual lane v adds the row's terms
+// v, v+64, ... in order, then the butterfly), so t has the same bits as with
+// any lane count.  A longer row is staged in chunks of kStreamNnz terms
+// (multiples of 64, so each lane keeps its virtual lane across chunks).
+constexpr int kStreamNnz = 2048;
+constexpr int kStreamRows = 256;
+template <typename VT, typename AT>
+__device__ __forceinline__ void stream_stage(const FwdArgs<VT>& a, const Gather& g, int e0, int e1, AT* prod) {
+    constexpr int PER = kStreamNnz / kBlock;
+    if (e1 <= e0) return;
+    int c[PER];
+    AT v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = min(e0 + int(threadIdx.x) + u * kBlock, e1 - 1);   // clamped: a valid address
+        c[u] = a.Jc[e];
+        v[u] = cvt<AT>(a.Jv[e]);
+    }
+    double xv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) xv[u] = g(c[u]);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int k = int(threadIdx.x) + u * kBlock;
+        if (e0 + k < e1) prod[k] = mul_nc(v[u], AT(xv[u]));
+    }
+}
+template <typename VT, typename AT>
+__global__ __launch_bounds__(kBlock) void k_op_fwd_stream(FwdArgs<VT> a, const int2* rb) {
+    __shared__ AT prod[kStreamNnz];
+    __shared__ int rp[kStreamRows + 1];
+    __shared__ double wl[kStreamRows];
+    if (pcg_stopped_ro(a.fl)) return;
+    const Gather g = make_gather(a.x, a.p2, a.sc);
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    if (b >= a.nbJ) {
+        fwd_a_rows(a, g, b - a.nbJ);
+        return;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int2 lo = rb[b], hi = rb[b + 1];
+    const int r0 = lo.x, nr = hi.x - lo.x, e0 = lo.y, e1 = hi.y;
+    if (e1 - e0 > kStreamNnz) {   // one long row (nr == 1)
+        AT s = AT(0);
+        for (int ch = e0; ch < e1; ch += kStreamNnz) {
+            const int ce = min(e1, ch + kStreamNnz);
+            stream_stage(a, g, ch, ce, prod);
+            __syncthreads();
+            if (w == 0)
+                for (int k = lane; k < ce - ch; k += 64) s += prod[k];
+            __syncthreads();
         }
+        if (w == 0) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+            if (lane == 0) a.t[r0] = a.W[r0] * double(s);
+        }
+        return;
+    }
+    // the rows' extents (relative to e0) and weights, loaded beside the nonzeros
+    for (int i = threadIdx.x; i <= nr; i += kBlock) {
+        rp[i] = a.Jp[r0 + i] - e0;
+        if (i < nr) wl[i] = a.W[r0 + i];
+    }
+    stream_stage(a, g, e0, e1, prod);
+    __syncthreads();
+    for (int i = w; i < nr; i += kBlock / 64) {
+        const int k0 = rp[i], k1 = rp[i + 1];
+        AT s = AT(0);
+        for (int k = k0 + lane; k < k1; k += 64) s += prod[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) a.t[r0 + i] = wl[i] * double(s);
     }
 }
 

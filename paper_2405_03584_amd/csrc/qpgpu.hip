@@ -75,6 +75,9 @@ struct qp_handle {
     int wb_cap_dir = 0;         // attempt cap of the current direction's constraint-block solves
     double* x0d = nullptr;      // caller's start point (qp_solve_from), allocated on first use
     int GJ = 16, GJt = 64;   // lanes per row of J and of J^T (and A^T)
+    bool fwd_stream = false;  // CSR forward pass over nonzero-balanced row blocks (k_op_fwd_stream)
+    int2* jrb = nullptr;      // those blocks (first row, first nonzero), nbs + 1 pairs
+    int nbs = 0;
 
     std::vector<void*> allocs;
 
@@ -287,12 +290,19 @@ int grid_rows(int64_t rows, int G) {
 }
 int grid_rows_capped(int64_t rows, int G) { return std::min(grid_rows(rows, G), kMaxPartials); }
 
+// rb non-null: the rows of J in the nbs blocks of rb (k_op_fwd_stream), else
+// G lanes per row (k_op_fwd).
 template <typename VT, typename AT>
-void launch_fwd(hipStream_t st, int G, const FwdArgs<VT>& a0, int nbA) {
+void launch_fwd(hipStream_t st, int G, const FwdArgs<VT>& a0, int nbA, const int2* rb = nullptr, int nbs = 0) {
     FwdArgs<VT> a = a0;
-    a.nbJ = (a.nJ > 0) ? grid_rows(a.nJ, G) : 0;
+    a.nbJ = (a.nJ > 0) ? (rb ? nbs : grid_rows(a.nJ, G)) : 0;
     const int grid = a.nbJ + nbA;
     if (grid == 0) return;
+    if (rb) {
+        hipLaunchKernelGGL((k_op_fwd_stream<VT, AT>), dim3(grid), dim3(kBlock), 0, st, a, rb);
+        HIPCHK(hipGetLastError());
+        return;
+    }
     switch (G) {
         case 4: hipLaunchKernelGGL((k_op_fwd<4, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
         case 8: hipLaunchKernelGGL((k_op_fwd<8, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
@@ -446,7 +456,7 @@ int apply_op(qp_handle* h, const OpWork& wk, const double* x, double* q, const d
         f.aug.dlu = h->dlu; f.aug.q = q; f.aug.n = h->n; f.aug.part = part ? part + n_pq_x : nullptr;
     }
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], wk.st));
-    launch_fwd<VT, AT>(wk.st, h->GJ, f, nbA);
+    launch_fwd<VT, AT>(wk.st, h->GJ, f, nbA, h->fwd_stream ? h->jrb : nullptr, h->nbs);
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], wk.st));
     lowrank_prepare(h, wk, x, pl.p2, fl);
     BwdArgs<VT> b{};
@@ -481,11 +491,18 @@ int apply_op_prec(qp_handle* h, int prec, const double* x, double* q, const doub
     return apply_op_prec(h, handle_work(h), prec, x, q, sigx, sigA, hs, pcg, timed, tslot);
 }
 
+// The operator's format and (CSR) schedule, as qp_info reports them.
+void set_format_info(const qp_handle* h, qp_info* info) {
+    info->spmv_format = h->line ? 1 : 0;
+    info->spmv_schedule = h->line ? 0 : (h->fwd_stream ? 1 : h->GJ);
+}
+
 // SpMV schedule autotuner for CSR matrices: time each lane-group size for the
-// J pass and the J^T pass (a few launches each, HIP events) and keep the
-// fastest; results are cached per (rows, cols, nnz) for the process.
+// J pass and the J^T pass, and the J pass over nonzero-balanced row blocks (a
+// few launches each, HIP events), and keep the fastest; results are cached
+// per (rows, cols, nnz) for the process.  Every schedule gives the same bits.
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int64_t, int, int>, std::pair<int, int>> g_tune_cache;
+std::map<std::tuple<int, int, int64_t, int, int>, std::tuple<int, int, int>> g_tune_cache;
 
 void autotune_schedule(qp_handle* h);
 
@@ -654,54 +671,60 @@ void autotune_schedule(qp_handle* h) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            h->GJ = it->second.first;
-            h->GJt = it->second.second;
+            h->GJ = std::get<0>(it->second);
+            h->GJt = std::get<1>(it->second);
+            h->fwd_stream = std::get<2>(it->second) != 0;
             return;
         }
     }
-    const int cand[] = {8, 16, 32, 64};
+    // lane counts (both passes), then the forward pass over row blocks (0)
+    const int cand[] = {8, 16, 32, 64, 0};
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    float best_f = 1e30f, best_b = 1e30f;
+    float best_f = 1e30f, best_b = 1e30f, t_stream = 1e30f;
     int gf = h->GJ, gb = h->GJt;
-    const int save_f = h->GJ, save_b = h->GJt;
+    auto timed = [&](auto&& launch) {
+        HIPCHK(hipEventRecord(e0, h->stream));
+        launch();
+        HIPCHK(hipEventRecord(e1, h->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        return ms;
+    };
     for (int g : cand) {
-        h->GJ = g;
-        h->GJt = g;
+        if (g == 0 && !h->jrb) continue;
         float tf = 0.f, tb = 0.f;
         for (int rep = 0; rep < 4; ++rep) {   // first repetition warms up
             FwdArgs<double> f{};
             f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = h->Jv; f.W = h->W; f.nJ = h->nJ;
             f.x = h->zero_n; f.t = h->t; f.u = h->u;
-            HIPCHK(hipEventRecord(e0, h->stream));
-            launch_fwd<double, double>(h->stream, g, f, 0);
-            HIPCHK(hipEventRecord(e1, h->stream));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (rep) tf += ms;
+            const float mf = timed([&] { launch_fwd<double, double>(h->stream, g ? g : 64, f, 0,
+                                                                     g ? nullptr : h->jrb, h->nbs); });
+            if (rep) tf += mf;
+            if (g == 0) continue;
             BwdArgs<double> b{};
             b.Jtp = h->Jtp; b.Jtc = h->Jtc; b.Jtv = h->Jtv; b.n = h->n;
             b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = h->m > 0;
             b.t = h->t; b.u = h->zero_m; b.x = h->zero_n; b.hs = 1.0; b.q = h->tmp_n;
-            HIPCHK(hipEventRecord(e0, h->stream));
-            launch_bwd<double, double>(h->stream, g, b);
-            HIPCHK(hipEventRecord(e1, h->stream));
-            HIPCHK(hipEventSynchronize(e1));
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (rep) tb += ms;
+            const float mb = timed([&] { launch_bwd<double, double>(h->stream, g, b); });
+            if (rep) tb += mb;
+        }
+        if (g == 0) {
+            t_stream = tf;
+            continue;
         }
         if (tf < best_f) { best_f = tf; gf = g; }
         if (tb < best_b) { best_b = tb; gb = g; }
     }
-    (void)save_f; (void)save_b;
-    h->GJ = gf;
+    h->GJ = gf;   // also the lane count of the residual pass's rows of J
     h->GJt = gb;
+    h->fwd_stream = t_stream < best_f;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {gf, gb};
+    g_tune_cache[key] = std::make_tuple(gf, gb, int(h->fwd_stream));
 }
 
 // One PCG solve of K dx = rhs (rhs = mu*rhs_a + rhs_b when rhs_a is given, mu
@@ -1419,7 +1442,7 @@ void ipm_finish(IpmRun& r, double* x, double* lam_A, double* lam_x, qp_info* inf
         HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
         info->t_solve_ms = ms;
         info->t_pcg_ms = r.pcg_ms;
-        info->spmv_format = h->line ? 1 : 0;
+        set_format_info(h, info);
         info->prec_fallbacks = r.fallbacks;
         info->prec_tier = (h->woodbury && h->m > 0) ? r.tier : TIER_JACOBI;
         info->eps_d = co.eps_d;
@@ -2305,7 +2328,11 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
         }
         h->cscale = 1.0 + cmax;
         h->mtot = mt;
-        if (h->set.schedule != 0) {
+        if (h->set.schedule == 1) {   // the J pass over row blocks, lane counts as by default
+            h->fwd_stream = true;
+            h->GJ = pick_lanes(h->nnzJ, nJ);
+            h->GJt = pick_lanes(h->nnzJ + h->nnzA, n);
+        } else if (h->set.schedule != 0) {
             h->GJ = h->GJt = h->set.schedule;
         } else {
             h->GJ = pick_lanes(h->nnzJ, nJ);
@@ -2333,6 +2360,11 @@ qp_status qp_create(qp_handle** out, const qp_hessian* H, const qp_csr* J, const
             h->Jtp = h->upload(hJt.ptr.data(), hJt.ptr.size());
             h->Jtc = h->upload(hJt.col.data(), hJt.col.size());
             h->Jtv = h->upload(hJt.val.data(), hJt.val.size());
+            std::vector<int32_t> rb;
+            build_row_blocks(hJ.ptr, nJ, kStreamNnz, kStreamRows, rb);
+            h->nbs = int(rb.size() / 2) - 1;
+            if (h->nbs > 0) h->jrb = reinterpret_cast<int2*>(h->upload(rb.data(), rb.size()));
+            else h->fwd_stream = false;
         }
         if (use_line) {
             h->line = true;
@@ -2615,7 +2647,7 @@ qp_status qp_operator_apply(qp_handle* h, const double* sigma_x, const double* s
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
             info->t_solve_ms = ms;
-            info->spmv_format = h->line ? 1 : 0;
+            set_format_info(h, info);
             harvest_timing(h, ta, info);
         }
     } catch (const HipError& he) {
@@ -2740,6 +2772,7 @@ qp_status qp_newton_step(qp_handle* h, const double* sigma_x, const double* sigm
             info->pcg_relres = ps.bnorm2 > 0 ? std::sqrt(ps.rr / ps.bnorm2) : 0.0;
             info->prec_fallbacks = fallbacks;
             info->prec_tier = (h->woodbury && m > 0) ? tier : TIER_JACOBI;
+            set_format_info(h, info);
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
             info->t_solve_ms = info->t_pcg_ms = ms;

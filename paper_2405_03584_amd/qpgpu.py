@@ -57,7 +57,8 @@ class qp_info(C.Structure):
                 ("t_spmv_fwd_ms", C.c_double), ("t_spmv_bwd_ms", C.c_double),
                 ("n_spmv_fwd", C.c_int64), ("n_spmv_bwd", C.c_int64), ("spmv_format", C.c_int32),
                 ("prec_fallbacks", C.c_int32), ("eps_d", C.c_double), ("eps_p", C.c_double),
-                ("eps_c", C.c_double), ("gap", C.c_double), ("prec_tier", C.c_int32)]
+                ("eps_c", C.c_double), ("gap", C.c_double), ("prec_tier", C.c_int32),
+                ("spmv_schedule", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -436,6 +436,39 @@ def tiny(instance: int) -> QPProblem:
                      name=f"tiny[{instance}]", meta={"seed": seed})
 
 
+def long_rows(seed: int = 96000) -> QPProblem:
+    """CSR row-length edge cases: n = 2600 spots, J 900 x 2600 with row lengths
+    U_int[0, 60), 200 of them set to 0 (empty rows), and 12 rows longer than
+    2048 entries (lengths U_int[2049, 2600), the first of them a full row of
+    2600); positions uniform without repeats, values lognormal(0, 1); W ~
+    U[0.5, 2]; A 40 x 2600 with N(0,1) entries at 5%, A x <= b feasible at x0
+    ~ U[0,1]; bounds [0, 10]; p = -J^T W J x_t, x_t ~ U[0, 5].
+
+    Draw order: row lengths, the empty rows, the long rows, their lengths,
+    then per row its positions; values; W; A's mask and entries; x0; s0; x_t."""
+    rng = np.random.default_rng(seed)
+    n, nJ, m = 2600, 900, 40
+    counts = rng.integers(0, 60, nJ)
+    counts[rng.choice(nJ, 200, replace=False)] = 0
+    longr = rng.choice(nJ, 12, replace=False)
+    counts[longr] = rng.integers(2049, n, 12)
+    counts[longr[0]] = n
+    indptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    indices = np.concatenate([np.sort(rng.choice(n, int(c), replace=False)) for c in counts]).astype(np.int32)
+    data = rng.lognormal(0.0, 1.0, int(indptr[-1]))
+    J = _csr(indptr, indices, data, (nJ, n))
+    W = rng.uniform(0.5, 2.0, nJ)
+    mask = rng.random((m, n)) < 0.05
+    A = sp.csr_matrix(np.where(mask, rng.standard_normal((m, n)), 0.0))
+    x0 = rng.uniform(0.0, 1.0, n)
+    s0 = rng.uniform(0.1, 1.0, m)
+    x_t = rng.uniform(0.0, 5.0, n)
+    return QPProblem(gamma=GAMMA, p=_linear_term(J, W, x_t), J=J, W=W,
+                     x_lo=np.zeros(n), x_hi=np.full(n, 10.0),
+                     A=A, A_lo=np.full(m, -np.inf), A_hi=_feasible_rhs(A, x0, s0),
+                     name="long_rows", meta={"seed": seed})
+
+
 def ragged_lines(seed: int = 95000) -> QPProblem:
     """Line-format edge cases: n = 400 spots, eight 64-row lines with 0, 1, 5,
     130, 300, 64, 3 and 0 slots (empty lines, the first and the last included;

@@ -46,4 +46,15 @@ int hp_line_format(int rows, int cols, const int* ptr, const int* col, const dou
     std::memcpy(sslot, lf.sslot.data(), sizeof(int) * lf.sslot.size());
     return 1;
 }
+
+// blocks of rows (pairs of first row and first nonzero, blocks + 1 pairs);
+// returns the block count, or -1 when it exceeds cap_blocks
+int hp_row_blocks(int rows, const int* ptr, int max_nnz, int max_rows, int cap_blocks, int* out) {
+    std::vector<int32_t> p(ptr, ptr + rows + 1), o;
+    build_row_blocks(p, rows, max_nnz, max_rows, o);
+    const int nb = int(o.size() / 2) - 1;
+    if (nb > cap_blocks) return -1;
+    std::memcpy(out, o.data(), sizeof(int) * o.size());
+    return nb;
+}
 }

@@ -86,7 +86,7 @@ def test_operator_deterministic():
     assert y1.tobytes() == y2.tobytes()
 
 
-@pytest.mark.parametrize("sched", [4, 8, 16, 32, 64])
+@pytest.mark.parametrize("sched", [1, 4, 8, 16, 32, 64])
 def test_operator_every_schedule(sched):
     prob = qpsynth.config1(2)
     it = qpsynth.random_iterate(prob, 5)
@@ -106,11 +106,11 @@ def test_schedules_give_identical_bits(prec):
     prob = qpsynth.config1(2)
     it = qpsynth.random_iterate(prob, 5)
     outs = []
-    for sched in [4, 8, 16, 32, 64]:
+    for sched in [1, 4, 8, 16, 32, 64]:
         print(f"schedule {sched} {prec}", flush=True)
         h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(schedule=sched, precision=prec))
         y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
-        assert info["spmv_format"] == 0
+        assert info["spmv_format"] == 0 and info["spmv_schedule"] == sched
         st, dx, _ = qpgpu.qp_newton_step(h, it["sigma_x"], it["sigma_A"], it["rhs"])
         assert st == qpgpu.QP_OK
         res = qpgpu.qp_solve(h)
@@ -118,6 +118,26 @@ def test_schedules_give_identical_bits(prec):
         outs.append((y.tobytes(), dx.tobytes(), res.x.tobytes()))
     for o in outs[1:]:
         assert o == outs[0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_streamed_j_pass_long_rows(prec):
+    """The J pass over nonzero-balanced row blocks (schedule 1) on rows longer
+    than a block (staged in chunks), empty rows and short rows: the operator
+    has the bits of every lane schedule, and matches the oracle's K v."""
+    prob = qpsynth.long_rows()
+    it = qpsynth.random_iterate(prob, 2)
+    outs = {}
+    for sched in [1, 8, 64]:
+        h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(schedule=sched, spmv_format=1))
+        y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
+        assert info["spmv_schedule"] == sched
+        outs[sched] = y
+    assert outs[1].tobytes() == outs[8].tobytes() == outs[64].tobytes()
+    if prec == "fp64":
+        ref = oracle.condensed_operator_dense(prob, it["sigma_x"], it["sigma_A"]) @ it["v"]
+        bound = _abs_op(prob, it["sigma_x"], it["sigma_A"]) @ np.abs(it["v"])
+        assert np.all(np.abs(outs[1] - ref) <= 1e-12 * bound)
 
 
 # ----------------------------------------------------------------------------

@@ -159,3 +159,39 @@ def test_line_format_pads_rows_that_miss_columns(hp):
 def test_line_format_rejects_unstructured(hp):
     M = qpsynth.config1(0).J   # 2000 x 200 at 5%, uniform positions: a line's rows share almost nothing
     assert _line_format(hp, M)[0] == 0
+
+
+def _row_blocks(hp, counts, max_nnz, max_rows):
+    ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    rows = len(counts)
+    cap = rows + 1
+    out = np.zeros(2 * (cap + 1), np.int32)
+    nb = hp.hp_row_blocks(rows, _p(ptr, C.c_int), max_nnz, max_rows, cap, _p(out, C.c_int))
+    assert nb >= 0
+    return ptr, out[:2 * (nb + 1)].reshape(-1, 2)
+
+
+@pytest.mark.parametrize("case", ["short", "mixed", "empty_rows", "long_only", "none"])
+def test_row_blocks_cover_every_row_once(hp, case):
+    """Nonzero-balanced row blocks of the streamed forward pass: consecutive,
+    covering every row once, each within the nonzero and row limits or a
+    single longer row, and maximal (the next row would break a limit)."""
+    rng = np.random.default_rng(7)
+    counts = {"short": rng.integers(0, 40, 3000),
+              "mixed": np.where(rng.random(800) < 0.05, rng.integers(2049, 9000, 800), rng.integers(0, 300, 800)),
+              "empty_rows": np.zeros(1000, np.int64),
+              "long_only": rng.integers(2049, 5000, 40),
+              "none": np.zeros(0, np.int64)}[case]
+    max_nnz, max_rows = 2048, 256
+    ptr, blk = _row_blocks(hp, counts, max_nnz, max_rows)
+    rows = len(counts)
+    assert blk[0].tolist() == [0, 0] and blk[-1].tolist() == [rows, int(ptr[rows])]
+    for (r0, e0), (r1, e1) in zip(blk[:-1], blk[1:]):
+        assert r1 > r0 and e0 == ptr[r0] and e1 == ptr[r1]
+        nnz, nr = e1 - e0, r1 - r0
+        assert (nnz <= max_nnz and nr <= max_rows) or (nr == 1 and nnz > max_nnz)
+        if r1 < rows and nnz <= max_nnz:   # maximal: one more row would not fit
+            assert nr == max_rows or ptr[r1 + 1] - e0 > max_nnz
+    if rows == 0:
+        assert len(blk) == 1
+
