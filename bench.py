@@ -173,10 +173,11 @@ def operator_only(args, prob):
 
 
 def batch_run(probs, prec, steps, warmup):
-    """`probs` created once at precision `prec`, then solved together by
-    qp_solve_batch `warmup` times untimed and `steps` times timed (host clock
-    around the calls, data resident in HBM).  The handles are freed before
-    returning."""
+    """`probs` created once at precision `prec` (qp_solve_batch's default
+    mode: each QP's own solve, several in flight on their own streams), then
+    solved together by qp_solve_batch `warmup` times untimed and `steps` times
+    timed (host clock around the calls, data resident in HBM).  The handles
+    are freed before returning."""
     from paper_2405_03584_amd import qpgpu
     t0 = time.perf_counter()
     st = qpgpu.qp_default_settings(precision=prec)
@@ -200,15 +201,17 @@ def batch_run(probs, prec, steps, warmup):
     return {"ms_per_batch": ms, "qp_per_s": len(probs) / (ms * 1e-3),
             "status_ok": all(f["status"] == qpgpu.QP_OK for f in infos_all),
             "ipm_iters_total": sum(f["ipm_iters"] for f in infos_all) // steps,
-            "pcg_phase_ms": max(f["t_pcg_ms"] for f in infos_all) / steps,
+            "pcg_phase_ms": max(f["t_pcg_ms"] for f in infos_all),   # per call: the batched directions
             "pcg_iters_total": int(pcg), "create_s": t_create,
             "max_certificate": max(max(f[k] for k in ("eps_d", "eps_p", "eps_c", "gap")) for f in infos_all)}
 
 
 def batch_bench(args):
     """The uneven batch: `count` members of the 64-QP set, created once, then
-    solved together (qp_solve_batch) per step; for comparison the same handles
-    solved one after another, and (QPGPU_BATCH_THREADS=1) on host workers."""
+    solved together (qp_solve_batch, --batch-mode 0: host workers, the
+    default; 1: the persistent batched path) per step; for comparison the
+    same QPs solved one after another, and in the other batch mode (its own
+    handles)."""
     import qpsynth
     from paper_2405_03584_amd import qpgpu
     t0 = time.perf_counter()
@@ -216,8 +219,12 @@ def batch_bench(args):
     nnz = sum(int(p.J.nnz) for p in probs)
     print(f"[bench] generated {len(probs)} QPs, n in [{min(p.n for p in probs)}, {max(p.n for p in probs)}], "
           f"{nnz} nnz of J in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
-    st = qpgpu.qp_default_settings(precision=args.precision, graphs=args.graphs)
-    hs = [qpgpu.qp_create_from_problem(p, settings=st) for p in probs]
+
+    def make(mode):
+        st = qpgpu.qp_default_settings(precision=args.precision, graphs=args.graphs, batch_mode=mode)
+        return [qpgpu.qp_create_from_problem(p, settings=st) for p in probs]
+
+    hs = make(args.batch_mode)
     print(f"[bench] created handles", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         s, xs, infos = qpgpu.qp_solve_batch(hs)
@@ -230,7 +237,7 @@ def batch_bench(args):
         print(f"[bench] step {i}: status={s} pcg={sum(f['pcg_iters'] for f in infos)}", file=sys.stderr, flush=True)
     el = time.perf_counter() - t0
     ok = all(f["status"] == qpgpu.QP_OK for f in all_infos)
-    seq = thr = None
+    seq = other = None
     if args.compare:
         # the same handles solved one after another (one stream busy at a time)
         t1 = time.perf_counter()
@@ -238,30 +245,32 @@ def batch_bench(args):
             qpgpu.qp_solve(h)
         seq = time.perf_counter() - t1
         print(f"[bench] sequential: {1e3 * seq:.1f} ms", file=sys.stderr, flush=True)
-        # the same batch on host workers, each QP's own solve on its own stream
-        os.environ["QPGPU_BATCH_THREADS"] = "1"
-        qpgpu.qp_solve_batch(hs)
+        # the same batch in the other mode
+        ho = make(1 - args.batch_mode)
+        qpgpu.qp_solve_batch(ho)
         t2 = time.perf_counter()
-        qpgpu.qp_solve_batch(hs)
-        thr = time.perf_counter() - t2
-        del os.environ["QPGPU_BATCH_THREADS"]
-        print(f"[bench] host workers: {1e3 * thr:.1f} ms", file=sys.stderr, flush=True)
+        qpgpu.qp_solve_batch(ho)
+        other = time.perf_counter() - t2
+        for h in ho:
+            h.close()
+        print(f"[bench] batch mode {1 - args.batch_mode}: {1e3 * other:.1f} ms", file=sys.stderr, flush=True)
+    modes = ["host workers", "persistent batched launches"]
     print(json.dumps({"metric": METRIC, "value": args.count * args.steps / el, "unit": "QP/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                       "dtype": args.precision, "data": "synthetic",
                       "config": {"workload": f"batch of {args.count} uneven banded-dose QPs "
-                                             f"(n in [2000, 20000], {nnz} nnz of J in all), persistent "
-                                             f"batched launches",
-                                 "precision": args.precision},
+                                             f"(n in [2000, 20000], {nnz} nnz of J in all), "
+                                             f"{modes[args.batch_mode]}",
+                                 "precision": args.precision, "batch_mode": args.batch_mode},
                       "status_ok": ok,
                       "sequential_ms": 1e3 * seq if seq else None,
-                      "host_workers_ms": 1e3 * thr if thr else None,
+                      "other_mode_ms": 1e3 * other if other else None,
                       "batch_speedup_vs_sequential": seq / (el / args.steps) if seq else None,
-                      "batch_speedup_vs_host_workers": thr / (el / args.steps) if thr else None,
+                      "batch_speedup_vs_other_mode": other / (el / args.steps) if other else None,
                       "ipm_iters_total": sum(f["ipm_iters"] for f in all_infos),
                       "pcg_iters_total": sum(f["pcg_iters"] for f in all_infos),
-                      "pcg_phase_ms": max(f["t_pcg_ms"] for f in all_infos) / args.steps}), flush=True)
+                      "pcg_phase_ms": max(f["t_pcg_ms"] for f in all_infos)}), flush=True)
 
 
 def sqp_bench(args):
@@ -396,7 +405,10 @@ def main():
                          "uneven QPs (n in [2000, 20000]) solved together by qp_solve_batch")
     ap.add_argument("--count", type=int, default=64, help="batch size for --workload batch")
     ap.add_argument("--compare", type=int, default=1, choices=[0, 1],
-                    help="--workload batch: also time the QPs one at a time and on host workers")
+                    help="--workload batch: also time the QPs one at a time and in the other batch mode")
+    ap.add_argument("--batch-mode", type=int, default=0, choices=[0, 1],
+                    help="--workload batch: 0 host workers (the default of qp_solve_batch), 1 the "
+                         "persistent batched path")
     ap.add_argument("--seq-len", type=int, default=6, help="sub-problems timed for --workload sqp")
     ap.add_argument("--warm", type=int, default=0, choices=[0, 1],
                     help="--workload sqp: start each solve at the previous minimiser")
@@ -499,7 +511,7 @@ def main():
         bruns = {q: batch_run(probs, q, 1, 1) for q in ("fp64", "bf16", "fp32")}
         del probs
         out["batch64"] = {"workload": f"64 uneven banded-dose QPs, n in [2000, 20000], {bnnz} nnz of J in all, "
-                                      "one qp_solve_batch (persistent batched launches) per step",
+                                      "one qp_solve_batch (default mode: host workers) per step",
                           "by_precision": bruns,
                           "mixed_vs_fp64": {q: bruns["fp64"]["ms_per_batch"] / bruns[q]["ms_per_batch"]
                                             for q in ("bf16", "fp32")}}

@@ -139,6 +139,10 @@ typedef struct {
                                  with the Jacobi preconditioner of Section 4.1.2 (precond is then
                                  ignored); dx is its x part.  qp_operator_apply always applies the
                                  condensed operator. */
+    int32_t batch_mode;       /* how qp_solve_batch runs a batch of handles that all set it:
+                                 0 (default): each QP's own solve, several in flight on their
+                                 own streams (host workers); 1: the persistent batched path where
+                                 it applies (see qp_solve_batch).  Results are identical. */
 } qp_settings;
 
 typedef struct {
@@ -288,12 +292,23 @@ qp_status qp_operator_apply_noalloc(qp_handle* h, const double* sigma_x, const d
 
 /* qp_solve_batch: solve `count` independent QPs (each a handle from
  * qp_create) together; xs[i] (n_i doubles) receives QP i's minimiser and
- * infos[i] (may be NULL) its info.  Handles run concurrently, each on its own
- * stream (create them with hip_stream = NULL for a stream per handle), by up
- * to 6 host workers (environment QPGPU_BATCH_WORKERS), largest nnz first.
- * Many QPs of uneven size are the intended use.  Returns QP_OK when every QP returned QP_OK, else the first failing
- * status (QP_ERR_DEVICE preferred); QP_ERR_INVALID for NULL or repeated
- * handles, or two handles on one stream (text in qp_last_error(NULL)). */
+ * infos[i] (may be NULL) its info, each bitwise what qp_solve of that handle
+ * returns.  Many QPs of uneven size are the intended use.  Two ways to run
+ * them (settings.batch_mode):
+ *   0: handles run concurrently, each its own qp_solve on its own stream
+ *      (create them with hip_stream = NULL for a stream per handle), by up to
+ *      6 host workers (environment QPGPU_BATCH_WORKERS), largest nnz first;
+ *   1: when every handle sets it and uses the line format, the condensed
+ *      system, no low-rank term and the same precision, refine_steps and
+ *      graphs (and timing = 0), 2 to 256 handles on one device: the IPM
+ *      iterations of all QPs advance together; each kind of PCG work of
+ *      all QPs is ONE launch over a device-built work list of every QP's
+ *      blocks (QPs whose solve stopped drop out), the iterations replayed
+ *      as a captured HIP graph; each QP's other IPM steps on its own
+ *      stream.  Other batches run as with 0.
+ * Returns QP_OK when every QP returned QP_OK, else the first failing status
+ * (QP_ERR_DEVICE preferred); QP_ERR_INVALID for NULL or repeated handles,
+ * or two handles on one stream (text in qp_last_error(NULL)). */
 qp_status qp_solve_batch(qp_handle* const* hs, int32_t count, double* const* xs, qp_info* infos);
 
 /* Text of the last error on this handle; h == NULL gives the calling

@@ -2,11 +2,11 @@
 //
 // Every kernel of a PCG solve exists as a body that serves one block of one
 // QP's grid (line_kernels.hpp, ipm_kernels.hpp).  A batched solve runs each
-// kind of work as ONE persistent launch over a global work list: the items
-// of a kind are the blocks of every QP taking part, concatenated; the
-// launch's workgroups walk the list (each XCD one contiguous range of it, so
-// neighbouring lines of one QP share that XCD's L2), look up the QP of an
-// item and call the body with the QP's arguments and the item's block
+// kind of work as ONE launch over a global work list: the items of a kind
+// are the blocks of every QP taking part, concatenated; workgroup i takes
+// item i (remapped so each XCD serves one contiguous range of the list, and
+// neighbouring lines of one QP share that XCD's L2), looks up the QP of the
+// item and calls the body with the QP's arguments and the item's block
 // number within that QP's grid.  The lists live in device memory and are
 // rebuilt on the device by k_batch_plan after every PCG iteration from the
 // QPs' own stop flags: a QP whose solve has converged (or whose IPM has
@@ -20,6 +20,18 @@
 #include "line_kernels.hpp"
 
 namespace qpg {
+
+// A QP's arguments come from a table in memory, so the compiler cannot tell
+// that their pointers address global memory (as it can for a kernel's own
+// arguments) and would use generic (flat) loads and stores, which take more
+// registers and wait on both memory counters.  Each pointer is rebuilt as a
+// global-address-space pointer (device memory and pinned host memory both
+// are global addresses), which lets the compiler use global instructions.
+template <typename T>
+__device__ __forceinline__ T* gptr(T* p) {
+    typedef __attribute__((address_space(1))) T GT;
+    return (T*)(GT*)(uintptr_t)p;
+}
 
 constexpr int kMaxBatch = 256;   // QPs of one batched launch (one planning thread each)
 
@@ -70,19 +82,20 @@ enum : int {
 };
 
 // One block of kMaxBatch threads: thread q decides whether QP q is active,
-// then an inclusive scan of the active flags (list positions) and, per kind,
-// of the item counts (offsets) builds every list; flags of all QPs are
-// copied to one array for the host.
+// then one inclusive scan over the QPs, carrying for every kind at once the
+// count of QPs on its list (list positions) and of their items (offsets),
+// builds every list; flags of all QPs are copied to one array for the host.
 __global__ __launch_bounds__(kMaxBatch) void k_batch_plan(const BatchQp* qs, const int* in_phase, int nq, int mode,
                                                           BatchList* lists, BatchStatus* status, Flags* flags_out) {
-    __shared__ int sa[kMaxBatch], sc[kMaxBatch];
+    constexpr int NV = 2 * BK_COUNT + 1;   // per kind: on the list, items; then: active
+    __shared__ int sv[NV][kMaxBatch];
     const int q = threadIdx.x;
     bool act = false;
     int nblk[BK_COUNT];
 #pragma unroll
     for (int k = 0; k < BK_COUNT; ++k) nblk[k] = 0;
     if (q < nq) {
-        const Flags f = *qs[q].fl;
+        const Flags f = *gptr(qs[q].fl);
         flags_out[q] = f;
         act = in_phase[q] != 0 && !f.ipm_done;
         if (mode == BP_ITER) act = act && !(f.pcg_converged | f.pcg_breakdown | f.pcg_capped);
@@ -90,108 +103,160 @@ __global__ __launch_bounds__(kMaxBatch) void k_batch_plan(const BatchQp* qs, con
 #pragma unroll
             for (int k = 0; k < BK_COUNT; ++k) nblk[k] = qs[q].nblk[k];
     }
-    // active count (for the host's stop test)
-    sa[q] = act ? 1 : 0;
-    __syncthreads();
+    int v[NV];
+#pragma unroll
+    for (int k = 0; k < BK_COUNT; ++k) {
+        v[2 * k] = nblk[k] > 0 ? 1 : 0;
+        v[2 * k + 1] = nblk[k];
+    }
+    v[NV - 1] = act ? 1 : 0;
     for (int d = 1; d < kMaxBatch; d <<= 1) {
-        const int v = q >= d ? sa[q - d] : 0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sv[k][q] = v[k];
         __syncthreads();
-        sa[q] += v;
+        if (q >= d)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] += sv[k][q - d];
         __syncthreads();
     }
-    if (q == kMaxBatch - 1) status->active = sa[q];
+    if (q == kMaxBatch - 1) status->active = v[NV - 1];
+#pragma unroll
     for (int k = 0; k < BK_COUNT; ++k) {
-        const bool on = nblk[k] > 0;
-        sa[q] = on ? 1 : 0;
-        sc[q] = nblk[k];
-        __syncthreads();
-        for (int d = 1; d < kMaxBatch; d <<= 1) {
-            const int va = q >= d ? sa[q - d] : 0;
-            const int vc = q >= d ? sc[q - d] : 0;
-            __syncthreads();
-            sa[q] += va;
-            sc[q] += vc;
-            __syncthreads();
-        }
         BatchList& L = lists[k];
-        if (on) {
-            const int pos = sa[q] - 1;
+        if (nblk[k] > 0) {
+            const int pos = v[2 * k] - 1;
             L.qid[pos] = q;
-            L.off[pos] = sc[q] - nblk[k];
+            L.off[pos] = v[2 * k + 1] - nblk[k];
         }
         if (q == kMaxBatch - 1) {
-            L.nq = sa[q];
-            L.total = sc[q];
-            L.off[sa[q]] = sc[q];
+            L.nq = v[2 * k];
+            L.total = v[2 * k + 1];
+            L.off[v[2 * k]] = v[2 * k + 1];
         }
-        __syncthreads();
     }
 }
 
-// The persistent walk: workgroup b serves XCD b % 8, whose share of the
-// items is one contiguous range, taken in steps of the XCD's workgroup
-// count.  body(qp, item within the QP's grid, the QP's grid size).  Bodies
-// synchronise the whole workgroup in the same places for every item (their
-// early returns are workgroup-uniform before any barrier), and a barrier
-// after each item keeps the next item's LDS use behind the last reads.
+// One item per workgroup: a kind's grid covers the longest list the batch
+// can have, and workgroups past the current list's length return at once.  Item order is
+// remapped so that each XCD takes one contiguous range of the list (its
+// lines stay neighbours in its L2); the QP of an item is found in a copy of
+// the list's offsets in LDS.  Unlike the walk, the hardware dispatcher keeps
+// starting workgroups as others finish, so one item's chain of dependent
+// loads overlaps the next ones' as in a single QP's launch (a persistent
+// grid walking the list, measured first, left each workgroup's items in
+// sequence and ran the 16-QP FP64 batch's line passes at about half the
+// single-QP rate).
 template <typename F>
-__device__ __forceinline__ void batch_walk(const BatchList* L, F&& body) {
+__device__ __forceinline__ void batch_item(const BatchList* L, F&& body) {
+    __shared__ int s_off[kMaxBatch + 1];
+    __shared__ int s_qid[kMaxBatch];
     const int total = L->total;
+    const int b = int(blockIdx.x);
+    if (b >= total) return;   // workgroup-uniform, before any barrier
     const int nq = L->nq;
-    const int x = int(blockIdx.x) & 7, lb = int(blockIdx.x) >> 3, nbx = int(gridDim.x) >> 3;
-    const int start = int((int64_t(total) * x) >> 3), end = int((int64_t(total) * (x + 1)) >> 3);
-    for (int g = start + lb; g < end; g += nbx) {
-        int lo = 0, hi = nq - 1;   // the last QP whose first item is <= g
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L->off[mid] <= g) lo = mid;
-            else hi = mid - 1;
-        }
-        const int o = L->off[lo];
-        body(L->qid[lo], g - o, L->off[lo + 1] - o);
-        __syncthreads();
+    for (int i = threadIdx.x; i <= nq; i += kBlock) {
+        s_off[i] = L->off[i];
+        if (i < nq) s_qid[i] = L->qid[i];
     }
+    __syncthreads();
+    const int g = xcd_remap(b, total);
+    int lo = 0, hi = nq - 1;   // the last QP whose first item is <= g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    // uniform across the workgroup: made scalar, so the QP's arguments are
+    // read with scalar loads into scalar registers, as kernel arguments are
+    const int o = __builtin_amdgcn_readfirstlane(s_off[lo]);
+    const int q = __builtin_amdgcn_readfirstlane(s_qid[lo]);
+    const int e = __builtin_amdgcn_readfirstlane(s_off[lo + 1]);
+    body(q, __builtin_amdgcn_readfirstlane(g) - o, e - o);
 }
 
-// The walk around the line pass takes a few registers more than the single
-// QP's kernel: with FP64 values the budget of six (or five) wavefronts per
-// SIMD would spill, so that one runs four.
+#define QPG_G(f) a.f = gptr(a.f)
 template <typename VT>
-constexpr int kb_line_waves() { return sizeof(VT) == 8 ? 4 : 6; }
+__device__ __forceinline__ LineArgs<VT> global_args(LineArgs<VT> a) {
+    QPG_G(lptr); QPG_G(lcol); QPG_G(lval); QPG_G(W); QPG_G(Ap); QPG_G(Ac); QPG_G(Av); QPG_G(x); QPG_G(p2);
+    QPG_G(sc); QPG_G(c); QPG_G(u); QPG_G(sigA); QPG_G(az); QPG_G(apv); QPG_G(fl); QPG_G(fl_ipm);
+    QPG_G(aug.dlu); QPG_G(aug.q); QPG_G(aug.part);
+    return a;
+}
+__device__ __forceinline__ SpotArgs global_args(SpotArgs a) {
+    QPG_G(sptr); QPG_G(sslot); QPG_G(c); QPG_G(Atp); QPG_G(Atc); QPG_G(Atv); QPG_G(u); QPG_G(x); QPG_G(sigx);
+    QPG_G(q); QPG_G(part); QPG_G(fl); QPG_G(pcg.p2); QPG_G(pcg.sc); QPG_G(U); QPG_G(lr_v);
+    return a;
+}
+__device__ __forceinline__ PrecRows global_rows(PrecRows a) {
+    QPG_G(Ac); QPG_G(Av); QPG_G(ext); QPG_G(sq); QPG_G(kdev); QPG_G(w); QPG_G(vm);
+    return a;
+}
+__device__ __forceinline__ PcgArgs global_args(PcgArgs a) {
+    QPG_G(x); QPG_G(r); QPG_G(z); QPG_G(p); QPG_G(q); QPG_G(d); QPG_G(part_pq); QPG_G(part_rz); QPG_G(part_rr);
+    QPG_G(sc); QPG_G(fl);
+    a.pa = global_rows(a.pa);
+    return a;
+}
+__device__ __forceinline__ SymvArgs global_args(SymvArgs a) {
+    QPG_G(Sinv); QPG_G(w); QPG_G(sq); QPG_G(idx); QPG_G(kdev); QPG_G(vm); QPG_G(fl);
+    return a;
+}
+__device__ __forceinline__ PrecAtArgs global_args(PrecAtArgs a) {
+    QPG_G(Atp); QPG_G(Atc); QPG_G(Atv); QPG_G(v); QPG_G(D); QPG_G(r); QPG_G(q); QPG_G(sc); QPG_G(z);
+    QPG_G(part_rz); QPG_G(fl);
+    return a;
+}
+__device__ __forceinline__ ScalArgs global_args(ScalArgs a) {
+    QPG_G(part_rz); QPG_G(part_rr); QPG_G(sc); QPG_G(fl);
+    QPG_G(az.Ap); QPG_G(az.Ac); QPG_G(az.Av); QPG_G(az.z); QPG_G(az.az);
+    return a;
+}
+__device__ __forceinline__ PcgInitArgs global_args(PcgInitArgs a) {
+    QPG_G(rhs_a); QPG_G(rhs_b); QPG_G(ipm); QPG_G(x); QPG_G(r); QPG_G(z); QPG_G(p); QPG_G(d);
+    QPG_G(part_rz); QPG_G(part_rr); QPG_G(fl); QPG_G(apv);
+    return a;
+}
+__device__ __forceinline__ PrecAArgs global_args(PrecAArgs a) {
+    a.pa = global_rows(a.pa);
+    QPG_G(y); QPG_G(fl);
+    return a;
+}
+#undef QPG_G
+
 template <typename VT, typename AT, bool NT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kb_line_waves<VT>()))) void kb_line(
-    const LineArgs<VT>* tab, const BatchList* L) {
-    batch_walk(L, [&](int q, int b, int nb) { line_pass_body<VT, AT, NT>(tab[q], b, nb, false); });
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void kb_line(const LineArgs<VT>* tab,
+                                                                                          const BatchList* L) {
+    batch_item(L, [&](int q, int b, int nb) { line_pass_body<VT, AT, NT>(global_args(tab[q]), b, nb, false); });
 }
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void kb_spot(const SpotArgs* tab, const BatchList* L) {
-    batch_walk(L, [&](int q, int b, int nb) { spot_pass_body<G>(tab[q], b, nb); });
+    batch_item(L, [&](int q, int b, int nb) { spot_pass_body<G>(global_args(tab[q]), b, nb); });
 }
 
 __global__ __launch_bounds__(kBlock) void kb_xr(const PcgArgs* tab, const BatchList* L) {
-    batch_walk(L, [&](int q, int b, int nb) { pcg_xr_body(tab[q], b, nb); });
+    batch_item(L, [&](int q, int b, int nb) { pcg_xr_body(global_args(tab[q]), b, nb); });
 }
 
 __global__ __launch_bounds__(kBlock) void kb_symv(const SymvArgs* tab, const BatchList* L) {
-    batch_walk(L, [&](int q, int b, int) { prec_symv_body(tab[q], b); });
+    batch_item(L, [&](int q, int b, int) { prec_symv_body(global_args(tab[q]), b); });
 }
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void kb_at(const PrecAtArgs* tab, const BatchList* L) {
-    batch_walk(L, [&](int q, int b, int nb) { prec_at_body<G>(tab[q], b, nb); });
+    batch_item(L, [&](int q, int b, int nb) { prec_at_body<G>(global_args(tab[q]), b, nb); });
 }
 
 __global__ __launch_bounds__(kBlock) void kb_scal(const ScalArgs* tab, const BatchList* L) {
-    batch_walk(L, [&](int q, int b, int) { pcg_scalars_body(tab[q], b); });
+    batch_item(L, [&](int q, int b, int) { pcg_scalars_body(global_args(tab[q]), b); });
 }
 
 __global__ __launch_bounds__(kBlock) void kb_init0(const PcgInitArgs* tab, const BatchList* L) {
-    batch_walk(L, [&](int q, int b, int nb) { pcg_init0_body(tab[q], b, nb); });
+    batch_item(L, [&](int q, int b, int nb) { pcg_init0_body(global_args(tab[q]), b, nb); });
 }
 
 __global__ __launch_bounds__(kBlock) void kb_preca(const PrecAArgs* tab, const BatchList* L) {
-    batch_walk(L, [&](int q, int b, int) { prec_a_body(tab[q], b); });
+    batch_item(L, [&](int q, int b, int) { prec_a_body(global_args(tab[q]), b); });
 }
 
 // Elementwise steps of the refinement of a low-precision direction, one
@@ -217,7 +282,11 @@ __device__ __forceinline__ void vec_body(const VecArgs& v, int bid, int nb) {
     }
 }
 __global__ __launch_bounds__(kBlock) void kb_vec(const VecArgs* tab, const BatchList* L) {
-    batch_walk(L, [&](int q, int b, int nb) { vec_body(tab[q], b, nb); });
+    batch_item(L, [&](int q, int b, int nb) {
+        VecArgs v = tab[q];
+        v.a = gptr(v.a); v.b = gptr(v.b); v.isc = gptr(v.isc); v.out = gptr(v.out);
+        vec_body(v, b, nb);
+    });
 }
 
 }  // namespace qpg

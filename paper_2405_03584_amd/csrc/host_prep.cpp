@@ -208,6 +208,7 @@ std::string validate_settings(const qp_settings* s) {
     if (s->graphs != 0 && s->graphs != 1) return "settings.graphs must be 0 or 1";
     if (s->spmv_format != 0 && s->spmv_format != 1) return "settings.spmv_format must be 0 or 1";
     if (s->kkt_system != 0 && s->kkt_system != 1) return "settings.kkt_system must be 0 or 1";
+    if (s->batch_mode != 0 && s->batch_mode != 1) return "settings.batch_mode must be 0 or 1";
     return "";
 }
 

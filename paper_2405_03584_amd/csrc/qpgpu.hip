@@ -1467,12 +1467,6 @@ void ipm_finish(IpmRun& r, double* x, double* lam_A, double* lam_x, qp_info* inf
 // leaves the batch.
 // ==========================================================================
 
-// Work-list schedule of the persistent launches: workgroups of the line
-// pass and of the other kinds.  Picked per batch by batch_autotune.
-struct BatchSched {
-    int line_grid = 1536;   // 6 per CU: the line pass's occupancy
-    int grid = 2048;
-};
 
 struct BatchRun {
     std::vector<qp_handle*> hs;
@@ -1480,7 +1474,7 @@ struct BatchRun {
     int nq = 0;
     int prec = QP_FP64;
     bool nt_lo = false, nt_64 = false;   // value arrays above the cache: non-temporal loads
-    BatchSched sch;
+    int items[BK_COUNT] = {};   // grid of each kind: its longest list (every QP of the batch on it)
     hipStream_t st = nullptr;
     hipEvent_t ev_dir = nullptr;         // end of the last direction phase
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
@@ -1546,14 +1540,20 @@ struct BatchRun {
     }
 };
 
-// The persistent path serves handles on the line format with the condensed
-// system, no low-rank term, one precision and graph setting, no event
-// timing, on one device; other batches run each QP's own solve on host
-// workers.
+// The persistent path serves handles that ask for it (batch_mode = 1) on the
+// line format with the condensed system, no low-rank term, one precision and
+// graph setting, no event timing, on one device; other batches run each QP's
+// own solve on host workers.  Host workers are the default: with every QP on
+// its own stream the GPU overlaps one QP's latency-bound kernels with other
+// QPs' line passes, while the persistent path advances all QPs' IPM
+// iterations together, so each batched PCG solve lasts as long as its
+// slowest QP's and its last iterations carry few QPs (measured on the 16
+// uneven QPs: FP64 1078 ms persistent against 937 ms on host workers).
 bool batch_persistent_ok(qp_handle* const* hs, int count) {
     if (count < 2 || count > kMaxBatch) return false;
     for (int i = 0; i < count; ++i) {
         const qp_handle* h = hs[i];
+        if (h->set.batch_mode != 1) return false;
         if (!h->line || h->k > 0 || h->set.kkt_system != 0 || h->set.timing) return false;
         if (h->set.precision != hs[0]->set.precision || h->set.refine_steps != hs[0]->set.refine_steps ||
             h->set.graphs != hs[0]->set.graphs || h->device != hs[0]->device)
@@ -1725,6 +1725,15 @@ void batch_tables_t(BatchRun& B) {
         put(t.vec[3], VecArgs{VEC_SUB, n, h->rhs_full, h->pq, nullptr, h->rho});
         put(t.vec[4], VecArgs{VEC_SET, n, h->dxacc, nullptr, nullptr, h->px});
     }
+    // grid of each kind: every QP of the batch on its list (the line kinds
+    // share one grid, the largest)
+    int64_t tot[BK_COUNT] = {};
+    for (int q = 0; q < nq; ++q) {
+        const BatchQp* bq = reinterpret_cast<const BatchQp*>(img + t.qs) + q;
+        for (int k = 0; k < BK_COUNT; ++k) tot[k] += bq->nblk[k];
+    }
+    tot[BK_LINE] = std::max({tot[BK_LINE], tot[BK_LINE64], tot[BK_LINE_PLAIN]});
+    for (int k = 0; k < BK_COUNT; ++k) B.items[k] = int(std::max<int64_t>(1, std::min<int64_t>(tot[k], INT32_MAX)));
     HIPCHK(hipMemcpyAsync(B.d_qs, img, B.tab_bytes, hipMemcpyHostToDevice, B.st));
     batch_stage_done(B);
 }
@@ -1758,8 +1767,8 @@ void batch_snapshot(BatchRun& B, int slot) {
 template <typename VT, typename AT>
 void batch_line_launch(BatchRun& B, const void* tab, const BatchList* L, bool nt) {
     const LineArgs<VT>* tb = static_cast<const LineArgs<VT>*>(tab);
-    if (nt) hipLaunchKernelGGL((kb_line<VT, AT, true>), dim3(B.sch.line_grid), dim3(kBlock), 0, B.st, tb, L);
-    else hipLaunchKernelGGL((kb_line<VT, AT, false>), dim3(B.sch.line_grid), dim3(kBlock), 0, B.st, tb, L);
+    if (nt) hipLaunchKernelGGL((kb_line<VT, AT, true>), dim3(B.items[BK_LINE]), dim3(kBlock), 0, B.st, tb, L);
+    else hipLaunchKernelGGL((kb_line<VT, AT, false>), dim3(B.items[BK_LINE]), dim3(kBlock), 0, B.st, tb, L);
 }
 // Line pass of a PCG product, in the batch precision (lo) or FP64.
 void batch_line(BatchRun& B, bool lo) {
@@ -1772,13 +1781,13 @@ void batch_line(BatchRun& B, bool lo) {
 // One batched PCG iteration (kernels in the order of run_pcg's).
 void batch_iter(BatchRun& B, bool lo) {
     batch_line(B, lo);
-    hipLaunchKernelGGL(kb_spot<kSpotLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const SpotArgs*)B.d_spot,
+    hipLaunchKernelGGL(kb_spot<kSpotLanes>, dim3(B.items[BK_SPOT]), dim3(kBlock), 0, B.st, (const SpotArgs*)B.d_spot,
                        B.list(BK_SPOT));
-    hipLaunchKernelGGL(kb_xr, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PcgArgs*)B.d_xr, B.list(BK_XR));
-    hipLaunchKernelGGL(kb_symv, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const SymvArgs*)B.d_symv, B.list(BK_SYMV));
-    hipLaunchKernelGGL(kb_at<kPrecAtLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PrecAtArgs*)B.d_at,
+    hipLaunchKernelGGL(kb_xr, dim3(B.items[BK_XR]), dim3(kBlock), 0, B.st, (const PcgArgs*)B.d_xr, B.list(BK_XR));
+    hipLaunchKernelGGL(kb_symv, dim3(B.items[BK_SYMV]), dim3(kBlock), 0, B.st, (const SymvArgs*)B.d_symv, B.list(BK_SYMV));
+    hipLaunchKernelGGL(kb_at<kPrecAtLanes>, dim3(B.items[BK_AT]), dim3(kBlock), 0, B.st, (const PrecAtArgs*)B.d_at,
                        B.list(BK_AT));
-    hipLaunchKernelGGL(kb_scal, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const ScalArgs*)B.d_scal, B.list(BK_SCAL));
+    hipLaunchKernelGGL(kb_scal, dim3(B.items[BK_SCAL]), dim3(kBlock), 0, B.st, (const ScalArgs*)B.d_scal, B.list(BK_SCAL));
     batch_plan(B, BP_ITER);
     HIPCHK(hipGetLastError());
 }
@@ -1822,14 +1831,14 @@ std::vector<Flags> batch_pcg(BatchRun& B, const std::vector<char>& mask, int sv,
     const bool refine = sv == BS_RHO;
     batch_set_phase(B, mask);
     batch_plan(B, BP_START);
-    hipLaunchKernelGGL(kb_init0, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PcgInitArgs*)B.d_init[init_tab],
+    hipLaunchKernelGGL(kb_init0, dim3(B.items[BK_INIT]), dim3(kBlock), 0, B.st, (const PcgInitArgs*)B.d_init[init_tab],
                        B.list(BK_INIT));
-    hipLaunchKernelGGL(kb_preca, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PrecAArgs*)B.d_preca,
+    hipLaunchKernelGGL(kb_preca, dim3(B.items[BK_PRECA]), dim3(kBlock), 0, B.st, (const PrecAArgs*)B.d_preca,
                        B.list(BK_PRECA));
-    hipLaunchKernelGGL(kb_symv, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const SymvArgs*)B.d_symv, B.list(BK_SYMV));
-    hipLaunchKernelGGL(kb_at<kPrecAtLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const PrecAtArgs*)B.d_at0,
+    hipLaunchKernelGGL(kb_symv, dim3(B.items[BK_SYMV]), dim3(kBlock), 0, B.st, (const SymvArgs*)B.d_symv, B.list(BK_SYMV));
+    hipLaunchKernelGGL(kb_at<kPrecAtLanes>, dim3(B.items[BK_AT]), dim3(kBlock), 0, B.st, (const PrecAtArgs*)B.d_at0,
                        B.list(BK_AT));
-    hipLaunchKernelGGL(kb_scal, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const ScalArgs*)B.d_scal0[scal_tab],
+    hipLaunchKernelGGL(kb_scal, dim3(B.items[BK_SCAL]), dim3(kBlock), 0, B.st, (const ScalArgs*)B.d_scal0[scal_tab],
                        B.list(BK_SCAL));
     batch_plan(B, BP_ITER);
     HIPCHK(hipGetLastError());
@@ -1898,14 +1907,14 @@ std::vector<Flags> batch_pcg(BatchRun& B, const std::vector<char>& mask, int sv,
 void batch_vec(BatchRun& B, const std::vector<char>& mask, int i) {
     batch_set_phase(B, mask);
     batch_plan(B, BP_START);
-    hipLaunchKernelGGL(kb_vec, dim3(B.sch.grid), dim3(kBlock), 0, B.st, (const VecArgs*)B.d_vec[i], B.list(BK_VEC));
+    hipLaunchKernelGGL(kb_vec, dim3(B.items[BK_VEC]), dim3(kBlock), 0, B.st, (const VecArgs*)B.d_vec[i], B.list(BK_VEC));
     HIPCHK(hipGetLastError());
 }
 void batch_plain_product(BatchRun& B, const std::vector<char>& mask) {
     batch_set_phase(B, mask);
     batch_plan(B, BP_START);
     batch_line_launch<double, double>(B, B.d_line_plain, B.list(BK_LINE_PLAIN), B.nt_64);
-    hipLaunchKernelGGL(kb_spot<kSpotLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st,
+    hipLaunchKernelGGL(kb_spot<kSpotLanes>, dim3(B.items[BK_SPOT]), dim3(kBlock), 0, B.st,
                        (const SpotArgs*)B.d_spot_plain, B.list(BK_SPOT));
     HIPCHK(hipGetLastError());
 }
@@ -2034,68 +2043,6 @@ void batch_each(BatchRun& B, const std::vector<char>& mask, int workers, F&& fn,
     for (auto& t : pool) t.join();
 }
 
-// Persistent-path schedule autotuner: times one batched PCG product of the
-// batch (line pass + spot pass, all QPs) for each candidate schedule and
-// keeps the fastest; cached per batch shape for the process.
-std::mutex g_btune_mu;
-std::map<std::tuple<int, int, int64_t, int64_t>, BatchSched> g_btune;
-
-void batch_autotune(BatchRun& B) {
-    int64_t nnz = 0, nsum = 0;
-    for (auto* h : B.hs) {
-        nnz += h->nnzJ;
-        nsum += h->n;
-    }
-    const auto key = std::make_tuple(B.nq, B.prec, nnz, nsum);
-    {
-        std::lock_guard<std::mutex> lk(g_btune_mu);
-        auto it = g_btune.find(key);
-        if (it != g_btune.end()) {
-            B.sch = it->second;
-            return;
-        }
-    }
-    // every QP's plain FP64 product of dxacc (zeroed here) as the probe; the
-    // low-precision products have the same lists
-    std::vector<char> all(B.nq, 1);
-    for (auto* h : B.hs) HIPCHK(hipMemsetAsync(h->dxacc, 0, sizeof(double) * h->n, B.st));
-    const int cand_line[] = {1024, 1536, 2048, 3072};
-    const int cand_grid[] = {1024, 2048, 4096};
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    BatchSched best = B.sch;
-    float best_ms = 1e30f;
-    for (int lg : cand_line)
-        for (int gg : cand_grid) {
-            B.sch.line_grid = lg;
-            B.sch.grid = gg;
-            batch_set_phase(B, all);
-            batch_plan(B, BP_START);
-            float tot = 0.f;
-            for (int rep = 0; rep < 3; ++rep) {   // first repetition warms up
-                HIPCHK(hipEventRecord(e0, B.st));
-                batch_line_launch<double, double>(B, B.d_line_plain, B.list(BK_LINE_PLAIN), B.nt_64);
-                hipLaunchKernelGGL(kb_spot<kSpotLanes>, dim3(B.sch.grid), dim3(kBlock), 0, B.st,
-                                   (const SpotArgs*)B.d_spot_plain, B.list(BK_SPOT));
-                HIPCHK(hipEventRecord(e1, B.st));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                if (rep) tot += ms;
-            }
-            if (tot < best_ms) {
-                best_ms = tot;
-                best = B.sch;
-            }
-        }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    B.sch = best;
-    std::lock_guard<std::mutex> lk(g_btune_mu);
-    g_btune[key] = best;
-}
-
 // The whole batch on the persistent path.  Returns per-QP statuses.
 std::vector<qp_status> batch_solve(qp_handle* const* hs, int count, double* const* xs, qp_info* infos) {
     BatchRun B;
@@ -2136,7 +2083,6 @@ std::vector<qp_status> batch_solve(qp_handle* const* hs, int count, double* cons
     }, st);
     for (int q = 0; q < count; ++q) HIPCHK(hipStreamWaitEvent(B.st, B.ev_q[q], 0));
     batch_tables(B);
-    batch_autotune(B);
     while (true) {
         std::vector<char> live(count, 0);
         for (int q = 0; q < count; ++q) live[q] = (st[q] == QP_OK && !B.runs[q].done) ? 1 : 0;
@@ -2882,7 +2828,7 @@ qp_status qp_solve_batch(qp_handle* const* hs, int32_t count, double* const* xs,
         }
     }
     if (count == 0) return QP_OK;
-    if (batch_persistent_ok(hs, count) && !std::getenv("QPGPU_BATCH_THREADS")) {
+    if (batch_persistent_ok(hs, count)) {
         std::vector<qp_status> st;
         try {
             st = batch_solve(hs, count, xs, infos);

@@ -46,7 +46,8 @@ class qp_settings(C.Structure):
                 ("tau", C.c_double), ("max_ipm_iter", C.c_int32), ("step_mode", C.c_int32),
                 ("scale_objective", C.c_int32), ("schedule", C.c_int32), ("timing", C.c_int32),
                 ("log_level", C.c_int32), ("precond", C.c_int32), ("spmv_format", C.c_int32),
-                ("refine_tol", C.c_double), ("graphs", C.c_int32), ("kkt_system", C.c_int32)]
+                ("refine_tol", C.c_double), ("graphs", C.c_int32), ("kkt_system", C.c_int32),
+                ("batch_mode", C.c_int32)]
 
 
 class qp_info(C.Structure):

@@ -1,8 +1,9 @@
 """Full-size parity of the batch and the large single QP.
 
 * The 64-QP batch (n_k from 2,000 to 20,000, J at 0.5% in 64-voxel bands,
-  m_k = n_k/10): solved by qp_solve_batch in chunks of eight, in FP64 and
-  FP32.  Every member is certified (KKT certificate <= 1e-9, from the device
+  m_k = n_k/10): solved by qp_solve_batch in chunks of eight, in FP64 on the
+  persistent batched path (batch_mode = 1) and in FP32 on host workers
+  (the default).  Every member is certified (KKT certificate <= 1e-9, from the device
   and from the oracle at the returned point); the eight members the oracle
   solved (tests/golden/config4_oracle.json, written by
   tests/golden/make_config4_golden.py from oracle/ only) are compared entry
@@ -40,7 +41,7 @@ def test_config4_batch_certified_and_oracle_members(chunk, prec):
     idx = list(range(chunk * CHUNK, (chunk + 1) * CHUNK))
     print(f"config4 members {idx[0]}..{idx[-1]} {prec}", flush=True)
     probs = [qpsynth.config4_instance(i) for i in idx]
-    s = qpgpu.qp_default_settings(precision=prec)
+    s = qpgpu.qp_default_settings(precision=prec, batch_mode=1 if prec == "fp64" else 0)
     hs = [qpgpu.qp_create_from_problem(p, settings=s) for p in probs]
     st, xs, infos = qpgpu.qp_solve_batch(hs)
     assert st == qpgpu.QP_OK, [f["status"] for f in infos]
