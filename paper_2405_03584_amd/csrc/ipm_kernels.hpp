@@ -179,7 +179,7 @@ __device__ __forceinline__ void stream_stage(const FwdArgs<VT>& a, const Gather&
     }
 }
 template <typename VT, typename AT>
-__global__ __launch_bounds__(kBlock) void k_op_fwd_stream(FwdArgs<VT> a, const int2* rb) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_op_fwd_stream(FwdArgs<VT> a, const int2* rb) {
     __shared__ AT prod[kStreamNnz];
     __shared__ int rp[kStreamRows + 1];
     __shared__ double wl[kStreamRows];
