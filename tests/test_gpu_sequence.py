@@ -133,6 +133,37 @@ def test_stalled_constraint_block_solve_falls_back_to_the_capped_block():
     check_certificate(q, res)
 
 
+def test_newton_step_at_a_late_iterate_repeats_with_the_next_tier():
+    """qp_newton_step at a late oracle iterate of the second ragged-lines
+    sub-problem (its IPM stopped at mu_tol = 1e-9; Sigma = lambda/s of every
+    bound and row; no objective scaling, so the system is zeta times the
+    IPM's scaled one, condition number about 2e15): the exact constraint
+    block breaks down there, the step is repeated with the next tier
+    (qp_info.prec_fallbacks, prec_tier), and the direction's residual is as
+    small as the dense LU solve of the same system achieves."""
+    q = qpsynth.sqp_sequence(qpsynth.ragged_lines(), 2)[1]
+    ref = oracle.solve(q, oracle.OracleSettings(mu_tol=1e-9))
+    G = oracle.make_groups(q)
+    sx = np.zeros(q.n)
+    sA = np.zeros(q.m)
+    for g in oracle.GROUPS:
+        idx = G.idx[g]
+        if len(idx) == 0:
+            continue
+        np.add.at(sx if g in ("lx", "ux") else sA, idx, ref.lam[g] / ref.s[g])
+    rhs = np.random.default_rng(404).standard_normal(q.n)
+    K = oracle.condensed_operator_dense(q, sx, sA)
+    res_lu = np.linalg.norm(K @ oracle.newton_solve_dense(K, rhs) - rhs) / np.linalg.norm(rhs)
+    h = qpgpu.qp_create_from_problem(q, settings=qpgpu.qp_default_settings(pcg_tol=1e-10))
+    st, dx, info = qpgpu.qp_newton_step(h, sx, sA, rhs)
+    res = np.linalg.norm(K @ dx - rhs) / np.linalg.norm(rhs)
+    print(f"newton step: status {st} pcg {info['pcg_iters']} fallbacks {info['prec_fallbacks']} "
+          f"tier {info['prec_tier']} residual {res:.1e} (dense LU {res_lu:.1e})", flush=True)
+    assert st == qpgpu.QP_OK, info
+    assert info["prec_fallbacks"] >= 1 and info["prec_tier"] >= 1
+    assert res <= max(1e-6, 30.0 * res_lu)
+
+
 def test_batch_of_updated_handles():
     """qp_solve_batch over handles whose objectives were replaced: each QP's
     bits equal its own qp_solve's, and its minimiser is the oracle's."""
