@@ -249,7 +249,7 @@ qp_status qp_solve_from(qp_handle* h, const double* x0, double* x, double* lam_A
 qp_status qp_update_hessian(qp_handle* h, const qp_hessian* H);
 
 /* qp_newton_step: one PCG solve of (H + diag(sigma_x) + A^T diag(sigma_A) A) dx = rhs
- * (the system of Algorithm 1's second line in condensed form) with the
+ * (the Newton system of Algorithm 1 in condensed form) with the
  * handle's precision and refinement settings and no objective scaling.
  *   sigma_x (n) >= 0, sigma_A (m) >= 0 (may be NULL when m = 0), rhs (n),
  *   dx (n) output.  Returns QP_OK, QP_ERR_NOT_CONVERGED (pcg_max_iter hit;

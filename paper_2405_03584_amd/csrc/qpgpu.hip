@@ -1309,7 +1309,7 @@ void harvest_pcg_ms(IpmRun& r, int slot) {
     r.pcg_timed[slot] = false;
 }
 
-// The Newton direction of the current iterate (Algorithm 1, first line) into
+// The Newton direction of the current iterate (the PCG solve of Algorithm 1) into
 // h->px, repeated with the Jacobi diagonal when a constraint-block solve
 // stalls.
 Flags ipm_direction(IpmRun& r, int* nsolves) {
@@ -1368,9 +1368,8 @@ bool ipm_after_direction(IpmRun& r, const Flags& f, int nsolves) {
     return true;
 }
 
-// Recovery of ds and dlambda, the ratio test, the update (Algorithm 1,
-// lines 2-6), then the residual pass, the barrier rule and the next
-// preconditioner.
+// Recovery of ds and dlambda, the ratio test and the update of Algorithm 1,
+// then the residual pass, the barrier rule and the next preconditioner.
 void ipm_step(IpmRun& r) {
     qp_handle* h = r.h;
     IpmVec& v = h->iv;

@@ -1,7 +1,9 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Bars (derived in the design doc):
-* operator y = K v in FP64: |y - y_ref|_i <= 1e-12 * (|K| |v|)_i;
+Bars (each from the rounding of the arithmetic it checks):
+* operator y = K v in FP64: |y - y_ref|_i <= 1e-12 * (|K| |v|)_i (FP64
+  summation of rows of at most 2048 terms errs by at most 2048 * 2^-53 of
+  (|K| |v|)_i per pass);
 * low-precision operator: |y - y_ref|_i <= c_p * (|K| |v|)_i with c_p from the
   value rounding (2^-24 FP32, 2^-8 BF16) plus FP32 accumulation over the row;
 * Newton step (PCG, tol 1e-10): ||K dx - rhs|| <= 1.01e-10 ||rhs|| (up to
