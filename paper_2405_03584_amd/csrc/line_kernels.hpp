@@ -208,7 +208,12 @@ __device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, in
         AT hv[RH];
         if (kh < k1) {
             const double pl = g(col[min(kh + (lane & (RH - 1)), k1 - 1)]);
-            const int plo = __double2loint(pl), phi = __double2hiint(pl);
+            // FP32 accumulation: each lane rounds its gathered value to float
+            // once, so a slot costs one 32-bit broadcast and no conversion
+            // (the same float as converting the broadcast double)
+            constexpr bool kF = sizeof(AT) == 4;
+            const int plo = kF ? __float_as_int(float(pl)) : __double2loint(pl);
+            const int phi = kF ? 0 : __double2hiint(pl);
 #pragma unroll
             for (int j = 0; j < RH / P; ++j) {
                 AT gv[P];
@@ -219,9 +224,13 @@ __device__ __forceinline__ void line_pass_body(const LineArgs<VT>& a, int bi, in
             AT a2[2] = {AT(0), AT(0)};   // two chains, no product array
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
-                const double xv = __hiloint2double(__builtin_amdgcn_readlane(phi, i),
-                                                   __builtin_amdgcn_readlane(plo, i));
-                a2[i & 1] = fma(hv[i], AT(xv), a2[i & 1]);
+                AT xv;
+                if constexpr (kF) {
+                    xv = __int_as_float(__builtin_amdgcn_readlane(plo, i));
+                } else {
+                    xv = AT(__hiloint2double(__builtin_amdgcn_readlane(phi, i), __builtin_amdgcn_readlane(plo, i)));
+                }
+                a2[i & 1] = fma(hv[i], xv, a2[i & 1]);
             }
             acc += a2[0] + a2[1];
         } else {
