@@ -617,7 +617,7 @@ bool build_precond(qp_handle* h, const double* D, const double* sigA, const int*
     hipLaunchKernelGGL(k_gj_pivot0, dim3(1), dim3(256), 0, h->stream, (const double*)h->Sm, ld, Pb[0], stop);
     const int gx = (T + 1) / 2;
     for (int b = 0; b < T; ++b)
-        hipLaunchKernelGGL(k_gj_step, dim3(gx * gx + (b + 1 < T ? 1 : 0)), dim3(256), 0, h->stream,
+        hipLaunchKernelGGL(k_gj_step, dim3(gx * (gx + 1) / 2 + (b + 1 < T ? 1 : 0)), dim3(256), 0, h->stream,
                            (const double*)Sb[b & 1],
                            Sb[(b + 1) & 1], ld, T, b, (const double*)Pb[b & 1], Pb[(b + 1) & 1], stop);
     const double* Sfin = Sb[T & 1];

@@ -427,7 +427,8 @@ __device__ __forceinline__ void tile_step(const double* __restrict__ So, int ld,
 // Pivot step b: So (matrix after step b-1) -> Sn; Pin = S_bb^{-1} in both
 // operand layouts.  When b+1 < T, workgroup 0 (dispatched first) recomputes
 // only tile (b+1, b+1) and writes its inverse to Pout; workgroups 1.. each
-// update a 2 x 2 group of tiles, a wavefront per tile.
+// update a 2 x 2 group of tiles of the lower triangle (and its mirror), a
+// wavefront per tile.  Grid: 1 + gx(gx+1)/2 workgroups, gx = (T+1)/2.
 __global__ __launch_bounds__(256) void k_gj_step(const double* __restrict__ So, double* __restrict__ Sn, int ld,
                                                  int T, int b, const double* __restrict__ Pin,
                                                  double* __restrict__ Pout, const int* stop) {
@@ -453,9 +454,17 @@ __global__ __launch_bounds__(256) void k_gj_step(const double* __restrict__ So, 
         store_pivot(piv, Pout);
         return;
     }
-    const int gx = (T + 1) / 2;
+    // Groups of the lower triangle only (by >= bx, L = by(by+1)/2 + bx): the
+    // sweep keeps S symmetric up to sign -- with K the blocks swept so far
+    // (0..b after this step), S_ji = -S_ij^T when exactly one of i, j is in K,
+    // else S_ji = S_ij^T -- so a group below the diagonal computes its four
+    // tiles (all with i > j) and writes each also transposed, with that sign,
+    // to (j, i); groups on the diagonal compute all four tiles.
     const int L = int(blockIdx.x) - lead;
-    const int by = L / gx, bx = L % gx;
+    int by = int((sqrt(8.0 * L + 1.0) - 1.0) * 0.5);
+    while ((by + 1) * (by + 2) / 2 <= L) ++by;
+    while (by * (by + 1) / 2 > L) --by;
+    const int bx = L - by * (by + 1) / 2;
     const int i = 2 * by + (w >> 1), j = 2 * bx + (w & 1);
     if (i >= T || j >= T) return;    // whole wavefronts; no barrier follows
     f64x4 o[2][2];
@@ -467,6 +476,17 @@ __global__ __launch_bounds__(256) void k_gj_step(const double* __restrict__ So, 
         for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) dst[size_t(res_row(ra, l, r)) * ld + res_col(cb, l)] = o[ra][cb][r];
+    if (by != bx) {
+        const double sg = (j <= b && b < i) ? -1.0 : 1.0;
+        double* dtr = Sn + size_t(j) * TS * ld + size_t(i) * TS;
+#pragma unroll
+        for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    dtr[size_t(res_col(cb, l)) * ld + res_row(ra, l, r)] = sg * o[ra][cb][r];
+    }
 }
 
 // Sinv = (S + S^T)/2: the sweep's result is symmetric up to rounding; PCG
