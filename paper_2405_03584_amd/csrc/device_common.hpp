@@ -85,6 +85,24 @@ template <> __device__ __forceinline__ double cvt<double, bf16_t>(bf16_t v) { re
 template <> __device__ __forceinline__ float cvt<float, float>(float v) { return v; }
 template <> __device__ __forceinline__ float cvt<float, bf16_t>(bf16_t v) { return to_f32(v); }
 
+// Loads of matrix values and column ids that are read once per product.
+// When the arrays streamed by one product are larger than the last-level
+// cache (MI355X: 256 MB Infinity Cache), cycling them through the caches
+// only evicts what is reused (the gathered vectors, W, the per-row or
+// per-slot sums), so such arrays are read with non-temporal loads
+// (NT = true); smaller arrays stay cacheable, and then stay resident between
+// products.
+template <bool NT, typename T>
+__device__ __forceinline__ T load_val(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ bf16_t load_val(const bf16_t* p) {
+    if constexpr (NT) return bf16_t{__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p))};
+    else return *p;
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b % 8).  Remap so that each XCD works on one contiguous range of logical
 // blocks: neighbouring rows gather neighbouring vector entries, which then

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_op_fwd(FwdArgs<VT> a) {
 // (multiples of 64, so each lane keeps its virtual lane across chunks).
 constexpr int kStreamNnz = 2048;
 constexpr int kStreamRows = 256;
-template <typename VT, typename AT>
+template <bool NT, typename VT, typename AT>
 __device__ __forceinline__ void stream_stage(const FwdArgs<VT>& a, const Gather& g, int e0, int e1, AT* prod) {
     constexpr int PER = kStreamNnz / kBlock;
     if (e1 <= e0) return;
@@ -166,8 +166,8 @@ __device__ __forceinline__ void stream_stage(const FwdArgs<VT>& a, const Gather&
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int e = min(e0 + int(threadIdx.x) + u * kBlock, e1 - 1);   // clamped: a valid address
-        c[u] = a.Jc[e];
-        v[u] = cvt<AT>(a.Jv[e]);
+        c[u] = load_val<NT>(a.Jc + e);
+        v[u] = cvt<AT>(load_val<NT>(a.Jv + e));
     }
     double xv[PER];
 #pragma unroll
@@ -178,7 +178,7 @@ __device__ __forceinline__ void stream_stage(const FwdArgs<VT>& a, const Gather&
         if (e0 + k < e1) prod[k] = mul_nc(v[u], AT(xv[u]));
     }
 }
-template <typename VT, typename AT>
+template <typename VT, typename AT, bool NT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_op_fwd_stream(FwdArgs<VT> a, const int2* rb) {
     __shared__ AT prod[kStreamNnz];
     __shared__ int rp[kStreamRows + 1];
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         AT s = AT(0);
         for (int ch = e0; ch < e1; ch += kStreamNnz) {
             const int ce = min(e1, ch + kStreamNnz);
-            stream_stage(a, g, ch, ce, prod);
+            stream_stage<NT>(a, g, ch, ce, prod);
             __syncthreads();
             if (w == 0)
                 for (int k = lane; k < ce - ch; k += 64) s += prod[k];
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         rp[i] = a.Jp[r0 + i] - e0;
         if (i < nr) wl[i] = a.W[r0 + i];
     }
-    stream_stage(a, g, e0, e1, prod);
+    stream_stage<NT>(a, g, e0, e1, prod);
     __syncthreads();
     for (int i = w; i < nr; i += kBlock / 64) {
         const int k0 = rp[i], k1 = rp[i + 1];
@@ -280,7 +280,7 @@ __device__ __forceinline__ void product_tail(double dot, double* part, int b, do
 // q_j = hs*(J^T t + gamma p + U(w .* U^T p))_j + Sigma_x,j p_j + (A^T u)_j and per-block
 // partials of p^T q.  Grid-stride over row groups with a capped grid so the
 // partial count stays small.
-template <int G, typename VT, typename AT>
+template <int G, typename VT, typename AT, bool NT>
 __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
     __shared__ double rowv[kBlock / 4];   // per row of one pass (RPB <= 64)
     if (pcg_stopped_ro(a.fl)) return;
@@ -296,7 +296,9 @@ __global__ __launch_bounds__(kBlock) void k_op_bwd(BwdArgs<VT> a) {
         if (row < a.n) {
             // each part summed in the schedule-independent order, then added
             const AT sj = canon_sum<G, AT>(a.Jtp[row], a.Jtp[row + 1], lane,
-                                           [&](int e) { return cvt<AT>(a.Jtv[e]) * AT(a.t[a.Jtc[e]]); });
+                                           [&](int e) {
+                                               return cvt<AT>(load_val<NT>(a.Jtv + e)) * AT(a.t[load_val<NT>(a.Jtc + e)]);
+                                           });
             double s = a.hs * double(sj);
             if (a.lr_k)
                 s += a.hs * canon_sum<G, double>(0, a.lr_k, lane, [&](int c) {

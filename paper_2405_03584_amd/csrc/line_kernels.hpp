@@ -35,23 +35,6 @@ namespace qpg {
 // 4*kLineHeld slots streams the rest from memory in both passes.
 constexpr int kLineHeld = 32;
 
-// Value loads of the line pass.  Every value is read once per product; when
-// the value array is larger than the last-level cache (MI355X: 256 MB
-// Infinity Cache), cycling it through the caches only evicts what is reused
-// (the gathered vectors, W, the per-slot sums), so such arrays are read with
-// non-temporal loads (NT = true); smaller arrays stay cacheable, and then
-// stay resident between products.
-template <bool NT, typename T>
-__device__ __forceinline__ T load_val(const T* p) {
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-template <bool NT>
-__device__ __forceinline__ bf16_t load_val(const bf16_t* p) {
-    if constexpr (NT) return bf16_t{__builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p))};
-    else return *p;
-}
-
 // Slot groups of the low-precision copies: the P values of one row in P
 // consecutive slots of a line sit together (8 bytes), so a lane loads its
 // row's group in one load and a wavefront moves 512 bytes per load, as with

@@ -291,15 +291,22 @@ int grid_rows(int64_t rows, int G) {
 int grid_rows_capped(int64_t rows, int G) { return std::min(grid_rows(rows, G), kMaxPartials); }
 
 // rb non-null: the rows of J in the nbs blocks of rb (k_op_fwd_stream), else
-// G lanes per row (k_op_fwd).
+// G lanes per row (k_op_fwd).  nt (csr_streamed): the row-block pass reads
+// J's values and column ids with non-temporal loads; its blocks read whole
+// contiguous runs of them.  The G-lane pass keeps cacheable loads: its
+// groups read a row in runs of G entries per load, and a run that ends
+// inside a cache line leaves the rest of that line to the next load, which
+// a non-temporal load would have evicted (measured: slower).
 template <typename VT, typename AT>
-void launch_fwd(hipStream_t st, int G, const FwdArgs<VT>& a0, int nbA, const int2* rb = nullptr, int nbs = 0) {
+void launch_fwd(hipStream_t st, int G, const FwdArgs<VT>& a0, int nbA, bool nt, const int2* rb = nullptr,
+                int nbs = 0) {
     FwdArgs<VT> a = a0;
     a.nbJ = (a.nJ > 0) ? (rb ? nbs : grid_rows(a.nJ, G)) : 0;
     const int grid = a.nbJ + nbA;
     if (grid == 0) return;
     if (rb) {
-        hipLaunchKernelGGL((k_op_fwd_stream<VT, AT>), dim3(grid), dim3(kBlock), 0, st, a, rb);
+        if (nt) hipLaunchKernelGGL((k_op_fwd_stream<VT, AT, true>), dim3(grid), dim3(kBlock), 0, st, a, rb);
+        else hipLaunchKernelGGL((k_op_fwd_stream<VT, AT, false>), dim3(grid), dim3(kBlock), 0, st, a, rb);
         HIPCHK(hipGetLastError());
         return;
     }
@@ -313,15 +320,21 @@ void launch_fwd(hipStream_t st, int G, const FwdArgs<VT>& a0, int nbA, const int
     HIPCHK(hipGetLastError());
 }
 
+// nt (csr_streamed): with 64 lanes per row, whose groups read whole runs of
+// 64 entries per load, J^T's values and row ids are read with non-temporal
+// loads; fewer lanes keep cacheable loads, as in the forward pass.
 template <typename VT, typename AT>
-int launch_bwd(hipStream_t st, int G, const BwdArgs<VT>& a) {
+int launch_bwd(hipStream_t st, int G, const BwdArgs<VT>& a, bool nt) {
     const int grid = grid_rows_capped(a.n, G);
     switch (G) {
-        case 4: hipLaunchKernelGGL((k_op_bwd<4, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 8: hipLaunchKernelGGL((k_op_bwd<8, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 16: hipLaunchKernelGGL((k_op_bwd<16, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        case 32: hipLaunchKernelGGL((k_op_bwd<32, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_op_bwd<64, VT, AT>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_op_bwd<4, VT, AT, false>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_op_bwd<8, VT, AT, false>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 16: hipLaunchKernelGGL((k_op_bwd<16, VT, AT, false>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        case 32: hipLaunchKernelGGL((k_op_bwd<32, VT, AT, false>), dim3(grid), dim3(kBlock), 0, st, a); break;
+        default:
+            if (nt) hipLaunchKernelGGL((k_op_bwd<64, VT, AT, true>), dim3(grid), dim3(kBlock), 0, st, a);
+            else hipLaunchKernelGGL((k_op_bwd<64, VT, AT, false>), dim3(grid), dim3(kBlock), 0, st, a);
+            break;
     }
     HIPCHK(hipGetLastError());
     return (a.n + kChunkRows - 1) / kChunkRows;   // p^T q partials: one per chunk of rows
@@ -351,6 +364,13 @@ constexpr size_t kStreamedValueBytes = size_t(192) << 20;
 template <typename VT>
 bool line_vals_streamed(const qp_handle* h) {
     return size_t(h->nvals) * sizeof(VT) > kStreamedValueBytes;
+}
+// The CSR operator reads J's values and column ids once in each of its two
+// passes (J, then the stored J^T): non-temporal when one pass's arrays
+// exceed the same threshold.
+template <typename VT>
+bool csr_streamed(const qp_handle* h) {
+    return size_t(h->nnzJ) * (sizeof(VT) + sizeof(int)) > kStreamedValueBytes;
 }
 
 // PCG link of a product: in a PCG product (pcg = true) the gathered vector is
@@ -456,7 +476,7 @@ int apply_op(qp_handle* h, const OpWork& wk, const double* x, double* q, const d
         f.aug.dlu = h->dlu; f.aug.q = q; f.aug.n = h->n; f.aug.part = part ? part + n_pq_x : nullptr;
     }
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot], wk.st));
-    launch_fwd<VT, AT>(wk.st, h->GJ, f, nbA, h->fwd_stream ? h->jrb : nullptr, h->nbs);
+    launch_fwd<VT, AT>(wk.st, h->GJ, f, nbA, csr_streamed<VT>(h), h->fwd_stream ? h->jrb : nullptr, h->nbs);
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 1], wk.st));
     lowrank_prepare(h, wk, x, pl.p2, fl);
     BwdArgs<VT> b{};
@@ -466,7 +486,7 @@ int apply_op(qp_handle* h, const OpWork& wk, const double* x, double* q, const d
     b.q = q; b.part = part; b.fl = fl; b.pcg = pl;
     b.U = h->U; b.lr_v = wk.lr_v; b.lr_k = h->k;
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 2], wk.st));
-    const int g = launch_bwd<VT, AT>(wk.st, h->GJt, b);
+    const int g = launch_bwd<VT, AT>(wk.st, h->GJt, b, csr_streamed<VT>(h));
     if (timed) HIPCHK(hipEventRecord(h->tev[4 * tslot + 3], wk.st));
     return part ? g + (aug ? f.m : 0) : 0;
 }
@@ -693,6 +713,7 @@ void autotune_schedule(qp_handle* h) {
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         return ms;
     };
+    const bool nt = csr_streamed<double>(h);
     for (int g : cand) {
         if (g == 0 && !h->jrb) continue;
         float tf = 0.f, tb = 0.f;
@@ -700,7 +721,7 @@ void autotune_schedule(qp_handle* h) {
             FwdArgs<double> f{};
             f.Jp = h->Jp; f.Jc = h->Jc; f.Jv = h->Jv; f.W = h->W; f.nJ = h->nJ;
             f.x = h->zero_n; f.t = h->t; f.u = h->u;
-            const float mf = timed([&] { launch_fwd<double, double>(h->stream, g ? g : 64, f, 0,
+            const float mf = timed([&] { launch_fwd<double, double>(h->stream, g ? g : 64, f, 0, nt,
                                                                      g ? nullptr : h->jrb, h->nbs); });
             if (rep) tf += mf;
             if (g == 0) continue;
@@ -708,7 +729,7 @@ void autotune_schedule(qp_handle* h) {
             b.Jtp = h->Jtp; b.Jtc = h->Jtc; b.Jtv = h->Jtv; b.n = h->n;
             b.Atp = h->Atp; b.Atc = h->Atc; b.Atv = h->Atv; b.hasA = h->m > 0;
             b.t = h->t; b.u = h->zero_m; b.x = h->zero_n; b.hs = 1.0; b.q = h->tmp_n;
-            const float mb = timed([&] { launch_bwd<double, double>(h->stream, g, b); });
+            const float mb = timed([&] { launch_bwd<double, double>(h->stream, g, b, nt); });
             if (rep) tb += mb;
         }
         if (g == 0) {

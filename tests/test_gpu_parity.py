@@ -570,16 +570,20 @@ def test_full_size_solve_matches_oracle(band_full, prec):
     print(f"config2 {prec}: max|x - x_oracle| = {dx:.3e}, certificate {cert.worst():.2e}", flush=True)
 
 
+@pytest.mark.parametrize("fmt", ["line", "csr"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_full_size_operator(band_full, prec):
+def test_full_size_operator(band_full, prec, fmt):
     """K v at full size against the oracle's factor-form H product plus the
     Sigma and A terms, within the rounding bound of the line test (doubled:
-    the reference is rounded too)."""
+    the reference is rounded too).  On CSR at this size (480 MB of FP64
+    values and column ids per pass) both passes read J with non-temporal
+    loads."""
     prob = band_full
     it = qpsynth.random_iterate(prob, 5)
-    h = qpgpu.qp_create_from_problem(prob)
+    settings = qpgpu.qp_default_settings(spmv_format=1) if fmt == "csr" else None
+    h = qpgpu.qp_create_from_problem(prob, settings=settings)
     y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
-    assert info["spmv_format"] == 1
+    assert info["spmv_format"] == (1 if fmt == "line" else 0)
     v, sx, sA = it["v"], it["sigma_x"], it["sigma_A"]
     ref = oracle.hessian_apply(prob, v) + sx * v + prob.A.T @ (sA * (prob.A @ v))
     aJ, aA, av = abs(prob.J), abs(prob.A), np.abs(v)
