@@ -555,19 +555,23 @@ def _golden(name):
         return json.load(f)
 
 
+@pytest.mark.parametrize("fmt", ["line", "csr"])
 @pytest.mark.parametrize("prec", ["fp64", "bf16"])
-def test_full_size_solve_matches_oracle(band_full, prec):
+def test_full_size_solve_matches_oracle(band_full, prec, fmt):
     """Every entry of x against the oracle's stored solution (written by
     tests/golden/make_config2_golden.py from oracle/ only), the objective, and
     the KKT certificate of the whole GPU solution, at the bars of the
-    precision."""
+    precision; in the line format (the default) and on the general CSR path
+    (autotuned schedule, non-temporal loads of J at this size)."""
     prob, g = band_full, _golden("config2_oracle.json")
-    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec))
+    fmt_id = 1 if fmt == "csr" else 0
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(precision=prec, spmv_format=fmt_id))
     res = qpgpu.qp_solve(h)
     assert res.status == qpgpu.QP_OK, res.info
+    assert res.info["spmv_format"] == (1 if fmt == "line" else 0)
     assert len(g["x"]) == prob.n
     dx, cert = check_solve(prob, res, np.array(g["x"]), g["objective"], g["zeta"], prec)
-    print(f"config2 {prec}: max|x - x_oracle| = {dx:.3e}, certificate {cert.worst():.2e}", flush=True)
+    print(f"config2 {prec} {fmt}: max|x - x_oracle| = {dx:.3e}, certificate {cert.worst():.2e}", flush=True)
 
 
 @pytest.mark.parametrize("fmt", ["line", "csr"])
