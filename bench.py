@@ -154,7 +154,8 @@ def operator_only(args, prob):
     from paper_2405_03584_amd import qpgpu
     import qpsynth
     it = qpsynth.random_iterate(prob, 1)
-    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(timing=1))
+    h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(timing=1,
+                                                                             spmv_format=args.spmv_format))
     y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=args.precision,
                                       reps=args.reps)
     n, m, nJ = prob.n, prob.m, prob.J.shape[0]
@@ -165,7 +166,7 @@ def operator_only(args, prob):
     fus = 1e3 * info["t_spmv_fwd_ms"] / max(info["n_spmv_fwd"], 1)
     bus = 1e3 * info["t_spmv_bwd_ms"] / max(info["n_spmv_bwd"], 1)
     print(json.dumps({"mode": "operator", "precision": args.precision, "reps": args.reps,
-                      "format": ["csr", "line"][fmt],
+                      "format": ["csr", "line"][fmt], "spmv_schedule": info.get("spmv_schedule"),
                       "fwd_us": fus, "bwd_us": bus, "fwd_GBs": bf / fus / 1e3, "bwd_GBs": bb / bus / 1e3,
                       "fwd_bytes": bf, "bwd_bytes": bb,
                       "csr_equivalent_fwd_GBs": cf / fus / 1e3, "csr_equivalent_bwd_GBs": cb / bus / 1e3,
@@ -396,6 +397,8 @@ def main():
                          "products only (for counter runs); copy: a plain device copy of the "
                          "J value+index bytes (counter calibration)")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--spmv-format", type=int, default=0, choices=[0, 1],
+                    help="--mode operator: 0 the line format where J has it (the default), 1 CSR")
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
                     help="1: PCG iterations replayed as captured HIP graphs (the production setting); "
                          "0: direct launches (for kernel-trace and counter runs)")
