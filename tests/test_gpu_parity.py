@@ -600,6 +600,23 @@ def test_full_size_operator(band_full, prec, fmt):
     assert np.all(np.abs(y - ref) <= c * bound)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_full_size_csr_schedules_give_identical_bits(band_full, prec):
+    """At full size the CSR passes switch to non-temporal loads of J (row
+    blocks for J, 64 lanes per column for J^T) while 16 lanes per row keep
+    cacheable loads: the load kind must not change a bit of K v."""
+    prob = band_full
+    it = qpsynth.random_iterate(prob, 7)
+    ys = []
+    for sched in (1, 16):
+        h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(spmv_format=1, schedule=sched))
+        y, info = qpgpu.qp_operator_apply(h, it["sigma_x"], it["sigma_A"], it["v"], precision=prec)
+        assert info["spmv_format"] == 0
+        ys.append(y.tobytes())
+        h.close()
+    assert ys[0] == ys[1]
+
+
 # ----------------------------------------------------------------------------
 # captured PCG graphs (a10): replays are exact repeats of the direct launches
 # ----------------------------------------------------------------------------
