@@ -274,6 +274,39 @@ def batch_bench(args):
                       "pcg_phase_ms": max(f["t_pcg_ms"] for f in all_infos)}), flush=True)
 
 
+def systems_bench(args):
+    """The PCG systems and preconditioners on one QP (--systems-qp): the
+    condensed system with the constraint-block preconditioner (the default),
+    the condensed system with the paper's Jacobi preconditioner, and the
+    paper's doubly augmented system (eq. (2x2_augmented), Jacobi).  The
+    Jacobi variants are bounded (--pcg-cap PCG iterations per solve, 60 IPM
+    iterations), since they stall once rows of A become active.  One solve
+    each, FP64, data resident in HBM."""
+    import qpsynth
+    from paper_2405_03584_amd import qpgpu
+    prob = qpsynth.config5(scale=args.scale) if args.systems_qp == "config5" else qpsynth.config2(scale=args.scale)
+    runs = [("condensed, constraint block", {}),
+            ("condensed, Jacobi", {"precond": 0, "pcg_max_iter": args.pcg_cap, "max_ipm_iter": 60}),
+            ("doubly augmented, Jacobi", {"kkt_system": 1, "pcg_max_iter": args.pcg_cap, "max_ipm_iter": 60})]
+    out = []
+    for name, kw in runs:
+        h = qpgpu.qp_create_from_problem(prob, settings=qpgpu.qp_default_settings(**kw))
+        t0 = time.perf_counter()
+        r = qpgpu.qp_solve(h)
+        ms = 1e3 * (time.perf_counter() - t0)
+        i = r.info
+        rec = {"system": name, "status": r.status, "ipm_iters": i["ipm_iters"], "pcg_iters": i["pcg_iters"],
+               "directions_at_pcg_cap": i["pcg_capped"], "ms": ms, "pcg_phase_ms": i["t_pcg_ms"],
+               "us_per_pcg_iter": 1e3 * i["t_pcg_ms"] / max(i["pcg_iters"], 1), "mu": i["mu"],
+               "rnorm": i["rnorm"], "objective": i["objective"]}
+        print(f"[bench] {name}: status {r.status} ipm {i['ipm_iters']} pcg {i['pcg_iters']} {ms:.0f} ms",
+              file=sys.stderr, flush=True)
+        out.append(rec)
+        h.close()
+    print(json.dumps({"workload": f"PCG systems on the {args.systems_qp} QP (scale {args.scale})",
+                      "pcg_cap": args.pcg_cap, "runs": out}), flush=True)
+
+
 def sqp_bench(args):
     """A sequence of `seq_len` SQP sub-problems on the n = 20,000 banded-dose
     QP (rank-2 growth of the quasi-Newton term per step): one handle, per
@@ -402,11 +435,15 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
                     help="1: PCG iterations replayed as captured HIP graphs (the production setting); "
                          "0: direct launches (for kernel-trace and counter runs)")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config5", "batch", "sqp"],
+    ap.add_argument("--workload", default="config2", choices=["config2", "config5", "batch", "sqp", "systems"],
                     help="config2: banded-dose QP n=20,000 (default, the benchmark line); config5: "
                          "n=60,000, BF16-valued J with 200M nnz and a rank-20 term; batch: the 64 "
                          "uneven QPs (n in [2000, 20000]) solved together by qp_solve_batch")
     ap.add_argument("--count", type=int, default=64, help="batch size for --workload batch")
+    ap.add_argument("--systems-qp", default="config2", choices=["config2", "config5"],
+                    help="--workload systems: the QP the PCG systems are compared on")
+    ap.add_argument("--pcg-cap", type=int, default=3000,
+                    help="--workload systems: PCG iterations per solve for the Jacobi variants")
     ap.add_argument("--compare", type=int, default=1, choices=[0, 1],
                     help="--workload batch: also time the QPs one at a time and in the other batch mode")
     ap.add_argument("--batch-mode", type=int, default=0, choices=[0, 1],
@@ -432,6 +469,8 @@ def main():
         return batch_bench(args)
     if args.workload == "sqp":
         return sqp_bench(args)
+    if args.workload == "systems":
+        return systems_bench(args)
     ceiling = stream_ceiling() if args.mode == "solve" else None   # before this process touches the GPU
     t0 = time.perf_counter()
     prob = qpsynth.config5(scale=args.scale) if args.workload == "config5" else qpsynth.config2(scale=args.scale)
